@@ -1,0 +1,199 @@
+/*
+ * dlic.h -- C ABI of the DLIC hot path on AMD Instinct MI355X (gfx950).
+ *
+ * Deep Lossless Image Coding (Barzen, Glazov, Geistert, Sikora, arXiv
+ * 2207.05152) codes an 8-bit greyscale image pixel by pixel: a small fully
+ * connected network turns each pixel's causal neighbourhood into a PDF over
+ * the 256 grey levels (Section II-A, Fig. 2), and an rANS coder codes the
+ * pixel with it (Section II-B, rANS).  Pixels whose neighbourhood is already
+ * coded are processed together in wavefront order (Section II-B,
+ * Preprocessor; Fig. 1 right), and everything stays on the GPU with one
+ * upload and one download (Section II-B, Preprocessor, last paragraph).
+ *
+ * Conventions for every entry point:
+ *   - d_ pointers are device memory owned by the caller; h_ pointers are
+ *     host memory owned by the caller.  The library never frees caller
+ *     memory.  Scratch space is passed in as d_ws of the size the matching
+ *     *_workspace function returns.
+ *   - Work is enqueued on the caller's stream and the call returns without
+ *     synchronising.  Argument errors found on the host are returned
+ *     directly; failures found by kernels (corrupt stream, timeout) are
+ *     written to a device status word that the caller reads after
+ *     synchronising.
+ *   - No call throws or exits.  The library has no CPU fallback: without a
+ *     usable gfx950 device every GPU entry point returns DLIC_ERR_HIP.
+ *   - Results are deterministic: the same inputs give the same bytes.
+ *
+ * Format constants (all fixed by this library): 12-neighbour causal window
+ * (rows y-2, y-1 at dx -2..+2, then (y, x-2), (y, x-1)), values scaled by
+ * (2v-255)/255, dummy 0 outside the image; network 12 -> h1 -> h2 -> 15 with
+ * ReLU; outputs [5 logits, 5 means, 5 log-scales >= -7]; frequency tables of
+ * total 2^16 with every symbol >= 1; 32-bit rANS state, 16-bit words;
+ * wavefront step t = x + 3y.
+ */
+#ifndef DLIC_H
+#define DLIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DLIC_OK = 0,
+  DLIC_ERR_ARG = 1,            /* bad pointer, size or parameter                 */
+  DLIC_ERR_CAPACITY = 2,       /* output or workspace buffer too small           */
+  DLIC_ERR_CORRUPT = 3,        /* stream malformed or inconsistent (device)      */
+  DLIC_ERR_MODEL_MISMATCH = 4, /* stream coded with another model (device)       */
+  DLIC_ERR_UNSUPPORTED = 5,    /* dims, dtype or layout this build does not run  */
+  DLIC_ERR_HIP = 6,            /* HIP runtime error or no usable device          */
+  DLIC_ERR_TIMEOUT = 7         /* a decode wait exceeded its spin limit (device) */
+} dlic_status;
+
+typedef enum { DLIC_FP32 = 0, DLIC_BF16 = 1, DLIC_FP8_E4M3 = 2 } dlic_dtype;
+
+/* Network weights (Section II-B, Neural Network Architecture; the mixture
+ * head of Section I / IV-C).  Matrices are row-major [out][in] in the given
+ * dtype; biases are FP32.  Supported widths: h1 == h2 in {32, 64, 128}. */
+typedef struct dlic_model {
+  int32_t k_in;          /* must be 12                                      */
+  int32_t h1, h2;        /* hidden widths                                   */
+  int32_t n_out;         /* must be 15                                      */
+  int32_t dtype;         /* dlic_dtype of d_w1, d_w2, d_w3                  */
+  int32_t reserved;      /* must be 0                                       */
+  const void *d_w1;      /* [h1][12]                                        */
+  const void *d_w2;      /* [h2][h1]                                        */
+  const void *d_w3;      /* [15][h2]                                        */
+  const float *d_b1, *d_b2, *d_b3;
+  const float *d_wscale; /* FP8: 3 per-layer scales (device); otherwise NULL */
+  uint64_t fingerprint;  /* dlic_fnv1a64 over W1,b1,W2,b2,W3,b3 bytes       */
+} dlic_model;
+
+/* Coder instances (Section II-B, rANS: several coder instances and
+ * bitstreams).  G groups of row strips, each one stream shared by
+ * lanes_per_group interleaved 32-bit rANS states.  Group g owns rows
+ * [g*H/G, (g+1)*H/G); row y of group g is lane (y - r_g) % L.
+ * Constraints: 1 <= L <= 64; G == 1 or H >= 2*G; G <= 1024. */
+typedef struct dlic_coder {
+  int32_t groups;
+  int32_t lanes_per_group;
+} dlic_coder;
+
+/* ---- host-only helpers (no device needed) ----------------------------- */
+
+/* Human-readable name of a status code.  Never NULL. */
+const char *dlic_status_string(dlic_status s);
+
+/* 64-bit FNV-1a of n bytes continuing from hash h (start with
+ * 0xcbf29ce484222325).  Used for the model fingerprint that the stream
+ * header carries, so a decoder refuses weights other than the encoder's
+ * (Section II-B, Preprocessor: both sides must evaluate the same network). */
+uint64_t dlic_fnv1a64(uint64_t h, const void *h_bytes, size_t n);
+
+/* The format's FP32 constant tables, as the kernels use them: the table
+ * logistic knots S[4097] and slopes D[4097] on [-16, 16] (step 2^-7), the
+ * bin edges beta[257] (beta[0] = -inf, beta[256] = +inf) and the scaled grey
+ * levels scale[256].  Any pointer may be NULL. */
+void dlic_host_constants(float *h_S, float *h_D, float *h_beta, float *h_scale);
+
+/* Worst-case stream size in bytes for an h x w image: header, word counts,
+ * at most one 16-bit word per pixel and the flushed states. */
+size_t dlic_encode_bound(int32_t h, int32_t w, const dlic_coder *coder);
+
+/* Scratch bytes dlic_encode / dlic_rans_encode_cf need (d_ws). */
+size_t dlic_encode_workspace(int32_t h, int32_t w, const dlic_coder *coder);
+
+/* Scratch bytes dlic_decode / dlic_rans_decode_tables need (d_ws). */
+size_t dlic_decode_workspace(int32_t h, int32_t w, const dlic_coder *coder);
+
+/* Parse the 36-byte stream header from host bytes.  Any out pointer may be
+ * NULL.  Returns DLIC_ERR_CORRUPT for a bad magic, version or length. */
+dlic_status dlic_peek_header(const uint8_t *h_bits, size_t n, int32_t *h, int32_t *w,
+                             dlic_coder *coder, uint64_t *fingerprint,
+                             int32_t *h1, int32_t *h2, int32_t *dtype);
+
+/* ---- device entry points ------------------------------------------------ */
+
+/* Select and prepare a device: uploads the constant tables once per device.
+ * Idempotent; every other device entry point calls it for the current
+ * device.  Returns DLIC_ERR_HIP if no gfx950 device is usable. */
+dlic_status dlic_init(int device);
+
+/* Encode an 8-bit image (Section II-A, Fig. 2 left; Section II-B).
+ * d_img: [h][w] uint8 row-major.  Phase one computes every pixel's mixture
+ * and frequency interval in parallel (the network on the matrix of all
+ * windows); phase two runs each group's rANS walk in reverse wavefront
+ * order; a pack kernel writes header, word counts and streams to d_out.
+ * out_cap must be >= dlic_encode_bound.  *d_out_len (device, u64) receives
+ * the stream length in bytes. */
+dlic_status dlic_encode(const dlic_model *model, const dlic_coder *coder,
+                        const uint8_t *d_img, int32_t h, int32_t w,
+                        uint8_t *d_out, size_t out_cap, uint64_t *d_out_len,
+                        void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Decode a stream (Section II-A, Fig. 2 right): one persistent workgroup per
+ * group walks the wavefront, evaluating the same network on already decoded
+ * windows and decoding every active pixel from its lane's state.  h, w and
+ * the coder layout are the header's (dlic_peek_header on the host copy of
+ * the first bytes); the kernel re-validates the header against them, the
+ * model and the stream length.  d_img: [h][w] uint8.  *d_status (device,
+ * int32) receives DLIC_OK, or DLIC_ERR_CORRUPT / DLIC_ERR_MODEL_MISMATCH /
+ * DLIC_ERR_TIMEOUT.  A corrupt stream never faults or hangs: every read is
+ * bounds-checked and every wait is bounded. */
+dlic_status dlic_decode(const dlic_model *model, const dlic_coder *coder,
+                        const uint8_t *d_bits, size_t n_bytes, uint8_t *d_img,
+                        int32_t h, int32_t w, int32_t *d_status,
+                        void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Spin limit of one decode wait (polls of an upstream record, each followed
+ * by a short sleep); a wait that exceeds it reports DLIC_ERR_TIMEOUT and the
+ * workgroup continues without waiting again.  Default 2^22.  For tests of the
+ * timeout path. */
+void dlic_set_spin_limit(uint32_t polls);
+
+/* Density of every pixel of a known image with the same device code the
+ * encoder and decoder run (Equation 1; Section II-A).  Outputs, each
+ * optional (NULL to skip), raster order:
+ *   d_out15  [h*w][15] FP32 raw network outputs (logits, means, log-scales)
+ *   d_cf     [h*w] u32: c | (f - 1) << 16 of the pixel's own value
+ *   d_tables [h*w][257] u32 cumulative tables F(0..256) (small images) */
+dlic_status dlic_density(const dlic_model *model, const uint8_t *d_img, int32_t h, int32_t w,
+                         float *d_out15, uint32_t *d_cf, uint32_t *d_tables,
+                         hipStream_t stream);
+
+/* rANS-only encode (Section II-B, rANS) of caller-given intervals:
+ * d_cf [h][w] u32 holds c | (f - 1) << 16 for each pixel (c + f <= 2^16,
+ * f >= 1).  Runs the same rANS and pack kernels as dlic_encode; the header
+ * carries zeros for the model fields.  Same buffers as dlic_encode. */
+dlic_status dlic_rans_encode_cf(const dlic_coder *coder, int32_t h, int32_t w,
+                                const uint32_t *d_cf, uint8_t *d_out, size_t out_cap,
+                                uint64_t *d_out_len, void *d_ws, size_t ws_bytes,
+                                hipStream_t stream);
+
+/* rANS-only decode with caller-given tables: pixel i uses the cumulative
+ * table d_tables[d_tidx[i]][0..256] (strictly increasing from 0 to 2^16).
+ * Runs the decoder's rANS code in wavefront order without the network.
+ * d_sym [h][w] uint8 receives the symbols; *d_status as for dlic_decode. */
+dlic_status dlic_rans_decode_tables(const dlic_coder *coder, int32_t h, int32_t w,
+                                    const uint32_t *d_tables, int32_t n_tables,
+                                    const uint32_t *d_tidx, const uint8_t *d_bits,
+                                    size_t n_bytes, uint8_t *d_sym, int32_t *d_status,
+                                    void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---- measurement ---------------------------------------------------------- */
+
+/* When enabled, every kernel launch of the library is bracketed by HIP
+ * events on the stream it runs on.  dlic_kernel_times copies the durations
+ * (ms) of the most recent call's launches, in launch order, and their
+ * kernel names; it synchronises on those events.  Returns the count. */
+void dlic_set_timing(int enable);
+int dlic_kernel_times(float *h_ms, const char **h_names, int max_n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DLIC_H */

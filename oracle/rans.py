@@ -46,12 +46,18 @@ def group_rows(h: int, groups: int) -> list:
     return [(g * h) // groups for g in range(groups + 1)]
 
 
-def canonical_order(h: int, w: int, groups: int, lanes: int, skew: int = SKEW) -> list:
-    """For each group, the list of (y, x, lane) in canonical order."""
+def canonical_order(h: int, w: int, groups: int, lanes: int, skew: int = SKEW, only=None) -> list:
+    """For each group, the list of (y, x, lane) in canonical order.
+
+    only: optional set of group indices to build (others are left empty).
+    """
     rows = group_rows(h, groups)
     out = []
     for g in range(groups):
         items = []
+        if only is not None and g not in only:
+            out.append([])
+            continue
         for y in range(rows[g], rows[g + 1]):
             r = y - rows[g]
             lane, blk = r % lanes, r // lanes

@@ -1,0 +1,290 @@
+"""Python binding of libdlic, the DLIC hot path on MI355X (gfx950).
+
+Argument marshalling only: every step of encoding and decoding runs in the
+HIP kernels behind the C ABI declared in include/dlic.h.  PyTorch supplies
+device memory and streams.  The functions named dlic_* mirror the C entry
+points one to one; encode()/decode()/density() are conveniences that
+allocate buffers with torch and call them.  There is no CPU fallback: if
+libdlic.so is missing or no gfx950 device is usable, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from ctypes import POINTER, c_char_p, c_float, c_int, c_int32, c_size_t, c_uint32, c_uint64, c_void_p
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdlic.so")
+
+DLIC_OK, DLIC_ERR_ARG, DLIC_ERR_CAPACITY, DLIC_ERR_CORRUPT = 0, 1, 2, 3
+DLIC_ERR_MODEL_MISMATCH, DLIC_ERR_UNSUPPORTED, DLIC_ERR_HIP, DLIC_ERR_TIMEOUT = 4, 5, 6, 7
+DLIC_FP32, DLIC_BF16, DLIC_FP8_E4M3 = 0, 1, 2
+FNV_OFFSET = 0xCBF29CE484222325
+HEADER_BYTES = 36
+
+# Every symbol include/dlic.h declares.
+EXPORTS = (
+    "dlic_status_string", "dlic_fnv1a64", "dlic_host_constants", "dlic_encode_bound",
+    "dlic_encode_workspace", "dlic_decode_workspace", "dlic_peek_header", "dlic_init",
+    "dlic_encode", "dlic_decode", "dlic_set_spin_limit", "dlic_density",
+    "dlic_rans_encode_cf", "dlic_rans_decode_tables", "dlic_set_timing", "dlic_kernel_times",
+)
+
+
+class DlicError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        self.status = int(status)
+        super().__init__(f"{where}: {status_string(self.status)} ({self.status})")
+
+
+class dlic_model(ctypes.Structure):
+    _fields_ = [("k_in", c_int32), ("h1", c_int32), ("h2", c_int32), ("n_out", c_int32),
+                ("dtype", c_int32), ("reserved", c_int32), ("d_w1", c_void_p), ("d_w2", c_void_p),
+                ("d_w3", c_void_p), ("d_b1", c_void_p), ("d_b2", c_void_p), ("d_b3", c_void_p),
+                ("d_wscale", c_void_p), ("fingerprint", c_uint64)]
+
+
+class dlic_coder(ctypes.Structure):
+    _fields_ = [("groups", c_int32), ("lanes_per_group", c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libdlic.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2207_05152_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P, S = c_void_p, c_size_t
+    sig = {
+        "dlic_status_string": (c_char_p, [c_int]),
+        "dlic_fnv1a64": (c_uint64, [c_uint64, P, S]),
+        "dlic_host_constants": (None, [P, P, P, P]),
+        "dlic_encode_bound": (S, [c_int32, c_int32, POINTER(dlic_coder)]),
+        "dlic_encode_workspace": (S, [c_int32, c_int32, POINTER(dlic_coder)]),
+        "dlic_decode_workspace": (S, [c_int32, c_int32, POINTER(dlic_coder)]),
+        "dlic_peek_header": (c_int, [P, S, POINTER(c_int32), POINTER(c_int32), POINTER(dlic_coder),
+                                     POINTER(c_uint64), POINTER(c_int32), POINTER(c_int32),
+                                     POINTER(c_int32)]),
+        "dlic_init": (c_int, [c_int]),
+        "dlic_encode": (c_int, [POINTER(dlic_model), POINTER(dlic_coder), P, c_int32, c_int32, P, S,
+                                P, P, S, P]),
+        "dlic_decode": (c_int, [POINTER(dlic_model), POINTER(dlic_coder), P, S, P, c_int32, c_int32,
+                                P, P, S, P]),
+        "dlic_set_spin_limit": (None, [c_uint32]),
+        "dlic_density": (c_int, [POINTER(dlic_model), P, c_int32, c_int32, P, P, P, P]),
+        "dlic_rans_encode_cf": (c_int, [POINTER(dlic_coder), c_int32, c_int32, P, P, S, P, P, S, P]),
+        "dlic_rans_decode_tables": (c_int, [POINTER(dlic_coder), c_int32, c_int32, P, c_int32, P, P,
+                                            S, P, P, P, S, P]),
+        "dlic_set_timing": (None, [c_int]),
+        "dlic_kernel_times": (c_int, [P, P, c_int]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def status_string(s: int) -> str:
+    try:
+        return lib().dlic_status_string(int(s)).decode()
+    except RuntimeError:
+        return f"status {s}"
+
+
+def _check(rc: int, where: str):
+    if rc != DLIC_OK:
+        raise DlicError(rc, where)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+# ---- one-to-one wrappers of the C entry points ---------------------------------
+
+def dlic_fnv1a64(h: int, data: bytes) -> int:
+    buf = ctypes.create_string_buffer(bytes(data), len(data))
+    return int(lib().dlic_fnv1a64(h, buf, len(data)))
+
+
+def dlic_host_constants():
+    S = np.empty(4097, np.float32); D = np.empty(4097, np.float32)
+    beta = np.empty(257, np.float32); scale = np.empty(256, np.float32)
+    lib().dlic_host_constants(S.ctypes.data, D.ctypes.data, beta.ctypes.data, scale.ctypes.data)
+    return S, D, beta, scale
+
+
+def dlic_encode_bound(h: int, w: int, coder: dlic_coder) -> int:
+    return int(lib().dlic_encode_bound(h, w, ctypes.byref(coder)))
+
+
+def dlic_encode_workspace(h: int, w: int, coder: dlic_coder) -> int:
+    return int(lib().dlic_encode_workspace(h, w, ctypes.byref(coder)))
+
+
+def dlic_decode_workspace(h: int, w: int, coder: dlic_coder) -> int:
+    return int(lib().dlic_decode_workspace(h, w, ctypes.byref(coder)))
+
+
+def dlic_peek_header(head: bytes) -> dict:
+    h, w, h1, h2, dt = (c_int32() for _ in range(5))
+    fp = c_uint64()
+    cd = dlic_coder()
+    buf = ctypes.create_string_buffer(bytes(head), len(head))
+    _check(lib().dlic_peek_header(buf, len(head), ctypes.byref(h), ctypes.byref(w), ctypes.byref(cd),
+                                  ctypes.byref(fp), ctypes.byref(h1), ctypes.byref(h2),
+                                  ctypes.byref(dt)), "dlic_peek_header")
+    return dict(h=h.value, w=w.value, coder=cd, fingerprint=fp.value, h1=h1.value, h2=h2.value,
+                dtype=dt.value)
+
+
+def dlic_init(device: int = 0):
+    _check(lib().dlic_init(device), "dlic_init")
+
+
+def dlic_encode(model: dlic_model, coder: dlic_coder, d_img, h, w, d_out, out_cap, d_out_len,
+                d_ws, ws_bytes, stream=None):
+    _check(lib().dlic_encode(ctypes.byref(model), ctypes.byref(coder), _ptr(d_img), h, w, _ptr(d_out),
+                             out_cap, _ptr(d_out_len), _ptr(d_ws), ws_bytes, _stream(stream)),
+           "dlic_encode")
+
+
+def dlic_decode(model: dlic_model, coder: dlic_coder, d_bits, n_bytes, d_img, h, w, d_status,
+                d_ws, ws_bytes, stream=None):
+    _check(lib().dlic_decode(ctypes.byref(model), ctypes.byref(coder), _ptr(d_bits), n_bytes,
+                             _ptr(d_img), h, w, _ptr(d_status), _ptr(d_ws), ws_bytes,
+                             _stream(stream)), "dlic_decode")
+
+
+def dlic_set_spin_limit(polls: int):
+    lib().dlic_set_spin_limit(int(polls))
+
+
+def dlic_density(model: dlic_model, d_img, h, w, d_out15=None, d_cf=None, d_tables=None,
+                 stream=None):
+    _check(lib().dlic_density(ctypes.byref(model), _ptr(d_img), h, w, _ptr(d_out15), _ptr(d_cf),
+                              _ptr(d_tables), _stream(stream)), "dlic_density")
+
+
+def dlic_rans_encode_cf(coder: dlic_coder, h, w, d_cf, d_out, out_cap, d_out_len, d_ws, ws_bytes,
+                        stream=None):
+    _check(lib().dlic_rans_encode_cf(ctypes.byref(coder), h, w, _ptr(d_cf), _ptr(d_out), out_cap,
+                                     _ptr(d_out_len), _ptr(d_ws), ws_bytes, _stream(stream)),
+           "dlic_rans_encode_cf")
+
+
+def dlic_rans_decode_tables(coder: dlic_coder, h, w, d_tables, n_tables, d_tidx, d_bits, n_bytes,
+                            d_sym, d_status, d_ws, ws_bytes, stream=None):
+    _check(lib().dlic_rans_decode_tables(ctypes.byref(coder), h, w, _ptr(d_tables), n_tables,
+                                         _ptr(d_tidx), _ptr(d_bits), n_bytes, _ptr(d_sym),
+                                         _ptr(d_status), _ptr(d_ws), ws_bytes, _stream(stream)),
+           "dlic_rans_decode_tables")
+
+
+def dlic_set_timing(enable: bool):
+    lib().dlic_set_timing(1 if enable else 0)
+
+
+def dlic_kernel_times(max_n: int = 16):
+    ms = (c_float * max_n)()
+    names = (c_char_p * max_n)()
+    n = lib().dlic_kernel_times(ctypes.cast(ms, c_void_p), ctypes.cast(names, c_void_p), max_n)
+    return [(names[i].decode(), float(ms[i])) for i in range(n)]
+
+
+# ---- conveniences (torch-allocated buffers) -------------------------------------
+
+def default_coder(h: int, lanes: int = 32, rows_per_group: int = 192) -> dlic_coder:
+    """G = ceil(h / rows_per_group) row strips of `lanes` interleaved lanes."""
+    g = max(1, math.ceil(h / rows_per_group))
+    if g > 1 and h < 2 * g:
+        g = max(1, h // 2)
+    return dlic_coder(g, lanes)
+
+
+class Model:
+    """FP32 network weights resident on a device, with their C descriptor."""
+
+    def __init__(self, weights: dict, device="cuda"):
+        import torch
+        self.np = {k: np.ascontiguousarray(weights[k], dtype=np.float32)
+                   for k in ("W1", "b1", "W2", "b2", "W3", "b3")}
+        self.t = {k: torch.from_numpy(v).to(device) for k, v in self.np.items()}
+        h = FNV_OFFSET
+        for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+            h = dlic_fnv1a64(h, self.np[k].tobytes())
+        self.fingerprint = h
+        h1, h2 = self.np["W1"].shape[0], self.np["W2"].shape[0]
+        self.c = dlic_model(12, h1, h2, 15, DLIC_FP32, 0, _ptr(self.t["W1"]), _ptr(self.t["W2"]),
+                            _ptr(self.t["W3"]), _ptr(self.t["b1"]), _ptr(self.t["b2"]),
+                            _ptr(self.t["b3"]), None, h)
+
+
+def _empty(n, dtype, device="cuda"):
+    import torch
+    return torch.empty(max(int(n), 1), dtype=dtype, device=device)
+
+
+def encode(img, model: Model, coder: dlic_coder | None = None, stream=None):
+    """Encode a [h, w] uint8 device tensor; returns the stream as a uint8 device tensor."""
+    import torch
+    h, w = img.shape
+    coder = coder or default_coder(h)
+    cap = dlic_encode_bound(h, w, coder)
+    out = _empty(cap, torch.uint8, img.device)
+    olen = _empty(1, torch.int64, img.device)
+    wsb = dlic_encode_workspace(h, w, coder)
+    ws = _empty(wsb, torch.uint8, img.device)
+    dlic_encode(model.c, coder, img.contiguous(), h, w, out, cap, olen, ws, wsb, stream)
+    n = int(olen.item())
+    return out[:n]
+
+
+def decode(bits, model: Model, stream=None, check=True):
+    """Decode a stream (uint8 device tensor); returns ([h, w] uint8 tensor, status)."""
+    import torch
+    head = bits[:HEADER_BYTES].cpu().numpy().tobytes()
+    hd = dlic_peek_header(head)
+    h, w, coder = hd["h"], hd["w"], hd["coder"]
+    img = torch.empty((h, w), dtype=torch.uint8, device=bits.device)
+    st = torch.zeros(1, dtype=torch.int32, device=bits.device)
+    wsb = dlic_decode_workspace(h, w, coder)
+    ws = _empty(wsb, torch.uint8, bits.device)
+    dlic_decode(model.c, coder, bits.contiguous(), bits.numel(), img, h, w, st, ws, wsb, stream)
+    status = int(st.item())
+    if check and status != DLIC_OK:
+        raise DlicError(status, "dlic_decode (device status)")
+    return img, status
+
+
+def density(img, model: Model, tables=False, stream=None):
+    """Raw outputs [n, 15], packed intervals [n] and optionally tables [n, 257] of an image."""
+    import torch
+    h, w = img.shape
+    n = h * w
+    out15 = torch.empty((n, 15), dtype=torch.float32, device=img.device)
+    cf = torch.empty(n, dtype=torch.int32, device=img.device)
+    tab = torch.empty((n, 257), dtype=torch.int32, device=img.device) if tables else None
+    dlic_density(model.c, img.contiguous(), h, w, out15, cf, tab, stream)
+    return out15, cf, tab

@@ -1,0 +1,439 @@
+// C ABI of the DLIC hot path (see include/dlic.h for the contract of every
+// entry point).  This file validates arguments, carves caller workspace,
+// builds the format's constant tables once per device and enqueues the
+// kernels; all per-pixel work happens in the kernels.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/dlic.h"
+#include "dlic_kernels.h"
+
+using namespace dlic;
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+constexpr int MAX_TIMED = 16;
+
+struct DeviceState {
+  bool ready = false;
+  Consts* consts = nullptr;
+};
+
+std::mutex g_mu;
+DeviceState g_dev[MAX_DEVICES];
+uint32_t g_spin_limit = 1u << 22;
+
+struct TimedLaunch {
+  const char* name;
+  hipEvent_t start, stop;
+};
+bool g_timing = false;
+std::vector<TimedLaunch> g_events;  // pool, reused
+int g_n_timed = 0;
+
+void build_consts(Consts* c) {
+  for (int j = 0; j < LUT_N; ++j) {
+    const double t = -16.0 + (double)j / 128.0;
+    double s;
+    if (t >= 0) {
+      s = 1.0 / (1.0 + exp(-t));
+    } else {
+      const double e = exp(t);
+      s = e / (1.0 + e);
+    }
+    c->sd[j].x = (float)s;
+  }
+  for (int j = 0; j < LUT_N; ++j) c->sd[j].y = (j + 1 < LUT_N) ? c->sd[j + 1].x - c->sd[j].x : 0.0f;
+  for (int v = 0; v <= 256; ++v) c->beta[v] = ((float)(2 * v) - 256.0f) / 255.0f;
+  c->beta[0] = -INFINITY;
+  c->beta[256] = INFINITY;
+  for (int v = 0; v < 256; ++v) c->scale[v] = ((float)(2 * v) - 255.0f) / 255.0f;
+}
+
+dlic_status ensure_device(int device, const Consts** out) {
+  if (device < 0 || device >= MAX_DEVICES) return DLIC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceState& st = g_dev[device];
+  if (!st.ready) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return DLIC_ERR_HIP;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return DLIC_ERR_UNSUPPORTED;
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return DLIC_ERR_HIP;
+    if (hipSetDevice(device) != hipSuccess) return DLIC_ERR_HIP;
+    Consts host;
+    build_consts(&host);
+    Consts* d = nullptr;
+    dlic_status rc = DLIC_OK;
+    if (hipMalloc((void**)&d, sizeof(Consts)) != hipSuccess ||
+        hipMemcpy(d, &host, sizeof(Consts), hipMemcpyHostToDevice) != hipSuccess)
+      rc = DLIC_ERR_HIP;
+    (void)hipSetDevice(prev);
+    if (rc != DLIC_OK) return rc;
+    st.consts = d;
+    st.ready = true;
+  }
+  if (out) *out = st.consts;
+  return DLIC_OK;
+}
+
+dlic_status current_consts(const Consts** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DLIC_ERR_HIP;
+  return ensure_device(dev, out);
+}
+
+// --- timing -----------------------------------------------------------------
+void timing_reset() { g_n_timed = 0; }
+
+void timing_begin(const char* name, hipStream_t s) {
+  if (!g_timing) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_n_timed >= MAX_TIMED) return;
+  if ((int)g_events.size() <= g_n_timed) {
+    TimedLaunch tl;
+    (void)hipEventCreate(&tl.start);
+    (void)hipEventCreate(&tl.stop);
+    g_events.push_back(tl);
+  }
+  g_events[g_n_timed].name = name;
+  (void)hipEventRecord(g_events[g_n_timed].start, s);
+}
+
+void timing_end(hipStream_t s) {
+  if (!g_timing) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_n_timed >= MAX_TIMED) return;
+  (void)hipEventRecord(g_events[g_n_timed].stop, s);
+  ++g_n_timed;
+}
+
+dlic_status launch_ok() {
+  return hipGetLastError() == hipSuccess ? DLIC_OK : DLIC_ERR_HIP;
+}
+
+// --- validation -------------------------------------------------------------
+bool coder_ok(int h, const dlic_coder* c) {
+  if (!c) return false;
+  const int G = c->groups, L = c->lanes_per_group;
+  if (L < 1 || L > 64 || G < 1 || G > 1024) return false;
+  if (G > 1 && h < 2 * G) return false;
+  return true;
+}
+
+int max_group_rows(int h, int G) {
+  int m = 0;
+  for (int g = 0; g < G; ++g) {
+    const int r = (int)(((long long)(g + 1) * h) / G - ((long long)g * h) / G);
+    if (r > m) m = r;
+  }
+  return m;
+}
+
+dlic_status model_ok(const dlic_model* m) {
+  if (!m) return DLIC_ERR_ARG;
+  if (m->k_in != K_IN || m->n_out != N_OUT || m->reserved != 0) return DLIC_ERR_ARG;
+  if (!m->d_w1 || !m->d_w2 || !m->d_w3 || !m->d_b1 || !m->d_b2 || !m->d_b3) return DLIC_ERR_ARG;
+  if (m->dtype != DLIC_FP32) return DLIC_ERR_UNSUPPORTED;
+  if (m->h1 != m->h2 || (m->h1 != 32 && m->h1 != 64)) return DLIC_ERR_UNSUPPORTED;
+  return DLIC_OK;
+}
+
+DevModel dev_model(const dlic_model* m) {
+  DevModel d;
+  d.w1 = (const float*)m->d_w1;
+  d.w2 = (const float*)m->d_w2;
+  d.w3 = (const float*)m->d_w3;
+  d.b1 = m->d_b1;
+  d.b2 = m->d_b2;
+  d.b3 = m->d_b3;
+  return d;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct EncWs {
+  uint32_t* cf;
+  uint16_t* words;
+  uint32_t* counts;
+};
+
+size_t enc_ws_layout(int h, int w, int G, int L, void* base, EncWs* out) {
+  const size_t n = (size_t)h * w;
+  const size_t o_cf = 0;
+  const size_t o_words = align256(o_cf + 4 * n);
+  const size_t o_counts = align256(o_words + 2 * (n + 2 * (size_t)L * G));
+  const size_t total = align256(o_counts + 4 * (size_t)G);
+  if (out && base) {
+    char* b = (char*)base;
+    out->cf = (uint32_t*)(b + o_cf);
+    out->words = (uint16_t*)(b + o_words);
+    out->counts = (uint32_t*)(b + o_counts);
+  }
+  return total;
+}
+
+long long n_steps(int h, int w) { return (long long)w + 3LL * h - 3; }
+
+int density_grid(long long n) {
+  long long blocks = (n + 255) / 256;
+  if (blocks > 768) blocks = 768;
+  if (blocks < 1) blocks = 1;
+  return (int)blocks;
+}
+
+int pack_chunks(long long n, int G) {
+  long long per_group = (n / (G > 0 ? G : 1)) / 4096 + 1;
+  if (per_group > 64) per_group = 64;
+  return (int)per_group;
+}
+
+dlic_status run_rans_and_pack(int h, int w, const dlic_coder* coder, const uint32_t* cf,
+                              const EncWs& ws, const HeaderFields& hf, uint8_t* d_out,
+                              uint64_t* d_out_len, hipStream_t s) {
+  const int G = coder->groups, L = coder->lanes_per_group;
+  timing_begin("rans_encode_kernel", s);
+  launch_rans_encode(cf, h, w, G, L, ws.words, ws.counts, s);
+  timing_end(s);
+  if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
+  timing_begin("pack_kernel", s);
+  launch_pack(ws.words, ws.counts, h, w, G, L, hf, d_out, d_out_len,
+              pack_chunks((long long)h * w, G), s);
+  timing_end(s);
+  return launch_ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dlic_status_string(dlic_status s) {
+  switch (s) {
+    case DLIC_OK: return "ok";
+    case DLIC_ERR_ARG: return "invalid argument";
+    case DLIC_ERR_CAPACITY: return "buffer too small";
+    case DLIC_ERR_CORRUPT: return "corrupt stream";
+    case DLIC_ERR_MODEL_MISMATCH: return "stream coded with another model";
+    case DLIC_ERR_UNSUPPORTED: return "unsupported parameters";
+    case DLIC_ERR_HIP: return "HIP error or no usable device";
+    case DLIC_ERR_TIMEOUT: return "decode wait timed out";
+  }
+  return "unknown status";
+}
+
+uint64_t dlic_fnv1a64(uint64_t h, const void* h_bytes, size_t n) {
+  const uint8_t* p = (const uint8_t*)h_bytes;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 0x100000001B3ull;
+  }
+  return h;
+}
+
+void dlic_host_constants(float* h_S, float* h_D, float* h_beta, float* h_scale) {
+  Consts* c = new Consts;
+  build_consts(c);
+  for (int j = 0; j < LUT_N; ++j) {
+    if (h_S) h_S[j] = c->sd[j].x;
+    if (h_D) h_D[j] = c->sd[j].y;
+  }
+  if (h_beta) memcpy(h_beta, c->beta, sizeof(c->beta));
+  if (h_scale) memcpy(h_scale, c->scale, sizeof(c->scale));
+  delete c;
+}
+
+size_t dlic_encode_bound(int32_t h, int32_t w, const dlic_coder* coder) {
+  if (h <= 0 || w <= 0 || !coder_ok(h, coder)) return 0;
+  const size_t G = coder->groups, L = coder->lanes_per_group;
+  return HEADER_BYTES + 4 * G + 2 * ((size_t)h * w + 2 * L * G);
+}
+
+size_t dlic_encode_workspace(int32_t h, int32_t w, const dlic_coder* coder) {
+  if (h <= 0 || w <= 0 || !coder_ok(h, coder)) return 0;
+  return enc_ws_layout(h, w, coder->groups, coder->lanes_per_group, nullptr, nullptr);
+}
+
+size_t dlic_decode_workspace(int32_t h, int32_t w, const dlic_coder* coder) {
+  if (h <= 0 || w <= 0 || !coder_ok(h, coder)) return 0;
+  return align256(4 * (size_t)coder->groups * (size_t)n_steps(h, w));
+}
+
+dlic_status dlic_peek_header(const uint8_t* b, size_t n, int32_t* h, int32_t* w,
+                             dlic_coder* coder, uint64_t* fingerprint, int32_t* h1, int32_t* h2,
+                             int32_t* dtype) {
+  if (!b || n < (size_t)HEADER_BYTES) return DLIC_ERR_CORRUPT;
+  if (memcmp(b, "DLIC", 4) != 0) return DLIC_ERR_CORRUPT;
+  auto u16 = [&](int o) { return (uint32_t)b[o] | ((uint32_t)b[o + 1] << 8); };
+  auto u32 = [&](int o) { return u16(o) | (u16(o + 2) << 16); };
+  if (u16(4) != 1u) return DLIC_ERR_CORRUPT;
+  const int G = (int)u16(26), L = b[25];
+  if (h) *h = (int32_t)u32(8);
+  if (w) *w = (int32_t)u32(12);
+  if (dtype) *dtype = b[18];
+  if (h1) *h1 = (int32_t)u16(20);
+  if (h2) *h2 = (int32_t)u16(22);
+  if (coder) {
+    coder->groups = G;
+    coder->lanes_per_group = L;
+  }
+  if (fingerprint) *fingerprint = (uint64_t)u32(28) | ((uint64_t)u32(32) << 32);
+  return DLIC_OK;
+}
+
+dlic_status dlic_init(int device) { return ensure_device(device, nullptr); }
+
+dlic_status dlic_encode(const dlic_model* model, const dlic_coder* coder, const uint8_t* d_img,
+                        int32_t h, int32_t w, uint8_t* d_out, size_t out_cap,
+                        uint64_t* d_out_len, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  timing_reset();
+  if (!d_img || !d_out || !d_out_len || !d_ws || h <= 0 || w <= 0) return DLIC_ERR_ARG;
+  if (!coder_ok(h, coder)) return DLIC_ERR_UNSUPPORTED;
+  dlic_status rc = model_ok(model);
+  if (rc != DLIC_OK) return rc;
+  if (out_cap < dlic_encode_bound(h, w, coder)) return DLIC_ERR_CAPACITY;
+  if (ws_bytes < dlic_encode_workspace(h, w, coder)) return DLIC_ERR_CAPACITY;
+  const Consts* K = nullptr;
+  if ((rc = current_consts(&K)) != DLIC_OK) return rc;
+  EncWs ws;
+  enc_ws_layout(h, w, coder->groups, coder->lanes_per_group, d_ws, &ws);
+  const long long n = (long long)h * w;
+  timing_begin("density_kernel", stream);
+  launch_density(model->h1, K, dev_model(model), d_img, h, w, ws.cf, nullptr, nullptr,
+                 density_grid(n), stream);
+  timing_end(stream);
+  if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
+  HeaderFields hf{model->dtype, model->h1, model->h2, model->fingerprint};
+  return run_rans_and_pack(h, w, coder, ws.cf, ws, hf, d_out, d_out_len, stream);
+}
+
+dlic_status dlic_rans_encode_cf(const dlic_coder* coder, int32_t h, int32_t w,
+                                const uint32_t* d_cf, uint8_t* d_out, size_t out_cap,
+                                uint64_t* d_out_len, void* d_ws, size_t ws_bytes,
+                                hipStream_t stream) {
+  timing_reset();
+  if (!d_cf || !d_out || !d_out_len || !d_ws || h <= 0 || w <= 0) return DLIC_ERR_ARG;
+  if (!coder_ok(h, coder)) return DLIC_ERR_UNSUPPORTED;
+  if (out_cap < dlic_encode_bound(h, w, coder)) return DLIC_ERR_CAPACITY;
+  if (ws_bytes < dlic_encode_workspace(h, w, coder)) return DLIC_ERR_CAPACITY;
+  dlic_status rc = current_consts(nullptr);
+  if (rc != DLIC_OK) return rc;
+  EncWs ws;
+  enc_ws_layout(h, w, coder->groups, coder->lanes_per_group, d_ws, &ws);
+  HeaderFields hf{0, 0, 0, 0ull};
+  return run_rans_and_pack(h, w, coder, d_cf, ws, hf, d_out, d_out_len, stream);
+}
+
+static dlic_status decode_common(const dlic_model* model, bool tables_mode,
+                                 const dlic_coder* coder, const uint32_t* d_tables,
+                                 int32_t n_tables, const uint32_t* d_tidx, const uint8_t* d_bits,
+                                 size_t n_bytes, uint8_t* d_img, int32_t h, int32_t w,
+                                 int32_t* d_status, void* d_ws, size_t ws_bytes,
+                                 hipStream_t stream) {
+  timing_reset();
+  if (!d_bits || !d_img || !d_status || !d_ws || h <= 0 || w <= 0) return DLIC_ERR_ARG;
+  if (!coder_ok(h, coder)) return DLIC_ERR_UNSUPPORTED;
+  if (max_group_rows(h, coder->groups) > DEC_RMAX) return DLIC_ERR_UNSUPPORTED;
+  if ((long long)w + 3LL * h > (1LL << 30)) return DLIC_ERR_UNSUPPORTED;
+  if (ws_bytes < dlic_decode_workspace(h, w, coder)) return DLIC_ERR_CAPACITY;
+  dlic_status rc;
+  const Consts* K = nullptr;
+  if ((rc = current_consts(&K)) != DLIC_OK) return rc;
+  DecArgs a;
+  memset(&a, 0, sizeof(a));
+  a.bits = d_bits;
+  a.n_bytes = n_bytes;
+  a.img = d_img;
+  a.H = h;
+  a.W = w;
+  a.G = coder->groups;
+  a.L = coder->lanes_per_group;
+  a.rec = (uint32_t*)d_ws;
+  a.T = n_steps(h, w);
+  a.status = d_status;
+  a.spin_limit = g_spin_limit;
+  DevModel dm;
+  memset(&dm, 0, sizeof(dm));
+  int width = 32;
+  if (tables_mode) {
+    if (!d_tables || !d_tidx || n_tables < 1) return DLIC_ERR_ARG;
+    a.tables = d_tables;
+    a.n_tables = n_tables;
+    a.tidx = d_tidx;
+  } else {
+    if ((rc = model_ok(model)) != DLIC_OK) return rc;
+    a.check_model = 1;
+    a.hf = HeaderFields{model->dtype, model->h1, model->h2, model->fingerprint};
+    dm = dev_model(model);
+    width = model->h1;
+  }
+  timing_begin("fill_u32_kernel", stream);
+  launch_fill_u32(a.rec, 0u, (long long)a.G * a.T, stream);
+  launch_fill_u32((uint32_t*)d_status, 0u, 1, stream);
+  timing_end(stream);
+  if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
+  timing_begin(tables_mode ? "wavefront_decode_kernel<tables>" : "wavefront_decode_kernel",
+               stream);
+  if (!launch_decode(width, tables_mode, K, dm, a, stream)) return DLIC_ERR_UNSUPPORTED;
+  timing_end(stream);
+  return launch_ok();
+}
+
+dlic_status dlic_decode(const dlic_model* model, const dlic_coder* coder,
+                        const uint8_t* d_bits, size_t n_bytes, uint8_t* d_img, int32_t h,
+                        int32_t w, int32_t* d_status, void* d_ws, size_t ws_bytes,
+                        hipStream_t stream) {
+  return decode_common(model, false, coder, nullptr, 0, nullptr, d_bits, n_bytes, d_img, h, w,
+                       d_status, d_ws, ws_bytes, stream);
+}
+
+dlic_status dlic_rans_decode_tables(const dlic_coder* coder, int32_t h, int32_t w,
+                                    const uint32_t* d_tables, int32_t n_tables,
+                                    const uint32_t* d_tidx, const uint8_t* d_bits,
+                                    size_t n_bytes, uint8_t* d_sym, int32_t* d_status,
+                                    void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  return decode_common(nullptr, true, coder, d_tables, n_tables, d_tidx, d_bits, n_bytes, d_sym,
+                       h, w, d_status, d_ws, ws_bytes, stream);
+}
+
+dlic_status dlic_density(const dlic_model* model, const uint8_t* d_img, int32_t h, int32_t w,
+                         float* d_out15, uint32_t* d_cf, uint32_t* d_tables, hipStream_t stream) {
+  timing_reset();
+  if (!d_img || h <= 0 || w <= 0) return DLIC_ERR_ARG;
+  dlic_status rc = model_ok(model);
+  if (rc != DLIC_OK) return rc;
+  const Consts* K = nullptr;
+  if ((rc = current_consts(&K)) != DLIC_OK) return rc;
+  timing_begin("density_kernel", stream);
+  launch_density(model->h1, K, dev_model(model), d_img, h, w, d_cf, d_out15, d_tables,
+                 density_grid((long long)h * w), stream);
+  timing_end(stream);
+  return launch_ok();
+}
+
+void dlic_set_spin_limit(uint32_t polls) { g_spin_limit = polls ? polls : 1u; }
+
+void dlic_set_timing(int enable) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_timing = enable != 0;
+}
+
+int dlic_kernel_times(float* h_ms, const char** h_names, int max_n) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int n = g_n_timed < max_n ? g_n_timed : max_n;
+  for (int i = 0; i < n; ++i) {
+    float ms = -1.0f;
+    if (hipEventSynchronize(g_events[i].stop) == hipSuccess)
+      (void)hipEventElapsedTime(&ms, g_events[i].start, g_events[i].stop);
+    if (h_ms) h_ms[i] = ms;
+    if (h_names) h_names[i] = g_events[i].name;
+  }
+  return n;
+}
+
+}  // extern "C"

@@ -1,0 +1,254 @@
+// Encoder kernels of the DLIC hot path (Section II-A, Fig. 2 left; Section II-B).
+//
+// Phase A, density_kernel: every pixel's window goes through the network as
+// one big matrix (Section II-B, Preprocessor: one row per window), 16-pixel
+// MFMA tiles, 64 pixels per wave; the head and the FP32 table rule then give
+// the pixel's interval (c, f) in its table.  All pixels are independent.
+//
+// Phase B, rans_encode_kernel: rANS is last-in first-out, so each group's
+// symbols are coded walking the canonical wavefront order backwards; one
+// wave per group, one lane per coder instance (Section II-B, rANS), words
+// placed by ballot rank so the stream reads forward in decoding order.
+//
+// pack_kernel: header, per-group word counts and the streams, concatenated.
+#include "dlic_device.hpp"
+#include "dlic_kernels.h"
+
+namespace dlic {
+
+// Stride (floats) of one pixel's outputs in the per-wave LDS staging area.
+constexpr int O_STRIDE = 16;
+
+template <int H1, int H2>
+__global__ __launch_bounds__(256) void density_kernel(const Consts* __restrict__ K, DevModel m,
+                                                      const uint8_t* __restrict__ img, int H,
+                                                      int W, uint32_t* __restrict__ cf,
+                                                      float* __restrict__ out15,
+                                                      uint32_t* __restrict__ tables) {
+  __shared__ float2 s_sd[LUT_N];
+  __shared__ float s_beta[257];
+  __shared__ float s_scale[256];
+  __shared__ __attribute__((aligned(16))) float s_o[4][64 * O_STRIDE];
+
+  const int tid = threadIdx.x;
+  for (int i = tid; i < LUT_N; i += 256) s_sd[i] = K->sd[i];
+  for (int i = tid; i < 257; i += 256) s_beta[i] = K->beta[i];
+  s_scale[tid] = K->scale[tid];
+  __syncthreads();
+
+  const int lane = tid & 63, wave = tid >> 6, q = lane >> 4;
+  NetF32<H1, H2> net;
+  net.load(m, lane);
+
+  const long long n = (long long)H * W;
+  const long long n_blk = (n + 255) / 256;
+  for (long long blk = blockIdx.x; blk < n_blk; blk += gridDim.x) {
+    const long long base = blk * 256 + wave * 64;
+#pragma unroll 1
+    for (int tile = 0; tile < 4; ++tile) {
+      const long long p = base + tile * 16 + (lane & 15);
+      float fk[3] = {0.0f, 0.0f, 0.0f};
+      if (p < n) {
+        const int y = (int)(p / W), x = (int)(p - (long long)y * W);
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+          const int k = 4 * kk + q;
+          const int yy = y + nb_dy(k), xx = x + nb_dx(k);
+          if (yy >= 0 && xx >= 0 && xx < W) fk[kk] = s_scale[img[(long long)yy * W + xx]];
+        }
+      }
+      const f4 o = net.run(fk[0], fk[1], fk[2]);
+      *reinterpret_cast<f4*>(&s_o[wave][(tile * 16 + (lane & 15)) * O_STRIDE + 4 * q]) = o;
+    }
+    __syncthreads();
+    const long long p = base + lane;
+    if (p < n) {
+      float o[16];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const f4 v = *reinterpret_cast<const f4*>(&s_o[wave][lane * O_STRIDE + 4 * i]);
+        o[4 * i] = v[0];
+        o[4 * i + 1] = v[1];
+        o[4 * i + 2] = v[2];
+        o[4 * i + 3] = v[3];
+      }
+      const Mix mix = mixture_head(o);
+      const int v = img[p];
+      const uint32_t Flo = cdf_F(v, mix, s_sd, s_beta);
+      const uint32_t Fhi = cdf_F(v + 1, mix, s_sd, s_beta);
+      if (cf) cf[p] = Flo | ((Fhi - Flo - 1u) << 16);
+      if (out15) {
+#pragma unroll
+        for (int k = 0; k < N_OUT; ++k) out15[p * N_OUT + k] = o[k];
+      }
+      if (tables) {
+        for (int lv = 0; lv <= 256; ++lv) tables[p * 257 + lv] = cdf_F(lv, mix, s_sd, s_beta);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Sub-round (t, j) of group g: lane l holds row r0 + j*L + l, column t - 3*row.
+struct SubroundCursor {
+  int t, j;
+};
+
+__device__ __forceinline__ uint32_t load_cf(const uint32_t* __restrict__ cf, int t, int j,
+                                            int lane, int L, int r0, int R, int W) {
+  const int rr = j * L + lane;
+  const int y = r0 + rr;
+  const int x = t - SKEW * y;
+  if (lane < L && rr < R && x >= 0 && x < W) return cf[(long long)y * W + x];
+  return INACTIVE;
+}
+
+constexpr int ENC_BATCH = 8;
+
+// One wave per group.  Words go below the top of the group's scratch slice
+// (cap_g = R*W + 2L words, the worst case), so a stream is contiguous at
+// [cap_g - count, cap_g).
+__global__ __launch_bounds__(64) void rans_encode_kernel(const uint32_t* __restrict__ cf, int H,
+                                                         int W, int G, int L,
+                                                         uint16_t* __restrict__ words,
+                                                         uint32_t* __restrict__ counts) {
+  const int g = blockIdx.x, lane = threadIdx.x;
+  const int r0 = group_row(g, H, G), r1 = group_row(g + 1, H, G);
+  const int R = r1 - r0;
+  const int J = (R + L - 1) / L;
+  const long long cap = (long long)R * W + 2LL * L;
+  uint16_t* out = words + (long long)r0 * W + 2LL * L * g;
+  uint32_t Q = (uint32_t)cap;
+  uint32_t x = RANS_L;
+
+  if (R > 0) {
+    const int t_first = SKEW * r0, t_last = SKEW * (r1 - 1) + W - 1;
+    // cursor walks (t, j) downwards from (t_last, J-1)
+    SubroundCursor ld = {t_last, J - 1};
+    long long remaining = (long long)(t_last - t_first + 1) * J;
+    uint32_t cur[ENC_BATCH], nxt[ENC_BATCH];
+#pragma unroll
+    for (int i = 0; i < ENC_BATCH; ++i) {
+      cur[i] = (ld.t >= t_first) ? load_cf(cf, ld.t, ld.j, lane, L, r0, R, W) : INACTIVE;
+      if (--ld.j < 0) { ld.j = J - 1; --ld.t; }
+    }
+    while (remaining > 0) {
+#pragma unroll
+      for (int i = 0; i < ENC_BATCH; ++i) {
+        nxt[i] = (ld.t >= t_first) ? load_cf(cf, ld.t, ld.j, lane, L, r0, R, W) : INACTIVE;
+        if (--ld.j < 0) { ld.j = J - 1; --ld.t; }
+      }
+#pragma unroll
+      for (int i = 0; i < ENC_BATCH; ++i) {
+        const uint32_t v = cur[i];
+        const bool act = v != INACTIVE;
+        const uint32_t c = v & 0xFFFFu, f = (v >> 16) + 1u;
+        Q = rans_enc_subround(x, act, c, f, out, Q);
+      }
+#pragma unroll
+      for (int i = 0; i < ENC_BATCH; ++i) cur[i] = nxt[i];
+      remaining -= ENC_BATCH;
+    }
+  }
+  // flush: states as (low, high) pairs for lanes 0..L-1 at the stream head
+  Q -= 2u * (uint32_t)L;
+  if (lane < L) {
+    out[Q + 2 * lane] = (uint16_t)(x & 0xFFFFu);
+    out[Q + 2 * lane + 1] = (uint16_t)(x >> 16);
+  }
+  if (lane == 0) counts[g] = (uint32_t)cap - Q;
+}
+
+__device__ __forceinline__ void put_u16(uint8_t* p, uint32_t v) {
+  p[0] = (uint8_t)v;
+  p[1] = (uint8_t)(v >> 8);
+}
+__device__ __forceinline__ void put_u32(uint8_t* p, uint32_t v) {
+  for (int i = 0; i < 4; ++i) p[i] = (uint8_t)(v >> (8 * i));
+}
+
+// grid (chunks, G): block (c, g) copies part of group g's stream; block (0, 0)
+// also writes the header, the counts and the total length.
+__global__ __launch_bounds__(256) void pack_kernel(const uint16_t* __restrict__ words,
+                                                   const uint32_t* __restrict__ counts, int H,
+                                                   int W, int G, int L, HeaderFields hf,
+                                                   uint8_t* __restrict__ out,
+                                                   uint64_t* __restrict__ out_len) {
+  const int g = blockIdx.y;
+  __shared__ unsigned long long s_before, s_total;
+  if (threadIdx.x == 0) {
+    unsigned long long before = 0, total = 0;
+    for (int i = 0; i < G; ++i) {
+      total += counts[i];
+      if (i < g) before += counts[i];
+    }
+    s_before = before;
+    s_total = total;
+  }
+  __syncthreads();
+  const long long hdr = HEADER_BYTES + 4LL * G;
+  if (g == 0 && blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      out[0] = 'D'; out[1] = 'L'; out[2] = 'I'; out[3] = 'C';
+      put_u16(out + 4, 1u);
+      put_u16(out + 6, 0u);
+      put_u32(out + 8, (uint32_t)H);
+      put_u32(out + 12, (uint32_t)W);
+      out[16] = (uint8_t)K_IN;
+      out[17] = (uint8_t)N_MIX;
+      out[18] = (uint8_t)hf.dtype;
+      out[19] = (uint8_t)SKEW;
+      put_u16(out + 20, (uint32_t)hf.h1);
+      put_u16(out + 22, (uint32_t)hf.h2);
+      out[24] = (uint8_t)PROB_BITS;
+      out[25] = (uint8_t)L;
+      put_u16(out + 26, (uint32_t)G);
+      put_u32(out + 28, (uint32_t)hf.fingerprint);
+      put_u32(out + 32, (uint32_t)(hf.fingerprint >> 32));
+      *out_len = (uint64_t)(hdr + 2LL * (long long)s_total);
+    }
+    for (int i = threadIdx.x; i < G; i += blockDim.x) put_u32(out + HEADER_BYTES + 4 * i, counts[i]);
+  }
+  const int r0 = group_row(g, H, G), r1 = group_row(g + 1, H, G);
+  const long long cap = (long long)(r1 - r0) * W + 2LL * L;
+  const uint32_t cnt = counts[g];
+  const uint16_t* src = words + (long long)r0 * W + 2LL * L * g + (cap - cnt);
+  uint8_t* dst = out + hdr + 2LL * (long long)s_before;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x)
+    put_u16(dst + 2 * i, src[i]);
+}
+
+// ---- host-side launchers -------------------------------------------------
+
+template <int H1, int H2>
+static void launch_density_t(const Consts* K, const DevModel& m, const uint8_t* img, int H,
+                             int W, uint32_t* cf, float* out15, uint32_t* tables, int grid,
+                             hipStream_t s) {
+  hipLaunchKernelGGL((density_kernel<H1, H2>), dim3(grid), dim3(256), 0, s, K, m, img, H, W, cf,
+                     out15, tables);
+}
+
+bool launch_density(int width, const Consts* K, const DevModel& m, const uint8_t* img, int H,
+                    int W, uint32_t* cf, float* out15, uint32_t* tables, int grid,
+                    hipStream_t s) {
+  switch (width) {
+    case 32: launch_density_t<32, 32>(K, m, img, H, W, cf, out15, tables, grid, s); return true;
+    case 64: launch_density_t<64, 64>(K, m, img, H, W, cf, out15, tables, grid, s); return true;
+    default: return false;
+  }
+}
+
+void launch_rans_encode(const uint32_t* cf, int H, int W, int G, int L, uint16_t* words,
+                        uint32_t* counts, hipStream_t s) {
+  hipLaunchKernelGGL(rans_encode_kernel, dim3(G), dim3(64), 0, s, cf, H, W, G, L, words, counts);
+}
+
+void launch_pack(const uint16_t* words, const uint32_t* counts, int H, int W, int G, int L,
+                 const HeaderFields& hf, uint8_t* out, uint64_t* out_len, int chunks,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(pack_kernel, dim3(chunks, G), dim3(256), 0, s, words, counts, H, W, G, L, hf,
+                     out, out_len);
+}
+
+}  // namespace dlic

@@ -1,0 +1,47 @@
+// Launchers shared between the kernel files and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dlic_device.hpp"
+
+namespace dlic {
+
+struct HeaderFields {
+  int dtype, h1, h2;
+  uint64_t fingerprint;
+};
+
+// Decoder limits: rows per group, and the per-group stream ring in LDS.
+constexpr int DEC_RMAX = 256;
+constexpr int DEC_RING = 4096;
+
+struct DecArgs {
+  const uint8_t* bits;
+  unsigned long long n_bytes;
+  uint8_t* img;
+  int H, W, G, L;
+  uint32_t* rec;          // [G][T] progress records, cleared before launch
+  long long T;            // wavefront steps W + 3H - 3
+  int* status;
+  uint32_t spin_limit;
+  int check_model;        // compare header model fields with the ones below
+  HeaderFields hf;
+  const uint32_t* tables;  // table mode: [n_tables][257]
+  int n_tables;
+  const uint32_t* tidx;    // table mode: [H*W]
+};
+
+bool launch_density(int width, const Consts* K, const DevModel& m, const uint8_t* img, int H,
+                    int W, uint32_t* cf, float* out15, uint32_t* tables, int grid, hipStream_t s);
+void launch_rans_encode(const uint32_t* cf, int H, int W, int G, int L, uint16_t* words,
+                        uint32_t* counts, hipStream_t s);
+void launch_pack(const uint16_t* words, const uint32_t* counts, int H, int W, int G, int L,
+                 const HeaderFields& hf, uint8_t* out, uint64_t* out_len, int chunks,
+                 hipStream_t s);
+bool launch_decode(int width, bool tables_mode, const Consts* K, const DevModel& m,
+                   const DecArgs& a, hipStream_t s);
+void launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t s);
+
+}  // namespace dlic

@@ -1,0 +1,70 @@
+"""The C-ABI library loads and exports what include/dlic.h declares; host-only
+helpers agree with the oracle (CPU, no device calls)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2207_05152_amd as dl
+from conftest import ROOT
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dlic.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dlic_\w+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(dl.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(dl.EXPORTS)
+
+
+def test_constant_tables_match_oracle_bit_for_bit():
+    S, D, beta, scale = dl.dlic_host_constants()
+    So, Do = oracle.sigma_lut32()
+    assert np.array_equal(S.view(np.uint32), So.view(np.uint32))
+    assert np.array_equal(D.view(np.uint32), Do.view(np.uint32))
+    assert np.array_equal(beta.view(np.uint32), oracle.beta32().view(np.uint32))
+    assert np.array_equal(scale.view(np.uint32), oracle.scale32().view(np.uint32))
+
+
+def test_fnv_and_fingerprint_match_oracle(golden):
+    for ln in golden("fnv1a64.txt"):
+        text, want = ln.rsplit(":", 1)
+        assert dl.dlic_fnv1a64(dl.FNV_OFFSET, text.strip().strip('"').encode()) == int(want, 16)
+    import synth
+    w = synth.xavier_mlp((12, 32, 32, 15), 7)
+    h = dl.FNV_OFFSET
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        h = dl.dlic_fnv1a64(h, w[k].tobytes())
+    assert h == oracle.weights_fingerprint(w)
+
+
+def test_bounds_and_workspace():
+    c = dl.dlic_coder(8, 32)
+    assert dl.dlic_encode_bound(1536, 2048, c) == 36 + 4 * 8 + 2 * (1536 * 2048 + 2 * 32 * 8)
+    assert dl.dlic_encode_workspace(1536, 2048, c) >= 6 * 1536 * 2048
+    assert dl.dlic_decode_workspace(1536, 2048, c) >= 4 * 8 * (2048 + 3 * 1536 - 3)
+    assert dl.dlic_encode_bound(10, 10, dl.dlic_coder(6, 32)) == 0      # H < 2G
+    assert dl.dlic_encode_bound(10, 10, dl.dlic_coder(1, 65)) == 0      # L > 64
+
+
+def test_peek_header_reads_oracle_header():
+    hdr = oracle.pack_header(1536, 2048, 8, 32, dtype=0, h1=64, h2=64, fp=0xFEEDFACE01234567)
+    raw = hdr + bytes(4 * 8)
+    p = dl.dlic_peek_header(raw)
+    assert (p["h"], p["w"], p["coder"].groups, p["coder"].lanes_per_group, p["h1"], p["h2"]) == \
+        (1536, 2048, 8, 32, 64, 64)
+    assert p["fingerprint"] == 0xFEEDFACE01234567
+    with pytest.raises(dl.DlicError):
+        dl.dlic_peek_header(b"XLIC" + raw[4:])
+    with pytest.raises(dl.DlicError):
+        dl.dlic_peek_header(raw[:20])
