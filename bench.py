@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Encode/decode throughput of the DLIC hot path on one MI355X.
+
+One step = encode the image (density kernel, rANS kernel, pack kernel),
+fetch the stream length, decode it (wavefront kernel).  The input image is
+resident in HBM before the timed region.  Prints one JSON line.
+
+Workload (default): a 2048x1536 synthetic greyscale image (seed 1), network
+12-64-64-15 FP32 (Glorot, seed 3), 8 row groups x 32 interleaved rANS lanes.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MI355X_FP32_MFMA = 157.3e12
+MI355X_CUS = 256
+
+
+def mlp_flops_per_px(h1, h2):
+    return 2 * (12 * h1 + h1 * h2 + h2 * 15)
+
+
+def schedule_bound_px(h, w, G):
+    """Sum over wavefront steps of the largest per-group active pixel count."""
+    rows = [(g * h) // G for g in range(G + 1)]
+    T = w + 3 * h - 3
+    t = np.arange(T)
+    worst = np.zeros(T, dtype=np.int64)
+    for g in range(G):
+        r0, r1 = rows[g], rows[g + 1]
+        ylo = np.maximum(r0, np.floor_divide(t - w, 3) + 1)
+        yhi = np.minimum(r1 - 1, np.floor_divide(t, 3))
+        worst = np.maximum(worst, np.maximum(0, yhi - ylo + 1))
+    return int(worst.sum())
+
+
+def cpu_baseline(img, weights, groups, lanes, target_s=15.0):
+    """Time the oracle's encode + decode on a crop of the image (1 thread)."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    crop_h = 16
+    with threadpool_limits(limits=1):
+        # size the crop so the run takes roughly target_s
+        probe = np.ascontiguousarray(img[:crop_h, :128])
+        t0 = time.perf_counter()
+        b = oracle.encode_image(probe, weights, oracle.OracleCoder(1, lanes))
+        oracle.decode_image(b, weights)
+        per_px = (time.perf_counter() - t0) / probe.size
+        n_px = int(min(img.size, max(4096, target_s / max(per_px, 1e-9))))
+        cw = min(img.shape[1], 512)
+        ch = max(2, min(img.shape[0], n_px // cw))
+        crop = np.ascontiguousarray(img[:ch, :cw])
+        t0 = time.perf_counter()
+        bits = oracle.encode_image(crop, weights, oracle.OracleCoder(max(1, min(groups, ch // 2)), lanes))
+        dec = oracle.decode_image(bits, weights)
+        dt = time.perf_counter() - t0
+    assert np.array_equal(dec, crop)
+    return {"value": crop.size / dt / 1e6, "unit": "MPix/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle encode+decode of the top-left {ch}x{cw} crop, 1 thread, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--height", type=int, default=1536)
+    ap.add_argument("--width", type=int, default=2048)
+    ap.add_argument("--hidden", type=int, default=64)
+    ap.add_argument("--groups", type=int, default=8)
+    ap.add_argument("--lanes", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the DLIC hot path here runs on a single MI355X "
+              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2207_05152_amd as dl
+    import synth
+
+    torch.cuda.set_device(0)
+    dl.dlic_init(0)
+    H, W, Hd = args.height, args.width, args.hidden
+    img_np = synth.synth_image(H, W, 1)
+    weights = synth.xavier_mlp((12, Hd, Hd, 15), 3)
+    model = dl.Model(weights, "cuda:0")
+    coder = dl.dlic_coder(args.groups, args.lanes)
+    img = torch.from_numpy(img_np).cuda()
+    n_px = H * W
+
+    cap = dl.dlic_encode_bound(H, W, coder)
+    out = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    olen = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ews = torch.empty(dl.dlic_encode_workspace(H, W, coder), dtype=torch.uint8, device="cuda")
+    dws = torch.empty(dl.dlic_decode_workspace(H, W, coder), dtype=torch.uint8, device="cuda")
+    dec = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    kt = {}
+
+    def step(record):
+        dl.dlic_encode(model.c, coder, img, H, W, out, cap, olen, ews, ews.numel(), stream)
+        if record:
+            for name, ms in dl.dlic_kernel_times():
+                kt.setdefault(name, []).append(ms)
+        n = int(olen.item())
+        dl.dlic_decode(model.c, coder, out, n, dec, H, W, st, dws, dws.numel(), stream)
+        if record:
+            for name, ms in dl.dlic_kernel_times():
+                kt.setdefault(name, []).append(ms)
+        return n
+
+    dl.dlic_set_timing(True)
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        n_bytes = step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    dl.dlic_set_timing(False)
+
+    assert int(st.item()) == 0, f"decode status {int(st.item())}"
+    assert torch.equal(dec, img), "round trip is not lossless"
+
+    avg = {k: float(np.mean(v)) for k, v in kt.items()}
+    enc_ms = avg.get("density_kernel", 0) + avg.get("rans_encode_kernel", 0) + avg.get("pack_kernel", 0)
+    dec_ms = avg.get("wavefront_decode_kernel", 0) + avg.get("fill_u32_kernel", 0)
+    ms_step = elapsed / args.steps * 1e3
+    flops = n_px * mlp_flops_per_px(Hd, Hd)
+    dom = max(avg, key=avg.get)
+    dom_flops = flops if dom in ("wavefront_decode_kernel", "density_kernel") else 0
+    achieved = dom_flops / (avg[dom] * 1e-3) if dom_flops else 0.0
+    crit_px = schedule_bound_px(H, W, args.groups)
+    sched_ms = crit_px * mlp_flops_per_px(Hd, Hd) / (MI355X_FP32_MFMA / MI355X_CUS) * 1e3
+
+    res = {
+        "metric": "encode/decode MPix/s on 1 MI355X + bpp",
+        "value": n_px / (ms_step * 1e-3) / 1e6,
+        "unit": "MPix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{W}x{H} synthetic greyscale image (seed 1), MLP 12-{Hd}-{Hd}-15 FP32 "
+                        f"(Glorot seed 3), {args.groups} row groups x {args.lanes} rANS lanes; "
+                        f"one step = encode + decode",
+            "image": [H, W], "hidden": Hd, "groups": args.groups, "lanes_per_group": args.lanes,
+        },
+        "encode_mpix_s": n_px / (enc_ms * 1e-3) / 1e6 if enc_ms else None,
+        "decode_mpix_s": n_px / (dec_ms * 1e-3) / 1e6 if dec_ms else None,
+        "bpp_total": 8.0 * n_bytes / n_px,
+        "bpp_payload": 8.0 * (n_bytes - 36 - 4 * args.groups) / n_px,
+        "kernel_ms": avg,
+        "roofline": {
+            "kernel": dom,
+            "bound": "mfma",
+            "achieved": achieved / 1e12,
+            "peak": MI355X_FP32_MFMA / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / MI355X_FP32_MFMA,
+            "traffic": None,
+        },
+        "decode_schedule_bound": {
+            "critical_px": crit_px,
+            "bound_ms": sched_ms,
+            "frac": sched_ms / avg["wavefront_decode_kernel"] if "wavefront_decode_kernel" in avg else None,
+            "note": "only one CU per row group can work on a group's step; bound = sum over steps "
+                    "of the busiest group's pixels x FLOP/px at one CU's FP32 MFMA peak",
+        },
+        "host": {"cpu": platform.processor() or platform.machine(), "os_cpus": os.cpu_count()},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(img_np, weights, args.groups, args.lanes)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()
