@@ -138,6 +138,20 @@ def main():
     elapsed = time.perf_counter() - t0
     dl.dlic_set_timing(False)
 
+    # one more decode with the in-kernel cycle counters on (outside the timed region)
+    prof = torch.zeros(8 * args.groups, dtype=torch.int64, device="cuda")
+    dl.dlic_set_decode_profile(prof)
+    dl.dlic_decode(model.c, coder, out, n_bytes, dec, H, W, st, dws, dws.numel(), stream)
+    torch.cuda.synchronize()
+    dl.dlic_set_decode_profile(None)
+    pc = prof.view(args.groups, 8).cpu().numpy().astype(np.float64)
+    busy = pc[:, 0] + pc[:, 1]
+    decode_profile = {
+        "coder_wait_frac": float(pc[:, 0].sum() / max(busy.sum(), 1)),
+        "worker_wait_frac": float(pc[:, 2].sum() / max((pc[:, 2] + pc[:, 3]).sum(), 1)),
+        "coder_cycles_per_group": [int(v) for v in busy],
+    }
+
     assert int(st.item()) == 0, f"decode status {int(st.item())}"
     assert torch.equal(dec, img), "round trip is not lossless"
 
@@ -192,6 +206,7 @@ def main():
             "note": "only one CU per row group can work on a group's step; bound = sum over steps "
                     "of the busiest group's pixels x FLOP/px at one CU's FP32 MFMA peak",
         },
+        "decode_profile": decode_profile,
         "host": {"cpu": platform.processor() or platform.machine(), "os_cpus": os.cpu_count()},
     }
     if not args.no_cpu_baseline:

@@ -76,7 +76,8 @@ typedef struct dlic_model {
  * bitstreams).  G groups of row strips, each one stream shared by
  * lanes_per_group interleaved 32-bit rANS states.  Group g owns rows
  * [g*H/G, (g+1)*H/G); row y of group g is lane (y - r_g) % L.
- * Constraints: 1 <= L <= 64; G == 1 or H >= 2*G; G <= 1024. */
+ * Constraints: 1 <= L <= 64; G <= 1024; G == 1 or H >= 2*G; at most 256
+ * rows per group (the decoder keeps a group's pixel ring in LDS). */
 typedef struct dlic_coder {
   int32_t groups;
   int32_t lanes_per_group;
@@ -191,6 +192,13 @@ dlic_status dlic_rans_decode_tables(const dlic_coder *coder, int32_t h, int32_t 
  * kernel names; it synchronises on those events.  Returns the count. */
 void dlic_set_timing(int enable);
 int dlic_kernel_times(float *h_ms, const char **h_names, int max_n);
+
+/* When d_counters is non-NULL, later dlic_decode calls add shader-clock
+ * cycle counts per group g to d_counters[8g .. 8g+3] (device, zeroed by the
+ * caller): coder waiting for densities, coder busy, density waves waiting
+ * for decoded pixels (sum over waves), density waves busy (sum).  NULL turns
+ * it off. */
+void dlic_set_decode_profile(unsigned long long *d_counters);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,8 @@ from .network import mlp_forward, mixture_head, N_MIX, N_OUT, LOG_SCALE_MIN
 from .mixture import (bin_edges, sigmoid, mixture_cdf, log_pmf, pmf_table,
                       ideal_bits, ideal_bits_image)
 from .freq import (PROB_BITS, M_TOTAL, M_PRIME, table_exact, sigma_lut32,
-                   sigma_hat32, beta32, scale32, table_levels32, table_full32)
+                   sigma_hat32, table_coords32, beta32, scale32, table_levels32,
+                   table_full32)
 from .rans import (RANS_L, group_rows, canonical_order, rans_encode, rans_decode)
 from .container import (HEADER_SIZE, pack_header, parse_header, fingerprint,
                          assemble, split_streams)

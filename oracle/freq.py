@@ -19,13 +19,18 @@ Two evaluations of C are provided:
   * the format rule in FP32 (``table_levels32`` / ``table_full32``), which
     is what a decoder must reproduce bit for bit: the logistic is a
     piecewise-linear table on [-16, 16] with step 2^-7 whose 4097 knots are
-    S_j = RN32(sigma(-16 + j/128)) and slopes D_j = S_{j+1} - S_j (exact),
-    and every operation is one FP32 multiply or add (no fused multiply-add):
-        t = (beta_v - mu_k) * inv_s_k
-        u = clamp((t + 16) * 128, 0, 4096);  j = min(floor(u), 4095);  w = u - j
-        sigma_hat = S_j + w * D_j
-        C = ((0 + pi_0 sigma_hat_0) + pi_1 sigma_hat_1) + ... + pi_4 sigma_hat_4
+    S_j = RN32(sigma(-16 + j/128)) and slopes D_j = S_{j+1} - S_j (exact,
+    D_4096 = 0), and every operation is one FP32 multiply or add (no fused
+    multiply-add).  Per pixel and component, from the FP32 parameters:
+        A_k = inv_s_k * 128            B_k = 2048 - mu_k * A_k
+    and per level v:
+        u = clamp(beta_v * A_k + B_k, 0, 4096)      (the table coordinate of
+                                                     (beta_v - mu_k) inv_s_k)
+        j = floor(u);  w = u - j;  sigma_hat = S_j + w * D_j
+        C = pi_0 sigma_hat_0;  C = C + pi_k sigma_hat_k for k = 1..4
         q = min(M', floor(C * 65280))
+    u is non-decreasing in beta (A_k > 0) and every rounding is monotone, so
+    F is non-decreasing in v for any parameters and every table is valid.
     The oracle takes this integer decision in FP32, the kernel's precision.
 
 Parity: pinned by table validity (sum M, every f >= 1) for random
@@ -87,16 +92,22 @@ def _lut():
     return _LUT
 
 
-def sigma_hat32(t) -> np.ndarray:
-    """Table logistic of FP32 arguments, every step in FP32."""
+def sigma_hat32(u) -> np.ndarray:
+    """Table logistic at FP32 table coordinates u (clamped to [0, 4096]), in FP32."""
     S, D = _lut()
-    t = np.asarray(t, dtype=np.float32)
-    u = (t + np.float32(16.0)) * np.float32(128.0)
+    u = np.asarray(u, dtype=np.float32)
     u = np.where(u > np.float32(0.0), u, np.float32(0.0))
     u = np.minimum(u, np.float32(4096.0))
-    j = np.minimum(u.astype(np.int64), LUT_SEGMENTS - 1)
+    j = u.astype(np.int64)
     w = u - j.astype(np.float32)
     return S[j] + w * D[j]
+
+
+def table_coords32(mu32, is32):
+    """Per-component affine map (A, B) of the table coordinate, FP32."""
+    A = np.asarray(is32, dtype=np.float32) * np.float32(128.0)
+    B = np.float32(2048.0) - np.asarray(mu32, dtype=np.float32) * A
+    return A.astype(np.float32), B.astype(np.float32)
 
 
 def beta32() -> np.ndarray:
@@ -116,10 +127,12 @@ def scale32() -> np.ndarray:
 
 
 def _cdf32(beta, pi32, mu32, is32):
-    C = np.zeros(beta.shape, dtype=np.float32)
+    A, B = table_coords32(mu32, is32)
+    C = None
     for k in range(pi32.shape[-1]):
-        t = (beta - mu32[..., k:k + 1]) * is32[..., k:k + 1]
-        C = C + pi32[..., k:k + 1] * sigma_hat32(t)
+        u = beta * A[..., k:k + 1] + B[..., k:k + 1]
+        term = pi32[..., k:k + 1] * sigma_hat32(u)
+        C = term if C is None else C + term
     return C
 
 

@@ -31,6 +31,7 @@ EXPORTS = (
     "dlic_encode_workspace", "dlic_decode_workspace", "dlic_peek_header", "dlic_init",
     "dlic_encode", "dlic_decode", "dlic_set_spin_limit", "dlic_density",
     "dlic_rans_encode_cf", "dlic_rans_decode_tables", "dlic_set_timing", "dlic_kernel_times",
+    "dlic_set_decode_profile",
 )
 
 
@@ -85,6 +86,7 @@ def lib():
                                             S, P, P, P, S, P]),
         "dlic_set_timing": (None, [c_int]),
         "dlic_kernel_times": (c_int, [P, P, c_int]),
+        "dlic_set_decode_profile": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -204,6 +206,10 @@ def dlic_rans_decode_tables(coder: dlic_coder, h, w, d_tables, n_tables, d_tidx,
 
 def dlic_set_timing(enable: bool):
     lib().dlic_set_timing(1 if enable else 0)
+
+
+def dlic_set_decode_profile(d_counters):
+    lib().dlic_set_decode_profile(_ptr(d_counters))
 
 
 def dlic_kernel_times(max_n: int = 16):

@@ -28,6 +28,7 @@ struct DeviceState {
 std::mutex g_mu;
 DeviceState g_dev[MAX_DEVICES];
 uint32_t g_spin_limit = 1u << 22;
+unsigned long long* g_prof = nullptr;
 
 struct TimedLaunch {
   const char* name;
@@ -119,14 +120,6 @@ dlic_status launch_ok() {
 }
 
 // --- validation -------------------------------------------------------------
-bool coder_ok(int h, const dlic_coder* c) {
-  if (!c) return false;
-  const int G = c->groups, L = c->lanes_per_group;
-  if (L < 1 || L > 64 || G < 1 || G > 1024) return false;
-  if (G > 1 && h < 2 * G) return false;
-  return true;
-}
-
 int max_group_rows(int h, int G) {
   int m = 0;
   for (int g = 0; g < G; ++g) {
@@ -134,6 +127,17 @@ int max_group_rows(int h, int G) {
     if (r > m) m = r;
   }
   return m;
+}
+
+// Layouts this library writes and reads: 1..64 lanes, at most 1024 groups,
+// every group at least 2 rows (G == 1 aside) and at most 256 rows.
+bool coder_ok(int h, const dlic_coder* c) {
+  if (!c) return false;
+  const int G = c->groups, L = c->lanes_per_group;
+  if (L < 1 || L > 64 || G < 1 || G > 1024) return false;
+  if (G > 1 && h < 2 * G) return false;
+  if (max_group_rows(h, G) > DEC_RMAX) return false;
+  return true;
 }
 
 dlic_status model_ok(const dlic_model* m) {
@@ -357,6 +361,7 @@ static dlic_status decode_common(const dlic_model* model, bool tables_mode,
   a.T = n_steps(h, w);
   a.status = d_status;
   a.spin_limit = g_spin_limit;
+  a.prof = tables_mode ? nullptr : g_prof;
   DevModel dm;
   memset(&dm, 0, sizeof(dm));
   int width = 32;
@@ -417,6 +422,8 @@ dlic_status dlic_density(const dlic_model* model, const uint8_t* d_img, int32_t 
 }
 
 void dlic_set_spin_limit(uint32_t polls) { g_spin_limit = polls ? polls : 1u; }
+
+void dlic_set_decode_profile(unsigned long long* d_counters) { g_prof = d_counters; }
 
 void dlic_set_timing(int enable) {
   std::lock_guard<std::mutex> lk(g_mu);

@@ -2,28 +2,41 @@
 // Section II-B, Preprocessor and rANS; Fig. 1 right).
 //
 // One persistent workgroup per group of rows.  In wavefront step t every
-// pixel (y, x) with x + 3y == t has all 12 window pixels decoded (the
-// up-right neighbour (y-1, x+2) finished in step t-1), so the workgroup
-//   1. receives the two rows above its strip from the upstream group,
-//   2. runs the network on all its active pixels (16-pixel MFMA tiles over
-//      the four waves) and the mixture head,
-//   3. decodes the active pixels lane by lane in canonical order with wave 0
-//      (slot -> symbol by halving search on the FP32 table rule -> state
-//      update -> ballot renormalisation from an LDS ring of the stream),
-//   4. publishes the values just decoded in its two bottom rows.
-// Records carry data and validity in one 32-bit word (bit 31 valid, bits
-// 8..15 row r1-2, bits 0..7 row r1-1), written and read with agent-scope
-// atomics, so no fences are needed.  A workgroup only ever waits for the
-// one before it, which the dispatcher started earlier, and every wait is
-// bounded by a spin limit, so the grid always drains.
+// pixel (y, x) with x + 3y == t has its whole 12-pixel window decoded (the
+// up-right neighbour (y-1, x+2) finished in step t-1).  A group's symbols
+// are decoded in canonical order: step t, then block j of L rows, then lane.
+// One block of one step is a sub-round q = (t - t_first) * J + j.
+//
+// Inside the workgroup the work is split by wave and synchronised through
+// LDS counters instead of barriers:
+//   * wave 0, the coder, walks the sub-rounds in order: for each active lane
+//     it locates the symbol from the slot of its state (16-level bucket from
+//     precomputed boundaries, then 4 halvings on the FP32 table rule), updates
+//     the state, renormalises by ballot from an LDS ring of the stream, writes
+//     the pixel, and publishes the sub-rounds done;
+//   * waves 1..7 compute densities ahead of the coder, one 16-pixel tile of
+//     one sub-round at a time: gather from the LDS pixel ring, network on
+//     MFMA, mixture head, and the table at the 15 bucket boundaries.  Sub-round
+//     (t, j) only needs (t-1, j) and (t-1, j-1) decoded, so densities run up
+//     to J-1 sub-rounds ahead of the coder.
+// Rows r0-2 and r0-1 come from the group above through 32-bit records that
+// carry validity and both pixels in one word (bit 31 valid, bits 8..15 row
+// r1-2, bits 0..7 row r1-1), written and read with agent-scope atomics.  A
+// group only waits for the one before it, which the dispatcher started
+// earlier, and every wait is bounded, so the grid always drains.
 #include "dlic_device.hpp"
 #include "dlic_kernels.h"
 
 namespace dlic {
 
 constexpr int RING_MASK = DEC_RING - 1;
-constexpr int RING_HALF = DEC_RING / 2;
-constexpr int REFILL_PER_THREAD = RING_HALF / 256;
+constexpr int REFILL_WORDS = 1024;           // one coder-wave refill: 16 words per lane
+constexpr int NWORK = DEC_WAVES - 1;         // density waves
+constexpr int NSLOT = 8;                     // sub-round densities in flight
+constexpr int SLOT_PX = 64;                  // lanes per group at most
+constexpr int PAR_STRIDE = 16;               // floats per pixel: pi[5], A[5], B[5]
+constexpr int N_BUCKET = 15;                 // F(16 m), m = 1..15
+constexpr uint32_t LDS_SPIN_LIMIT = 1u << 24;
 
 __device__ __forceinline__ int floordiv(int a, int b) {
   return a >= 0 ? a / b : -((-a + b - 1) / b);
@@ -34,6 +47,13 @@ __device__ __forceinline__ uint32_t rd_u32(const uint8_t* p) {
 }
 __device__ __forceinline__ uint32_t rd_u16(const uint8_t* p) {
   return (uint32_t)p[0] | ((uint32_t)p[1] << 8);
+}
+
+__device__ __forceinline__ int lds_acquire(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_release(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Header check; returns 0 or a status code.  Every workgroup computes the
@@ -55,36 +75,69 @@ __device__ int check_header(const DecArgs& a) {
   return 0;
 }
 
+// Record of step s from the group above, spinning up to `limit` polls.
+// Returns false on timeout (the caller then stops waiting for good).
+__device__ bool receive_record(const uint32_t* up_rec, int s, uint32_t limit, uint32_t& v) {
+  v = __hip_atomic_load(up_rec + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t spins = 0;
+  while (!(v >> 31)) {
+    if (++spins > limit) {
+      v = 0x80000000u;
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    v = __hip_atomic_load(up_rec + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return true;
+}
+
+// Put the two pixels of upstream record s into ring rows 0 (r0-2) and 1 (r0-1).
+__device__ __forceinline__ void stash_record(uint8_t* ring, uint32_t v, int s, int r0, int W) {
+  const int c1 = s - SKEW * (r0 - 1);
+  const int c2 = s - SKEW * (r0 - 2);
+  if (c1 >= 0 && c1 < W) ring[1 * 16 + (c1 & 15)] = (uint8_t)(v & 0xFF);
+  if (c2 >= 0 && c2 < W) ring[0 * 16 + (c2 & 15)] = (uint8_t)((v >> 8) & 0xFF);
+}
+
 template <int H1, int H2, bool TABLES>
-__global__ __launch_bounds__(256) void wavefront_decode_kernel(const Consts* __restrict__ K,
-                                                               DevModel m, DecArgs a) {
+__global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
+    const Consts* __restrict__ K, DevModel m, DecArgs a) {
   __shared__ float2 s_sd[LUT_N];
-  __shared__ float s_beta[257];
+  __shared__ __attribute__((aligned(16))) float s_beta[260];
   __shared__ float s_scale[256];
-  __shared__ __attribute__((aligned(16))) float s_par[DEC_RMAX * 16];
+  __shared__ __attribute__((aligned(16))) float s_par[NSLOT][SLOT_PX * PAR_STRIDE];
+  __shared__ __attribute__((aligned(16))) uint16_t s_bk[NSLOT][SLOT_PX * 16];
   __shared__ uint8_t s_ring[(DEC_RMAX + 2) * 16];
   __shared__ uint16_t s_words[DEC_RING];
+  __shared__ int s_done[NSLOT][4];
+  __shared__ int s_decoded;
+  __shared__ uint32_t s_pw, s_end;  // words consumed by the coder / loaded into the ring
   __shared__ unsigned long long s_total, s_before;
-  __shared__ int s_err;
-  __shared__ uint32_t s_P;
+  __shared__ int s_err, s_flag;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = blockIdx.x;
   const int H = a.H, W = a.W, G = a.G, L = a.L;
+  constexpr int NTH = DEC_WAVES * 64;
 
   if (!TABLES) {
-    for (int i = tid; i < LUT_N; i += 256) s_sd[i] = K->sd[i];
-    for (int i = tid; i < 257; i += 256) s_beta[i] = K->beta[i];
-    s_scale[tid] = K->scale[tid];
+    for (int i = tid; i < LUT_N; i += NTH) s_sd[i] = K->sd[i];
+    for (int i = tid; i < 257; i += NTH) s_beta[i] = K->beta[i];
+    for (int i = tid; i < 256; i += NTH) s_scale[i] = K->scale[i];
   }
+  if (tid < NSLOT * 4) s_done[tid / 4][tid % 4] = -1;
   if (tid == 0) {
     s_err = check_header(a);
     s_total = 0;
     s_before = 0;
+    s_decoded = 0;
+    s_flag = 0;
+    s_pw = 0;
+    s_end = 0;
   }
   __syncthreads();
   if (s_err == 0) {
-    for (int i = tid; i < G; i += 256) {
+    for (int i = tid; i < G; i += NTH) {
       const unsigned long long c = rd_u32(a.bits + HEADER_BYTES + 4 * i);
       atomicAdd(&s_total, c);
       if (i < g) atomicAdd(&s_before, c);
@@ -103,168 +156,309 @@ __global__ __launch_bounds__(256) void wavefront_decode_kernel(const Consts* __r
   const int r0 = group_row(g, H, G), r1 = group_row(g + 1, H, G);
   const int R = r1 - r0;
   const int J = (R + L - 1) / L;
+  const int NT = (L + 15) / 16;
   const int t_first = SKEW * r0, t_last = SKEW * (r1 - 1) + W - 1;
+  const long long P = (long long)(t_last - t_first + 1) * J;
   const int up_last = (g > 0) ? SKEW * (r0 - 1) + W - 1 : -1;
-  const int t_begin = (g > 0) ? t_first - 2 * SKEW + 1 : t_first;
   const uint32_t n_words = rd_u32(a.bits + HEADER_BYTES + 4 * g);
   const uint16_t* gw = reinterpret_cast<const uint16_t*>(
       a.bits + HEADER_BYTES + 4LL * G + 2ull * s_before);
-  bool bad = n_words < 2u * (uint32_t)L;
-  bool over = false, timeout = false;
-
-  NetF32<H1, H2> net;
-  if (!TABLES) net.load(m, lane);
-
-  // stream ring: first DEC_RING words; lane states from the stream head
-  uint32_t E = bad ? 0u : min(n_words, (uint32_t)DEC_RING);
-  for (uint32_t i = tid; i < E; i += 256) s_words[i] = gw[i];
-  uint32_t x = RANS_L;
-  if (wave == 0 && lane < L && !bad) x = (uint32_t)gw[2 * lane] | ((uint32_t)gw[2 * lane + 1] << 16);
-  if (tid == 0) s_P = 2u * (uint32_t)L;
-  __syncthreads();
-
-  uint32_t* up_rec = a.rec + (long long)(g - 1) * a.T;
+  const bool bad = n_words < 2u * (uint32_t)L;
+  const uint32_t* up_rec = a.rec + (long long)(g - 1) * a.T;
   uint32_t* my_rec = a.rec + (long long)g * a.T;
 
-  for (int t = t_begin; t <= t_last; ++t) {
-    // (1) rows r0-2 and r0-1 from the upstream group (its step t-1)
-    if (tid == 0 && g > 0 && t - 1 <= up_last && !timeout) {
-      uint32_t v = __hip_atomic_load(up_rec + (t - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      uint32_t spins = 0;
-      while (!(v >> 31)) {
-        if (++spins > a.spin_limit) {
-          timeout = true;
-          v = 0x80000000u;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        v = __hip_atomic_load(up_rec + (t - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      const int c1 = (t - 1) - SKEW * (r0 - 1);  // row r0-1
-      const int c2 = (t - 1) - SKEW * (r0 - 2);  // row r0-2
-      if (c1 >= 0 && c1 < W) s_ring[1 * 16 + (c1 & 15)] = (uint8_t)(v & 0xFF);
-      if (c2 >= 0 && c2 < W) s_ring[0 * 16 + (c2 & 15)] = (uint8_t)((v >> 8) & 0xFF);
+  // upstream records of the steps before this group's first one
+  if (tid == 0 && g > 0) {
+    bool ok = true;
+    for (int s = t_first - 2 * SKEW; s <= t_first - 2 && ok; ++s) {
+      uint32_t v;
+      ok = receive_record(up_rec, s, a.spin_limit, v);
+      stash_record(s_ring, v, s, r0, W);
     }
-    __syncthreads();
+    if (!ok) s_flag = 7;
+  }
+  const uint32_t E0 = bad ? 0u : min(n_words, (uint32_t)DEC_RING);
+  for (uint32_t i = tid; i < E0; i += NTH) s_words[i] = gw[i];
+  if (tid == 0) s_end = E0;
+  __syncthreads();
 
-    // stream refill: fetch the next half ring now, store it after the coder
-    const uint32_t P0 = s_P;
-    const bool refill = !bad && E < n_words && E - P0 <= (uint32_t)RING_HALF;
-    uint16_t pre[REFILL_PER_THREAD];
-    if (refill) {
+  unsigned long long t_wait = 0, t_busy = 0;
+
+  if (wave == 0) {
+    // ------------------------------------------------------------------ coder
+    uint32_t x = RANS_L;
+    if (lane < L && !bad) x = (uint32_t)gw[2 * lane] | ((uint32_t)gw[2 * lane + 1] << 16);
+    uint32_t Pw = 2u * (uint32_t)L;  // words consumed
+    bool over = false, stuck = false, timeout = s_flag != 0;
+    uint32_t E = E0;                   // words known to be in the ring
+    for (long long q = 0; q < P; ++q) {
+      const int t = t_first + (int)(q / J), j = (int)(q % J);
+      if (TABLES) {
+        // no density waves here: the coder keeps its own ring filled
+        if (!bad && E < n_words && E - Pw <= (uint32_t)(DEC_RING - 2 * REFILL_WORDS)) {
+          uint16_t pre[REFILL_WORDS / 64];
 #pragma unroll
-      for (int i = 0; i < REFILL_PER_THREAD; ++i) {
-        const uint32_t pos = E + (uint32_t)(i * 256 + tid);
-        pre[i] = pos < n_words ? gw[pos] : (uint16_t)0;
-      }
-    }
-
-    const int ylo = max(r0, floordiv(t - W, SKEW) + 1);
-    const int yhi = min(r1 - 1, floordiv(t, SKEW));
-    const int n_act = yhi - ylo + 1;
-
-    if (!TABLES) {
-      // (2) network on the active pixels, raw outputs to s_par
-      for (int tile = wave; tile * 16 < n_act; tile += 4) {
-        const int i = tile * 16 + (lane & 15);
-        const int y = ylo + i;
-        const bool valid = i < n_act;
-        const int xc = t - SKEW * y;
-        float fk[3];
+          for (int i = 0; i < REFILL_WORDS / 64; ++i) {
+            const uint32_t pos = E + (uint32_t)(i * 64 + lane);
+            pre[i] = pos < n_words ? gw[pos] : (uint16_t)0;
+          }
 #pragma unroll
-        for (int kk = 0; kk < 3; ++kk) {
-          const int k = 4 * kk + q;
-          const int yy = y + nb_dy(k), xx = xc + nb_dx(k);
-          fk[kk] = (valid && yy >= 0 && xx >= 0 && xx < W)
-                       ? s_scale[s_ring[(yy - r0 + 2) * 16 + (xx & 15)]]
-                       : 0.0f;
+          for (int i = 0; i < REFILL_WORDS / 64; ++i)
+            s_words[(E + (uint32_t)(i * 64 + lane)) & RING_MASK] = pre[i];
+          E = min(n_words, E + (uint32_t)REFILL_WORDS);
         }
-        const f4 o = net.run(fk[0], fk[1], fk[2]);
-        if (valid) *reinterpret_cast<f4*>(&s_par[(y - r0) * 16 + 4 * q]) = o;
-      }
-      __syncthreads();
-      for (int i = tid; i < n_act; i += 256) {
-        float* pp = &s_par[(ylo + i - r0) * 16];
-        float o[N_OUT];
-#pragma unroll
-        for (int k = 0; k < N_OUT; ++k) o[k] = pp[k];
-        const Mix mix = mixture_head(o);
-#pragma unroll
-        for (int k = 0; k < N_MIX; ++k) {
-          pp[k] = mix.pi[k];
-          pp[N_MIX + k] = mix.mu[k];
-          pp[2 * N_MIX + k] = mix.is[k];
+      } else if (!bad && E < n_words && Pw + 64u > E && !stuck) {
+        // a sub-round takes at most 64 words; the ring owner keeps ahead
+        uint32_t spins = 0;
+        while ((E = __hip_atomic_load(&s_end, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) <
+                   min(n_words, Pw + 64u)) {
+          if (++spins > LDS_SPIN_LIMIT) {
+            stuck = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
         }
       }
-      __syncthreads();
-    }
-
-    // (3) coder: one sub-round per block of L rows, canonical order
-    if (wave == 0 && n_act > 0) {
-      uint32_t P = P0;
-      for (int j = 0; j < J; ++j) {
-        const int rr = j * L + lane;
-        const int y = r0 + rr;
-        const bool act = lane < L && rr < R && y >= ylo && y <= yhi;
-        const int xc = t - SKEW * y;
+      const int rr = j * L + lane;
+      const int y = r0 + rr;
+      const int xc = t - SKEW * y;
+      const bool act = lane < L && rr < R && xc >= 0 && xc < W;
+      const bool any = __ballot(act) != 0ull;
+      const int slot_i = (int)(q % NSLOT);
+      const unsigned long long c0 = a.prof ? clock64() : 0ull;
+      if (!TABLES && any && !stuck) {
+        for (int i = 0; i < NT && !stuck; ++i) {
+          uint32_t spins = 0;
+          while (lds_acquire(&s_done[slot_i][i]) != (int)q) {
+            if (++spins > LDS_SPIN_LIMIT) {
+              stuck = true;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+        }
+      }
+      const unsigned long long c1 = a.prof ? clock64() : 0ull;
+      if (any) {
         const uint32_t slot = x & 0xFFFFu;
         int v = 0;
         uint32_t c = 0, f = 1;
         if (TABLES) {
           uint32_t ti = act ? a.tidx[(long long)y * W + xc] : 0u;
           if (ti >= (uint32_t)a.n_tables) {
-            bad = bad || act;
+            over = over || act;
             ti = 0;
           }
           const uint32_t* tab = a.tables + (long long)ti * 257;
           find_symbol(slot, [&](int lv) { return tab[lv]; }, v, c, f);
         } else {
-          const float* pp = &s_par[(act ? rr : 0) * 16];
+          const int px = act ? lane : 0;
+          const float* pp = &s_par[slot_i][px * PAR_STRIDE];
           Mix mix;
 #pragma unroll
           for (int k = 0; k < N_MIX; ++k) {
             mix.pi[k] = pp[k];
-            mix.mu[k] = pp[N_MIX + k];
-            mix.is[k] = pp[2 * N_MIX + k];
+            mix.A[k] = pp[N_MIX + k];
+            mix.B[k] = pp[2 * N_MIX + k];
           }
-          find_symbol(slot, [&](int lv) { return cdf_F(lv, mix, s_sd, s_beta); }, v, c, f);
+          const uint16_t* bk = &s_bk[slot_i][px * 16];
+          int nb = 0;
+#pragma unroll
+          for (int i = 0; i < N_BUCKET; ++i) nb += ((uint32_t)bk[i] <= slot) ? 1 : 0;
+          const int base = 16 * nb;
+          uint32_t Flo = nb > 0 ? (uint32_t)bk[nb - 1] : 0u;
+          uint32_t Fhi = nb < N_BUCKET ? (uint32_t)bk[nb] : M_TOTAL;
+          // bin edges of the whole bucket in registers (levels base .. base+15)
+          float be[16];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const f4 v4 = *reinterpret_cast<const f4*>(&s_beta[base + 4 * i]);
+            be[4 * i] = v4[0];
+            be[4 * i + 1] = v4[1];
+            be[4 * i + 2] = v4[2];
+            be[4 * i + 3] = v4[3];
+          }
+          int off = 0;
+#pragma unroll
+          for (int it = 0; it < 4; ++it) {
+            const int step = 8 >> it;
+            // edge of level base + off + step, picked from registers
+            float b = be[0];
+#pragma unroll
+            for (int c = 1; c < 16; ++c)
+              if (c % step == 0) b = (off + step == c) ? be[c] : b;
+            const int mid = base + off + step;
+            const uint32_t Fm = cdf_F_at(mid, b, mix, s_sd);
+            if (Fm <= slot) {
+              off += step;
+              Flo = Fm;
+            } else {
+              Fhi = Fm;
+            }
+          }
+          const int lo = base + off;
+          v = lo;
+          c = Flo;
+          f = Fhi - Flo;
         }
         if (act) x = f * (x >> 16) + slot - c;
-        P = rans_dec_renorm(x, act && !bad, P, n_words,
-                            [&](uint32_t pos) { return (uint32_t)s_words[pos & RING_MASK]; }, over);
+        Pw = rans_dec_renorm(x, act && !bad, Pw, n_words,
+                             [&](uint32_t pos) { return (uint32_t)s_words[pos & RING_MASK]; }, over);
         if (act) {
           s_ring[(rr + 2) * 16 + (xc & 15)] = (uint8_t)v;
-          a.img[(long long)y * W + xc] = (uint8_t)v;
+          // density waves store a pixel to the image one step later; a row's
+          // last pixel has no later step, so the coder stores it
+          if (TABLES || xc == W - 1) a.img[(long long)y * W + xc] = (uint8_t)v;
         }
       }
-      if (lane == 0) s_P = P;
+      if (lane == 0) {
+        s_pw = Pw;
+        lds_release(&s_decoded, (int)(q + 1));
+      }
+      if (a.prof) {
+        const unsigned long long c2 = clock64();
+        t_wait += c1 - c0;
+        t_busy += c2 - c1;
+      }
+      // after the last block of step t, hand rows r1-2 and r1-1 to the next group
+      if (j == J - 1 && lane == 0 && g + 1 < G) {
+        const int d1 = t - SKEW * (r1 - 1), d2 = t - SKEW * (r1 - 2);
+        uint32_t rv = 0x80000000u;
+        if (d1 >= 0 && d1 < W) rv |= (uint32_t)s_ring[(R - 1 + 2) * 16 + (d1 & 15)];
+        if (d2 >= 0 && d2 < W) rv |= (uint32_t)s_ring[(R - 2 + 2) * 16 + (d2 & 15)] << 8;
+        __hip_atomic_store(my_rec + t, rv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
-    // (4) publish this step's values of rows r1-2 and r1-1 for the next group
-    if (tid == 0 && t >= t_first && g + 1 < G) {
-      const int c1 = t - SKEW * (r1 - 1), c2 = t - SKEW * (r1 - 2);
-      uint32_t rv = 0x80000000u;
-      if (c1 >= 0 && c1 < W) rv |= (uint32_t)s_ring[(R - 1 + 2) * 16 + (c1 & 15)];
-      if (c2 >= 0 && c2 < W) rv |= (uint32_t)s_ring[(R - 2 + 2) * 16 + (c2 & 15)] << 8;
-      __hip_atomic_store(my_rec + t, rv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (refill) {
-#pragma unroll
-      for (int i = 0; i < REFILL_PER_THREAD; ++i)
-        s_words[(E + (uint32_t)(i * 256 + tid)) & RING_MASK] = pre[i];
-      E = min(n_words, E + (uint32_t)RING_HALF);
-    }
-  }
-
-  // every lane back at the initial state and every word consumed
-  if (wave == 0) {
     const bool lane_bad = (lane < L) && (x != RANS_L);
     const bool any_bad = __ballot(lane_bad || over || bad) != 0ull;
     if (lane == 0) {
-      const uint32_t P = s_P;
-      if (any_bad || P != n_words) atomicMax(a.status, 3);
+      if (any_bad || Pw != n_words || stuck) atomicMax(a.status, 3);
+      if (timeout) atomicMax(a.status, 7);
+      if (a.prof) {
+        a.prof[g * 8 + 0] = t_wait;
+        a.prof[g * 8 + 1] = t_busy;
+      }
+    }
+  } else if (!TABLES) {
+    // -------------------------------------------------------- density waves
+    NetF32<H1, H2> net;
+    net.load(m, lane);
+    const int w = wave - 1, q4 = lane >> 4;
+    bool timeout = s_flag != 0;
+    bool stuck = false;
+    for (long long tau = w;; tau += NWORK) {
+      const long long q = tau / NT;
+      const int ti = (int)(tau % NT);
+      if (q >= P) break;
+      const int t = t_first + (int)(q / J), j = (int)(q % J);
+      const int slot_i = (int)(q % NSLOT);
+      const long long need = max(q - J + 1, q - NSLOT + 1);
+      const unsigned long long c0 = a.prof ? clock64() : 0ull;
+      if (!stuck) {
+        uint32_t spins = 0;
+        while (lds_acquire(&s_decoded) < need) {
+          if (++spins > LDS_SPIN_LIMIT) {
+            stuck = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      const unsigned long long c1 = a.prof ? clock64() : 0ull;
+      // density wave 0 keeps the stream ring ahead of the coder
+      if (w == 0 && !bad) {
+        const uint32_t end = s_end;
+        const uint32_t pw = __hip_atomic_load(&s_pw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (end < n_words && end - pw <= (uint32_t)(DEC_RING - 2 * REFILL_WORDS)) {
+          uint16_t pre[REFILL_WORDS / 64];
+#pragma unroll
+          for (int i = 0; i < REFILL_WORDS / 64; ++i) {
+            const uint32_t pos = end + (uint32_t)(i * 64 + lane);
+            pre[i] = pos < n_words ? gw[pos] : (uint16_t)0;
+          }
+#pragma unroll
+          for (int i = 0; i < REFILL_WORDS / 64; ++i)
+            s_words[(end + (uint32_t)(i * 64 + lane)) & RING_MASK] = pre[i];
+          if (lane == 0)
+            __hip_atomic_store(&s_end, min(n_words, end + (uint32_t)REFILL_WORDS), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
+      const int ln = 16 * ti + (lane & 15);  // coder lane of this pixel
+      const int rr = j * L + ln;
+      const int y = r0 + rr;
+      const int xc = t - SKEW * y;
+      const bool valid = ln < L && rr < R && xc >= 0 && xc < W;
+      if (__ballot(valid) != 0ull) {
+        // the tile holding row r0 takes the upstream record of step t-1
+        if (rr == 0 && valid && lane == 0 && g > 0 && t - 1 <= up_last && !timeout) {
+          uint32_t v;
+          timeout = !receive_record(up_rec, t - 1, a.spin_limit, v);
+          stash_record(s_ring, v, t - 1, r0, W);
+        }
+        float fk[3];
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+          const int k = 4 * kk + q4;
+          const int yy = y + nb_dy(k), xx = xc + nb_dx(k);
+          fk[kk] = (valid && yy >= 0 && xx >= 0 && xx < W)
+                       ? s_scale[s_ring[(yy - r0 + 2) * 16 + (xx & 15)]]
+                       : 0.0f;
+        }
+        // the left neighbour (decoded last step) goes to the image now
+        if (valid && q4 == 0 && xc >= 1)
+          a.img[(long long)y * W + xc - 1] = s_ring[(rr + 2) * 16 + ((xc - 1) & 15)];
+        const f4 o = net.run(fk[0], fk[1], fk[2]);
+        float* par = &s_par[slot_i][0];
+        if (valid) *reinterpret_cast<f4*>(&par[ln * PAR_STRIDE + 4 * q4]) = o;
+        // mixture head, one lane per pixel
+        if (lane < 16 && valid) {
+          float* pp = &par[ln * PAR_STRIDE];
+          float ov[N_OUT];
+#pragma unroll
+          for (int k = 0; k < N_OUT; ++k) ov[k] = pp[k];
+          const Mix mx = mixture_head(ov);
+#pragma unroll
+          for (int k = 0; k < N_MIX; ++k) {
+            pp[k] = mx.pi[k];
+            pp[N_MIX + k] = mx.A[k];
+            pp[2 * N_MIX + k] = mx.B[k];
+          }
+        }
+        // table at the bucket boundaries 16, 32, ..., 240: four per lane
+        if (valid) {
+          const float* pp = &par[ln * PAR_STRIDE];
+          Mix mx;
+#pragma unroll
+          for (int k = 0; k < N_MIX; ++k) {
+            mx.pi[k] = pp[k];
+            mx.A[k] = pp[N_MIX + k];
+            mx.B[k] = pp[2 * N_MIX + k];
+          }
+          uint16_t* bk = &s_bk[slot_i][ln * 16];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int mb = q4 + 4 * i + 1;
+            if (mb <= N_BUCKET) bk[mb - 1] = (uint16_t)cdf_F(16 * mb, mx, s_sd, s_beta);
+          }
+        }
+      }
+      if (lane == 0) lds_release(&s_done[slot_i][ti], (int)q);
+      if (a.prof) {
+        const unsigned long long c2 = clock64();
+        t_wait += c1 - c0;
+        t_busy += c2 - c1;
+      }
+    }
+    if (lane == 0) {
+      if (stuck) atomicMax(a.status, 3);
+      if (timeout) atomicMax(a.status, 7);
+      if (a.prof) {
+        atomicAdd(&a.prof[g * 8 + 2], t_wait);
+        atomicAdd(&a.prof[g * 8 + 3], t_busy);
+      }
     }
   }
-  if (tid == 0 && timeout) atomicMax(a.status, 7);
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, long long n) {
@@ -282,7 +476,8 @@ void launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t s) {
 
 template <int H1, int H2, bool TB>
 static void launch_decode_t(const Consts* K, const DevModel& m, const DecArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((wavefront_decode_kernel<H1, H2, TB>), dim3(a.G), dim3(256), 0, s, K, m, a);
+  hipLaunchKernelGGL((wavefront_decode_kernel<H1, H2, TB>), dim3(a.G), dim3(DEC_WAVES * 64), 0, s,
+                     K, m, a);
 }
 
 bool launch_decode(int width, bool tables_mode, const Consts* K, const DevModel& m,

@@ -138,8 +138,11 @@ struct NetF32 {
 // -----------------------------------------------------------------------------
 // Mixture head and the FP32 table rule.
 // -----------------------------------------------------------------------------
+// Mixture of one pixel in the form the table rule consumes: weights pi and
+// the affine map u = beta * A + B of each component's table coordinate
+// (A = 128 inv_s, B = 2048 - mu A, so u = 128 (beta - mu) inv_s + 2048).
 struct Mix {
-  float pi[N_MIX], mu[N_MIX], is[N_MIX];
+  float pi[N_MIX], A[N_MIX], B[N_MIX];
 };
 
 // pi = softmax(o[0:5]); mu = o[5:10]; inv_s = exp(-max(o[10:15], -7)).
@@ -157,21 +160,22 @@ __device__ __forceinline__ Mix mixture_head(const float* o) {
 #pragma unroll
   for (int k = 0; k < N_MIX; ++k) {
     p.pi[k] = e[k] / s;
-    p.mu[k] = o[N_MIX + k];
-    p.is[k] = expf(-fmaxf(o[2 * N_MIX + k], LOG_SCALE_MIN));
+    const float inv_s = expf(-fmaxf(o[2 * N_MIX + k], LOG_SCALE_MIN));
+    p.A[k] = inv_s * 128.0f;
+    p.B[k] = 2048.0f - o[N_MIX + k] * p.A[k];
   }
   return p;
 }
 
-// Table logistic: piecewise linear through RN32(sigma) knots, monotone by
-// construction (non-negative exact slopes, segment end == next knot).
-__device__ __forceinline__ float sigma_hat(float t, const float2* sd) {
-  float u = (t + 16.0f) * 128.0f;
+// Table logistic at table coordinate u: piecewise linear through RN32(sigma)
+// knots, monotone by construction (non-negative exact slopes, each segment
+// ends on the next knot; the last knot has slope 0).
+__device__ __forceinline__ float sigma_hat(float u, const float2* sd) {
   u = u > 0.0f ? u : 0.0f;
   u = fminf(u, 4096.0f);
-  int j = min((int)u, LUT_N - 2);
-  float w = u - (float)j;
-  float2 e = sd[j];
+  const int j = (int)u;
+  const float w = u - (float)j;
+  const float2 e = sd[j];
   return e.x + w * e.y;
 }
 
@@ -182,12 +186,19 @@ __device__ __forceinline__ uint32_t cdf_F(int v, const Mix& p, const float2* sd,
   if (v <= 0) return 0u;
   if (v >= 256) return M_TOTAL;
   const float b = beta[v];
-  float C = 0.0f;
+  float C = p.pi[0] * sigma_hat(b * p.A[0] + p.B[0], sd);
 #pragma unroll
-  for (int k = 0; k < N_MIX; ++k) {
-    float t = (b - p.mu[k]) * p.is[k];
-    C = C + p.pi[k] * sigma_hat(t, sd);
-  }
+  for (int k = 1; k < N_MIX; ++k) C = C + p.pi[k] * sigma_hat(b * p.A[k] + p.B[k], sd);
+  uint32_t q = (uint32_t)(C * 65280.0f);
+  q = min(q, M_PRIME);
+  return (uint32_t)v + q;
+}
+
+// F(v) for 0 < v < 256 with the bin edge beta_v already at hand.
+__device__ __forceinline__ uint32_t cdf_F_at(int v, float b, const Mix& p, const float2* sd) {
+  float C = p.pi[0] * sigma_hat(b * p.A[0] + p.B[0], sd);
+#pragma unroll
+  for (int k = 1; k < N_MIX; ++k) C = C + p.pi[k] * sigma_hat(b * p.A[k] + p.B[k], sd);
   uint32_t q = (uint32_t)(C * 65280.0f);
   q = min(q, M_PRIME);
   return (uint32_t)v + q;

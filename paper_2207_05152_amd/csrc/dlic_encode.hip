@@ -89,74 +89,82 @@ __global__ __launch_bounds__(256) void density_kernel(const Consts* __restrict__
   }
 }
 
-// Sub-round (t, j) of group g: lane l holds row r0 + j*L + l, column t - 3*row.
-struct SubroundCursor {
-  int t, j;
-};
+constexpr int ENC_CHUNK = 32;   // wavefront steps staged in LDS per chunk
+constexpr int ENC_BATCH = 8;    // sub-rounds read from LDS ahead of coding
 
-__device__ __forceinline__ uint32_t load_cf(const uint32_t* __restrict__ cf, int t, int j,
-                                            int lane, int L, int r0, int R, int W) {
-  const int rr = j * L + lane;
-  const int y = r0 + rr;
-  const int x = t - SKEW * y;
-  if (lane < L && rr < R && x >= 0 && x < W) return cf[(long long)y * W + x];
-  return INACTIVE;
-}
-
-constexpr int ENC_BATCH = 8;
-
-// One wave per group.  Words go below the top of the group's scratch slice
-// (cap_g = R*W + 2L words, the worst case), so a stream is contiguous at
-// [cap_g - count, cap_g).
-__global__ __launch_bounds__(64) void rans_encode_kernel(const uint32_t* __restrict__ cf, int H,
-                                                         int W, int G, int L,
-                                                         uint16_t* __restrict__ words,
-                                                         uint32_t* __restrict__ counts) {
-  const int g = blockIdx.x, lane = threadIdx.x;
+// One workgroup (4 waves) per group.  Wave 0 codes; while it walks one chunk
+// of 32 steps in reverse canonical order from LDS, waves 1..3 stage the next
+// chunk's intervals (row-contiguous global reads).  Words go below the top of
+// the group's scratch slice (cap_g = R*W + 2L words, the worst case), so a
+// stream is contiguous at [cap_g - count, cap_g).
+__global__ __launch_bounds__(256) void rans_encode_kernel(const uint32_t* __restrict__ cf, int H,
+                                                          int W, int G, int L,
+                                                          uint16_t* __restrict__ words,
+                                                          uint32_t* __restrict__ counts) {
+  __shared__ uint32_t s_cf[2][ENC_CHUNK * DEC_RMAX];
+  const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r0 = group_row(g, H, G), r1 = group_row(g + 1, H, G);
   const int R = r1 - r0;
   const int J = (R + L - 1) / L;
   const long long cap = (long long)R * W + 2LL * L;
   uint16_t* out = words + (long long)r0 * W + 2LL * L * g;
+  const int t_first = SKEW * r0, t_last = SKEW * (r1 - 1) + W - 1;
+  const int n_chunks = R > 0 ? (t_last - t_first + ENC_CHUNK) / ENC_CHUNK : 0;
+
+  // chunk c holds steps [t_last - 32c - 31, t_last - 32c] as [k][row], k = t - t_lo
+  auto stage = [&](int c, uint32_t* buf, int first, int stride) {
+    const int t_lo = t_last - ENC_CHUNK * c - (ENC_CHUNK - 1);
+    for (int idx = first; idx < R * ENC_CHUNK; idx += stride) {
+      const int rr = idx / ENC_CHUNK, k = idx - rr * ENC_CHUNK;
+      const int y = r0 + rr, t = t_lo + k, x = t - SKEW * y;
+      buf[k * DEC_RMAX + rr] =
+          (t >= t_first && x >= 0 && x < W) ? cf[(long long)y * W + x] : INACTIVE;
+    }
+  };
+  if (n_chunks > 0) stage(0, s_cf[0], tid, 256);
+  __syncthreads();
+
   uint32_t Q = (uint32_t)cap;
   uint32_t x = RANS_L;
-
-  if (R > 0) {
-    const int t_first = SKEW * r0, t_last = SKEW * (r1 - 1) + W - 1;
-    // cursor walks (t, j) downwards from (t_last, J-1)
-    SubroundCursor ld = {t_last, J - 1};
-    long long remaining = (long long)(t_last - t_first + 1) * J;
-    uint32_t cur[ENC_BATCH], nxt[ENC_BATCH];
+  for (int c = 0; c < n_chunks; ++c) {
+    if (wave > 0) {
+      if (c + 1 < n_chunks) stage(c + 1, s_cf[(c + 1) & 1], tid - 64, 192);
+    } else {
+      const uint32_t* buf = s_cf[c & 1];
+      const int t_lo = t_last - ENC_CHUNK * c - (ENC_CHUNK - 1);
+      int k = ENC_CHUNK - 1, j = J - 1;
+      const int n_sub = ENC_CHUNK * J;
+      for (int s0 = 0; s0 < n_sub; s0 += ENC_BATCH) {
+        uint32_t v[ENC_BATCH];
 #pragma unroll
-    for (int i = 0; i < ENC_BATCH; ++i) {
-      cur[i] = (ld.t >= t_first) ? load_cf(cf, ld.t, ld.j, lane, L, r0, R, W) : INACTIVE;
-      if (--ld.j < 0) { ld.j = J - 1; --ld.t; }
-    }
-    while (remaining > 0) {
+        for (int i = 0; i < ENC_BATCH; ++i) {
+          const int rr = j * L + lane;
+          v[i] = (s0 + i < n_sub && t_lo + k >= t_first && lane < L && rr < R)
+                     ? buf[k * DEC_RMAX + rr]
+                     : INACTIVE;
+          if (--j < 0) {
+            j = J - 1;
+            --k;
+          }
+        }
 #pragma unroll
-      for (int i = 0; i < ENC_BATCH; ++i) {
-        nxt[i] = (ld.t >= t_first) ? load_cf(cf, ld.t, ld.j, lane, L, r0, R, W) : INACTIVE;
-        if (--ld.j < 0) { ld.j = J - 1; --ld.t; }
+        for (int i = 0; i < ENC_BATCH; ++i) {
+          const bool act = v[i] != INACTIVE;
+          Q = rans_enc_subround(x, act, v[i] & 0xFFFFu, (v[i] >> 16) + 1u, out, Q);
+        }
       }
-#pragma unroll
-      for (int i = 0; i < ENC_BATCH; ++i) {
-        const uint32_t v = cur[i];
-        const bool act = v != INACTIVE;
-        const uint32_t c = v & 0xFFFFu, f = (v >> 16) + 1u;
-        Q = rans_enc_subround(x, act, c, f, out, Q);
-      }
-#pragma unroll
-      for (int i = 0; i < ENC_BATCH; ++i) cur[i] = nxt[i];
-      remaining -= ENC_BATCH;
     }
+    __syncthreads();
   }
-  // flush: states as (low, high) pairs for lanes 0..L-1 at the stream head
-  Q -= 2u * (uint32_t)L;
-  if (lane < L) {
-    out[Q + 2 * lane] = (uint16_t)(x & 0xFFFFu);
-    out[Q + 2 * lane + 1] = (uint16_t)(x >> 16);
+  if (wave == 0) {
+    // flush: states as (low, high) pairs for lanes 0..L-1 at the stream head
+    Q -= 2u * (uint32_t)L;
+    if (lane < L) {
+      out[Q + 2 * lane] = (uint16_t)(x & 0xFFFFu);
+      out[Q + 2 * lane + 1] = (uint16_t)(x >> 16);
+    }
+    if (lane == 0) counts[g] = (uint32_t)cap - Q;
   }
-  if (lane == 0) counts[g] = (uint32_t)cap - Q;
 }
 
 __device__ __forceinline__ void put_u16(uint8_t* p, uint32_t v) {
@@ -241,7 +249,7 @@ bool launch_density(int width, const Consts* K, const DevModel& m, const uint8_t
 
 void launch_rans_encode(const uint32_t* cf, int H, int W, int G, int L, uint16_t* words,
                         uint32_t* counts, hipStream_t s) {
-  hipLaunchKernelGGL(rans_encode_kernel, dim3(G), dim3(64), 0, s, cf, H, W, G, L, words, counts);
+  hipLaunchKernelGGL(rans_encode_kernel, dim3(G), dim3(256), 0, s, cf, H, W, G, L, words, counts);
 }
 
 void launch_pack(const uint16_t* words, const uint32_t* counts, int H, int W, int G, int L,

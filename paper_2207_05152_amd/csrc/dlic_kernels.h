@@ -16,6 +16,7 @@ struct HeaderFields {
 // Decoder limits: rows per group, and the per-group stream ring in LDS.
 constexpr int DEC_RMAX = 256;
 constexpr int DEC_RING = 4096;
+constexpr int DEC_WAVES = 8;  // wave 0 codes, waves 1..7 compute densities
 
 struct DecArgs {
   const uint8_t* bits;
@@ -31,6 +32,7 @@ struct DecArgs {
   const uint32_t* tables;  // table mode: [n_tables][257]
   int n_tables;
   const uint32_t* tidx;    // table mode: [H*W]
+  unsigned long long* prof;  // optional per-group cycle counters (8 per group)
 };
 
 bool launch_density(int width, const Consts* K, const DevModel& m, const uint8_t* img, int H,

@@ -55,6 +55,7 @@ def test_bounds_and_workspace():
     assert dl.dlic_decode_workspace(1536, 2048, c) >= 4 * 8 * (2048 + 3 * 1536 - 3)
     assert dl.dlic_encode_bound(10, 10, dl.dlic_coder(6, 32)) == 0      # H < 2G
     assert dl.dlic_encode_bound(10, 10, dl.dlic_coder(1, 65)) == 0      # L > 64
+    assert dl.dlic_encode_bound(257, 10, dl.dlic_coder(1, 32)) == 0     # > 256 rows per group
 
 
 def test_peek_header_reads_oracle_header():

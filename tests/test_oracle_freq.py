@@ -70,16 +70,29 @@ def test_sigma_lut_knots_and_slopes():
 
 
 def test_sigma_hat_monotone_and_accurate():
-    knots = (-16.0 + np.arange(4097) / 128.0).astype(np.float32)
+    knots = np.arange(4097).astype(np.float32)
     near = np.concatenate([np.nextafter(knots, np.float32(-np.inf)), knots,
                            np.nextafter(knots, np.float32(np.inf))])
-    t = np.sort(np.concatenate([near, np.linspace(-40, 40, 200001).astype(np.float32),
+    u = np.sort(np.concatenate([near, np.linspace(-3000, 7000, 400001).astype(np.float32),
                                 np.array([-np.inf, np.inf], np.float32)]))
-    s = oracle.sigma_hat32(t)
+    s = oracle.sigma_hat32(u)
     assert (np.diff(s) >= 0).all()
-    fin = np.isfinite(t) & (np.abs(t) <= 16)
-    exact = 1.0 / (1.0 + np.exp(-t[fin].astype(np.float64)))
+    fin = np.isfinite(u) & (u >= 0) & (u <= 4096)
+    t = u[fin].astype(np.float64) / 128.0 - 16.0
+    exact = 1.0 / (1.0 + np.exp(-t))
     assert np.abs(s[fin] - exact).max() < 1e-6
+
+
+def test_table_coordinate_tracks_the_logistic_argument():
+    # u = beta A + B is (beta - mu) inv_s on the table's scale, up to FP32 rounding
+    rng = np.random.default_rng(4)
+    mu = rng.uniform(-1.5, 1.5, 1000).astype(np.float32)
+    inv_s = np.exp(rng.uniform(-2, 7, 1000)).astype(np.float32)
+    A, B = oracle.table_coords32(mu, inv_s)
+    beta = oracle.beta32()[rng.integers(1, 256, 1000)]
+    u = beta * A + B
+    exact = (beta.astype(np.float64) - mu) * inv_s * 128.0 + 2048.0
+    assert np.all(np.abs(u - exact) <= 4 * np.spacing(np.maximum(np.abs(beta * A), np.abs(B))) + 1e-3)
 
 
 def test_fp32_constants_are_roundings_of_exact_values():
