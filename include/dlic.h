@@ -53,7 +53,12 @@ typedef enum {
   DLIC_ERR_TIMEOUT = 7         /* a decode wait exceeded its spin limit (device) */
 } dlic_status;
 
-typedef enum { DLIC_FP32 = 0, DLIC_BF16 = 1, DLIC_FP8_E4M3 = 2 } dlic_dtype;
+typedef enum {
+  DLIC_FP32 = 0,
+  DLIC_BF16 = 1,
+  DLIC_FP8_E4M3 = 2,
+  DLIC_FP64 = 3 /* training entry points only (gradient checks) */
+} dlic_dtype;
 
 /* Network weights (Section II-B, Neural Network Architecture; the mixture
  * head of Section I / IV-C).  Matrices are row-major [out][in] in the given
@@ -183,6 +188,35 @@ dlic_status dlic_rans_decode_tables(const dlic_coder *coder, int32_t h, int32_t 
                                     const uint32_t *d_tidx, const uint8_t *d_bits,
                                     size_t n_bytes, uint8_t *d_sym, int32_t *d_status,
                                     void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---- retraining ------------------------------------------------------------ */
+
+/* Scratch bytes of dlic_nll_fwd_bwd for n samples (d_ws). */
+size_t dlic_nll_workspace(int64_t n, const dlic_model *model);
+
+/* Mean discretised-logistic-mixture NLL in bits over n sampled pixels and its
+ * gradient with respect to every weight (Section III-A: cross-entropy loss
+ * in bits; Section IV: retraining on domain data).  d_slices: [n_slices][sh]
+ * [sw] uint8 stack; d_idx: [n][3] int32 (slice, y, x), windows taken inside
+ * the slice with the coding rule (dummy 0 outside); samples whose index lies
+ * outside the stack contribute nothing.  model->dtype is DLIC_FP32 or
+ * DLIC_FP64 (weights AND biases in that type; h1 == h2 in {32, 64}).
+ * d_loss: one scalar of that type; d_grad: NULL for the loss only, else the
+ * gradient in the concatenated layout W1, b1, W2, b2, W3, b3 (row-major).
+ * The reduction over samples has a fixed order, so results are
+ * deterministic. */
+dlic_status dlic_nll_fwd_bwd(const dlic_model *model, const uint8_t *d_slices,
+                             int32_t n_slices, int32_t sh, int32_t sw, const int32_t *d_idx,
+                             int64_t n, void *d_loss, void *d_grad, void *d_ws,
+                             size_t ws_bytes, hipStream_t stream);
+
+/* One Adam step (Kingma and Ba) on n_params FP32 parameters in place:
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr / (1 - b1^step) * m / (sqrt(v) / sqrt(1 - b2^step) + eps), with the
+ * bias corrections evaluated in double on the host.  step >= 1. */
+dlic_status dlic_adam_step(int64_t n_params, float *d_params, const float *d_grad, float *d_m,
+                           float *d_v, int32_t step, float lr, float b1, float b2, float eps,
+                           hipStream_t stream);
 
 /* ---- measurement ---------------------------------------------------------- */
 

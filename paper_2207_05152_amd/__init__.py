@@ -17,11 +17,12 @@ from ctypes import POINTER, c_char_p, c_float, c_int, c_int32, c_size_t, c_uint3
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdlic.so")
+# DLIC_LIB may name another build of the same library (e.g. an experiment).
+LIB_PATH = os.environ.get("DLIC_LIB") or os.path.join(_HERE, "libdlic.so")
 
 DLIC_OK, DLIC_ERR_ARG, DLIC_ERR_CAPACITY, DLIC_ERR_CORRUPT = 0, 1, 2, 3
 DLIC_ERR_MODEL_MISMATCH, DLIC_ERR_UNSUPPORTED, DLIC_ERR_HIP, DLIC_ERR_TIMEOUT = 4, 5, 6, 7
-DLIC_FP32, DLIC_BF16, DLIC_FP8_E4M3 = 0, 1, 2
+DLIC_FP32, DLIC_BF16, DLIC_FP8_E4M3, DLIC_FP64 = 0, 1, 2, 3
 FNV_OFFSET = 0xCBF29CE484222325
 HEADER_BYTES = 36
 
@@ -31,7 +32,7 @@ EXPORTS = (
     "dlic_encode_workspace", "dlic_decode_workspace", "dlic_peek_header", "dlic_init",
     "dlic_encode", "dlic_decode", "dlic_set_spin_limit", "dlic_density",
     "dlic_rans_encode_cf", "dlic_rans_decode_tables", "dlic_set_timing", "dlic_kernel_times",
-    "dlic_set_decode_profile",
+    "dlic_set_decode_profile", "dlic_nll_workspace", "dlic_nll_fwd_bwd", "dlic_adam_step",
 )
 
 
@@ -87,6 +88,11 @@ def lib():
         "dlic_set_timing": (None, [c_int]),
         "dlic_kernel_times": (c_int, [P, P, c_int]),
         "dlic_set_decode_profile": (None, [P]),
+        "dlic_nll_workspace": (S, [ctypes.c_int64, POINTER(dlic_model)]),
+        "dlic_nll_fwd_bwd": (c_int, [POINTER(dlic_model), P, c_int32, c_int32, c_int32, P,
+                                     ctypes.c_int64, P, P, P, S, P]),
+        "dlic_adam_step": (c_int, [ctypes.c_int64, P, P, P, P, c_int32, c_float, c_float, c_float,
+                                   c_float, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -294,3 +300,123 @@ def density(img, model: Model, tables=False, stream=None):
     tab = torch.empty((n, 257), dtype=torch.int32, device=img.device) if tables else None
     dlic_density(model.c, img.contiguous(), h, w, out15, cf, tab, stream)
     return out15, cf, tab
+
+
+# ---- retraining -------------------------------------------------------------------
+
+PARAM_NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def dlic_nll_workspace(n: int, model: dlic_model) -> int:
+    return int(lib().dlic_nll_workspace(int(n), ctypes.byref(model)))
+
+
+def dlic_nll_fwd_bwd(model: dlic_model, d_slices, n_slices, sh, sw, d_idx, n, d_loss, d_grad,
+                     d_ws, ws_bytes, stream=None):
+    _check(lib().dlic_nll_fwd_bwd(ctypes.byref(model), _ptr(d_slices), n_slices, sh, sw,
+                                  _ptr(d_idx), int(n), _ptr(d_loss), _ptr(d_grad), _ptr(d_ws),
+                                  ws_bytes, _stream(stream)), "dlic_nll_fwd_bwd")
+
+
+def dlic_adam_step(n_params, d_params, d_grad, d_m, d_v, step, lr=1e-3, b1=0.9, b2=0.999,
+                   eps=1e-8, stream=None):
+    _check(lib().dlic_adam_step(int(n_params), _ptr(d_params), _ptr(d_grad), _ptr(d_m), _ptr(d_v),
+                                int(step), lr, b1, b2, eps, _stream(stream)), "dlic_adam_step")
+
+
+def param_shapes(h1: int, h2: int):
+    return {"W1": (h1, 12), "b1": (h1,), "W2": (h2, h1), "b2": (h2,), "W3": (15, h2), "b3": (15,)}
+
+
+def _model_over(tensors, dtype_code, h1, h2):
+    return dlic_model(12, h1, h2, 15, dtype_code, 0, _ptr(tensors["W1"]), _ptr(tensors["W2"]),
+                      _ptr(tensors["W3"]), _ptr(tensors["b1"]), _ptr(tensors["b2"]),
+                      _ptr(tensors["b3"]), None, 0)
+
+
+class TrainModel:
+    """Weights in one flat device buffer (FP32 or FP64) in the gradient layout."""
+
+    def __init__(self, weights: dict, device="cuda", dtype=None):
+        import torch
+        dtype = dtype or torch.float32
+        h1, h2 = weights["W1"].shape[0], weights["W2"].shape[0]
+        self.h1, self.h2 = h1, h2
+        flat = np.concatenate([np.asarray(weights[k], dtype=np.float64).ravel() for k in PARAM_NAMES])
+        self.flat = torch.from_numpy(flat).to(device=device, dtype=dtype)
+        self.views = {}
+        off = 0
+        for k, shp in param_shapes(h1, h2).items():
+            n = int(np.prod(shp))
+            self.views[k] = self.flat[off:off + n].view(*shp)
+            off += n
+        code = DLIC_FP64 if dtype == torch.float64 else DLIC_FP32
+        self.c = _model_over(self.views, code, h1, h2)
+
+
+def nll(model: TrainModel, slices, idx, want_grad=True, stream=None):
+    """(loss, grad) of the mean mixture NLL in bits; grad is flat in the weight layout."""
+    import torch
+    n = idx.shape[0]
+    ns, sh, sw = slices.shape
+    loss = torch.zeros(1, dtype=model.flat.dtype, device=model.flat.device)
+    grad = torch.empty_like(model.flat) if want_grad else None
+    wsb = dlic_nll_workspace(n, model.c)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=model.flat.device)
+    dlic_nll_fwd_bwd(model.c, slices.contiguous(), ns, sh, sw, idx.contiguous(), n, loss, grad, ws,
+                     wsb, stream)
+    return loss, grad
+
+
+def _autograd_fn():
+    import torch
+
+    class DLICNLL(torch.autograd.Function):
+        """Mean mixture NLL (bits) with the hand-written backward kernel.
+
+        forward(W1, b1, W2, b2, W3, b3, slices, idx) -> scalar loss.  The
+        gradient is computed together with the loss by dlic_nll_fwd_bwd and
+        scaled by the incoming gradient in backward.
+        """
+
+        @staticmethod
+        def forward(ctx, W1, b1, W2, b2, W3, b3, slices, idx):
+            tensors = {"W1": W1.contiguous(), "b1": b1.contiguous(), "W2": W2.contiguous(),
+                       "b2": b2.contiguous(), "W3": W3.contiguous(), "b3": b3.contiguous()}
+            code = DLIC_FP64 if W1.dtype == torch.float64 else DLIC_FP32
+            m = _model_over(tensors, code, W1.shape[0], W2.shape[0])
+            n = idx.shape[0]
+            ns, sh, sw = slices.shape
+            loss = torch.zeros(1, dtype=W1.dtype, device=W1.device)
+            grad = torch.empty(sum(t.numel() for t in tensors.values()), dtype=W1.dtype,
+                               device=W1.device)
+            wsb = dlic_nll_workspace(n, m)
+            ws = torch.empty(wsb, dtype=torch.uint8, device=W1.device)
+            dlic_nll_fwd_bwd(m, slices.contiguous(), ns, sh, sw, idx.contiguous(), n, loss, grad,
+                             ws, wsb)
+            ctx.save_for_backward(grad)
+            ctx.shapes = [t.shape for t in tensors.values()]
+            return loss[0]
+
+        @staticmethod
+        def backward(ctx, g):
+            (grad,) = ctx.saved_tensors
+            outs, off = [], 0
+            for shp in ctx.shapes:
+                n = int(np.prod(shp))
+                outs.append((grad[off:off + n] * g).view(shp))
+                off += n
+            return (*outs, None, None)
+
+    return DLICNLL
+
+
+_DLICNLL = None
+
+
+def DLICNLL():
+    """The torch.autograd.Function class for the hand-written NLL backward."""
+    global _DLICNLL
+    if _DLICNLL is None:
+        _DLICNLL = _autograd_fn()
+    return _DLICNLL

@@ -343,7 +343,8 @@ static dlic_status decode_common(const dlic_model* model, bool tables_mode,
   if (!d_bits || !d_img || !d_status || !d_ws || h <= 0 || w <= 0) return DLIC_ERR_ARG;
   if (!coder_ok(h, coder)) return DLIC_ERR_UNSUPPORTED;
   if (max_group_rows(h, coder->groups) > DEC_RMAX) return DLIC_ERR_UNSUPPORTED;
-  if ((long long)w + 3LL * h > (1LL << 30)) return DLIC_ERR_UNSUPPORTED;
+  // sub-round counters are 32-bit: (W + 3R) * ceil(R / L) < 2^31
+  if (((long long)w + 3LL * DEC_RMAX) * DEC_RMAX >= (1LL << 31)) return DLIC_ERR_UNSUPPORTED;
   if (ws_bytes < dlic_decode_workspace(h, w, coder)) return DLIC_ERR_CAPACITY;
   dlic_status rc;
   const Consts* K = nullptr;
@@ -417,6 +418,50 @@ dlic_status dlic_density(const dlic_model* model, const uint8_t* d_img, int32_t 
   timing_begin("density_kernel", stream);
   launch_density(model->h1, K, dev_model(model), d_img, h, w, d_cf, d_out15, d_tables,
                  density_grid((long long)h * w), stream);
+  timing_end(stream);
+  return launch_ok();
+}
+
+size_t dlic_nll_workspace(int64_t n, const dlic_model* model) {
+  if (!model || n <= 0) return 0;
+  const bool f64 = model->dtype == DLIC_FP64;
+  const size_t rows = (size_t)TRAIN_GRID * (f64 ? TRAIN_WAVES_F64 : TRAIN_WAVES_F32);
+  return align256(rows * (size_t)(train_n_params(model->h1, model->h2) + 1) *
+                  (f64 ? sizeof(double) : sizeof(float)));
+}
+
+dlic_status dlic_nll_fwd_bwd(const dlic_model* m, const uint8_t* d_slices, int32_t n_slices,
+                             int32_t sh, int32_t sw, const int32_t* d_idx, int64_t n, void* d_loss,
+                             void* d_grad, void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  timing_reset();
+  if (!m || !d_slices || !d_idx || !d_loss || !d_ws || n <= 0 || n_slices <= 0 || sh <= 0 ||
+      sw <= 0)
+    return DLIC_ERR_ARG;
+  if (m->k_in != K_IN || m->n_out != N_OUT || !m->d_w1 || !m->d_w2 || !m->d_w3 || !m->d_b1 ||
+      !m->d_b2 || !m->d_b3)
+    return DLIC_ERR_ARG;
+  if (m->dtype != DLIC_FP32 && m->dtype != DLIC_FP64) return DLIC_ERR_UNSUPPORTED;
+  if (m->h1 != m->h2 || (m->h1 != 32 && m->h1 != 64)) return DLIC_ERR_UNSUPPORTED;
+  if (ws_bytes < dlic_nll_workspace(n, m)) return DLIC_ERR_CAPACITY;
+  dlic_status rc = current_consts(nullptr);
+  if (rc != DLIC_OK) return rc;
+  timing_begin("nll_fwd_bwd_kernel", stream);
+  const bool ok = launch_nll(m->dtype == DLIC_FP64, m->h1, m->d_w1, m->d_b1, m->d_w2, m->d_b2,
+                             m->d_w3, m->d_b3, d_slices, n_slices, sh, sw, d_idx, n, d_ws,
+                             TRAIN_GRID, d_grad != nullptr, d_grad, d_loss, stream);
+  timing_end(stream);
+  if (!ok) return DLIC_ERR_UNSUPPORTED;
+  return launch_ok();
+}
+
+dlic_status dlic_adam_step(int64_t n_params, float* d_params, const float* d_grad, float* d_m,
+                           float* d_v, int32_t step, float lr, float b1, float b2, float eps,
+                           hipStream_t stream) {
+  if (n_params <= 0 || !d_params || !d_grad || !d_m || !d_v || step < 1) return DLIC_ERR_ARG;
+  dlic_status rc = current_consts(nullptr);
+  if (rc != DLIC_OK) return rc;
+  timing_begin("adam_kernel", stream);
+  launch_adam(n_params, d_params, d_grad, d_m, d_v, step, lr, b1, b2, eps, stream);
   timing_end(stream);
   return launch_ok();
 }

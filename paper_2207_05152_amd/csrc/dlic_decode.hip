@@ -31,12 +31,14 @@ namespace dlic {
 
 constexpr int RING_MASK = DEC_RING - 1;
 constexpr int REFILL_WORDS = 1024;           // one coder-wave refill: 16 words per lane
-constexpr int NWORK = DEC_WAVES - 1;         // density waves
+constexpr int CODER_SIMD_TWIN = 4;          // wave sharing the coder's SIMD (left idle)
+constexpr int NWORK = DEC_WAVES - 2;         // density waves
 constexpr int NSLOT = 8;                     // sub-round densities in flight
 constexpr int SLOT_PX = 64;                  // lanes per group at most
 constexpr int PAR_STRIDE = 16;               // floats per pixel: pi[5], A[5], B[5]
 constexpr int N_BUCKET = 15;                 // F(16 m), m = 1..15
 constexpr uint32_t LDS_SPIN_LIMIT = 1u << 24;
+
 
 __device__ __forceinline__ int floordiv(int a, int b) {
   return a >= 0 ? a / b : -((-a + b - 1) / b);
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
   const int J = (R + L - 1) / L;
   const int NT = (L + 15) / 16;
   const int t_first = SKEW * r0, t_last = SKEW * (r1 - 1) + W - 1;
-  const long long P = (long long)(t_last - t_first + 1) * J;
+  const int P = (t_last - t_first + 1) * J;  // sub-rounds (host keeps this below 2^31)
   const int up_last = (g > 0) ? SKEW * (r0 - 1) + W - 1 : -1;
   const uint32_t n_words = rd_u32(a.bits + HEADER_BYTES + 4 * g);
   const uint16_t* gw = reinterpret_cast<const uint16_t*>(
@@ -191,8 +193,12 @@ __global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
     uint32_t Pw = 2u * (uint32_t)L;  // words consumed
     bool over = false, stuck = false, timeout = s_flag != 0;
     uint32_t E = E0;                   // words known to be in the ring
-    for (long long q = 0; q < P; ++q) {
-      const int t = t_first + (int)(q / J), j = (int)(q % J);
+    int t = t_first, j = -1;
+    for (int q = 0; q < P; ++q) {
+      if (++j == J) {
+        j = 0;
+        ++t;
+      }
       if (TABLES) {
         // no density waves here: the coder keeps its own ring filled
         if (!bad && E < n_words && E - Pw <= (uint32_t)(DEC_RING - 2 * REFILL_WORDS)) {
@@ -224,12 +230,12 @@ __global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
       const int xc = t - SKEW * y;
       const bool act = lane < L && rr < R && xc >= 0 && xc < W;
       const bool any = __ballot(act) != 0ull;
-      const int slot_i = (int)(q % NSLOT);
+      const int slot_i = q & (NSLOT - 1);
       const unsigned long long c0 = a.prof ? clock64() : 0ull;
       if (!TABLES && any && !stuck) {
         for (int i = 0; i < NT && !stuck; ++i) {
           uint32_t spins = 0;
-          while (lds_acquire(&s_done[slot_i][i]) != (int)q) {
+          while (lds_acquire(&s_done[slot_i][i]) != q) {
             if (++spins > LDS_SPIN_LIMIT) {
               stuck = true;
               break;
@@ -313,7 +319,7 @@ __global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
       }
       if (lane == 0) {
         s_pw = Pw;
-        lds_release(&s_decoded, (int)(q + 1));
+        lds_release(&s_decoded, q + 1);
       }
       if (a.prof) {
         const unsigned long long c2 = clock64();
@@ -341,18 +347,28 @@ __global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
     }
   } else if (!TABLES) {
     // -------------------------------------------------------- density waves
+    // density waves: waves are placed on SIMDs round-robin, so wave 4 would
+    // share the coder's SIMD; it stays idle and the coder keeps its SIMD
+    if (wave == CODER_SIMD_TWIN) return;
+    const int nwork = NWORK;
+    const int w = wave > CODER_SIMD_TWIN ? wave - 2 : wave - 1;
     NetF32<H1, H2> net;
     net.load(m, lane);
-    const int w = wave - 1, q4 = lane >> 4;
+    const int q4 = lane >> 4;
     bool timeout = s_flag != 0;
     bool stuck = false;
-    for (long long tau = w;; tau += NWORK) {
-      const long long q = tau / NT;
-      const int ti = (int)(tau % NT);
+    // tile tau = NT * q + ti of sub-round q = (t - t_first) * J + j, every NWORK-th
+    int q = 0, ti = w, t = t_first, j = 0;
+    while (ti >= NT) {
+      ti -= NT;
+      ++q;
+    }
+    j = q % J;
+    t = t_first + q / J;
+    for (;; ) {
       if (q >= P) break;
-      const int t = t_first + (int)(q / J), j = (int)(q % J);
-      const int slot_i = (int)(q % NSLOT);
-      const long long need = max(q - J + 1, q - NSLOT + 1);
+      const int slot_i = q & (NSLOT - 1);
+      const int need = max(q - J + 1, q - NSLOT + 1);
       const unsigned long long c0 = a.prof ? clock64() : 0ull;
       if (!stuck) {
         uint32_t spins = 0;
@@ -443,11 +459,21 @@ __global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
           }
         }
       }
-      if (lane == 0) lds_release(&s_done[slot_i][ti], (int)q);
+      if (lane == 0) lds_release(&s_done[slot_i][ti], q);
       if (a.prof) {
         const unsigned long long c2 = clock64();
         t_wait += c1 - c0;
         t_busy += c2 - c1;
+      }
+      // next tile of this wave
+      ti += nwork;
+      while (ti >= NT) {
+        ti -= NT;
+        ++q;
+        if (++j == J) {
+          j = 0;
+          ++t;
+        }
       }
     }
     if (lane == 0) {

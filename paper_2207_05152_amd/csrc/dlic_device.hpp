@@ -174,7 +174,7 @@ __device__ __forceinline__ float sigma_hat(float u, const float2* sd) {
   u = u > 0.0f ? u : 0.0f;
   u = fminf(u, 4096.0f);
   const int j = (int)u;
-  const float w = u - (float)j;
+  const float w = __builtin_amdgcn_fractf(u);  // u - floor(u), exact for u >= 0
   const float2 e = sd[j];
   return e.x + w * e.y;
 }

@@ -16,7 +16,7 @@ struct HeaderFields {
 // Decoder limits: rows per group, and the per-group stream ring in LDS.
 constexpr int DEC_RMAX = 256;
 constexpr int DEC_RING = 4096;
-constexpr int DEC_WAVES = 8;  // wave 0 codes, waves 1..7 compute densities
+constexpr int DEC_WAVES = 8;  // wave 0 codes, six of waves 1..7 compute densities
 
 struct DecArgs {
   const uint8_t* bits;
@@ -45,5 +45,17 @@ void launch_pack(const uint16_t* words, const uint32_t* counts, int H, int W, in
 bool launch_decode(int width, bool tables_mode, const Consts* K, const DevModel& m,
                    const DecArgs& a, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t s);
+
+// Training: waves per workgroup of the FP32 / FP64 loss-and-gradient kernel.
+constexpr int TRAIN_WAVES_F32 = 4;
+constexpr int TRAIN_WAVES_F64 = 1;
+constexpr int TRAIN_GRID = 256;
+int train_n_params(int h1, int h2);
+bool launch_nll(bool fp64, int width, const void* w1, const void* b1, const void* w2,
+                const void* b2, const void* w3, const void* b3, const uint8_t* slices,
+                int n_slices, int sh, int sw, const int32_t* idx, long long n, void* partials,
+                int grid, bool want_grad, void* grad, void* loss, hipStream_t s);
+void launch_adam(long long np, float* p, const float* g, float* m, float* v, int step, float lr,
+                 float b1, float b2, float eps, hipStream_t s);
 
 }  // namespace dlic
