@@ -62,7 +62,10 @@ typedef enum {
 
 /* Network weights (Section II-B, Neural Network Architecture; the mixture
  * head of Section I / IV-C).  Matrices are row-major [out][in] in the given
- * dtype; biases are FP32.  Supported widths: h1 == h2 in {32, 64, 128}. */
+ * dtype (FP32 values, BF16 bit patterns or e4m3 codes, as
+ * dlic_quantize_weights writes them); biases are FP32.  Supported widths:
+ * h1 == h2 in {32, 64, 128} for FP32, BF16 and FP8 inference; {32, 64} for
+ * training (FP32, FP64). */
 typedef struct dlic_model {
   int32_t k_in;          /* must be 12                                      */
   int32_t h1, h2;        /* hidden widths                                   */
@@ -74,7 +77,8 @@ typedef struct dlic_model {
   const void *d_w3;      /* [15][h2]                                        */
   const float *d_b1, *d_b2, *d_b3;
   const float *d_wscale; /* FP8: 3 per-layer scales (device); otherwise NULL */
-  uint64_t fingerprint;  /* dlic_fnv1a64 over W1,b1,W2,b2,W3,b3 bytes       */
+  uint64_t fingerprint;  /* dlic_fnv1a64 over W1,b1,W2,b2,W3,b3 bytes (then
+                            the 3 scales for FP8)                          */
 } dlic_model;
 
 /* Coder instances (Section II-B, rANS: several coder instances and
@@ -104,6 +108,21 @@ uint64_t dlic_fnv1a64(uint64_t h, const void *h_bytes, size_t n);
  * bin edges beta[257] (beta[0] = -inf, beta[256] = +inf) and the scaled grey
  * levels scale[256].  Any pointer may be NULL. */
 void dlic_host_constants(float *h_S, float *h_D, float *h_beta, float *h_scale);
+
+/* Weight storage of the reduced-precision networks (the network of Section
+ * II-B run with BF16 or FP8 operands and FP32 accumulation).  Converts one
+ * FP32 matrix of n finite elements, host to host:
+ *   DLIC_BF16      h_out: n uint16 BF16 bit patterns, round to nearest even;
+ *                  *h_scale (if not NULL) = 1.
+ *   DLIC_FP8_E4M3  *h_scale = max|W| / 448 in FP32 (1 for an all-zero
+ *                  matrix); h_out: n OCP e4m3 codes (bias 7, no infinities)
+ *                  of W / scale computed in FP32, rounded to nearest even and
+ *                  saturated at +-448.  The net computes scale * (Q a) + b.
+ * Returns DLIC_ERR_ARG for NULL pointers, n == 0, a non-finite weight or
+ * another dtype.  A model's fingerprint covers the converted bytes of W1,
+ * b1, W2, b2, W3, b3 in that order, then for FP8 the three scales. */
+dlic_status dlic_quantize_weights(int32_t dtype, const float *h_w, size_t n, void *h_out,
+                                  float *h_scale);
 
 /* Worst-case stream size in bytes for an h x w image: header, word counts,
  * at most one 16-bit word per pixel and the flushed states. */

@@ -28,7 +28,8 @@ HEADER_BYTES = 36
 
 # Every symbol include/dlic.h declares.
 EXPORTS = (
-    "dlic_status_string", "dlic_fnv1a64", "dlic_host_constants", "dlic_encode_bound",
+    "dlic_status_string", "dlic_fnv1a64", "dlic_host_constants", "dlic_quantize_weights",
+    "dlic_encode_bound",
     "dlic_encode_workspace", "dlic_decode_workspace", "dlic_peek_header", "dlic_init",
     "dlic_encode", "dlic_decode", "dlic_set_spin_limit", "dlic_density",
     "dlic_rans_encode_cf", "dlic_rans_decode_tables", "dlic_set_timing", "dlic_kernel_times",
@@ -69,6 +70,7 @@ def lib():
         "dlic_status_string": (c_char_p, [c_int]),
         "dlic_fnv1a64": (c_uint64, [c_uint64, P, S]),
         "dlic_host_constants": (None, [P, P, P, P]),
+        "dlic_quantize_weights": (c_int, [c_int32, P, S, P, P]),
         "dlic_encode_bound": (S, [c_int32, c_int32, POINTER(dlic_coder)]),
         "dlic_encode_workspace": (S, [c_int32, c_int32, POINTER(dlic_coder)]),
         "dlic_decode_workspace": (S, [c_int32, c_int32, POINTER(dlic_coder)]),
@@ -134,6 +136,16 @@ def _stream(stream):
 def dlic_fnv1a64(h: int, data: bytes) -> int:
     buf = ctypes.create_string_buffer(bytes(data), len(data))
     return int(lib().dlic_fnv1a64(h, buf, len(data)))
+
+
+def dlic_quantize_weights(dtype: int, w) -> tuple:
+    """Stored form of one FP32 matrix: (uint16 BF16 bits or uint8 e4m3 codes, FP32 scale)."""
+    a = np.ascontiguousarray(w, dtype=np.float32)
+    out = np.empty(a.shape, np.uint16 if dtype == DLIC_BF16 else np.uint8)
+    sc = np.zeros(1, np.float32)
+    _check(lib().dlic_quantize_weights(dtype, a.ctypes.data, a.size, out.ctypes.data,
+                                       sc.ctypes.data), "dlic_quantize_weights")
+    return out, np.float32(sc[0])
 
 
 def dlic_host_constants():
@@ -235,22 +247,44 @@ def default_coder(h: int, lanes: int = 32, rows_per_group: int = 192) -> dlic_co
     return dlic_coder(g, lanes)
 
 
-class Model:
-    """FP32 network weights resident on a device, with their C descriptor."""
+DTYPES = {"fp32": DLIC_FP32, "bf16": DLIC_BF16, "fp8": DLIC_FP8_E4M3}
 
-    def __init__(self, weights: dict, device="cuda"):
+
+class Model:
+    """Network weights resident on a device, with their C descriptor.
+
+    dtype 'fp32' keeps the FP32 matrices; 'bf16' and 'fp8' store them as the
+    library's dlic_quantize_weights converts them (biases stay FP32)."""
+
+    def __init__(self, weights: dict, device="cuda", dtype: str = "fp32"):
         import torch
-        self.np = {k: np.ascontiguousarray(weights[k], dtype=np.float32)
-                   for k in ("W1", "b1", "W2", "b2", "W3", "b3")}
+        code = DTYPES[dtype]
+        self.dtype = dtype
+        self.np = {}
+        scales = []
+        for k in ("W1", "W2", "W3"):
+            w32 = np.ascontiguousarray(weights[k], dtype=np.float32)
+            if code == DLIC_FP32:
+                self.np[k], s = w32, np.float32(1.0)
+            else:
+                self.np[k], s = dlic_quantize_weights(code, w32)
+            scales.append(s)
+        for k in ("b1", "b2", "b3"):
+            self.np[k] = np.ascontiguousarray(weights[k], dtype=np.float32)
+        self.scales = np.array(scales, dtype=np.float32)
         self.t = {k: torch.from_numpy(v).to(device) for k, v in self.np.items()}
+        self.t_scales = torch.from_numpy(self.scales).to(device)
         h = FNV_OFFSET
         for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
             h = dlic_fnv1a64(h, self.np[k].tobytes())
+        if code == DLIC_FP8_E4M3:
+            h = dlic_fnv1a64(h, self.scales.tobytes())
         self.fingerprint = h
         h1, h2 = self.np["W1"].shape[0], self.np["W2"].shape[0]
-        self.c = dlic_model(12, h1, h2, 15, DLIC_FP32, 0, _ptr(self.t["W1"]), _ptr(self.t["W2"]),
+        self.c = dlic_model(12, h1, h2, 15, code, 0, _ptr(self.t["W1"]), _ptr(self.t["W2"]),
                             _ptr(self.t["W3"]), _ptr(self.t["b1"]), _ptr(self.t["b2"]),
-                            _ptr(self.t["b3"]), None, h)
+                            _ptr(self.t["b3"]),
+                            _ptr(self.t_scales) if code == DLIC_FP8_E4M3 else None, h)
 
 
 def _empty(n, dtype, device="cuda"):

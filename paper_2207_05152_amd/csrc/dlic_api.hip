@@ -144,19 +144,31 @@ dlic_status model_ok(const dlic_model* m) {
   if (!m) return DLIC_ERR_ARG;
   if (m->k_in != K_IN || m->n_out != N_OUT || m->reserved != 0) return DLIC_ERR_ARG;
   if (!m->d_w1 || !m->d_w2 || !m->d_w3 || !m->d_b1 || !m->d_b2 || !m->d_b3) return DLIC_ERR_ARG;
-  if (m->dtype != DLIC_FP32) return DLIC_ERR_UNSUPPORTED;
-  if (m->h1 != m->h2 || (m->h1 != 32 && m->h1 != 64)) return DLIC_ERR_UNSUPPORTED;
+  if (m->dtype != DLIC_FP32 && m->dtype != DLIC_BF16 && m->dtype != DLIC_FP8_E4M3)
+    return DLIC_ERR_UNSUPPORTED;
+  if (m->dtype == DLIC_FP8_E4M3 && !m->d_wscale) return DLIC_ERR_ARG;
+  if (m->h1 != m->h2 || (m->h1 != 32 && m->h1 != 64 && m->h1 != 128))
+    return DLIC_ERR_UNSUPPORTED;
   return DLIC_OK;
+}
+
+int weight_type(const dlic_model* m) {
+  switch (m->dtype) {
+    case DLIC_BF16: return WT_BF16;
+    case DLIC_FP8_E4M3: return WT_FP8;
+    default: return WT_F32;
+  }
 }
 
 DevModel dev_model(const dlic_model* m) {
   DevModel d;
-  d.w1 = (const float*)m->d_w1;
-  d.w2 = (const float*)m->d_w2;
-  d.w3 = (const float*)m->d_w3;
+  d.w1 = m->d_w1;
+  d.w2 = m->d_w2;
+  d.w3 = m->d_w3;
   d.b1 = m->d_b1;
   d.b2 = m->d_b2;
   d.b3 = m->d_b3;
+  d.wscale = m->dtype == DLIC_FP8_E4M3 ? m->d_wscale : nullptr;
   return d;
 }
 
@@ -252,6 +264,53 @@ void dlic_host_constants(float* h_S, float* h_D, float* h_beta, float* h_scale) 
   delete c;
 }
 
+dlic_status dlic_quantize_weights(int32_t dtype, const float* h_w, size_t n, void* h_out,
+                                  float* h_scale) {
+  if (!h_w || !h_out || n == 0) return DLIC_ERR_ARG;
+  for (size_t i = 0; i < n; ++i)
+    if (!isfinite(h_w[i])) return DLIC_ERR_ARG;
+  if (dtype == DLIC_BF16) {
+    uint16_t* out = (uint16_t*)h_out;
+    for (size_t i = 0; i < n; ++i) {
+      uint32_t u;
+      memcpy(&u, &h_w[i], 4);
+      u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+      out[i] = (uint16_t)(u >> 16);
+    }
+    if (h_scale) *h_scale = 1.0f;
+    return DLIC_OK;
+  }
+  if (dtype != DLIC_FP8_E4M3 || !h_scale) return DLIC_ERR_ARG;
+  float amax = 0.0f;
+  for (size_t i = 0; i < n; ++i) amax = fmaxf(amax, fabsf(h_w[i]));
+  const float scale = amax > 0.0f ? amax / 448.0f : 1.0f;
+  uint8_t* out = (uint8_t*)h_out;
+  for (size_t i = 0; i < n; ++i) {
+    const float x = h_w[i] / scale;
+    const double a = fabs((double)x);
+    uint32_t code;
+    if (a >= 448.0) {
+      code = 0x7Eu;  // saturate at the largest finite e4m3 value
+    } else if (a < 0.015625) {
+      code = (uint32_t)nearbyint(a * 512.0);  // subnormal step 2^-9; 8 is 2^-6 itself
+    } else {
+      int e = (int)floor(log2(a));
+      if (ldexp(1.0, e) > a) --e;
+      if (ldexp(1.0, e + 1) <= a) ++e;
+      uint32_t m = (uint32_t)nearbyint(ldexp(a, 3 - e)) - 8u;
+      if (m == 8u) {
+        m = 0;
+        ++e;
+      }
+      code = ((uint32_t)(e + 7) << 3) | m;
+      if (code > 0x7Eu) code = 0x7Eu;
+    }
+    out[i] = (uint8_t)(code | (signbit(x) && code != 0 ? 0x80u : 0u));
+  }
+  *h_scale = scale;
+  return DLIC_OK;
+}
+
 size_t dlic_encode_bound(int32_t h, int32_t w, const dlic_coder* coder) {
   if (h <= 0 || w <= 0 || !coder_ok(h, coder)) return 0;
   const size_t G = coder->groups, L = coder->lanes_per_group;
@@ -308,7 +367,7 @@ dlic_status dlic_encode(const dlic_model* model, const dlic_coder* coder, const 
   enc_ws_layout(h, w, coder->groups, coder->lanes_per_group, d_ws, &ws);
   const long long n = (long long)h * w;
   timing_begin("density_kernel", stream);
-  launch_density(model->h1, K, dev_model(model), d_img, h, w, ws.cf, nullptr, nullptr,
+  launch_density(weight_type(model), model->h1, K, dev_model(model), d_img, h, w, ws.cf, nullptr, nullptr,
                  density_grid(n), stream);
   timing_end(stream);
   if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
@@ -365,7 +424,7 @@ static dlic_status decode_common(const dlic_model* model, bool tables_mode,
   a.prof = tables_mode ? nullptr : g_prof;
   DevModel dm;
   memset(&dm, 0, sizeof(dm));
-  int width = 32;
+  int width = 32, wtype = WT_F32;
   if (tables_mode) {
     if (!d_tables || !d_tidx || n_tables < 1) return DLIC_ERR_ARG;
     a.tables = d_tables;
@@ -377,6 +436,7 @@ static dlic_status decode_common(const dlic_model* model, bool tables_mode,
     a.hf = HeaderFields{model->dtype, model->h1, model->h2, model->fingerprint};
     dm = dev_model(model);
     width = model->h1;
+    wtype = weight_type(model);
   }
   timing_begin("fill_u32_kernel", stream);
   launch_fill_u32(a.rec, 0u, (long long)a.G * a.T, stream);
@@ -385,7 +445,7 @@ static dlic_status decode_common(const dlic_model* model, bool tables_mode,
   if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
   timing_begin(tables_mode ? "wavefront_decode_kernel<tables>" : "wavefront_decode_kernel",
                stream);
-  if (!launch_decode(width, tables_mode, K, dm, a, stream)) return DLIC_ERR_UNSUPPORTED;
+  if (!launch_decode(wtype, width, tables_mode, K, dm, a, stream)) return DLIC_ERR_UNSUPPORTED;
   timing_end(stream);
   return launch_ok();
 }
@@ -416,7 +476,7 @@ dlic_status dlic_density(const dlic_model* model, const uint8_t* d_img, int32_t 
   const Consts* K = nullptr;
   if ((rc = current_consts(&K)) != DLIC_OK) return rc;
   timing_begin("density_kernel", stream);
-  launch_density(model->h1, K, dev_model(model), d_img, h, w, d_cf, d_out15, d_tables,
+  launch_density(weight_type(model), model->h1, K, dev_model(model), d_img, h, w, d_cf, d_out15, d_tables,
                  density_grid((long long)h * w), stream);
   timing_end(stream);
   return launch_ok();

@@ -101,7 +101,7 @@ __device__ __forceinline__ void stash_record(uint8_t* ring, uint32_t v, int s, i
   if (c2 >= 0 && c2 < W) ring[0 * 16 + (c2 & 15)] = (uint8_t)((v >> 8) & 0xFF);
 }
 
-template <int H1, int H2, bool TABLES>
+template <class Net, bool TABLES>
 __global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
     const Consts* __restrict__ K, DevModel m, DecArgs a) {
   __shared__ float2 s_sd[LUT_N];
@@ -116,6 +116,7 @@ __global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
   __shared__ uint32_t s_pw, s_end;  // words consumed by the coder / loaded into the ring
   __shared__ unsigned long long s_total, s_before;
   __shared__ int s_err, s_flag;
+  __shared__ __attribute__((aligned(16))) char s_w2[Net::LDS_BYTES > 0 ? Net::LDS_BYTES : 16];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = blockIdx.x;
@@ -126,6 +127,7 @@ __global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
     for (int i = tid; i < LUT_N; i += NTH) s_sd[i] = K->sd[i];
     for (int i = tid; i < 257; i += NTH) s_beta[i] = K->beta[i];
     for (int i = tid; i < 256; i += NTH) s_scale[i] = K->scale[i];
+    Net::stage(m, s_w2, tid, NTH);
   }
   if (tid < NSLOT * 4) s_done[tid / 4][tid % 4] = -1;
   if (tid == 0) {
@@ -352,7 +354,7 @@ __global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
     if (wave == CODER_SIMD_TWIN) return;
     const int nwork = NWORK;
     const int w = wave > CODER_SIMD_TWIN ? wave - 2 : wave - 1;
-    NetF32<H1, H2> net;
+    Net net;
     net.load(m, lane);
     const int q4 = lane >> 4;
     bool timeout = s_flag != 0;
@@ -424,7 +426,7 @@ __global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
         // the left neighbour (decoded last step) goes to the image now
         if (valid && q4 == 0 && xc >= 1)
           a.img[(long long)y * W + xc - 1] = s_ring[(rr + 2) * 16 + ((xc - 1) & 15)];
-        const f4 o = net.run(fk[0], fk[1], fk[2]);
+        const f4 o = net.run(fk[0], fk[1], fk[2], s_w2);
         float* par = &s_par[slot_i][0];
         if (valid) *reinterpret_cast<f4*>(&par[ln * PAR_STRIDE + 4 * q4]) = o;
         // mixture head, one lane per pixel
@@ -500,21 +502,35 @@ void launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t s) {
   hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
 }
 
-template <int H1, int H2, bool TB>
+template <class Net, bool TB>
 static void launch_decode_t(const Consts* K, const DevModel& m, const DecArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((wavefront_decode_kernel<H1, H2, TB>), dim3(a.G), dim3(DEC_WAVES * 64), 0, s,
+  hipLaunchKernelGGL((wavefront_decode_kernel<Net, TB>), dim3(a.G), dim3(DEC_WAVES * 64), 0, s,
                      K, m, a);
 }
 
-bool launch_decode(int width, bool tables_mode, const Consts* K, const DevModel& m,
+// Layer-2 weights of the BF16 nets go to LDS at H = 128: six density waves
+// share one copy instead of holding 128 VGPRs each.
+template <int H>
+static bool launch_decode_h(int wtype, const Consts* K, const DevModel& m, const DecArgs& a,
+                            hipStream_t s) {
+  switch (wtype) {
+    case WT_F32: launch_decode_t<NetF32<H>, false>(K, m, a, s); return true;
+    case WT_BF16: launch_decode_t<NetBF16<H, WT_BF16, (H > 64)>, false>(K, m, a, s); return true;
+    case WT_FP8: launch_decode_t<NetBF16<H, WT_FP8, (H > 64)>, false>(K, m, a, s); return true;
+    default: return false;
+  }
+}
+
+bool launch_decode(int wtype, int width, bool tables_mode, const Consts* K, const DevModel& m,
                    const DecArgs& a, hipStream_t s) {
   if (tables_mode) {
-    launch_decode_t<32, 32, true>(K, m, a, s);
+    launch_decode_t<NetF32<32>, true>(K, m, a, s);
     return true;
   }
   switch (width) {
-    case 32: launch_decode_t<32, 32, false>(K, m, a, s); return true;
-    case 64: launch_decode_t<64, 64, false>(K, m, a, s); return true;
+    case 32: return launch_decode_h<32>(wtype, K, m, a, s);
+    case 64: return launch_decode_h<64>(wtype, K, m, a, s);
+    case 128: return launch_decode_h<128>(wtype, K, m, a, s);
     default: return false;
   }
 }

@@ -38,17 +38,29 @@ struct Consts {
   float scale[256];   // RN32((2v - 255) / 255)
 };
 
-// Network weights as the kernels see them (FP32, row-major [out][in]).
+// Network weights as the kernels see them: row-major [out][in] matrices in
+// the model's storage type (FP32, BF16 bit patterns, or FP8 e4m3 codes), FP32
+// biases, and for FP8 one FP32 scale per layer (W = scale * code value).
 struct DevModel {
-  const float *w1, *b1, *w2, *b2, *w3, *b3;
+  const void *w1, *w2, *w3;
+  const float *b1, *b2, *b3;
+  const float* wscale;
 };
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // D(16x16) = A(16x4) B(4x16) + C with lane l holding A[l%16][l/16],
 // B[l/16][l%16] and D[4*(l/16) + r][l%16] (r = 0..3).
 __device__ __forceinline__ f4 mfma_f32(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// D(16x16) = A(16x32) B(32x16) + C in BF16 with FP32 accumulation; lane l
+// holds A[l%16][8*(l/16) + e] and B[8*(l/16) + e][l%16] (e = 0..7), and D as
+// for mfma_f32.
+__device__ __forceinline__ f4 mfma_bf16(bf16x8 a, bf16x8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 // Causal window offset of feature k (rows y-2, y-1 at dx -2..2, then (y, x-2), (y, x-1)).
@@ -57,57 +69,117 @@ __device__ __forceinline__ int nb_dx(int k) { return k < 5 ? k - 2 : (k < 10 ? k
 
 __device__ __forceinline__ float relu(float v) { return v > 0.0f ? v : 0.0f; }
 
+// Storage types of the weight matrices.
+enum WeightType { WT_F32 = 0, WT_BF16 = 1, WT_FP8 = 2 };
+
+// OCP e4m3 (FN) code -> BF16 bit pattern: bias 7, 3 mantissa bits,
+// subnormal step 2^-9; every code is exact in BF16 (exponent bias 127).
+__device__ __forceinline__ uint32_t e4m3_bf16_bits(uint32_t b) {
+  const uint32_t e = (b >> 3) & 15u, m = b & 7u;
+  const uint32_t normal = ((e + 120u) << 7) | (m << 4);
+  const uint32_t sub = __float_as_uint((float)m * 0.001953125f) >> 16;
+  return (e ? normal : sub) | ((b & 0x80u) << 8);
+}
+
+// BF16 bit pattern of element idx of a weight matrix (exact for BF16 and
+// FP8 storage), in the low half of the result.
+template <int WT>
+__device__ __forceinline__ uint32_t weight_bf16_bits(const void* p, long idx) {
+  if constexpr (WT == WT_BF16) {
+    return ((const uint16_t*)p)[idx];
+  } else {
+    return e4m3_bf16_bits(((const uint8_t*)p)[idx]);
+  }
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Eight BF16 bit patterns (element e in half e % 2 of word e / 2) as one operand.
+__device__ __forceinline__ bf16x8 pack_bf16x8(const uint32_t* h) {
+  const u32x4 w = {h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                   h[6] | (h[7] << 16)};
+  return __builtin_bit_cast(bf16x8, w);
+}
+
 // -----------------------------------------------------------------------------
-// Network tile: 16 pixels through 12 -> H1 -> H2 -> 15 on v_mfma_f32_16x16x4f32.
+// Network tiles: 16 pixels through 12 -> H -> H -> 15 on MFMA.
 //
 // Activations are the B operand (K x 16 pixels) and weights the A operand
 // (16 neurons x K), so a layer's D registers (neuron 16*nt + 4*(l/16) + r of
-// pixel l%16) are directly the next layer's B operand for the k-step (nt, r):
-// the weights are loaded with the matching permutation of their input index.
-// Biases seed the accumulators.  Weights stay resident in VGPRs.
+// pixel l%16) are directly the next layer's B operand: the weights are
+// loaded with the matching permutation of their input index.  Every net has
+// the same interface:
+//   LDS_BYTES            workgroup LDS the net reads its layer-2 weights from
+//                        (0 when they live in registers)
+//   stage(m, lds, t, n)  thread t of n copies layer-2 weights into LDS
+//   load(m, lane)        per-lane weights and biases into registers
+//   run(f0, f1, f2, lds) features 4e + l/16 (e = 0, 1, 2) of pixel l%16 in,
+//                        outputs 4*(l/16) .. 4*(l/16)+3 of that pixel out.
 // -----------------------------------------------------------------------------
-template <int H1, int H2>
+
+// FP32 weights, v_mfma_f32_16x16x4f32, biases seed the accumulators.
+// Layer-2 weights sit in VGPRs up to H = 64 and in LDS above (64 KB at 128).
+template <int H>
 struct NetF32 {
-  static constexpr int NT1 = H1 / 16, NT2 = H2 / 16;
-  float a1[NT1][3];
-  float a2[NT2][NT1 * 4];
-  float a3[NT2 * 4];
-  float c1[NT1][4], c2[NT2][4], c3[4];
+  static constexpr int NT = H / 16;
+  static constexpr bool W2_LDS = H > 64;
+  static constexpr int LDS_BYTES = W2_LDS ? NT * NT * 64 * 16 : 0;
+  float a1[NT][3];
+  float a2[W2_LDS ? 1 : NT][W2_LDS ? 1 : NT * 4];
+  float a3[NT * 4];
+  float c1[NT][4], c2[NT][4], c3[4];
+
+  // LDS order: f4 index (n2 * NT + n1) * 64 + lane holds r = 0..3.
+  __device__ __forceinline__ static void stage(const DevModel& m, void* lds, int t, int n) {
+    if constexpr (W2_LDS) {
+      const float* w2 = (const float*)m.w2;
+      float* d = (float*)lds;
+      for (int idx = t; idx < NT * NT * 256; idx += n) {
+        const int r = idx & 3, lane = (idx >> 2) & 63, blk = idx >> 8;
+        const int n2 = blk / NT, n1 = blk - n2 * NT;
+        d[idx] = w2[(16 * n2 + (lane & 15)) * H + 16 * n1 + 4 * (lane >> 4) + r];
+      }
+    }
+  }
 
   __device__ __forceinline__ void load(const DevModel& m, int lane) {
+    const float* w1 = (const float*)m.w1;
+    const float* w2 = (const float*)m.w2;
+    const float* w3 = (const float*)m.w3;
     const int i = lane & 15, q = lane >> 4;
 #pragma unroll
-    for (int nt = 0; nt < NT1; ++nt)
+    for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-      for (int kk = 0; kk < 3; ++kk) a1[nt][kk] = m.w1[(16 * nt + i) * K_IN + 4 * kk + q];
+      for (int kk = 0; kk < 3; ++kk) a1[nt][kk] = w1[(16 * nt + i) * K_IN + 4 * kk + q];
+    if constexpr (!W2_LDS) {
 #pragma unroll
-    for (int n2 = 0; n2 < NT2; ++n2)
+      for (int n2 = 0; n2 < NT; ++n2)
 #pragma unroll
-      for (int n1 = 0; n1 < NT1; ++n1)
+        for (int n1 = 0; n1 < NT; ++n1)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          a2[n2][n1 * 4 + r] = m.w2[(16 * n2 + i) * H1 + 16 * n1 + 4 * q + r];
+          for (int r = 0; r < 4; ++r)
+            a2[n2][n1 * 4 + r] = w2[(16 * n2 + i) * H + 16 * n1 + 4 * q + r];
+    }
 #pragma unroll
-    for (int n2 = 0; n2 < NT2; ++n2)
+    for (int n2 = 0; n2 < NT; ++n2)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        a3[n2 * 4 + r] = (i < N_OUT) ? m.w3[i * H2 + 16 * n2 + 4 * q + r] : 0.0f;
+        a3[n2 * 4 + r] = (i < N_OUT) ? w3[i * H + 16 * n2 + 4 * q + r] : 0.0f;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
 #pragma unroll
-      for (int nt = 0; nt < NT1; ++nt) c1[nt][r] = m.b1[16 * nt + 4 * q + r];
-#pragma unroll
-      for (int nt = 0; nt < NT2; ++nt) c2[nt][r] = m.b2[16 * nt + 4 * q + r];
+      for (int nt = 0; nt < NT; ++nt) {
+        c1[nt][r] = m.b1[16 * nt + 4 * q + r];
+        c2[nt][r] = m.b2[16 * nt + 4 * q + r];
+      }
       c3[r] = (4 * q + r < N_OUT) ? m.b3[4 * q + r] : 0.0f;
     }
   }
 
-  // f0, f1, f2: this lane's window features k = l/16, 4 + l/16, 8 + l/16 of
-  // pixel l%16.  Returns outputs 4*(l/16) .. 4*(l/16)+3 of pixel l%16.
-  __device__ __forceinline__ f4 run(float f0, float f1, float f2) const {
-    f4 h1[NT1];
+  __device__ __forceinline__ f4 run(float f0, float f1, float f2, const void* lds) const {
+    f4 h1[NT];
 #pragma unroll
-    for (int nt = 0; nt < NT1; ++nt) {
+    for (int nt = 0; nt < NT; ++nt) {
       f4 acc = {c1[nt][0], c1[nt][1], c1[nt][2], c1[nt][3]};
       acc = mfma_f32(a1[nt][0], f0, acc);
       acc = mfma_f32(a1[nt][1], f1, acc);
@@ -115,22 +187,178 @@ struct NetF32 {
 #pragma unroll
       for (int r = 0; r < 4; ++r) h1[nt][r] = relu(acc[r]);
     }
-    f4 h2[NT2];
+    f4 h2[NT];
+    const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 #pragma unroll
-    for (int n2 = 0; n2 < NT2; ++n2) {
+    for (int n2 = 0; n2 < NT; ++n2) {
       f4 acc = {c2[n2][0], c2[n2][1], c2[n2][2], c2[n2][3]};
 #pragma unroll
-      for (int n1 = 0; n1 < NT1; ++n1)
+      for (int n1 = 0; n1 < NT; ++n1) {
+        f4 w;
+        if constexpr (W2_LDS) {
+          w = ((const f4*)lds)[(n2 * NT + n1) * 64 + lane];
+        } else {
+          w = f4{a2[n2][n1 * 4], a2[n2][n1 * 4 + 1], a2[n2][n1 * 4 + 2], a2[n2][n1 * 4 + 3]};
+        }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc = mfma_f32(a2[n2][n1 * 4 + r], h1[n1][r], acc);
+        for (int r = 0; r < 4; ++r) acc = mfma_f32(w[r], h1[n1][r], acc);
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) h2[n2][r] = relu(acc[r]);
     }
     f4 o = {c3[0], c3[1], c3[2], c3[3]};
 #pragma unroll
-    for (int n2 = 0; n2 < NT2; ++n2)
+    for (int n2 = 0; n2 < NT; ++n2)
 #pragma unroll
       for (int r = 0; r < 4; ++r) o = mfma_f32(a3[n2 * 4 + r], h2[n2][r], o);
+    return o;
+  }
+};
+
+// BF16 operands with FP32 accumulation on v_mfma_f32_16x16x32_bf16.  Inputs
+// and hidden activations are rounded to BF16 (round to nearest even) before
+// each product; biases and accumulators stay FP32.
+//
+// WT_BF16: weights are BF16; the bias seeds the accumulator.
+// WT_FP8:  weights are e4m3 codes, widened exactly to BF16; a layer's FP32
+//          scale multiplies the finished accumulator, then the bias is added
+//          (z = scale * (Q a) + b).
+//
+// K slots: a lane holds slots 8*(l/16) + e.  Layer 1 puts feature 4e + l/16
+// in slot e < 3 (zero for e >= 3), so every lane gathers three features.
+// Layers 2 and 3 take k-step s from the D registers of neuron tiles 2s
+// (e = r) and 2s + 1 (e = 4 + r): slot e of lane group q is neuron
+// 32s + 16*(e/4) + 4q + e%4.  Layer-2 weights sit in VGPRs by default; with
+// W2_LDS they are read from LDS (32 KB at H = 128).
+template <int H, int WT, bool W2_LDS_>
+struct NetBF16 {
+  static constexpr int NT = H / 16, NK = H / 32;
+  static constexpr bool W2_LDS = W2_LDS_;
+  static constexpr bool SCALED = WT == WT_FP8;
+  static constexpr int LDS_BYTES = W2_LDS ? NT * NK * 64 * 16 : 0;
+  bf16x8 a1[NT];
+  bf16x8 a2[W2_LDS ? 1 : NT][W2_LDS ? 1 : NK];
+  bf16x8 a3[NK];
+  float c1[NT][4], c2[NT][4], c3[4];
+  float s1, s2, s3;
+
+  __device__ __forceinline__ static int slot_neuron(int s, int q, int e) {
+    return 32 * s + 16 * (e >> 2) + 4 * q + (e & 3);
+  }
+
+  // LDS order: bf16x8 index (n2 * NK + s) * 64 + lane.
+  __device__ __forceinline__ static void stage(const DevModel& m, void* lds, int t, int n) {
+    if constexpr (W2_LDS) {
+      uint16_t* d = (uint16_t*)lds;
+      for (int idx = t; idx < NT * NK * 512; idx += n) {
+        const int e = idx & 7, lane = (idx >> 3) & 63, blk = idx >> 9;
+        const int n2 = blk / NK, s = blk - n2 * NK;
+        d[idx] = (uint16_t)weight_bf16_bits<WT>(
+            m.w2, (16 * n2 + (lane & 15)) * H + slot_neuron(s, lane >> 4, e));
+      }
+    }
+  }
+
+  __device__ __forceinline__ void load(const DevModel& m, int lane) {
+    const int i = lane & 15, q = lane >> 4;
+    uint32_t h[8];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        h[e] = e < 3 ? weight_bf16_bits<WT>(m.w1, (16 * nt + i) * K_IN + 4 * e + q) : 0u;
+      a1[nt] = pack_bf16x8(h);
+    }
+    if constexpr (!W2_LDS) {
+#pragma unroll
+      for (int n2 = 0; n2 < NT; ++n2)
+#pragma unroll
+        for (int s = 0; s < NK; ++s) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            h[e] = weight_bf16_bits<WT>(m.w2, (16 * n2 + i) * H + slot_neuron(s, q, e));
+          a2[n2][s] = pack_bf16x8(h);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        h[e] = i < N_OUT ? weight_bf16_bits<WT>(m.w3, i * H + slot_neuron(s, q, e)) : 0u;
+      a3[s] = pack_bf16x8(h);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        c1[nt][r] = m.b1[16 * nt + 4 * q + r];
+        c2[nt][r] = m.b2[16 * nt + 4 * q + r];
+      }
+      c3[r] = (4 * q + r < N_OUT) ? m.b3[4 * q + r] : 0.0f;
+    }
+    if constexpr (SCALED) {
+      s1 = m.wscale[0];
+      s2 = m.wscale[1];
+      s3 = m.wscale[2];
+    } else {
+      s1 = s2 = s3 = 1.0f;
+    }
+  }
+
+  // Accumulator start and finished pre-activation of one layer.
+  __device__ __forceinline__ static f4 seed(const float* c) {
+    if constexpr (SCALED) return f4{0.0f, 0.0f, 0.0f, 0.0f};
+    return f4{c[0], c[1], c[2], c[3]};
+  }
+  __device__ __forceinline__ static float finish(float acc, float scale, float bias) {
+    if constexpr (SCALED) return acc * scale + bias;
+    return acc;
+  }
+
+  __device__ __forceinline__ f4 run(float f0, float f1, float f2, const void* lds) const {
+    const __bf16 zero = (__bf16)0.0f;
+    const bf16x8 x = {(__bf16)f0, (__bf16)f1, (__bf16)f2, zero, zero, zero, zero, zero};
+    float h1[NT][4];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      f4 acc = mfma_bf16(a1[nt], x, seed(c1[nt]));
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h1[nt][r] = relu(finish(acc[r], s1, c1[nt][r]));
+    }
+    bf16x8 b1[NK];
+#pragma unroll
+    for (int s = 0; s < NK; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) b1[s][e] = (__bf16)h1[2 * s + (e >> 2)][e & 3];
+    float h2[NT][4];
+    const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+#pragma unroll
+    for (int n2 = 0; n2 < NT; ++n2) {
+      f4 acc = seed(c2[n2]);
+#pragma unroll
+      for (int s = 0; s < NK; ++s) {
+        bf16x8 w;
+        if constexpr (W2_LDS) {
+          w = ((const bf16x8*)lds)[(n2 * NK + s) * 64 + lane];
+        } else {
+          w = a2[n2][s];
+        }
+        acc = mfma_bf16(w, b1[s], acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h2[n2][r] = relu(finish(acc[r], s2, c2[n2][r]));
+    }
+    bf16x8 b2[NK];
+#pragma unroll
+    for (int s = 0; s < NK; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) b2[s][e] = (__bf16)h2[2 * s + (e >> 2)][e & 3];
+    f4 acc = seed(c3);
+#pragma unroll
+    for (int s = 0; s < NK; ++s) acc = mfma_bf16(a3[s], b2[s], acc);
+    f4 o;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[r] = finish(acc[r], s3, c3[r]);
     return o;
   }
 };

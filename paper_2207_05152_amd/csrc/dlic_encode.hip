@@ -19,7 +19,7 @@ namespace dlic {
 // Stride (floats) of one pixel's outputs in the per-wave LDS staging area.
 constexpr int O_STRIDE = 16;
 
-template <int H1, int H2>
+template <class Net>
 __global__ __launch_bounds__(256) void density_kernel(const Consts* __restrict__ K, DevModel m,
                                                       const uint8_t* __restrict__ img, int H,
                                                       int W, uint32_t* __restrict__ cf,
@@ -29,15 +29,17 @@ __global__ __launch_bounds__(256) void density_kernel(const Consts* __restrict__
   __shared__ float s_beta[257];
   __shared__ float s_scale[256];
   __shared__ __attribute__((aligned(16))) float s_o[4][64 * O_STRIDE];
+  __shared__ __attribute__((aligned(16))) char s_w2[Net::LDS_BYTES > 0 ? Net::LDS_BYTES : 16];
 
   const int tid = threadIdx.x;
   for (int i = tid; i < LUT_N; i += 256) s_sd[i] = K->sd[i];
   for (int i = tid; i < 257; i += 256) s_beta[i] = K->beta[i];
   s_scale[tid] = K->scale[tid];
+  Net::stage(m, s_w2, tid, 256);
   __syncthreads();
 
   const int lane = tid & 63, wave = tid >> 6, q = lane >> 4;
-  NetF32<H1, H2> net;
+  Net net;
   net.load(m, lane);
 
   const long long n = (long long)H * W;
@@ -57,7 +59,7 @@ __global__ __launch_bounds__(256) void density_kernel(const Consts* __restrict__
           if (yy >= 0 && xx >= 0 && xx < W) fk[kk] = s_scale[img[(long long)yy * W + xx]];
         }
       }
-      const f4 o = net.run(fk[0], fk[1], fk[2]);
+      const f4 o = net.run(fk[0], fk[1], fk[2], s_w2);
       *reinterpret_cast<f4*>(&s_o[wave][(tile * 16 + (lane & 15)) * O_STRIDE + 4 * q]) = o;
     }
     __syncthreads();
@@ -229,20 +231,39 @@ __global__ __launch_bounds__(256) void pack_kernel(const uint16_t* __restrict__ 
 
 // ---- host-side launchers -------------------------------------------------
 
-template <int H1, int H2>
+template <class Net>
 static void launch_density_t(const Consts* K, const DevModel& m, const uint8_t* img, int H,
                              int W, uint32_t* cf, float* out15, uint32_t* tables, int grid,
                              hipStream_t s) {
-  hipLaunchKernelGGL((density_kernel<H1, H2>), dim3(grid), dim3(256), 0, s, K, m, img, H, W, cf,
+  hipLaunchKernelGGL((density_kernel<Net>), dim3(grid), dim3(256), 0, s, K, m, img, H, W, cf,
                      out15, tables);
 }
 
-bool launch_density(int width, const Consts* K, const DevModel& m, const uint8_t* img, int H,
-                    int W, uint32_t* cf, float* out15, uint32_t* tables, int grid,
+template <int H>
+static bool launch_density_h(int wtype, const Consts* K, const DevModel& m, const uint8_t* img,
+                             int Hh, int W, uint32_t* cf, float* out15, uint32_t* tables,
+                             int grid, hipStream_t s) {
+  switch (wtype) {
+    case WT_F32:
+      launch_density_t<NetF32<H>>(K, m, img, Hh, W, cf, out15, tables, grid, s);
+      return true;
+    case WT_BF16:
+      launch_density_t<NetBF16<H, WT_BF16, false>>(K, m, img, Hh, W, cf, out15, tables, grid, s);
+      return true;
+    case WT_FP8:
+      launch_density_t<NetBF16<H, WT_FP8, false>>(K, m, img, Hh, W, cf, out15, tables, grid, s);
+      return true;
+    default: return false;
+  }
+}
+
+bool launch_density(int wtype, int width, const Consts* K, const DevModel& m, const uint8_t* img,
+                    int H, int W, uint32_t* cf, float* out15, uint32_t* tables, int grid,
                     hipStream_t s) {
   switch (width) {
-    case 32: launch_density_t<32, 32>(K, m, img, H, W, cf, out15, tables, grid, s); return true;
-    case 64: launch_density_t<64, 64>(K, m, img, H, W, cf, out15, tables, grid, s); return true;
+    case 32: return launch_density_h<32>(wtype, K, m, img, H, W, cf, out15, tables, grid, s);
+    case 64: return launch_density_h<64>(wtype, K, m, img, H, W, cf, out15, tables, grid, s);
+    case 128: return launch_density_h<128>(wtype, K, m, img, H, W, cf, out15, tables, grid, s);
     default: return false;
   }
 }

@@ -35,14 +35,16 @@ struct DecArgs {
   unsigned long long* prof;  // optional per-group cycle counters (8 per group)
 };
 
-bool launch_density(int width, const Consts* K, const DevModel& m, const uint8_t* img, int H,
-                    int W, uint32_t* cf, float* out15, uint32_t* tables, int grid, hipStream_t s);
+// wtype: WeightType of the model; width: h1 == h2.  False for an unsupported pair.
+bool launch_density(int wtype, int width, const Consts* K, const DevModel& m, const uint8_t* img,
+                    int H, int W, uint32_t* cf, float* out15, uint32_t* tables, int grid,
+                    hipStream_t s);
 void launch_rans_encode(const uint32_t* cf, int H, int W, int G, int L, uint16_t* words,
                         uint32_t* counts, hipStream_t s);
 void launch_pack(const uint16_t* words, const uint32_t* counts, int H, int W, int G, int L,
                  const HeaderFields& hf, uint8_t* out, uint64_t* out_len, int chunks,
                  hipStream_t s);
-bool launch_decode(int width, bool tables_mode, const Consts* K, const DevModel& m,
+bool launch_decode(int wtype, int width, bool tables_mode, const Consts* K, const DevModel& m,
                    const DecArgs& a, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t s);
 

@@ -69,3 +69,46 @@ def test_peek_header_reads_oracle_header():
         dl.dlic_peek_header(b"XLIC" + raw[4:])
     with pytest.raises(dl.DlicError):
         dl.dlic_peek_header(raw[:20])
+
+
+def _quant_inputs():
+    import synth
+    from oracle import lowp
+    w = synth.xavier_mlp((12, 128, 128, 15), 3)
+    rng = np.random.default_rng(11)
+    codes = np.arange(0x7F)
+    vals = lowp.e4m3_value(codes)
+    mids = (vals[1:] + vals[:-1]) / 2
+    # a matrix whose scale is exactly 1: e4m3 ties, subnormals, zeros, saturation
+    edge = np.concatenate([[448.0], vals, -vals, mids, -mids, [0.0, -0.0, 2 ** -10, 3 * 2 ** -10]])
+    bf_ties = (np.arange(300, dtype=np.uint32) << 16 | 0x8000).view(np.float32)
+    return [w["W1"], w["W2"], w["W3"], rng.standard_normal((7, 9)).astype(np.float32) * 1e-3,
+            edge.astype(np.float32), bf_ties]
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_quantize_weights_matches_oracle(dtype):
+    from oracle import lowp
+    code = dl.DTYPES[dtype]
+    for w in _quant_inputs():
+        got, s = dl.dlic_quantize_weights(code, w)
+        want, ws = lowp.quantize_matrix(w, dtype)
+        assert got.dtype == want.dtype
+        np.testing.assert_array_equal(got, want)
+        assert np.float32(s).view(np.uint32) == np.float32(ws).view(np.uint32)
+
+
+def test_quantize_weights_rejects_bad_input():
+    lib = dl.lib()
+    w = np.ones(4, np.float32)
+    out = np.empty(4, np.uint16)
+    sc = np.zeros(1, np.float32)
+    assert lib.dlic_quantize_weights(dl.DLIC_FP32, w.ctypes.data, 4, out.ctypes.data,
+                                     sc.ctypes.data) == dl.DLIC_ERR_ARG
+    assert lib.dlic_quantize_weights(dl.DLIC_BF16, w.ctypes.data, 0, out.ctypes.data,
+                                     sc.ctypes.data) == dl.DLIC_ERR_ARG
+    w[2] = np.inf
+    assert lib.dlic_quantize_weights(dl.DLIC_BF16, w.ctypes.data, 4, out.ctypes.data,
+                                     sc.ctypes.data) == dl.DLIC_ERR_ARG
+    assert lib.dlic_quantize_weights(dl.DLIC_FP8_E4M3, np.ones(4, np.float32).ctypes.data, 4,
+                                     out.ctypes.data, None) == dl.DLIC_ERR_ARG

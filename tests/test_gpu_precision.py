@@ -1,0 +1,145 @@
+"""Reduced-precision inference (BF16 operands / FP8 e4m3 weights, FP32
+accumulation) and the 128-wide FP32 net: GPU network outputs against the
+oracle's statement of each form, lossless round trips, and the rate drift of
+BF16 against FP32 on the full-size workload."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import lowp
+import paper_2207_05152_amd as dl
+import synth
+from gpu_util import dev, say, to_dev  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+# GPU vs the oracle's reduced-precision form.  The GPU accumulates in FP32 in
+# an order the oracle cannot follow, so a hidden activation that sits within
+# that rounding error of a BF16 tie can round the other way: one BF16 step
+# (2^-8 relative) in one activation.  Every output must stay within one such
+# step (LOWP_ALL); nearly every pixel must agree to FP32 accumulation error
+# (LOWP_TIGHT on at least LOWP_FRAC of the pixels).
+LOWP_ALL = 2.0 ** -8
+LOWP_TIGHT = 1e-5
+LOWP_FRAC = 0.995
+TOL32 = 1e-4   # FP32 net vs FP64: |gpu - ref| <= TOL32 * max(1, |ref|)
+BPP_GATE = 0.01
+
+
+def _rel_err(gpu, ref):
+    return np.abs(gpu.astype(np.float64) - ref) / np.maximum(1.0, np.abs(ref))
+
+
+def _check_lowp(gpu, ref):
+    err = _rel_err(gpu, ref)
+    assert err.max() <= LOWP_ALL, err.max()
+    frac = float((err.max(axis=1) <= LOWP_TIGHT).mean())
+    assert frac >= LOWP_FRAC, frac
+    return err
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+@pytest.mark.parametrize("width", [32, 64, 128])
+def test_lowp_outputs_match_oracle(dev, dtype, width):
+    img = synth.synth_image(45, 83, 17 + width)
+    wts = synth.xavier_mlp((12, width, width, 15), 3)
+    wts["b1"] = np.linspace(-0.1, 0.1, width).astype(np.float32)
+    wts["b3"] = np.linspace(-0.5, 0.5, 15).astype(np.float32)
+    m = dl.Model(wts, dev, dtype=dtype)
+    qm = lowp.quantize_weights(wts, dtype)
+    for k in ("W1", "W2", "W3"):
+        np.testing.assert_array_equal(m.np[k], qm[k])
+    assert m.fingerprint == lowp.stored_fingerprint(qm)
+    say("lowp density", dtype, width)
+    out15, _, _ = dl.density(to_dev(img, dev), m)
+    torch.cuda.synchronize()
+    ref = lowp.mlp_forward_lowp(oracle.causal_features(img).reshape(-1, 12), qm)
+    _check_lowp(out15.cpu().numpy(), ref)
+
+
+def test_fp32_width128_matches_fp64(dev):
+    img = synth.synth_image(45, 83, 5)
+    wts = synth.xavier_mlp((12, 128, 128, 15), 3)
+    wts["b2"] = np.linspace(-0.2, 0.2, 128).astype(np.float32)
+    m = dl.Model(wts, dev)
+    say("fp32 density width 128")
+    out15, _, _ = dl.density(to_dev(img, dev), m)
+    torch.cuda.synchronize()
+    feats = oracle.causal_features(img).reshape(-1, 12)
+    ref = oracle.mlp_forward(feats, *(wts[k] for k in ("W1", "b1", "W2", "b2", "W3", "b3")))
+    err = _rel_err(out15.cpu().numpy(), ref)
+    assert err.max() <= TOL32, err.max()
+
+
+@pytest.mark.parametrize("dtype,width,h,w", [
+    ("bf16", 64, 67, 90), ("bf16", 128, 41, 77), ("fp8", 64, 50, 33), ("fp8", 128, 20, 129),
+    ("fp32", 128, 61, 47), ("bf16", 32, 5, 300)])
+def test_lowp_roundtrip(dev, dtype, width, h, w):
+    img = synth.synth_image(h, w, 3 * h + w)
+    m = dl.Model(synth.xavier_mlp((12, width, width, 15), 3), dev, dtype=dtype)
+    coder = dl.default_coder(h, rows_per_group=24)
+    say("lowp roundtrip", dtype, width, h, w, coder.groups)
+    bits = dl.encode(to_dev(img, dev), m, coder)
+    hd = dl.dlic_peek_header(bits[:dl.HEADER_BYTES].cpu().numpy().tobytes())
+    assert hd["dtype"] == dl.DTYPES[dtype] and hd["h1"] == width
+    assert hd["fingerprint"] == m.fingerprint
+    out, status = dl.decode(bits, m)
+    torch.cuda.synchronize()
+    assert status == dl.DLIC_OK
+    assert np.array_equal(out.cpu().numpy(), img)
+
+
+def test_decode_refuses_other_precision(dev):
+    img = synth.synth_image(30, 40, 2)
+    wts = synth.xavier_mlp((12, 64, 64, 15), 3)
+    m32 = dl.Model(wts, dev)
+    mbf = dl.Model(wts, dev, dtype="bf16")
+    say("precision mismatch")
+    bits = dl.encode(to_dev(img, dev), mbf)
+    _, status = dl.decode(bits, m32, check=False)
+    torch.cuda.synchronize()
+    assert status == dl.DLIC_ERR_MODEL_MISMATCH
+
+
+def _bpp(bits, img):
+    return 8.0 * bits.numel() / img.size
+
+
+@pytest.mark.parametrize("width", [64, 128])
+def test_bf16_rate_within_gate_full_size(dev, width):
+    img = synth.synth_image(1536, 2048, 1)
+    wts = synth.xavier_mlp((12, width, width, 15), 3)
+    d_img = to_dev(img, dev)
+    bpp = {}
+    for dtype in ("fp32", "bf16", "fp8"):
+        say("full-size rate", dtype, width)
+        bits = dl.encode(d_img, dl.Model(wts, dev, dtype=dtype))
+        torch.cuda.synchronize()
+        bpp[dtype] = _bpp(bits, img)
+    say("bpp", width, bpp)
+    assert abs(bpp["bf16"] - bpp["fp32"]) <= BPP_GATE, bpp
+    # FP8 has no gate; a gross error in its scales would still show here
+    assert abs(bpp["fp8"] - bpp["fp32"]) <= 0.25, bpp
+
+
+def test_bf16_full_size_sampled_and_roundtrip(dev):
+    img = synth.synth_image(1536, 2048, 1)
+    wts = synth.xavier_mlp((12, 128, 128, 15), 3)
+    m = dl.Model(wts, dev, dtype="bf16")
+    d_img = to_dev(img, dev)
+    say("bf16 full size density")
+    out15, _, _ = dl.density(d_img, m)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    idx = np.concatenate([rng.integers(0, img.size, 4000), [0, 1, 2047, 2048, img.size - 1]])
+    feats = np.stack([oracle.pixel_features(img, int(p) // 2048, int(p) % 2048) for p in idx])
+    ref = lowp.mlp_forward_lowp(feats, lowp.quantize_weights(wts, "bf16"))
+    _check_lowp(out15.cpu().numpy()[idx], ref)
+    del out15
+    say("bf16 full size roundtrip")
+    bits = dl.encode(d_img, m)
+    out, status = dl.decode(bits, m)
+    torch.cuda.synchronize()
+    assert status == dl.DLIC_OK
+    assert torch.equal(out, d_img)
