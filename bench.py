@@ -72,6 +72,53 @@ def cpu_baseline(img, weights, groups, lanes, target_s=15.0):
                       f"{dt:.1f} s"}
 
 
+def precision_sweep(dl, torch, img, H, W, coder, hidden=128, reps=3):
+    """Encode + decode of the same image with the 12-128-128-15 net stored as
+    FP32, BF16 and FP8 e4m3: kernel-timed MPix/s, bpp and the bpp change
+    against FP32 (outside the timed region of the headline step)."""
+    import synth
+    weights = synth.xavier_mlp((12, hidden, hidden, 15), 3)
+    n_px = H * W
+    cap = dl.dlic_encode_bound(H, W, coder)
+    out = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    olen = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ews = torch.empty(dl.dlic_encode_workspace(H, W, coder), dtype=torch.uint8, device="cuda")
+    dws = torch.empty(dl.dlic_decode_workspace(H, W, coder), dtype=torch.uint8, device="cuda")
+    dec = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = {}
+    dl.dlic_set_timing(True)
+    for dtype in ("fp32", "bf16", "fp8"):
+        model = dl.Model(weights, "cuda:0", dtype=dtype)
+        kt = {}
+        for r in range(reps + 1):
+            dl.dlic_encode(model.c, coder, img, H, W, out, cap, olen, ews, ews.numel(), stream)
+            ke = dict(dl.dlic_kernel_times())
+            n = int(olen.item())
+            dl.dlic_decode(model.c, coder, out, n, dec, H, W, st, dws, dws.numel(), stream)
+            kd = dict(dl.dlic_kernel_times())
+            if r:
+                for k, v in list(ke.items()) + list(kd.items()):
+                    kt.setdefault(k, []).append(v)
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0 and torch.equal(dec, img), f"{dtype} round trip failed"
+        avg = {k: float(np.mean(v)) for k, v in kt.items()}
+        enc = avg["density_kernel"] + avg["rans_encode_kernel"] + avg["pack_kernel"]
+        dcd = avg["wavefront_decode_kernel"] + avg.get("fill_u32_kernel", 0.0)
+        res[dtype] = {"encode_mpix_s": n_px / enc / 1e3, "decode_mpix_s": n_px / dcd / 1e3,
+                      "density_ms": avg["density_kernel"], "decode_ms": dcd,
+                      "bpp_total": 8.0 * n / n_px}
+    dl.dlic_set_timing(False)
+    for dtype in ("bf16", "fp8"):
+        res[dtype]["bpp_delta_vs_fp32"] = res[dtype]["bpp_total"] - res["fp32"]["bpp_total"]
+    res["bf16_gate_0.01bpp"] = abs(res["bf16"]["bpp_delta_vs_fp32"]) <= 0.01
+    res["workload"] = (f"{W}x{H} image (seed 1), MLP 12-{hidden}-{hidden}-15 (Glorot seed 3) "
+                       f"stored as FP32 / BF16 / FP8 e4m3 with per-layer scales, "
+                       f"{coder.groups}x{coder.lanes_per_group} lanes")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +130,8 @@ def main():
     ap.add_argument("--groups", type=int, default=8)
     ap.add_argument("--lanes", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the precision sweep after the headline step")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the DLIC hot path here runs on a single MI355X "
@@ -167,7 +216,7 @@ def main():
     sched_ms = crit_px * mlp_flops_per_px(Hd, Hd) / (MI355X_FP32_MFMA / MI355X_CUS) * 1e3
 
     res = {
-        "metric": "encode/decode MPix/s on 1 MI355X + bpp",
+        "metric": "encode/decode MPix/s on 1 MI355X + bpp; BF16 vs FP32 at \u22640.01 bpp \u0394",
         "value": n_px / (ms_step * 1e-3) / 1e6,
         "unit": "MPix/s",
         "n_gpus": 1,
@@ -209,6 +258,8 @@ def main():
         "decode_profile": decode_profile,
         "host": {"cpu": platform.processor() or platform.machine(), "os_cpus": os.cpu_count()},
     }
+    if not args.no_extras:
+        res["precision"] = precision_sweep(dl, torch, img, H, W, coder)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(img_np, weights, args.groups, args.lanes)
     print(json.dumps(res))
