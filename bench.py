@@ -119,6 +119,73 @@ def precision_sweep(dl, torch, img, H, W, coder, hidden=128, reps=3):
     return res
 
 
+def _synth_job(args):
+    import synth
+    h, w, seed = args
+    return synth.synth_image(h, w, seed)
+
+
+def batch_sweep(dl, torch, reps=3, tune_budget_s=60.0):
+    """The 64-image batch (seeds 100..163, sizes drawn from 256x256 .. 2048x1536)
+    with the 12-64-64-15 net in BF16: autotuned knobs, one captured graph per
+    direction, aggregate MPix/s, per-image latency percentiles, bpp."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    import synth
+    from paper_2207_05152_amd import autotune
+    seeds = list(range(100, 164))
+    sizes = synth.batch_sizes(seeds)
+    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        images = list(ex.map(_synth_job, [(h, w, sd) for (h, w), sd in zip(sizes, seeds)]))
+    model = dl.Model(synth.xavier_mlp((12, 64, 64, 15), 3), "cuda:0", dtype="bf16")
+    n_px = sum(h * w for h, w in sizes)
+    tuned = autotune.tune(model, sizes, images, budget_s=tune_budget_s)
+
+    def run(knobs):
+        b = dl.Batch(model, sizes, coders=autotune.coders_for(sizes, knobs["rows_per_group"],
+                                                                knobs["lanes"]),
+                     density_grid=knobs["density_grid"])
+        b.load(images)
+        b.capture()
+        s = torch.cuda.current_stream()
+        b.replay(False, s)
+        b.replay(True, s)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        enc, dec, lat_e, lat_d = [], [], [], []
+        for _ in range(reps):
+            ev[0].record(s)
+            b.replay(False, s)
+            ev[1].record(s)
+            b.replay(True, s)
+            ev[2].record(s)
+            torch.cuda.synchronize()
+            enc.append(ev[0].elapsed_time(ev[1]))
+            dec.append(ev[1].elapsed_time(ev[2]))
+            lat_e.append(b.latencies_s(False))
+            lat_d.append(b.latencies_s(True))
+        assert bool((b.status == 0).all().item()), "batch decode status"
+        assert torch.equal(b.decoded, b.pixels), "batch round trip is not lossless"
+        nbytes = int(b.lens.sum().item())
+        le, ld = np.concatenate(lat_e) * 1e3, np.concatenate(lat_d) * 1e3
+        out = {"encode_ms": float(np.mean(enc)), "decode_ms": float(np.mean(dec)),
+               "encode_mpix_s": n_px / np.mean(enc) / 1e3, "decode_mpix_s": n_px / np.mean(dec) / 1e3,
+               "encode_latency_ms_p50_p99": [float(np.percentile(le, 50)), float(np.percentile(le, 99))],
+               "decode_latency_ms_p50_p99": [float(np.percentile(ld, 50)), float(np.percentile(ld, 99))],
+               "bpp_total": 8.0 * nbytes / n_px, "groups": int(sum(c[0] for c in b.coders)),
+               "knobs": knobs}
+        b.close()
+        return out
+
+    res = {"workload": f"64 synthetic images (seeds 100-163, sizes from 256x256 to 2048x1536, "
+                       f"{n_px / 1e6:.1f} Mpx), MLP 12-64-64-15 BF16 (Glorot seed 3); one captured "
+                       f"graph per direction",
+           "tuned": run(tuned["knobs"]), "default": run(dict(autotune.DEFAULT)),
+           "autotune": {"key": tuned["key"], "cached": tuned["cached"],
+                        "trials": len(tuned["trials"])}}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,8 +197,11 @@ def main():
     ap.add_argument("--groups", type=int, default=8)
     ap.add_argument("--lanes", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="before the timed steps, run one plain elementwise copy of MIB MiB "
+                         "(FP32 negation) so that counter runs can scale FETCH_SIZE/WRITE_SIZE")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the precision sweep after the headline step")
+                    help="skip the precision and batch sweeps after the headline step")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the DLIC hot path here runs on a single MI355X "
@@ -175,6 +245,14 @@ def main():
             for name, ms in dl.dlic_kernel_times():
                 kt.setdefault(name, []).append(ms)
         return n
+
+    if args.calibrate_copy > 0:
+        n_el = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n_el, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     dl.dlic_set_timing(True)
     for _ in range(args.warmup):
@@ -260,6 +338,7 @@ def main():
     }
     if not args.no_extras:
         res["precision"] = precision_sweep(dl, torch, img, H, W, coder)
+        res["batch"] = batch_sweep(dl, torch)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(img_np, weights, args.groups, args.lanes)
     print(json.dumps(res))

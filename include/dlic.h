@@ -208,6 +208,73 @@ dlic_status dlic_rans_decode_tables(const dlic_coder *coder, int32_t h, int32_t 
                                     size_t n_bytes, uint8_t *d_sym, int32_t *d_status,
                                     void *d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* ---- batches of images --------------------------------------------------- */
+
+/* Many images of any sizes coded with one model in one launch per direction
+ * (the wavefront decode of Section II-B, Preprocessor, applied to every
+ * group of every image at once).  A plan fixes the images' sizes and coder
+ * layouts; work items are (image, group) pairs ordered longest wavefront
+ * first, an image's groups in order.  Decode workgroups take items by
+ * ticket, so every group an item waits for was taken earlier by a resident
+ * or finished workgroup, and all waits end.  Encode = density over all
+ * pixels, rANS per item, pack per item: three kernels, one graph. */
+typedef struct dlic_batch dlic_batch;
+
+/* Plan for n_img images; h_hw: [n_img][2] (h, w).  h_coders: one layout per
+ * image, or NULL for G = ceil(h / 192) groups of 32 lanes.  density_grid:
+ * workgroups of the density kernel, 0 for the default.  The plan owns a
+ * small device table on the current device until dlic_batch_destroy; its
+ * model's weights must stay valid while it is used.  DLIC_ERR_UNSUPPORTED
+ * for a layout dlic_encode would refuse. */
+dlic_status dlic_batch_create(const dlic_model *model, int32_t n_img, const int32_t *h_hw,
+                              const dlic_coder *h_coders, int32_t density_grid,
+                              dlic_batch **out);
+void dlic_batch_destroy(dlic_batch *b);
+
+/* Bytes of the concatenated pixel buffer (images back to back, raster
+ * order), of the stream regions (one per image, dlic_encode_bound bytes,
+ * 256-aligned), of the workspace both directions need, and the number of
+ * work items.  Any out pointer may be NULL. */
+dlic_status dlic_batch_sizes(const dlic_batch *b, size_t *pixels, size_t *out_bytes,
+                             size_t *ws_bytes, int32_t *n_items);
+
+/* Per image: first pixel, first byte of its stream region, and (G, L) into
+ * h_coders[2i], h_coders[2i+1].  Any out pointer may be NULL. */
+dlic_status dlic_batch_layout(const dlic_batch *b, uint64_t *h_px_off, uint64_t *h_out_off,
+                              int32_t *h_coders);
+
+/* Encode every image: image i's stream (the same bytes dlic_encode writes
+ * for it) goes to its region of d_out, its length to d_out_len[i].
+ * d_t_done, if not NULL, has n_img + 1 entries: the device realtime counter
+ * when image i's stream was complete, and at [n_img] the start of the call
+ * (dlic_wallclock_hz gives the counter's rate). */
+dlic_status dlic_encode_batch(dlic_batch *b, const uint8_t *d_pixels, uint8_t *d_out,
+                              uint64_t *d_out_len, uint64_t *d_t_done, void *d_ws,
+                              size_t ws_bytes, hipStream_t stream);
+
+/* Decode every image from its region of d_bits (d_len[i] bytes) into its
+ * place in d_pixels; d_status[i] as dlic_decode's status; d_t_done as for
+ * dlic_encode_batch. */
+dlic_status dlic_decode_batch(dlic_batch *b, const uint8_t *d_bits, const uint64_t *d_len,
+                              uint8_t *d_pixels, int32_t *d_status, uint64_t *d_t_done,
+                              void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Capture one direction's kernels (decode = 0: dlic_encode_batch with
+ * d_in = pixels, d_out = streams, d_len = lengths; decode = 1:
+ * dlic_decode_batch with d_in = streams, d_out = pixels) into a hipGraph
+ * kept by the plan, replacing an earlier one.  Counters are cleared by
+ * kernels, not memset nodes, so replays start clean.  Buffers are baked in:
+ * they must stay valid while the graph is replayed. */
+dlic_status dlic_batch_capture(dlic_batch *b, int32_t decode, const uint8_t *d_in,
+                               uint8_t *d_out, uint64_t *d_len, int32_t *d_status,
+                               uint64_t *d_t_done, void *d_ws, size_t ws_bytes);
+
+/* Launch the captured graph of one direction on a stream. */
+dlic_status dlic_batch_replay(dlic_batch *b, int32_t decode, hipStream_t stream);
+
+/* Rate (Hz) of the device realtime counter behind the d_t_done stamps. */
+double dlic_wallclock_hz(void);
+
 /* ---- retraining ------------------------------------------------------------ */
 
 /* Scratch bytes of dlic_nll_fwd_bwd for n samples (d_ws). */

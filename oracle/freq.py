@@ -27,7 +27,8 @@ Two evaluations of C are provided:
         u = clamp(beta_v * A_k + B_k, 0, 4096)      (the table coordinate of
                                                      (beta_v - mu_k) inv_s_k)
         j = floor(u);  w = u - j;  sigma_hat = S_j + w * D_j
-        C = pi_0 sigma_hat_0;  C = C + pi_k sigma_hat_k for k = 1..4
+        C = (pi_0 sh_0 + pi_1 sh_1 + pi_2 sh_2) + (pi_3 sh_3 + pi_4 sh_4)
+            (each part summed left to right, sh_k = sigma_hat_k)
         q = min(M', floor(C * 65280))
     u is non-decreasing in beta (A_k > 0) and every rounding is monotone, so
     F is non-decreasing in v for any parameters and every table is valid.
@@ -128,12 +129,16 @@ def scale32() -> np.ndarray:
 
 def _cdf32(beta, pi32, mu32, is32):
     A, B = table_coords32(mu32, is32)
-    C = None
-    for k in range(pi32.shape[-1]):
-        u = beta * A[..., k:k + 1] + B[..., k:k + 1]
-        term = pi32[..., k:k + 1] * sigma_hat32(u)
-        C = term if C is None else C + term
-    return C
+
+    def part(ks):
+        s = None
+        for k in ks:
+            u = beta * A[..., k:k + 1] + B[..., k:k + 1]
+            term = pi32[..., k:k + 1] * sigma_hat32(u)
+            s = term if s is None else s + term
+        return s
+
+    return part((0, 1, 2)) + part((3, 4))
 
 
 def table_levels32(levels, pi32, mu32, is32) -> np.ndarray:

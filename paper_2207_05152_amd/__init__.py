@@ -34,6 +34,9 @@ EXPORTS = (
     "dlic_encode", "dlic_decode", "dlic_set_spin_limit", "dlic_density",
     "dlic_rans_encode_cf", "dlic_rans_decode_tables", "dlic_set_timing", "dlic_kernel_times",
     "dlic_set_decode_profile", "dlic_nll_workspace", "dlic_nll_fwd_bwd", "dlic_adam_step",
+    "dlic_batch_create", "dlic_batch_destroy", "dlic_batch_sizes", "dlic_batch_layout",
+    "dlic_encode_batch", "dlic_decode_batch", "dlic_batch_capture", "dlic_batch_replay",
+    "dlic_wallclock_hz",
 )
 
 
@@ -95,6 +98,15 @@ def lib():
                                      ctypes.c_int64, P, P, P, S, P]),
         "dlic_adam_step": (c_int, [ctypes.c_int64, P, P, P, P, c_int32, c_float, c_float, c_float,
                                    c_float, P]),
+        "dlic_batch_create": (c_int, [POINTER(dlic_model), c_int32, P, P, c_int32, POINTER(P)]),
+        "dlic_batch_destroy": (None, [P]),
+        "dlic_batch_sizes": (c_int, [P, POINTER(S), POINTER(S), POINTER(S), POINTER(c_int32)]),
+        "dlic_batch_layout": (c_int, [P, P, P, P]),
+        "dlic_encode_batch": (c_int, [P, P, P, P, P, P, S, P]),
+        "dlic_decode_batch": (c_int, [P, P, P, P, P, P, P, S, P]),
+        "dlic_batch_capture": (c_int, [P, c_int32, P, P, P, P, P, P, S]),
+        "dlic_batch_replay": (c_int, [P, c_int32, P]),
+        "dlic_wallclock_hz": (ctypes.c_double, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -454,3 +466,136 @@ def DLICNLL():
     if _DLICNLL is None:
         _DLICNLL = _autograd_fn()
     return _DLICNLL
+
+
+# ---- batches ----------------------------------------------------------------------
+
+def dlic_batch_create(model: dlic_model, sizes, coders=None, density_grid: int = 0) -> int:
+    hw = np.ascontiguousarray(np.asarray(sizes, dtype=np.int32).reshape(-1, 2))
+    n = hw.shape[0]
+    cd = None
+    if coders is not None:
+        cd = (dlic_coder * n)(*[dlic_coder(int(g), int(l)) for g, l in coders])
+    out = c_void_p()
+    _check(lib().dlic_batch_create(ctypes.byref(model), n, hw.ctypes.data, cd, density_grid,
+                                   ctypes.byref(out)), "dlic_batch_create")
+    return out.value
+
+
+def dlic_batch_destroy(b: int):
+    lib().dlic_batch_destroy(b)
+
+
+def dlic_batch_sizes(b: int) -> dict:
+    px, ob, ws, ni = c_size_t(), c_size_t(), c_size_t(), c_int32()
+    _check(lib().dlic_batch_sizes(b, ctypes.byref(px), ctypes.byref(ob), ctypes.byref(ws),
+                                  ctypes.byref(ni)), "dlic_batch_sizes")
+    return dict(pixels=px.value, out_bytes=ob.value, ws_bytes=ws.value, n_items=ni.value)
+
+
+def dlic_batch_layout(b: int, n_img: int):
+    px = np.zeros(n_img, np.uint64)
+    ob = np.zeros(n_img, np.uint64)
+    cd = np.zeros((n_img, 2), np.int32)
+    _check(lib().dlic_batch_layout(b, px.ctypes.data, ob.ctypes.data, cd.ctypes.data),
+           "dlic_batch_layout")
+    return px, ob, cd
+
+
+def dlic_encode_batch(b, d_pixels, d_out, d_out_len, d_t_done, d_ws, ws_bytes, stream=None):
+    _check(lib().dlic_encode_batch(b, _ptr(d_pixels), _ptr(d_out), _ptr(d_out_len), _ptr(d_t_done),
+                                   _ptr(d_ws), ws_bytes, _stream(stream)), "dlic_encode_batch")
+
+
+def dlic_decode_batch(b, d_bits, d_len, d_pixels, d_status, d_t_done, d_ws, ws_bytes, stream=None):
+    _check(lib().dlic_decode_batch(b, _ptr(d_bits), _ptr(d_len), _ptr(d_pixels), _ptr(d_status),
+                                   _ptr(d_t_done), _ptr(d_ws), ws_bytes, _stream(stream)),
+           "dlic_decode_batch")
+
+
+def dlic_batch_capture(b, decode, d_in, d_out, d_len, d_status, d_t_done, d_ws, ws_bytes):
+    _check(lib().dlic_batch_capture(b, int(decode), _ptr(d_in), _ptr(d_out), _ptr(d_len),
+                                    _ptr(d_status), _ptr(d_t_done), _ptr(d_ws), ws_bytes),
+           "dlic_batch_capture")
+
+
+def dlic_batch_replay(b, decode, stream=None):
+    _check(lib().dlic_batch_replay(b, int(decode), _stream(stream)), "dlic_batch_replay")
+
+
+def dlic_wallclock_hz() -> float:
+    return float(lib().dlic_wallclock_hz())
+
+
+class Batch:
+    """A batch plan with its torch-allocated buffers: images in, streams,
+    decoded images out, lengths, statuses, completion stamps, workspace."""
+
+    def __init__(self, model: Model, sizes, coders=None, density_grid: int = 0, device="cuda"):
+        import torch
+        self.model = model  # keeps the weights alive for the plan
+        self.sizes = [(int(h), int(w)) for h, w in sizes]
+        self.n = len(self.sizes)
+        self.plan = dlic_batch_create(model.c, self.sizes, coders, density_grid)
+        sz = dlic_batch_sizes(self.plan)
+        self.n_items = sz["n_items"]
+        self.px_off, self.out_off, self.coders = dlic_batch_layout(self.plan, self.n)
+        self.pixels = torch.zeros(max(sz["pixels"], 1), dtype=torch.uint8, device=device)
+        self.decoded = torch.zeros_like(self.pixels)
+        self.out = torch.zeros(max(sz["out_bytes"], 1), dtype=torch.uint8, device=device)
+        self.lens = torch.zeros(self.n, dtype=torch.int64, device=device)
+        self.status = torch.zeros(self.n, dtype=torch.int32, device=device)
+        self.t_enc = torch.zeros(self.n + 1, dtype=torch.int64, device=device)
+        self.t_dec = torch.zeros(self.n + 1, dtype=torch.int64, device=device)
+        self.ws_bytes = sz["ws_bytes"]
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
+
+    def load(self, images):
+        """Copy [h, w] uint8 images (numpy or torch) into the pixel buffer."""
+        import torch
+        for i, im in enumerate(images):
+            t = im if isinstance(im, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(im))
+            o = int(self.px_off[i])
+            self.pixels[o:o + t.numel()].copy_(t.reshape(-1))
+
+    def image(self, i, decoded=True):
+        h, w = self.sizes[i]
+        o = int(self.px_off[i])
+        return (self.decoded if decoded else self.pixels)[o:o + h * w].view(h, w)
+
+    def stream(self, i):
+        o = int(self.out_off[i])
+        return self.out[o:o + int(self.lens[i].item())]
+
+    def encode(self, stream=None):
+        dlic_encode_batch(self.plan, self.pixels, self.out, self.lens, self.t_enc, self.ws,
+                          self.ws_bytes, stream)
+
+    def decode(self, stream=None):
+        dlic_decode_batch(self.plan, self.out, self.lens, self.decoded, self.status, self.t_dec,
+                          self.ws, self.ws_bytes, stream)
+
+    def capture(self):
+        dlic_batch_capture(self.plan, 0, self.pixels, self.out, self.lens, None, self.t_enc,
+                           self.ws, self.ws_bytes)
+        dlic_batch_capture(self.plan, 1, self.out, self.decoded, self.lens, self.status, self.t_dec,
+                           self.ws, self.ws_bytes)
+
+    def replay(self, decode: bool, stream=None):
+        dlic_batch_replay(self.plan, decode, stream)
+
+    def latencies_s(self, decode: bool) -> np.ndarray:
+        """Per-image completion time since the start of the last call (seconds)."""
+        t = (self.t_dec if decode else self.t_enc).cpu().numpy().astype(np.float64)
+        return (t[:self.n] - t[self.n]) / dlic_wallclock_hz()
+
+    def close(self):
+        if self.plan:
+            dlic_batch_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

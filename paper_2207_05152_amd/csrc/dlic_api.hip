@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -223,6 +224,102 @@ dlic_status run_rans_and_pack(int h, int w, const dlic_coder* coder, const uint3
               pack_chunks((long long)h * w, G), s);
   timing_end(s);
   return launch_ok();
+}
+
+}  // namespace
+
+// A batch plan: per-image layout, the work items in longest-wavefront-first
+// order, their device copies, and up to one captured graph per direction.
+struct dlic_batch {
+  int device = 0;
+  dlic_model model{};
+  int n_img = 0, n_blk = 0, density_grid = 0, pack_parts = 1;
+  std::vector<BatchImage> images;
+  std::vector<BatchItem> items;
+  BatchImage* d_images = nullptr;
+  BatchItem* d_items = nullptr;
+  size_t pixels = 0, out_bytes = 0;
+  long long n_words = 0, n_rec = 0;
+  int n_counts = 0;
+  size_t off_words = 0, off_counts = 0, off_rec = 0, off_ctrl = 0, ws_bytes = 0;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+// Device-side arguments of a batch call on the plan's workspace.
+BatchArgs batch_args(const dlic_batch* b, void* d_ws) {
+  BatchArgs a;
+  memset(&a, 0, sizeof(a));
+  uint8_t* ws = (uint8_t*)d_ws;
+  a.images = b->d_images;
+  a.items = b->d_items;
+  a.n_img = b->n_img;
+  a.n_items = (int)b->items.size();
+  a.n_blk = b->n_blk;
+  a.cf = (uint32_t*)ws;
+  a.words = (uint16_t*)(ws + b->off_words);
+  a.counts = (uint32_t*)(ws + b->off_counts);
+  a.rec = (uint32_t*)(ws + b->off_rec);
+  a.ticket = (unsigned*)(ws + b->off_ctrl);
+  a.done = a.ticket + 1;
+  a.hf = HeaderFields{b->model.dtype, b->model.h1, b->model.h2, b->model.fingerprint};
+  a.spin_limit = g_spin_limit;
+  return a;
+}
+
+dlic_status batch_enqueue(dlic_batch* b, bool decode, const uint8_t* in, uint8_t* out,
+                          uint64_t* len, int32_t* status, uint64_t* t_done, void* ws,
+                          hipStream_t s) {
+  const Consts* K = nullptr;
+  dlic_status rc = current_consts(&K);
+  if (rc != DLIC_OK) return rc;
+  BatchArgs a = batch_args(b, ws);
+  a.len = len;
+  a.t_done = (unsigned long long*)t_done;
+  const DevModel dm = dev_model(&b->model);
+  const int wtype = weight_type(&b->model);
+  // control words: ticket, then one completion counter per image
+  launch_fill_u32(a.ticket, 0u, 1 + b->n_img, s);
+  if (t_done) launch_stamp(a.t_done + b->n_img, s);
+  if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
+  if (!decode) {
+    a.pix_in = in;
+    a.out = out;
+    timing_begin("batch_density_kernel", s);
+    if (!launch_batch_density(wtype, b->model.h1, K, dm, a, b->density_grid, s))
+      return DLIC_ERR_UNSUPPORTED;
+    timing_end(s);
+    timing_begin("batch_rans_encode_kernel", s);
+    launch_batch_rans_encode(a, s);
+    timing_end(s);
+    timing_begin("batch_pack_kernel", s);
+    launch_batch_pack(a, b->pack_parts, s);
+    timing_end(s);
+  } else {
+    a.bits = in;
+    a.pix_out = out;
+    a.status = status;
+    launch_fill_u32(a.rec, 0u, b->n_rec, s);
+    launch_fill_u32((uint32_t*)status, 0u, b->n_img, s);
+    if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
+    timing_begin("batch_decode_kernel", s);
+    bool split = true;
+    for (const BatchImage& im : b->images) split = split && im.L <= 32;
+    if (!launch_batch_decode(wtype, b->model.h1, K, dm, a, split, s)) return DLIC_ERR_UNSUPPORTED;
+    timing_end(s);
+  }
+  return launch_ok();
+}
+
+dlic_status batch_call_ok(const dlic_batch* b, const void* in, const void* out, const void* len,
+                          const void* ws, size_t ws_bytes) {
+  if (!b || !in || !out || !len || !ws) return DLIC_ERR_ARG;
+  if (ws_bytes < b->ws_bytes) return DLIC_ERR_CAPACITY;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DLIC_ERR_HIP;
+  if (dev != b->device) return DLIC_ERR_ARG;
+  return DLIC_OK;
 }
 
 }  // namespace
@@ -546,6 +643,206 @@ int dlic_kernel_times(float* h_ms, const char** h_names, int max_n) {
     if (h_names) h_names[i] = g_events[i].name;
   }
   return n;
+}
+
+// ---- batches -----------------------------------------------------------------
+
+dlic_status dlic_batch_create(const dlic_model* model, int32_t n_img, const int32_t* h_hw,
+                              const dlic_coder* h_coders, int32_t density_grid,
+                              dlic_batch** out) {
+  if (!out || !h_hw || n_img < 1 || n_img > (1 << 20) || density_grid < 0) return DLIC_ERR_ARG;
+  *out = nullptr;
+  dlic_status rc = model_ok(model);
+  if (rc != DLIC_OK) return rc;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DLIC_ERR_HIP;
+  if ((rc = ensure_device(dev, nullptr)) != DLIC_OK) return rc;
+  dlic_batch* b = new dlic_batch;
+  b->device = dev;
+  b->model = *model;
+  b->n_img = n_img;
+  b->images.resize(n_img);
+  long long px = 0, words = 0, rec = 0, outb = 0, blk = 0, maxper = 1;
+  int counts = 0;
+  for (int i = 0; i < n_img; ++i) {
+    const int h = h_hw[2 * i], w = h_hw[2 * i + 1];
+    dlic_coder c;
+    if (h_coders) {
+      c = h_coders[i];
+    } else {
+      c.groups = h > 192 ? (h + 191) / 192 : 1;
+      c.lanes_per_group = 32;
+    }
+    if (h <= 0 || w <= 0 || !coder_ok(h, &c) ||
+        ((long long)w + 3LL * DEC_RMAX) * DEC_RMAX >= (1LL << 31)) {
+      delete b;
+      return h <= 0 || w <= 0 ? DLIC_ERR_ARG : DLIC_ERR_UNSUPPORTED;
+    }
+    BatchImage& im = b->images[i];
+    const long long n = (long long)h * w;
+    im.H = h;
+    im.W = w;
+    im.G = c.groups;
+    im.L = c.lanes_per_group;
+    im.T = n_steps(h, w);
+    im.px_off = px;
+    im.words_off = words;
+    im.out_off = outb;
+    im.out_cap = (long long)dlic_encode_bound(h, w, &c);
+    im.rec_off = rec;
+    im.counts_off = counts;
+    im.blk_off = (int)blk;
+    px += n;
+    words += n + 2LL * im.L * im.G;
+    outb += (im.out_cap + 255) & ~255LL;
+    rec += (long long)im.G * im.T;
+    counts += im.G;
+    blk += (n + 255) / 256;
+    if (n / im.G > maxper) maxper = n / im.G;
+  }
+  if (blk >= (1LL << 31) || counts > (1 << 24)) {
+    delete b;
+    return DLIC_ERR_UNSUPPORTED;
+  }
+  // longest wavefront first; an image's groups in order (the decode waits
+  // only ever point to an earlier item)
+  std::vector<int> order(n_img);
+  for (int i = 0; i < n_img; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return b->images[x].T > b->images[y].T;
+  });
+  for (int i : order)
+    for (int g = 0; g < b->images[i].G; ++g) b->items.push_back(BatchItem{i, g});
+  b->n_blk = (int)blk;
+  b->density_grid = density_grid > 0 ? density_grid : (int)std::min<long long>(blk, 1024);
+  b->pack_parts = (int)std::min<long long>(64, maxper / 4096 + 1);
+  b->pixels = (size_t)px;
+  b->out_bytes = (size_t)outb;
+  b->n_words = words;
+  b->n_rec = rec;
+  b->n_counts = counts;
+  b->off_words = align256(4 * (size_t)px);
+  b->off_counts = align256(b->off_words + 2 * (size_t)words);
+  b->off_rec = align256(b->off_counts + 4 * (size_t)counts);
+  b->off_ctrl = align256(b->off_rec + 4 * (size_t)rec);
+  b->ws_bytes = align256(b->off_ctrl + 4 * (size_t)(1 + n_img));
+  if (hipMalloc((void**)&b->d_images, sizeof(BatchImage) * n_img) != hipSuccess ||
+      hipMalloc((void**)&b->d_items, sizeof(BatchItem) * b->items.size()) != hipSuccess ||
+      hipMemcpy(b->d_images, b->images.data(), sizeof(BatchImage) * n_img,
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_items, b->items.data(), sizeof(BatchItem) * b->items.size(),
+                hipMemcpyHostToDevice) != hipSuccess) {
+    dlic_batch_destroy(b);
+    return DLIC_ERR_HIP;
+  }
+  *out = b;
+  return DLIC_OK;
+}
+
+void dlic_batch_destroy(dlic_batch* b) {
+  if (!b) return;
+  for (int d = 0; d < 2; ++d)
+    if (b->exec[d]) (void)hipGraphExecDestroy(b->exec[d]);
+  if (b->d_images) (void)hipFree(b->d_images);
+  if (b->d_items) (void)hipFree(b->d_items);
+  delete b;
+}
+
+dlic_status dlic_batch_sizes(const dlic_batch* b, size_t* pixels, size_t* out_bytes,
+                             size_t* ws_bytes, int32_t* n_items) {
+  if (!b) return DLIC_ERR_ARG;
+  if (pixels) *pixels = b->pixels;
+  if (out_bytes) *out_bytes = b->out_bytes;
+  if (ws_bytes) *ws_bytes = b->ws_bytes;
+  if (n_items) *n_items = (int32_t)b->items.size();
+  return DLIC_OK;
+}
+
+dlic_status dlic_batch_layout(const dlic_batch* b, uint64_t* h_px_off, uint64_t* h_out_off,
+                              int32_t* h_coders) {
+  if (!b) return DLIC_ERR_ARG;
+  for (int i = 0; i < b->n_img; ++i) {
+    if (h_px_off) h_px_off[i] = (uint64_t)b->images[i].px_off;
+    if (h_out_off) h_out_off[i] = (uint64_t)b->images[i].out_off;
+    if (h_coders) {
+      h_coders[2 * i] = b->images[i].G;
+      h_coders[2 * i + 1] = b->images[i].L;
+    }
+  }
+  return DLIC_OK;
+}
+
+dlic_status dlic_encode_batch(dlic_batch* b, const uint8_t* d_pixels, uint8_t* d_out,
+                              uint64_t* d_out_len, uint64_t* d_t_done, void* d_ws,
+                              size_t ws_bytes, hipStream_t stream) {
+  timing_reset();
+  dlic_status rc = batch_call_ok(b, d_pixels, d_out, d_out_len, d_ws, ws_bytes);
+  if (rc != DLIC_OK) return rc;
+  return batch_enqueue(b, false, d_pixels, d_out, d_out_len, nullptr, d_t_done, d_ws, stream);
+}
+
+dlic_status dlic_decode_batch(dlic_batch* b, const uint8_t* d_bits, const uint64_t* d_len,
+                              uint8_t* d_pixels, int32_t* d_status, uint64_t* d_t_done,
+                              void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  timing_reset();
+  dlic_status rc = batch_call_ok(b, d_bits, d_pixels, d_len, d_ws, ws_bytes);
+  if (rc != DLIC_OK) return rc;
+  if (!d_status) return DLIC_ERR_ARG;
+  return batch_enqueue(b, true, d_bits, d_pixels, (uint64_t*)d_len, d_status, d_t_done, d_ws,
+                       stream);
+}
+
+dlic_status dlic_batch_capture(dlic_batch* b, int32_t decode, const uint8_t* d_in,
+                               uint8_t* d_out, uint64_t* d_len, int32_t* d_status,
+                               uint64_t* d_t_done, void* d_ws, size_t ws_bytes) {
+  dlic_status rc = batch_call_ok(b, d_in, d_out, d_len, d_ws, ws_bytes);
+  if (rc != DLIC_OK) return rc;
+  if (decode && !d_status) return DLIC_ERR_ARG;
+  const int d = decode ? 1 : 0;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return DLIC_ERR_HIP;
+  const bool timing = g_timing;
+  g_timing = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  rc = DLIC_ERR_HIP;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    const dlic_status er = batch_enqueue(b, decode != 0, d_in, d_out, d_len, d_status, d_t_done,
+                                         d_ws, cs);
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (er != DLIC_OK) {
+      rc = er;
+    } else if (ec == hipSuccess && graph &&
+               hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+      rc = DLIC_OK;
+    }
+  }
+  g_timing = timing;
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cs);
+  (void)hipGetLastError();
+  if (rc != DLIC_OK) return rc;
+  if (b->exec[d]) (void)hipGraphExecDestroy(b->exec[d]);
+  b->exec[d] = exec;
+  return DLIC_OK;
+}
+
+dlic_status dlic_batch_replay(dlic_batch* b, int32_t decode, hipStream_t stream) {
+  if (!b) return DLIC_ERR_ARG;
+  const int d = decode ? 1 : 0;
+  if (!b->exec[d]) return DLIC_ERR_ARG;
+  timing_reset();
+  timing_begin(decode ? "batch_decode_graph" : "batch_encode_graph", stream);
+  const hipError_t e = hipGraphLaunch(b->exec[d], stream);
+  timing_end(stream);
+  return e == hipSuccess ? DLIC_OK : DLIC_ERR_HIP;
+}
+
+double dlic_wallclock_hz(void) {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0.0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0.0;
+  return 1000.0 * (double)khz;
 }
 
 }  // extern "C"

@@ -101,9 +101,11 @@ __device__ __forceinline__ void stash_record(uint8_t* ring, uint32_t v, int s, i
   if (c2 >= 0 && c2 < W) ring[0 * 16 + (c2 & 15)] = (uint8_t)((v >> 8) & 0xFF);
 }
 
-template <class Net, bool TABLES>
-__global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
-    const Consts* __restrict__ K, DevModel m, DecArgs a) {
+// Decode of group g of one stream by the whole workgroup.  SPLIT (L <= 32):
+// the coder's two half-waves share each pixel's symbol search.
+template <class Net, bool TABLES, bool SPLIT>
+__device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const DevModel& m,
+                                             const DecArgs& a, const int g) {
   __shared__ float2 s_sd[LUT_N];
   __shared__ __attribute__((aligned(16))) float s_beta[260];
   __shared__ float s_scale[256];
@@ -119,7 +121,6 @@ __global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
   __shared__ __attribute__((aligned(16))) char s_w2[Net::LDS_BYTES > 0 ? Net::LDS_BYTES : 16];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int g = blockIdx.x;
   const int H = a.H, W = a.W, G = a.G, L = a.L;
   constexpr int NTH = DEC_WAVES * 64;
 
@@ -260,19 +261,57 @@ __global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
           const uint32_t* tab = a.tables + (long long)ti * 257;
           find_symbol(slot, [&](int lv) { return tab[lv]; }, v, c, f);
         } else {
-          const int px = act ? lane : 0;
+          // With L <= 32 the two half-waves share the work of each pixel:
+          // lanes i and 32 + i both serve pixel i, the low half evaluating
+          // mixture components 0..2 and the high half components 3..4 (plus
+          // a zero-weight pad), joined by one cross-half swap.  With L > 32
+          // every lane evaluates both parts.  Either way C is the format's
+          // (part 0..2) + (part 3..4), so every lane takes the same decisions.
+          constexpr bool split = SPLIT;
+          const int hlf = split ? (lane >> 5) : 0;
+          uint32_t sl = slot;
+          int px = act ? lane : 0;
+          if (split) {
+            const auto sx = __builtin_amdgcn_permlane32_swap(slot, slot, false, false);
+            const auto sa = __builtin_amdgcn_permlane32_swap((uint32_t)px, (uint32_t)px, false, false);
+            sl = sx[0];
+            px = (int)sa[0];
+          }
           const float* pp = &s_par[slot_i][px * PAR_STRIDE];
-          Mix mix;
+          // component slots of this lane: k0 .. k0+2 (k0 = 0 or 3); slot 2 of
+          // the high half is the pad
+          const int k0 = 3 * hlf;
+          float cp[3], cA[3], cB[3], dp[2], dA[2], dB[2];
 #pragma unroll
-          for (int k = 0; k < N_MIX; ++k) {
-            mix.pi[k] = pp[k];
-            mix.A[k] = pp[N_MIX + k];
-            mix.B[k] = pp[2 * N_MIX + k];
+          for (int i = 0; i < 3; ++i) {
+            const bool pad = hlf == 1 && i == 2;
+            cp[i] = pad ? 0.0f : pp[k0 + i];
+            cA[i] = pad ? 0.0f : pp[N_MIX + k0 + i];
+            cB[i] = pad ? 0.0f : pp[2 * N_MIX + k0 + i];
+          }
+          if (!split) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+              dp[i] = pp[3 + i];
+              dA[i] = pp[N_MIX + 3 + i];
+              dB[i] = pp[2 * N_MIX + 3 + i];
+            }
           }
           const uint16_t* bk = &s_bk[slot_i][px * 16];
           int nb = 0;
+          if (split) {
+            // low half counts boundaries 0..7, high half 8..14
 #pragma unroll
-          for (int i = 0; i < N_BUCKET; ++i) nb += ((uint32_t)bk[i] <= slot) ? 1 : 0;
+            for (int i = 0; i < 8; ++i) {
+              const int bi = 8 * hlf + i;
+              nb += (bi < N_BUCKET && (uint32_t)bk[bi] <= sl) ? 1 : 0;
+            }
+            const auto sn = __builtin_amdgcn_permlane32_swap((uint32_t)nb, (uint32_t)nb, false, false);
+            nb = (int)(sn[0] + sn[1]);
+          } else {
+#pragma unroll
+            for (int i = 0; i < N_BUCKET; ++i) nb += ((uint32_t)bk[i] <= sl) ? 1 : 0;
+          }
           const int base = 16 * nb;
           uint32_t Flo = nb > 0 ? (uint32_t)bk[nb - 1] : 0u;
           uint32_t Fhi = nb < N_BUCKET ? (uint32_t)bk[nb] : M_TOTAL;
@@ -296,8 +335,17 @@ __global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
             for (int c = 1; c < 16; ++c)
               if (c % step == 0) b = (off + step == c) ? be[c] : b;
             const int mid = base + off + step;
-            const uint32_t Fm = cdf_F_at(mid, b, mix, s_sd);
-            if (Fm <= slot) {
+            const float part = cdf_part(b, cp, cA, cB, 3, s_sd);
+            float C;
+            if (split) {
+              const auto pc = __builtin_amdgcn_permlane32_swap(__float_as_uint(part),
+                                                               __float_as_uint(part), false, false);
+              C = __uint_as_float(pc[0]) + __uint_as_float(pc[1]);
+            } else {
+              C = part + cdf_part(b, dp, dA, dB, 2, s_sd);
+            }
+            const uint32_t Fm = F_of_C(mid, C);
+            if (Fm <= sl) {
               off += step;
               Flo = Fm;
             } else {
@@ -489,6 +537,62 @@ __global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
   }
 }
 
+template <class Net, bool TABLES, bool SPLIT>
+__global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
+    const Consts* __restrict__ K, DevModel m, DecArgs a) {
+  decode_group<Net, TABLES, SPLIT>(K, m, a, blockIdx.x);
+}
+
+// Batched decode: every workgroup takes the next work item by ticket.  Items
+// list the groups of an image in order, so the group a workgroup waits for
+// was taken earlier by a workgroup that is resident or done: the waits end.
+// The last group of an image to finish stamps the image's completion time.
+template <class Net, bool SPLIT>
+__global__ __launch_bounds__(DEC_WAVES * 64) void batch_decode_kernel(
+    const Consts* __restrict__ K, DevModel m, BatchArgs b) {
+  __shared__ int s_item;
+  if (threadIdx.x == 0) s_item = (int)atomicAdd(b.ticket, 1u);
+  __syncthreads();
+  const int item = s_item;
+  if (item >= b.n_items) return;
+  const BatchItem it = b.items[item];
+  const BatchImage im = b.images[it.image];
+  DecArgs a;
+  a.bits = b.bits + im.out_off;
+  // a length beyond the region is corrupt; 0 makes the header check say so
+  a.n_bytes = b.len[it.image] <= (unsigned long long)im.out_cap ? b.len[it.image] : 0ull;
+  a.img = b.pix_out + im.px_off;
+  a.H = im.H;
+  a.W = im.W;
+  a.G = im.G;
+  a.L = im.L;
+  a.rec = b.rec + im.rec_off;
+  a.T = im.T;
+  a.status = b.status + it.image;
+  a.spin_limit = b.spin_limit;
+  a.check_model = 1;
+  a.hf = b.hf;
+  a.tables = nullptr;
+  a.n_tables = 0;
+  a.tidx = nullptr;
+  a.prof = nullptr;
+  decode_group<Net, false, SPLIT>(K, m, a, it.group);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(b.done + it.image, 1u) + 1u == (unsigned)im.G && b.t_done)
+      b.t_done[it.image] = __builtin_amdgcn_s_memrealtime();
+  }
+}
+
+__global__ void stamp_kernel(unsigned long long* t) {
+  if (threadIdx.x == 0) *t = __builtin_amdgcn_s_memrealtime();
+}
+
+void launch_stamp(unsigned long long* t, hipStream_t s) {
+  hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(64), 0, s, t);
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -502,10 +606,50 @@ void launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t s) {
   hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
 }
 
+template <class Net>
+static void launch_batch_decode_t(const Consts* K, const DevModel& m, const BatchArgs& b,
+                                  bool split, hipStream_t s) {
+  if (split)
+    hipLaunchKernelGGL((batch_decode_kernel<Net, true>), dim3(b.n_items), dim3(DEC_WAVES * 64), 0,
+                       s, K, m, b);
+  else
+    hipLaunchKernelGGL((batch_decode_kernel<Net, false>), dim3(b.n_items), dim3(DEC_WAVES * 64),
+                       0, s, K, m, b);
+}
+
+template <int H>
+static bool launch_batch_decode_h(int wtype, const Consts* K, const DevModel& m,
+                                  const BatchArgs& b, bool split, hipStream_t s) {
+  switch (wtype) {
+    case WT_F32: launch_batch_decode_t<NetF32<H>>(K, m, b, split, s); return true;
+    case WT_BF16:
+      launch_batch_decode_t<NetBF16<H, WT_BF16, (H > 64)>>(K, m, b, split, s);
+      return true;
+    case WT_FP8:
+      launch_batch_decode_t<NetBF16<H, WT_FP8, (H > 64)>>(K, m, b, split, s);
+      return true;
+    default: return false;
+  }
+}
+
+bool launch_batch_decode(int wtype, int width, const Consts* K, const DevModel& m,
+                         const BatchArgs& b, bool split, hipStream_t s) {
+  switch (width) {
+    case 32: return launch_batch_decode_h<32>(wtype, K, m, b, split, s);
+    case 64: return launch_batch_decode_h<64>(wtype, K, m, b, split, s);
+    case 128: return launch_batch_decode_h<128>(wtype, K, m, b, split, s);
+    default: return false;
+  }
+}
+
 template <class Net, bool TB>
 static void launch_decode_t(const Consts* K, const DevModel& m, const DecArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((wavefront_decode_kernel<Net, TB>), dim3(a.G), dim3(DEC_WAVES * 64), 0, s,
-                     K, m, a);
+  if (a.L <= 32)
+    hipLaunchKernelGGL((wavefront_decode_kernel<Net, TB, true>), dim3(a.G), dim3(DEC_WAVES * 64),
+                       0, s, K, m, a);
+  else
+    hipLaunchKernelGGL((wavefront_decode_kernel<Net, TB, false>), dim3(a.G), dim3(DEC_WAVES * 64),
+                       0, s, K, m, a);
 }
 
 // Layer-2 weights of the BF16 nets go to LDS at H = 128: six density waves

@@ -407,29 +407,42 @@ __device__ __forceinline__ float sigma_hat(float u, const float2* sd) {
   return e.x + w * e.y;
 }
 
-// Cumulative frequency F(v) = v + min(M', floor(C(beta_v) * M')), F(0) = 0,
-// F(256) = 2^16; C summed over components in index order.
-__device__ __forceinline__ uint32_t cdf_F(int v, const Mix& p, const float2* sd,
-                                          const float* beta) {
-  if (v <= 0) return 0u;
-  if (v >= 256) return M_TOTAL;
-  const float b = beta[v];
-  float C = p.pi[0] * sigma_hat(b * p.A[0] + p.B[0], sd);
+// Mixture CDF at bin edge b in the format's order: two partial sums, the
+// first three components and the last two, each left to right, then their
+// sum.  (The split lets a decoder evaluate the parts on two half-waves.)
+__device__ __forceinline__ float cdf_part(float b, const float* pi, const float* A, const float* B,
+                                          int n, const float2* sd) {
+  float s = pi[0] * sigma_hat(b * A[0] + B[0], sd);
 #pragma unroll
-  for (int k = 1; k < N_MIX; ++k) C = C + p.pi[k] * sigma_hat(b * p.A[k] + p.B[k], sd);
+  for (int k = 1; k < n; ++k) s = s + pi[k] * sigma_hat(b * A[k] + B[k], sd);
+  return s;
+}
+
+__device__ __forceinline__ float cdf_C(float b, const Mix& p, const float2* sd) {
+  const float lo = cdf_part(b, p.pi, p.A, p.B, 3, sd);
+  const float hi = cdf_part(b, p.pi + 3, p.A + 3, p.B + 3, 2, sd);
+  return lo + hi;
+}
+
+// F(v) = v + min(M', floor(C * M')) from C = C(beta_v).
+__device__ __forceinline__ uint32_t F_of_C(int v, float C) {
   uint32_t q = (uint32_t)(C * 65280.0f);
   q = min(q, M_PRIME);
   return (uint32_t)v + q;
 }
 
+// Cumulative frequency F(v) = v + min(M', floor(C(beta_v) * M')), F(0) = 0,
+// F(256) = 2^16.
+__device__ __forceinline__ uint32_t cdf_F(int v, const Mix& p, const float2* sd,
+                                          const float* beta) {
+  if (v <= 0) return 0u;
+  if (v >= 256) return M_TOTAL;
+  return F_of_C(v, cdf_C(beta[v], p, sd));
+}
+
 // F(v) for 0 < v < 256 with the bin edge beta_v already at hand.
 __device__ __forceinline__ uint32_t cdf_F_at(int v, float b, const Mix& p, const float2* sd) {
-  float C = p.pi[0] * sigma_hat(b * p.A[0] + p.B[0], sd);
-#pragma unroll
-  for (int k = 1; k < N_MIX; ++k) C = C + p.pi[k] * sigma_hat(b * p.A[k] + p.B[k], sd);
-  uint32_t q = (uint32_t)(C * 65280.0f);
-  q = min(q, M_PRIME);
-  return (uint32_t)v + q;
+  return F_of_C(v, cdf_C(b, p, sd));
 }
 
 // Largest v with F(v) <= slot, by 8 halvings of [0, 256); returns (v, c, f).

@@ -19,92 +19,139 @@ namespace dlic {
 // Stride (floats) of one pixel's outputs in the per-wave LDS staging area.
 constexpr int O_STRIDE = 16;
 
+// LDS of the density kernels: logistic table, bin edges, scaled grey levels,
+// per-wave output staging and the net's layer-2 weights when they live in LDS.
+template <class Net>
+struct DensityLds {
+  float2 sd[LUT_N];
+  float beta[257];
+  float scale[256];
+  __attribute__((aligned(16))) float o[4][64 * O_STRIDE];
+  __attribute__((aligned(16))) char w2[Net::LDS_BYTES > 0 ? Net::LDS_BYTES : 16];
+};
+
+template <class Net>
+__device__ __forceinline__ void density_prologue(const Consts* K, const DevModel& m,
+                                                 DensityLds<Net>& S, Net& net) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < LUT_N; i += 256) S.sd[i] = K->sd[i];
+  for (int i = tid; i < 257; i += 256) S.beta[i] = K->beta[i];
+  S.scale[tid] = K->scale[tid];
+  Net::stage(m, S.w2, tid, 256);
+  __syncthreads();
+  net.load(m, tid & 63);
+}
+
+// One block of 256 consecutive raster pixels of an image: four 16-pixel MFMA
+// tiles per wave, then one lane per pixel for the head and the table rule.
+template <class Net>
+__device__ __forceinline__ void density_block(const Net& net, DensityLds<Net>& S,
+                                              const uint8_t* __restrict__ img, int W, long long n,
+                                              long long blk, uint32_t* __restrict__ cf,
+                                              float* __restrict__ out15,
+                                              uint32_t* __restrict__ tables) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4;
+  const long long base = blk * 256 + wave * 64;
+#pragma unroll 1
+  for (int tile = 0; tile < 4; ++tile) {
+    const long long p = base + tile * 16 + (lane & 15);
+    float fk[3] = {0.0f, 0.0f, 0.0f};
+    if (p < n) {
+      const int y = (int)(p / W), x = (int)(p - (long long)y * W);
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) {
+        const int k = 4 * kk + q;
+        const int yy = y + nb_dy(k), xx = x + nb_dx(k);
+        if (yy >= 0 && xx >= 0 && xx < W) fk[kk] = S.scale[img[(long long)yy * W + xx]];
+      }
+    }
+    const f4 o = net.run(fk[0], fk[1], fk[2], S.w2);
+    *reinterpret_cast<f4*>(&S.o[wave][(tile * 16 + (lane & 15)) * O_STRIDE + 4 * q]) = o;
+  }
+  __syncthreads();
+  const long long p = base + lane;
+  if (p < n) {
+    float o[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const f4 v = *reinterpret_cast<const f4*>(&S.o[wave][lane * O_STRIDE + 4 * i]);
+      o[4 * i] = v[0];
+      o[4 * i + 1] = v[1];
+      o[4 * i + 2] = v[2];
+      o[4 * i + 3] = v[3];
+    }
+    const Mix mix = mixture_head(o);
+    const int v = img[p];
+    const uint32_t Flo = cdf_F(v, mix, S.sd, S.beta);
+    const uint32_t Fhi = cdf_F(v + 1, mix, S.sd, S.beta);
+    if (cf) cf[p] = Flo | ((Fhi - Flo - 1u) << 16);
+    if (out15) {
+#pragma unroll
+      for (int k = 0; k < N_OUT; ++k) out15[p * N_OUT + k] = o[k];
+    }
+    if (tables) {
+      for (int lv = 0; lv <= 256; ++lv) tables[p * 257 + lv] = cdf_F(lv, mix, S.sd, S.beta);
+    }
+  }
+  __syncthreads();
+}
+
 template <class Net>
 __global__ __launch_bounds__(256) void density_kernel(const Consts* __restrict__ K, DevModel m,
                                                       const uint8_t* __restrict__ img, int H,
                                                       int W, uint32_t* __restrict__ cf,
                                                       float* __restrict__ out15,
                                                       uint32_t* __restrict__ tables) {
-  __shared__ float2 s_sd[LUT_N];
-  __shared__ float s_beta[257];
-  __shared__ float s_scale[256];
-  __shared__ __attribute__((aligned(16))) float s_o[4][64 * O_STRIDE];
-  __shared__ __attribute__((aligned(16))) char s_w2[Net::LDS_BYTES > 0 ? Net::LDS_BYTES : 16];
-
-  const int tid = threadIdx.x;
-  for (int i = tid; i < LUT_N; i += 256) s_sd[i] = K->sd[i];
-  for (int i = tid; i < 257; i += 256) s_beta[i] = K->beta[i];
-  s_scale[tid] = K->scale[tid];
-  Net::stage(m, s_w2, tid, 256);
-  __syncthreads();
-
-  const int lane = tid & 63, wave = tid >> 6, q = lane >> 4;
+  __shared__ DensityLds<Net> S;
   Net net;
-  net.load(m, lane);
-
+  density_prologue(K, m, S, net);
   const long long n = (long long)H * W;
   const long long n_blk = (n + 255) / 256;
-  for (long long blk = blockIdx.x; blk < n_blk; blk += gridDim.x) {
-    const long long base = blk * 256 + wave * 64;
-#pragma unroll 1
-    for (int tile = 0; tile < 4; ++tile) {
-      const long long p = base + tile * 16 + (lane & 15);
-      float fk[3] = {0.0f, 0.0f, 0.0f};
-      if (p < n) {
-        const int y = (int)(p / W), x = (int)(p - (long long)y * W);
-#pragma unroll
-        for (int kk = 0; kk < 3; ++kk) {
-          const int k = 4 * kk + q;
-          const int yy = y + nb_dy(k), xx = x + nb_dx(k);
-          if (yy >= 0 && xx >= 0 && xx < W) fk[kk] = s_scale[img[(long long)yy * W + xx]];
-        }
-      }
-      const f4 o = net.run(fk[0], fk[1], fk[2], s_w2);
-      *reinterpret_cast<f4*>(&s_o[wave][(tile * 16 + (lane & 15)) * O_STRIDE + 4 * q]) = o;
-    }
-    __syncthreads();
-    const long long p = base + lane;
-    if (p < n) {
-      float o[16];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const f4 v = *reinterpret_cast<const f4*>(&s_o[wave][lane * O_STRIDE + 4 * i]);
-        o[4 * i] = v[0];
-        o[4 * i + 1] = v[1];
-        o[4 * i + 2] = v[2];
-        o[4 * i + 3] = v[3];
-      }
-      const Mix mix = mixture_head(o);
-      const int v = img[p];
-      const uint32_t Flo = cdf_F(v, mix, s_sd, s_beta);
-      const uint32_t Fhi = cdf_F(v + 1, mix, s_sd, s_beta);
-      if (cf) cf[p] = Flo | ((Fhi - Flo - 1u) << 16);
-      if (out15) {
-#pragma unroll
-        for (int k = 0; k < N_OUT; ++k) out15[p * N_OUT + k] = o[k];
-      }
-      if (tables) {
-        for (int lv = 0; lv <= 256; ++lv) tables[p * 257 + lv] = cdf_F(lv, mix, s_sd, s_beta);
-      }
-    }
-    __syncthreads();
+  for (long long blk = blockIdx.x; blk < n_blk; blk += gridDim.x)
+    density_block(net, S, img, W, n, blk, cf, out15, tables);
+}
+
+// Batched form: blocks of all images in one grid-stride loop; block b belongs
+// to the last image whose first block is <= b.
+__device__ __forceinline__ int batch_image_of_block(const BatchArgs& b, int blk) {
+  int lo = 0, hi = b.n_img - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.images[mid].blk_off <= blk) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <class Net>
+__global__ __launch_bounds__(256) void batch_density_kernel(const Consts* __restrict__ K,
+                                                            DevModel m, BatchArgs b) {
+  __shared__ DensityLds<Net> S;
+  Net net;
+  density_prologue(K, m, S, net);
+  for (int blk = blockIdx.x; blk < b.n_blk; blk += gridDim.x) {
+    const BatchImage im = b.images[batch_image_of_block(b, blk)];
+    density_block(net, S, b.pix_in + im.px_off, im.W, (long long)im.H * im.W,
+                  (long long)(blk - im.blk_off), b.cf + im.px_off, nullptr, nullptr);
   }
 }
 
 constexpr int ENC_CHUNK = 32;   // wavefront steps staged in LDS per chunk
 constexpr int ENC_BATCH = 8;    // sub-rounds read from LDS ahead of coding
+constexpr int ENC_STAGERS = 192;  // threads of waves 1..3
+constexpr int ENC_PER_STAGER = (ENC_CHUNK * DEC_RMAX + ENC_STAGERS - 1) / ENC_STAGERS;
 
-// One workgroup (4 waves) per group.  Wave 0 codes; while it walks one chunk
-// of 32 steps in reverse canonical order from LDS, waves 1..3 stage the next
-// chunk's intervals (row-contiguous global reads).  Words go below the top of
-// the group's scratch slice (cap_g = R*W + 2L words, the worst case), so a
-// stream is contiguous at [cap_g - count, cap_g).
-__global__ __launch_bounds__(256) void rans_encode_kernel(const uint32_t* __restrict__ cf, int H,
-                                                          int W, int G, int L,
-                                                          uint16_t* __restrict__ words,
-                                                          uint32_t* __restrict__ counts) {
-  __shared__ uint32_t s_cf[2][ENC_CHUNK * DEC_RMAX];
-  const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// One group's rANS walk (one workgroup of 4 waves).  Wave 0 codes; while it
+// walks one chunk of 32 steps in reverse canonical order from LDS, waves 1..3
+// stage the next chunk's intervals, all of a thread's loads issued before any
+// LDS store so their latencies overlap.  Words go below the top of the
+// group's scratch slice (cap_g = R*W + 2L words, the worst case), so a stream
+// is contiguous at [cap_g - count, cap_g).
+__device__ __forceinline__ void rans_encode_group(uint32_t (*s_cf)[ENC_CHUNK * DEC_RMAX],
+                                                  const uint32_t* __restrict__ cf, int H, int W,
+                                                  int G, int L, int g,
+                                                  uint16_t* __restrict__ words,
+                                                  uint32_t* __restrict__ counts) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r0 = group_row(g, H, G), r1 = group_row(g + 1, H, G);
   const int R = r1 - r0;
   const int J = (R + L - 1) / L;
@@ -116,21 +163,33 @@ __global__ __launch_bounds__(256) void rans_encode_kernel(const uint32_t* __rest
   // chunk c holds steps [t_last - 32c - 31, t_last - 32c] as [k][row], k = t - t_lo
   auto stage = [&](int c, uint32_t* buf, int first, int stride) {
     const int t_lo = t_last - ENC_CHUNK * c - (ENC_CHUNK - 1);
-    for (int idx = first; idx < R * ENC_CHUNK; idx += stride) {
+    uint32_t v[ENC_PER_STAGER];
+#pragma unroll
+    for (int i = 0; i < ENC_PER_STAGER; ++i) {
+      const int idx = first + i * stride;
       const int rr = idx / ENC_CHUNK, k = idx - rr * ENC_CHUNK;
       const int y = r0 + rr, t = t_lo + k, x = t - SKEW * y;
-      buf[k * DEC_RMAX + rr] =
-          (t >= t_first && x >= 0 && x < W) ? cf[(long long)y * W + x] : INACTIVE;
+      v[i] = (idx < R * ENC_CHUNK && t >= t_first && x >= 0 && x < W)
+                 ? cf[(long long)y * W + x]
+                 : INACTIVE;
+    }
+#pragma unroll
+    for (int i = 0; i < ENC_PER_STAGER; ++i) {
+      const int idx = first + i * stride;
+      if (idx < R * ENC_CHUNK) {
+        const int rr = idx / ENC_CHUNK, k = idx - rr * ENC_CHUNK;
+        buf[k * DEC_RMAX + rr] = v[i];
+      }
     }
   };
-  if (n_chunks > 0) stage(0, s_cf[0], tid, 256);
+  if (n_chunks > 0 && wave > 0) stage(0, s_cf[0], tid - 64, ENC_STAGERS);
   __syncthreads();
 
   uint32_t Q = (uint32_t)cap;
   uint32_t x = RANS_L;
   for (int c = 0; c < n_chunks; ++c) {
     if (wave > 0) {
-      if (c + 1 < n_chunks) stage(c + 1, s_cf[(c + 1) & 1], tid - 64, 192);
+      if (c + 1 < n_chunks) stage(c + 1, s_cf[(c + 1) & 1], tid - 64, ENC_STAGERS);
     } else {
       const uint32_t* buf = s_cf[c & 1];
       const int t_lo = t_last - ENC_CHUNK * c - (ENC_CHUNK - 1);
@@ -169,6 +228,23 @@ __global__ __launch_bounds__(256) void rans_encode_kernel(const uint32_t* __rest
   }
 }
 
+__global__ __launch_bounds__(256) void rans_encode_kernel(const uint32_t* __restrict__ cf, int H,
+                                                          int W, int G, int L,
+                                                          uint16_t* __restrict__ words,
+                                                          uint32_t* __restrict__ counts) {
+  __shared__ uint32_t s_cf[2][ENC_CHUNK * DEC_RMAX];
+  rans_encode_group(s_cf, cf, H, W, G, L, blockIdx.x, words, counts);
+}
+
+// Batched form: workgroup i codes work item i (image, group).
+__global__ __launch_bounds__(256) void batch_rans_encode_kernel(BatchArgs b) {
+  __shared__ uint32_t s_cf[2][ENC_CHUNK * DEC_RMAX];
+  const BatchItem it = b.items[blockIdx.x];
+  const BatchImage im = b.images[it.image];
+  rans_encode_group(s_cf, b.cf + im.px_off, im.H, im.W, im.G, im.L, it.group,
+                    b.words + im.words_off, b.counts + im.counts_off);
+}
+
 __device__ __forceinline__ void put_u16(uint8_t* p, uint32_t v) {
   p[0] = (uint8_t)v;
   p[1] = (uint8_t)(v >> 8);
@@ -177,14 +253,14 @@ __device__ __forceinline__ void put_u32(uint8_t* p, uint32_t v) {
   for (int i = 0; i < 4; ++i) p[i] = (uint8_t)(v >> (8 * i));
 }
 
-// grid (chunks, G): block (c, g) copies part of group g's stream; block (0, 0)
-// also writes the header, the counts and the total length.
-__global__ __launch_bounds__(256) void pack_kernel(const uint16_t* __restrict__ words,
-                                                   const uint32_t* __restrict__ counts, int H,
-                                                   int W, int G, int L, HeaderFields hf,
-                                                   uint8_t* __restrict__ out,
-                                                   uint64_t* __restrict__ out_len) {
-  const int g = blockIdx.y;
+// Part `part` of `parts` of group g's stream copy; part 0 of group 0 also
+// writes the header, the counts and the total length.
+__device__ __forceinline__ void pack_group_part(const uint16_t* __restrict__ words,
+                                                const uint32_t* __restrict__ counts, int H,
+                                                int W, int G, int L, const HeaderFields& hf,
+                                                uint8_t* __restrict__ out,
+                                                uint64_t* __restrict__ out_len, int g, int part,
+                                                int parts) {
   __shared__ unsigned long long s_before, s_total;
   if (threadIdx.x == 0) {
     unsigned long long before = 0, total = 0;
@@ -197,7 +273,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const uint16_t* __restrict__ 
   }
   __syncthreads();
   const long long hdr = HEADER_BYTES + 4LL * G;
-  if (g == 0 && blockIdx.x == 0) {
+  if (g == 0 && part == 0) {
     if (threadIdx.x == 0) {
       out[0] = 'D'; out[1] = 'L'; out[2] = 'I'; out[3] = 'C';
       put_u16(out + 4, 1u);
@@ -224,9 +300,34 @@ __global__ __launch_bounds__(256) void pack_kernel(const uint16_t* __restrict__ 
   const uint32_t cnt = counts[g];
   const uint16_t* src = words + (long long)r0 * W + 2LL * L * g + (cap - cnt);
   uint8_t* dst = out + hdr + 2LL * (long long)s_before;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
-       i += (long long)gridDim.x * blockDim.x)
+  for (long long i = (long long)part * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)parts * blockDim.x)
     put_u16(dst + 2 * i, src[i]);
+}
+
+// grid (chunks, G): block (c, g) copies part c of group g's stream.
+__global__ __launch_bounds__(256) void pack_kernel(const uint16_t* __restrict__ words,
+                                                   const uint32_t* __restrict__ counts, int H,
+                                                   int W, int G, int L, HeaderFields hf,
+                                                   uint8_t* __restrict__ out,
+                                                   uint64_t* __restrict__ out_len) {
+  pack_group_part(words, counts, H, W, G, L, hf, out, out_len, blockIdx.y, blockIdx.x, gridDim.x);
+}
+
+// Batched form, grid (parts, items).  The last block of an image to finish
+// stamps the image's completion time.
+__global__ __launch_bounds__(256) void batch_pack_kernel(BatchArgs b) {
+  const BatchItem it = b.items[blockIdx.y];
+  const BatchImage im = b.images[it.image];
+  pack_group_part(b.words + im.words_off, b.counts + im.counts_off, im.H, im.W, im.G, im.L, b.hf,
+                  b.out + im.out_off, b.len + it.image, it.group, blockIdx.x, gridDim.x);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned need = (unsigned)(im.G * gridDim.x);
+    if (atomicAdd(b.done + it.image, 1u) + 1u == need && b.t_done)
+      b.t_done[it.image] = __builtin_amdgcn_s_memrealtime();
+  }
 }
 
 // ---- host-side launchers -------------------------------------------------
@@ -266,6 +367,41 @@ bool launch_density(int wtype, int width, const Consts* K, const DevModel& m, co
     case 128: return launch_density_h<128>(wtype, K, m, img, H, W, cf, out15, tables, grid, s);
     default: return false;
   }
+}
+
+template <class Net>
+static void launch_batch_density_t(const Consts* K, const DevModel& m, const BatchArgs& b,
+                                   int grid, hipStream_t s) {
+  hipLaunchKernelGGL((batch_density_kernel<Net>), dim3(grid), dim3(256), 0, s, K, m, b);
+}
+
+template <int H>
+static bool launch_batch_density_h(int wtype, const Consts* K, const DevModel& m,
+                                   const BatchArgs& b, int grid, hipStream_t s) {
+  switch (wtype) {
+    case WT_F32: launch_batch_density_t<NetF32<H>>(K, m, b, grid, s); return true;
+    case WT_BF16: launch_batch_density_t<NetBF16<H, WT_BF16, false>>(K, m, b, grid, s); return true;
+    case WT_FP8: launch_batch_density_t<NetBF16<H, WT_FP8, false>>(K, m, b, grid, s); return true;
+    default: return false;
+  }
+}
+
+bool launch_batch_density(int wtype, int width, const Consts* K, const DevModel& m,
+                          const BatchArgs& b, int grid, hipStream_t s) {
+  switch (width) {
+    case 32: return launch_batch_density_h<32>(wtype, K, m, b, grid, s);
+    case 64: return launch_batch_density_h<64>(wtype, K, m, b, grid, s);
+    case 128: return launch_batch_density_h<128>(wtype, K, m, b, grid, s);
+    default: return false;
+  }
+}
+
+void launch_batch_rans_encode(const BatchArgs& b, hipStream_t s) {
+  hipLaunchKernelGGL(batch_rans_encode_kernel, dim3(b.n_items), dim3(256), 0, s, b);
+}
+
+void launch_batch_pack(const BatchArgs& b, int parts, hipStream_t s) {
+  hipLaunchKernelGGL(batch_pack_kernel, dim3(parts, b.n_items), dim3(256), 0, s, b);
 }
 
 void launch_rans_encode(const uint32_t* cf, int H, int W, int G, int L, uint16_t* words,

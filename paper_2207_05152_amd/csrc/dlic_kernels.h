@@ -36,6 +36,44 @@ struct DecArgs {
 };
 
 // wtype: WeightType of the model; width: h1 == h2.  False for an unsupported pair.
+// ---- batches of images (one plan, work items = (image, group)) ----------
+struct BatchImage {
+  long long px_off;     // first pixel in the concatenated pixel buffers (also the cf index)
+  long long words_off;  // first u16 of the image's word scratch
+  long long out_off;    // first byte of the image's stream region
+  long long out_cap;    // bytes of that region (dlic_encode_bound of the image)
+  long long rec_off;    // first u32 of the image's decode records
+  long long T;          // wavefront steps W + 3H - 3
+  int H, W, G, L;
+  int counts_off;       // first u32 of the image's per-group word counts
+  int blk_off;          // first 256-pixel density block of the image
+};
+
+struct BatchItem {
+  int image, group;
+};
+
+struct BatchArgs {
+  const BatchImage* images;
+  const BatchItem* items;  // longest wavefront first; groups of an image in order
+  int n_img, n_items, n_blk;
+  const uint8_t* pix_in;   // encode: the images
+  uint8_t* pix_out;        // decode: the images
+  uint32_t* cf;
+  uint16_t* words;
+  uint32_t* counts;
+  uint8_t* out;            // encode: stream regions
+  const uint8_t* bits;     // decode: stream regions
+  uint64_t* len;           // encode writes / decode reads one length per image
+  uint32_t* rec;
+  int* status;             // decode: one per image
+  unsigned* ticket;        // decode: next work item
+  unsigned* done;          // per image: finished blocks (encode) or groups (decode)
+  unsigned long long* t_done;  // optional per-image completion times (realtime counter)
+  HeaderFields hf;
+  uint32_t spin_limit;
+};
+
 bool launch_density(int wtype, int width, const Consts* K, const DevModel& m, const uint8_t* img,
                     int H, int W, uint32_t* cf, float* out15, uint32_t* tables, int grid,
                     hipStream_t s);
@@ -47,6 +85,16 @@ void launch_pack(const uint16_t* words, const uint32_t* counts, int H, int W, in
 bool launch_decode(int wtype, int width, bool tables_mode, const Consts* K, const DevModel& m,
                    const DecArgs& a, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t s);
+// Stamps the realtime counter into *t (the start of a batch).
+void launch_stamp(unsigned long long* t, hipStream_t s);
+
+bool launch_batch_density(int wtype, int width, const Consts* K, const DevModel& m,
+                          const BatchArgs& b, int grid, hipStream_t s);
+void launch_batch_rans_encode(const BatchArgs& b, hipStream_t s);
+void launch_batch_pack(const BatchArgs& b, int parts, hipStream_t s);
+// split: every image of the batch has L <= 32 (the coder's half-wave split).
+bool launch_batch_decode(int wtype, int width, const Consts* K, const DevModel& m,
+                         const BatchArgs& b, bool split, hipStream_t s);
 
 // Training: waves per workgroup of the FP32 / FP64 loss-and-gradient kernel.
 constexpr int TRAIN_WAVES_F32 = 4;

@@ -143,3 +143,58 @@ def test_bf16_full_size_sampled_and_roundtrip(dev):
     torch.cuda.synchronize()
     assert status == dl.DLIC_OK
     assert torch.equal(out, d_img)
+
+
+def _pmf_rows(o):
+    pi, mu, inv_s = oracle.mixture_head(o)
+    return np.stack([oracle.pmf_table(pi[i], mu[i], inv_s[i]) for i in range(len(pi))])
+
+
+def test_precision_report(dev):
+    """PDF error of each precision against the FP64 network (FP32 weights):
+    e_net = max |P_dtype(v) - P_64(v)| with P_dtype the mixture of the dtype
+    run's own outputs evaluated in FP64 (network precision alone), sampled
+    over the full-size image; e_tab = max |f_v / 2^16 - P_64(v)| of the
+    dtype run's integer tables (end to end), over a 64 x 256 crop.  Writes
+    the numbers to $DLIC_REPORT_DIR/precision_report.json when set."""
+    import json
+    import os
+    img = synth.synth_image(1536, 2048, 1)
+    wts = synth.xavier_mlp((12, 128, 128, 15), 3)
+    rng = np.random.default_rng(2)
+    idx = rng.integers(0, img.size, 1500)
+    feats = np.stack([oracle.pixel_features(img, int(p) // 2048, int(p) % 2048) for p in idx])
+    keys = ("W1", "b1", "W2", "b2", "W3", "b3")
+    p64 = _pmf_rows(oracle.mlp_forward(feats, *(wts[k] for k in keys)))
+    crop = np.ascontiguousarray(img[700:764, 1000:1256])
+    p64c = _pmf_rows(oracle.mlp_forward(oracle.causal_features(crop).reshape(-1, 12),
+                                        *(wts[k] for k in keys)))
+    d_img, d_crop = to_dev(img, dev), to_dev(crop, dev)
+    report = {}
+    for dtype in ("fp32", "bf16", "fp8"):
+        m = dl.Model(wts, dev, dtype=dtype)
+        say("precision report", dtype)
+        out15, _, _ = dl.density(d_img, m)
+        _, _, tab = dl.density(d_crop, m, tables=True)
+        torch.cuda.synchronize()
+        o = out15.cpu().numpy()[idx].astype(np.float64)
+        del out15
+        pd = _pmf_rows(o)
+        F = tab.cpu().numpy().astype(np.int64)
+        f = np.diff(F, axis=1)
+        assert np.all(F[:, 0] == 0) and np.all(F[:, 256] == 65536) and np.all(f >= 1)
+        report[dtype] = {"e_net": float(np.abs(pd - p64).max()),
+                         "e_tab": float(np.abs(f / 65536.0 - p64c).max())}
+    say("report", report)
+    # FP32 network error is at the 1e-4 parameter tolerance; the table error
+    # is bounded by the format's spreading (each bin +1, M' = 65280) and the
+    # piecewise-linear logistic
+    assert report["fp32"]["e_net"] <= 1e-4, report
+    assert max(r["e_tab"] for r in report.values()) <= 0.05, report
+    out_dir = os.environ.get("DLIC_REPORT_DIR")
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, "precision_report.json"), "w") as fh:
+            json.dump({"workload": "2048x1536 image seed 1, 12-128-128-15 Glorot seed 3; e_net "
+                                   "over 1500 sampled pixels, e_tab over the crop rows 700-763, "
+                                   "columns 1000-1255", "dtypes": report}, fh, indent=1)
