@@ -72,6 +72,34 @@ def cpu_baseline(img, weights, groups, lanes, target_s=15.0):
                       f"{dt:.1f} s"}
 
 
+def kernel_sources_sha256() -> str:
+    """Digest of the HIP sources; counter readings are valid only for the code they measured."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2207_05152_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".h")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of a kernel from the committed counter summary
+    (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch, each scaled
+    by what the same counter read for a plain copy of known size), or None when
+    the kernels changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_sources_sha256() or kernel not in t.get("kernels", {}):
+        return None
+    return float(t["kernels"][kernel]["bytes_per_launch"])
+
+
 def precision_sweep(dl, torch, img, H, W, coder, hidden=128, reps=3):
     """Encode + decode of the same image with the 12-128-128-15 net stored as
     FP32, BF16 and FP8 e4m3: kernel-timed MPix/s, bpp and the bpp change
@@ -117,6 +145,35 @@ def precision_sweep(dl, torch, img, H, W, coder, hidden=128, reps=3):
                        f"stored as FP32 / BF16 / FP8 e4m3 with per-layer scales, "
                        f"{coder.groups}x{coder.lanes_per_group} lanes")
     return res
+
+
+def layout_sweep(dl, torch, img, H, W, model, layouts=((8, 32), (8, 64), (16, 32), (24, 64),
+                                                        (48, 32)), reps=3):
+    """The headline image and net coded with other coder layouts (G groups x L
+    lanes; 8 x 32 is the headline's 256 lanes).  More lanes per row cut the
+    sequential sub-rounds per wavefront step, ceil(rows per group / L), and
+    spread one image over more CUs, at the price of 4 flushed bytes per lane."""
+    out = []
+    dl.dlic_set_timing(True)
+    for G, L in layouts:
+        coder = dl.dlic_coder(G, L)
+        bits = dl.encode(img, model, coder)
+        dec = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        ws = torch.empty(dl.dlic_decode_workspace(H, W, coder), dtype=torch.uint8, device="cuda")
+        ms = []
+        for r in range(reps + 1):
+            dl.dlic_decode(model.c, coder, bits, bits.numel(), dec, H, W, st, ws, ws.numel())
+            if r:
+                ms.append(dict(dl.dlic_kernel_times())["wavefront_decode_kernel"])
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0 and torch.equal(dec, img), f"layout {G}x{L} round trip"
+        rows = -(-H // G)
+        out.append({"groups": G, "lanes": L, "sub_rounds_per_step": -(-rows // L),
+                    "decode_ms": float(np.mean(ms)), "decode_mpix_s": H * W / np.mean(ms) / 1e3,
+                    "bpp_total": 8.0 * bits.numel() / (H * W)})
+    dl.dlic_set_timing(False)
+    return out
 
 
 def _synth_job(args):
@@ -186,6 +243,53 @@ def batch_sweep(dl, torch, reps=3, tune_budget_s=60.0):
     return res
 
 
+def _phantom_job(seed):
+    import synth
+    return synth.mri_phantom(seed, 256)
+
+
+def training_sweep(dl, torch, steps=20, n=1 << 20):
+    """Retraining steps on MRI-like slices: 2^20 sampled windows per step from a
+    256-slice 256x256 phantom stack, 12-64-64-15 FP32, hand-written loss+gradient
+    kernel then Adam; steps/s and MFMA rate (forward + backward ~ 3x forward FLOP)."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    import synth
+    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        stack = np.stack(list(ex.map(_phantom_job, range(2000, 2256))))
+    slices = torch.from_numpy(stack).cuda()
+    model = dl.TrainModel(synth.xavier_mlp((12, 64, 64, 15), 3), "cuda")
+    idx = [torch.from_numpy(synth.train_indices(k, n, 256, 256, 256)).cuda() for k in range(steps)]
+    npar = model.flat.numel()
+    m = torch.zeros_like(model.flat)
+    v = torch.zeros_like(model.flat)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    grad = torch.empty_like(model.flat)
+    wsb = dl.dlic_nll_workspace(n, model.c)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    losses = []
+
+    def one(k):
+        dl.dlic_nll_fwd_bwd(model.c, slices, 256, 256, 256, idx[k], n, loss, grad, ws, wsb)
+        dl.dlic_adam_step(npar, model.flat, grad, m, v, k + 1)
+
+    one(0)
+    losses.append(float(loss.item()))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, steps):
+        one(k)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / (steps - 1)
+    losses.append(float(loss.item()))
+    flop = 3 * n * mlp_flops_per_px(64, 64)
+    return {"workload": f"{n} windows per step from 256 phantom slices of 256x256, MLP 12-64-64-15 "
+                        f"FP32 (Glorot seed 3), loss + gradient kernel then Adam",
+            "ms_per_step": dt * 1e3, "steps_per_s": 1.0 / dt, "samples_per_s": n / dt,
+            "tflops_approx": flop / dt / 1e12, "frac_fp32_mfma": flop / dt / MI355X_FP32_MFMA,
+            "loss_bits_first_last": losses}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,7 +305,7 @@ def main():
                     help="before the timed steps, run one plain elementwise copy of MIB MiB "
                          "(FP32 negation) so that counter runs can scale FETCH_SIZE/WRITE_SIZE")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the precision and batch sweeps after the headline step")
+                    help="skip the precision, batch and training sweeps after the headline step")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the DLIC hot path here runs on a single MI355X "
@@ -273,10 +377,15 @@ def main():
     dl.dlic_set_decode_profile(None)
     pc = prof.view(args.groups, 8).cpu().numpy().astype(np.float64)
     busy = pc[:, 0] + pc[:, 1]
+    tiles = max(pc[:, 7].sum(), 1)
     decode_profile = {
         "coder_wait_frac": float(pc[:, 0].sum() / max(busy.sum(), 1)),
         "worker_wait_frac": float(pc[:, 2].sum() / max((pc[:, 2] + pc[:, 3]).sum(), 1)),
         "coder_cycles_per_group": [int(v) for v in busy],
+        "worker_cycles_per_tile": {"gather_net": float(pc[:, 4].sum() / tiles),
+                                   "head": float(pc[:, 5].sum() / tiles),
+                                   "buckets_publish": float(pc[:, 6].sum() / tiles),
+                                   "tiles": int(tiles)},
     }
 
     assert int(st.item()) == 0, f"decode status {int(st.item())}"
@@ -324,7 +433,7 @@ def main():
             "peak": MI355X_FP32_MFMA / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / MI355X_FP32_MFMA,
-            "traffic": None,
+            "traffic": measured_traffic(dom),
         },
         "decode_schedule_bound": {
             "critical_px": crit_px,
@@ -337,8 +446,10 @@ def main():
         "host": {"cpu": platform.processor() or platform.machine(), "os_cpus": os.cpu_count()},
     }
     if not args.no_extras:
+        res["layouts"] = layout_sweep(dl, torch, img, H, W, model)
         res["precision"] = precision_sweep(dl, torch, img, H, W, coder)
         res["batch"] = batch_sweep(dl, torch)
+        res["training"] = training_sweep(dl, torch)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(img_np, weights, args.groups, args.lanes)
     print(json.dumps(res))

@@ -31,8 +31,12 @@ namespace dlic {
 
 constexpr int RING_MASK = DEC_RING - 1;
 constexpr int REFILL_WORDS = 1024;           // one coder-wave refill: 16 words per lane
-constexpr int CODER_SIMD_TWIN = 4;          // wave sharing the coder's SIMD (left idle)
-constexpr int NWORK = DEC_WAVES - 2;         // density waves
+// Waves are placed on the four SIMDs round-robin, so waves 4, 8, ... share
+// the coder's SIMD; they stay idle and leave that SIMD to the coder.
+constexpr int NWORK = DEC_WAVES - DEC_WAVES / 4;  // density waves
+// Layer-2 weights of the 64-wide FP32 net in LDS instead of VGPRs (frees 64
+// VGPRs per density wave, for more waves per SIMD).
+constexpr bool DEC_F32_W2_LDS = false;
 constexpr int NSLOT = 8;                     // sub-round densities in flight
 constexpr int SLOT_PX = 64;                  // lanes per group at most
 constexpr int PAR_STRIDE = 16;               // floats per pixel: pi[5], A[5], B[5]
@@ -357,7 +361,8 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           c = Flo;
           f = Fhi - Flo;
         }
-        if (act) x = f * (x >> 16) + slot - c;
+        // f <= 2^16 - 255 and x >> 16 < 2^16: the 24-bit multiplier is exact
+        if (act) x = __umul24(f, x >> 16) + slot - c;
         Pw = rans_dec_renorm(x, act && !bad, Pw, n_words,
                              [&](uint32_t pos) { return (uint32_t)s_words[pos & RING_MASK]; }, over);
         if (act) {
@@ -399,12 +404,13 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     // -------------------------------------------------------- density waves
     // density waves: waves are placed on SIMDs round-robin, so wave 4 would
     // share the coder's SIMD; it stays idle and the coder keeps its SIMD
-    if (wave == CODER_SIMD_TWIN) return;
+    if ((wave & 3) == 0) return;
     const int nwork = NWORK;
-    const int w = wave > CODER_SIMD_TWIN ? wave - 2 : wave - 1;
+    const int w = wave - 1 - (wave >> 2);
     Net net;
     net.load(m, lane);
     const int q4 = lane >> 4;
+    unsigned long long t_net = 0, t_head = 0, t_tab = 0, n_tiles = 0, c_net = 0, c_head = 0;
     bool timeout = s_flag != 0;
     bool stuck = false;
     // tile tau = NT * q + ti of sub-round q = (t - t_first) * J + j, every NWORK-th
@@ -477,6 +483,10 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         const f4 o = net.run(fk[0], fk[1], fk[2], s_w2);
         float* par = &s_par[slot_i][0];
         if (valid) *reinterpret_cast<f4*>(&par[ln * PAR_STRIDE + 4 * q4]) = o;
+        if (a.prof) {
+          c_net = clock64();
+          ++n_tiles;
+        }
         // mixture head, one lane per pixel
         if (lane < 16 && valid) {
           float* pp = &par[ln * PAR_STRIDE];
@@ -491,6 +501,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
             pp[2 * N_MIX + k] = mx.B[k];
           }
         }
+        if (a.prof) c_head = clock64();
         // table at the bucket boundaries 16, 32, ..., 240: four per lane
         if (valid) {
           const float* pp = &par[ln * PAR_STRIDE];
@@ -514,6 +525,12 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         const unsigned long long c2 = clock64();
         t_wait += c1 - c0;
         t_busy += c2 - c1;
+        if (c_net) {
+          t_net += c_net - c1;
+          t_head += c_head - c_net;
+          t_tab += c2 - c_head;
+        }
+        c_net = c_head = 0;
       }
       // next tile of this wave
       ti += nwork;
@@ -532,6 +549,10 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       if (a.prof) {
         atomicAdd(&a.prof[g * 8 + 2], t_wait);
         atomicAdd(&a.prof[g * 8 + 3], t_busy);
+        atomicAdd(&a.prof[g * 8 + 4], t_net);
+        atomicAdd(&a.prof[g * 8 + 5], t_head);
+        atomicAdd(&a.prof[g * 8 + 6], t_tab);
+        atomicAdd(&a.prof[g * 8 + 7], n_tiles);
       }
     }
   }
@@ -621,7 +642,7 @@ template <int H>
 static bool launch_batch_decode_h(int wtype, const Consts* K, const DevModel& m,
                                   const BatchArgs& b, bool split, hipStream_t s) {
   switch (wtype) {
-    case WT_F32: launch_batch_decode_t<NetF32<H>>(K, m, b, split, s); return true;
+    case WT_F32: launch_batch_decode_t<NetF32<H, (H > 64 || DEC_F32_W2_LDS)>>(K, m, b, split, s); return true;
     case WT_BF16:
       launch_batch_decode_t<NetBF16<H, WT_BF16, (H > 64)>>(K, m, b, split, s);
       return true;
@@ -658,7 +679,7 @@ template <int H>
 static bool launch_decode_h(int wtype, const Consts* K, const DevModel& m, const DecArgs& a,
                             hipStream_t s) {
   switch (wtype) {
-    case WT_F32: launch_decode_t<NetF32<H>, false>(K, m, a, s); return true;
+    case WT_F32: launch_decode_t<NetF32<H, (H > 64 || DEC_F32_W2_LDS)>, false>(K, m, a, s); return true;
     case WT_BF16: launch_decode_t<NetBF16<H, WT_BF16, (H > 64)>, false>(K, m, a, s); return true;
     case WT_FP8: launch_decode_t<NetBF16<H, WT_FP8, (H > 64)>, false>(K, m, a, s); return true;
     default: return false;

@@ -118,11 +118,12 @@ __device__ __forceinline__ bf16x8 pack_bf16x8(const uint32_t* h) {
 // -----------------------------------------------------------------------------
 
 // FP32 weights, v_mfma_f32_16x16x4f32, biases seed the accumulators.
-// Layer-2 weights sit in VGPRs up to H = 64 and in LDS above (64 KB at 128).
-template <int H>
+// Layer-2 weights sit in VGPRs up to H = 64 and in LDS above (64 KB at 128),
+// or in LDS at any width with W2L.
+template <int H, bool W2L = (H > 64)>
 struct NetF32 {
   static constexpr int NT = H / 16;
-  static constexpr bool W2_LDS = H > 64;
+  static constexpr bool W2_LDS = W2L;
   static constexpr int LDS_BYTES = W2_LDS ? NT * NT * 64 * 16 : 0;
   float a1[NT][3];
   float a2[W2_LDS ? 1 : NT][W2_LDS ? 1 : NT * 4];
@@ -373,7 +374,8 @@ struct Mix {
   float pi[N_MIX], A[N_MIX], B[N_MIX];
 };
 
-// pi = softmax(o[0:5]); mu = o[5:10]; inv_s = exp(-max(o[10:15], -7)).
+// pi = softmax(o[0:5]) (one reciprocal of the sum, then products);
+// mu = o[5:10]; inv_s = exp(-max(o[10:15], -7)).
 __device__ __forceinline__ Mix mixture_head(const float* o) {
   Mix p;
   float m = o[0];
@@ -385,9 +387,10 @@ __device__ __forceinline__ Mix mixture_head(const float* o) {
     e[k] = expf(o[k] - m);
     s = s + e[k];
   }
+  const float rs = 1.0f / s;
 #pragma unroll
   for (int k = 0; k < N_MIX; ++k) {
-    p.pi[k] = e[k] / s;
+    p.pi[k] = e[k] * rs;
     const float inv_s = expf(-fmaxf(o[2 * N_MIX + k], LOG_SCALE_MIN));
     p.A[k] = inv_s * 128.0f;
     p.B[k] = 2048.0f - o[N_MIX + k] * p.A[k];
@@ -478,18 +481,18 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
 
 // x' = floor(x / f) * 2^16 + x mod f + c for x < f * 2^16.  The quotient
 // (< 2^16) comes from an FP32 reciprocal estimate within 0.02 of x / f and
-// one integer correction step.
+// one integer correction step, all by selects (no branches); q * f < 2^32
+// with both factors below 2^24, so the 24-bit multiplier is exact.
 __device__ __forceinline__ uint32_t rans_enc_update(uint32_t x, uint32_t c, uint32_t f) {
   const float rcp = __builtin_amdgcn_rcpf((float)f);
   uint32_t q = (uint32_t)((float)x * rcp);
-  int32_t r = (int32_t)(x - q * f);
-  if (r < 0) {
-    q -= 1u;
-    r += (int32_t)f;
-  } else if (r >= (int32_t)f) {
-    q += 1u;
-    r -= (int32_t)f;
-  }
+  int32_t r = (int32_t)(x - __umul24(q, f));
+  const bool below = r < 0;
+  q = below ? q - 1u : q;
+  r = below ? r + (int32_t)f : r;
+  const bool above = r >= (int32_t)f;
+  q = above ? q + 1u : q;
+  r = above ? r - (int32_t)f : r;
   return (q << 16) + (uint32_t)r + c;
 }
 
@@ -501,11 +504,10 @@ __device__ __forceinline__ uint32_t rans_enc_subround(uint32_t& x, bool act, uin
   const bool ren = act && (x >= (f << 16));
   const uint64_t mask = __ballot(ren);
   const uint32_t cnt = (uint32_t)__popcll(mask);
-  if (ren) {
-    out[Q - cnt + lane_rank(mask)] = (uint16_t)(x & 0xFFFFu);
-    x >>= 16;
-  }
-  if (act) x = rans_enc_update(x, c, f);
+  if (ren) out[Q - cnt + lane_rank(mask)] = (uint16_t)(x & 0xFFFFu);
+  const uint32_t xs = ren ? (x >> 16) : x;
+  const uint32_t xn = rans_enc_update(xs, c, f);
+  x = act ? xn : xs;
   return Q - cnt;
 }
 

@@ -200,9 +200,10 @@ __device__ __forceinline__ void rans_encode_group(uint32_t (*s_cf)[ENC_CHUNK * D
 #pragma unroll
         for (int i = 0; i < ENC_BATCH; ++i) {
           const int rr = j * L + lane;
-          v[i] = (s0 + i < n_sub && t_lo + k >= t_first && lane < L && rr < R)
-                     ? buf[k * DEC_RMAX + rr]
-                     : INACTIVE;
+          const bool ok = s0 + i < n_sub && t_lo + k >= t_first && lane < L && rr < R;
+          // read an in-bounds slot unconditionally, then select
+          const uint32_t w = buf[max(k, 0) * DEC_RMAX + min(rr, DEC_RMAX - 1)];
+          v[i] = ok ? w : INACTIVE;
           if (--j < 0) {
             j = J - 1;
             --k;
