@@ -370,12 +370,12 @@ def main():
     dl.dlic_set_timing(False)
 
     # one more decode with the in-kernel cycle counters on (outside the timed region)
-    prof = torch.zeros(8 * args.groups, dtype=torch.int64, device="cuda")
+    prof = torch.zeros(16 * args.groups, dtype=torch.int64, device="cuda")
     dl.dlic_set_decode_profile(prof)
     dl.dlic_decode(model.c, coder, out, n_bytes, dec, H, W, st, dws, dws.numel(), stream)
     torch.cuda.synchronize()
     dl.dlic_set_decode_profile(None)
-    pc = prof.view(args.groups, 8).cpu().numpy().astype(np.float64)
+    pc = prof.view(args.groups, 16).cpu().numpy().astype(np.float64)
     busy = pc[:, 0] + pc[:, 1]
     tiles = max(pc[:, 7].sum(), 1)
     decode_profile = {
@@ -386,6 +386,9 @@ def main():
                                    "head": float(pc[:, 5].sum() / tiles),
                                    "buckets_publish": float(pc[:, 6].sum() / tiles),
                                    "tiles": int(tiles)},
+        "coder_cycles_per_sub_round": {"busy": float(pc[:, 1].sum() / max(pc[:, 10].sum(), 1)),
+                                       "to_search": float(pc[:, 8].sum() / max(pc[:, 10].sum(), 1)),
+                                       "search": float(pc[:, 9].sum() / max(pc[:, 10].sum(), 1))},
     }
 
     assert int(st.item()) == 0, f"decode status {int(st.item())}"

@@ -314,12 +314,14 @@ void dlic_set_timing(int enable);
 int dlic_kernel_times(float *h_ms, const char **h_names, int max_n);
 
 /* When d_counters is non-NULL, later dlic_decode calls add shader-clock
- * cycle counts per group g to d_counters[8g .. 8g+7] (device, zeroed by the
- * caller): [0] coder waiting for densities, [1] coder busy, [2] density
+ * cycle counts per group g to d_counters[16g .. 16g+15] (device, zeroed by
+ * the caller): [0] coder waiting for densities, [1] coder busy, [2] density
  * waves waiting for decoded pixels (sum over waves), [3] density waves busy
  * (sum), and of that busy time [4] gather + network, [5] mixture head,
- * [6] bucket boundaries + publish, then [7] the number of tiles.  NULL
- * turns it off. */
+ * [6] bucket boundaries + publish, then [7] the number of tiles; of the
+ * coder's busy time [8] from the densities' arrival to the start of the
+ * symbol search, [9] the search itself, and [10] the group's sub-rounds.
+ * NULL turns it off. */
 void dlic_set_decode_profile(unsigned long long *d_counters);
 
 #ifdef __cplusplus

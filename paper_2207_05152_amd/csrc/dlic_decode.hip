@@ -31,17 +31,21 @@ namespace dlic {
 
 constexpr int RING_MASK = DEC_RING - 1;
 constexpr int REFILL_WORDS = 1024;           // one coder-wave refill: 16 words per lane
-// Waves are placed on the four SIMDs round-robin, so waves 4, 8, ... share
-// the coder's SIMD; they stay idle and leave that SIMD to the coder.
-constexpr int NWORK = DEC_WAVES - DEC_WAVES / 4;  // density waves
-// Layer-2 weights of the 64-wide FP32 net in LDS instead of VGPRs (frees 64
-// VGPRs per density wave, for more waves per SIMD).
-constexpr bool DEC_F32_W2_LDS = false;
+// Waves per decoder workgroup: 12 where a density wave's registers allow
+// three waves per SIMD (nets up to 64 wide, the FP32 net's layer-2 weights
+// then in LDS), else 8.  Waves are placed on the four SIMDs round-robin, so
+// waves 4, 8, ... share the coder's SIMD; they stay idle and leave that SIMD
+// to the coder.  The others compute densities.
+template <class Net>
+constexpr int dec_waves() { return Net::DEC_WIDE ? 12 : 8; }
+template <class Net>
+constexpr int dec_workers() { return dec_waves<Net>() - dec_waves<Net>() / 4; }
 constexpr int NSLOT = 8;                     // sub-round densities in flight
 constexpr int SLOT_PX = 64;                  // lanes per group at most
 constexpr int PAR_STRIDE = 16;               // floats per pixel: pi[5], A[5], B[5]
 constexpr int N_BUCKET = 15;                 // F(16 m), m = 1..15
 constexpr uint32_t LDS_SPIN_LIMIT = 1u << 24;
+constexpr int PROF_SLOTS = 16;               // decode profile counters per group
 
 
 __device__ __forceinline__ int floordiv(int a, int b) {
@@ -126,7 +130,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int H = a.H, W = a.W, G = a.G, L = a.L;
-  constexpr int NTH = DEC_WAVES * 64;
+  constexpr int NTH = dec_waves<Net>() * 64;
 
   if (!TABLES) {
     for (int i = tid; i < LUT_N; i += NTH) s_sd[i] = K->sd[i];
@@ -191,7 +195,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
   if (tid == 0) s_end = E0;
   __syncthreads();
 
-  unsigned long long t_wait = 0, t_busy = 0;
+  unsigned long long t_wait = 0, t_busy = 0, t_load = 0, t_search = 0, c_ld = 0, c_sr = 0;
 
   if (wave == 0) {
     // ------------------------------------------------------------------ coder
@@ -240,16 +244,24 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       const int slot_i = q & (NSLOT - 1);
       const unsigned long long c0 = a.prof ? clock64() : 0ull;
       if (!TABLES && any && !stuck) {
-        for (int i = 0; i < NT && !stuck; ++i) {
-          uint32_t spins = 0;
-          while (lds_acquire(&s_done[slot_i][i]) != q) {
-            if (++spins > LDS_SPIN_LIMIT) {
-              stuck = true;
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
+        // all tiles' flags in one round of relaxed loads, then one acquire
+        uint32_t spins = 0;
+        for (;;) {
+          int n_ready = 0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int d = __hip_atomic_load(&s_done[slot_i][i], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+            n_ready += (i < NT && d == q) ? 1 : 0;
           }
+          if (n_ready == NT) break;
+          if (++spins > LDS_SPIN_LIMIT) {
+            stuck = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       }
       const unsigned long long c1 = a.prof ? clock64() : 0ull;
       if (any) {
@@ -329,6 +341,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
             be[4 * i + 2] = v4[2];
             be[4 * i + 3] = v4[3];
           }
+          if (a.prof) c_ld = clock64();
           int off = 0;
 #pragma unroll
           for (int it = 0; it < 4; ++it) {
@@ -360,6 +373,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           v = lo;
           c = Flo;
           f = Fhi - Flo;
+          if (a.prof) c_sr = clock64();
         }
         // f <= 2^16 - 255 and x >> 16 < 2^16: the 24-bit multiplier is exact
         if (act) x = __umul24(f, x >> 16) + slot - c;
@@ -380,6 +394,11 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         const unsigned long long c2 = clock64();
         t_wait += c1 - c0;
         t_busy += c2 - c1;
+        if (c_sr) {
+          t_load += c_ld - c1;
+          t_search += c_sr - c_ld;
+        }
+        c_ld = c_sr = 0;
       }
       // after the last block of step t, hand rows r1-2 and r1-1 to the next group
       if (j == J - 1 && lane == 0 && g + 1 < G) {
@@ -396,8 +415,11 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       if (any_bad || Pw != n_words || stuck) atomicMax(a.status, 3);
       if (timeout) atomicMax(a.status, 7);
       if (a.prof) {
-        a.prof[g * 8 + 0] = t_wait;
-        a.prof[g * 8 + 1] = t_busy;
+        a.prof[g * PROF_SLOTS + 0] = t_wait;
+        a.prof[g * PROF_SLOTS + 1] = t_busy;
+        a.prof[g * PROF_SLOTS + 8] = t_load;
+        a.prof[g * PROF_SLOTS + 9] = t_search;
+        a.prof[g * PROF_SLOTS + 10] = (unsigned long long)P;
       }
     }
   } else if (!TABLES) {
@@ -405,7 +427,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     // density waves: waves are placed on SIMDs round-robin, so wave 4 would
     // share the coder's SIMD; it stays idle and the coder keeps its SIMD
     if ((wave & 3) == 0) return;
-    const int nwork = NWORK;
+    constexpr int nwork = dec_workers<Net>();
     const int w = wave - 1 - (wave >> 2);
     Net net;
     net.load(m, lane);
@@ -413,7 +435,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     unsigned long long t_net = 0, t_head = 0, t_tab = 0, n_tiles = 0, c_net = 0, c_head = 0;
     bool timeout = s_flag != 0;
     bool stuck = false;
-    // tile tau = NT * q + ti of sub-round q = (t - t_first) * J + j, every NWORK-th
+    // tile tau = NT * q + ti of sub-round q = (t - t_first) * J + j, every nwork-th
     int q = 0, ti = w, t = t_first, j = 0;
     while (ti >= NT) {
       ti -= NT;
@@ -482,11 +504,11 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           a.img[(long long)y * W + xc - 1] = s_ring[(rr + 2) * 16 + ((xc - 1) & 15)];
         const f4 o = net.run(fk[0], fk[1], fk[2], s_w2);
         float* par = &s_par[slot_i][0];
-        if (valid) *reinterpret_cast<f4*>(&par[ln * PAR_STRIDE + 4 * q4]) = o;
         if (a.prof) {
           c_net = clock64();
           ++n_tiles;
         }
+        if (valid) *reinterpret_cast<f4*>(&par[ln * PAR_STRIDE + 4 * q4]) = o;
         // mixture head, one lane per pixel
         if (lane < 16 && valid) {
           float* pp = &par[ln * PAR_STRIDE];
@@ -547,19 +569,19 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       if (stuck) atomicMax(a.status, 3);
       if (timeout) atomicMax(a.status, 7);
       if (a.prof) {
-        atomicAdd(&a.prof[g * 8 + 2], t_wait);
-        atomicAdd(&a.prof[g * 8 + 3], t_busy);
-        atomicAdd(&a.prof[g * 8 + 4], t_net);
-        atomicAdd(&a.prof[g * 8 + 5], t_head);
-        atomicAdd(&a.prof[g * 8 + 6], t_tab);
-        atomicAdd(&a.prof[g * 8 + 7], n_tiles);
+        atomicAdd(&a.prof[g * PROF_SLOTS + 2], t_wait);
+        atomicAdd(&a.prof[g * PROF_SLOTS + 3], t_busy);
+        atomicAdd(&a.prof[g * PROF_SLOTS + 4], t_net);
+        atomicAdd(&a.prof[g * PROF_SLOTS + 5], t_head);
+        atomicAdd(&a.prof[g * PROF_SLOTS + 6], t_tab);
+        atomicAdd(&a.prof[g * PROF_SLOTS + 7], n_tiles);
       }
     }
   }
 }
 
 template <class Net, bool TABLES, bool SPLIT>
-__global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
+__global__ __launch_bounds__(dec_waves<Net>() * 64) void wavefront_decode_kernel(
     const Consts* __restrict__ K, DevModel m, DecArgs a) {
   decode_group<Net, TABLES, SPLIT>(K, m, a, blockIdx.x);
 }
@@ -569,7 +591,7 @@ __global__ __launch_bounds__(DEC_WAVES * 64) void wavefront_decode_kernel(
 // was taken earlier by a workgroup that is resident or done: the waits end.
 // The last group of an image to finish stamps the image's completion time.
 template <class Net, bool SPLIT>
-__global__ __launch_bounds__(DEC_WAVES * 64) void batch_decode_kernel(
+__global__ __launch_bounds__(dec_waves<Net>() * 64) void batch_decode_kernel(
     const Consts* __restrict__ K, DevModel m, BatchArgs b) {
   __shared__ int s_item;
   if (threadIdx.x == 0) s_item = (int)atomicAdd(b.ticket, 1u);
@@ -631,10 +653,10 @@ template <class Net>
 static void launch_batch_decode_t(const Consts* K, const DevModel& m, const BatchArgs& b,
                                   bool split, hipStream_t s) {
   if (split)
-    hipLaunchKernelGGL((batch_decode_kernel<Net, true>), dim3(b.n_items), dim3(DEC_WAVES * 64), 0,
+    hipLaunchKernelGGL((batch_decode_kernel<Net, true>), dim3(b.n_items), dim3(dec_waves<Net>() * 64), 0,
                        s, K, m, b);
   else
-    hipLaunchKernelGGL((batch_decode_kernel<Net, false>), dim3(b.n_items), dim3(DEC_WAVES * 64),
+    hipLaunchKernelGGL((batch_decode_kernel<Net, false>), dim3(b.n_items), dim3(dec_waves<Net>() * 64),
                        0, s, K, m, b);
 }
 
@@ -642,7 +664,7 @@ template <int H>
 static bool launch_batch_decode_h(int wtype, const Consts* K, const DevModel& m,
                                   const BatchArgs& b, bool split, hipStream_t s) {
   switch (wtype) {
-    case WT_F32: launch_batch_decode_t<NetF32<H, (H > 64 || DEC_F32_W2_LDS)>>(K, m, b, split, s); return true;
+    case WT_F32: launch_batch_decode_t<NetF32<H, (H >= 64)>>(K, m, b, split, s); return true;
     case WT_BF16:
       launch_batch_decode_t<NetBF16<H, WT_BF16, (H > 64)>>(K, m, b, split, s);
       return true;
@@ -666,10 +688,10 @@ bool launch_batch_decode(int wtype, int width, const Consts* K, const DevModel& 
 template <class Net, bool TB>
 static void launch_decode_t(const Consts* K, const DevModel& m, const DecArgs& a, hipStream_t s) {
   if (a.L <= 32)
-    hipLaunchKernelGGL((wavefront_decode_kernel<Net, TB, true>), dim3(a.G), dim3(DEC_WAVES * 64),
+    hipLaunchKernelGGL((wavefront_decode_kernel<Net, TB, true>), dim3(a.G), dim3(dec_waves<Net>() * 64),
                        0, s, K, m, a);
   else
-    hipLaunchKernelGGL((wavefront_decode_kernel<Net, TB, false>), dim3(a.G), dim3(DEC_WAVES * 64),
+    hipLaunchKernelGGL((wavefront_decode_kernel<Net, TB, false>), dim3(a.G), dim3(dec_waves<Net>() * 64),
                        0, s, K, m, a);
 }
 
@@ -679,7 +701,7 @@ template <int H>
 static bool launch_decode_h(int wtype, const Consts* K, const DevModel& m, const DecArgs& a,
                             hipStream_t s) {
   switch (wtype) {
-    case WT_F32: launch_decode_t<NetF32<H, (H > 64 || DEC_F32_W2_LDS)>, false>(K, m, a, s); return true;
+    case WT_F32: launch_decode_t<NetF32<H, (H >= 64)>, false>(K, m, a, s); return true;
     case WT_BF16: launch_decode_t<NetBF16<H, WT_BF16, (H > 64)>, false>(K, m, a, s); return true;
     case WT_FP8: launch_decode_t<NetBF16<H, WT_FP8, (H > 64)>, false>(K, m, a, s); return true;
     default: return false;

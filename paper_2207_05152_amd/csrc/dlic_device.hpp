@@ -124,6 +124,8 @@ template <int H, bool W2L = (H > 64)>
 struct NetF32 {
   static constexpr int NT = H / 16;
   static constexpr bool W2_LDS = W2L;
+  // few enough VGPRs for three decoder waves per SIMD
+  static constexpr bool DEC_WIDE = H <= 32 || (H == 64 && W2L);
   static constexpr int LDS_BYTES = W2_LDS ? NT * NT * 64 * 16 : 0;
   float a1[NT][3];
   float a2[W2_LDS ? 1 : NT][W2_LDS ? 1 : NT * 4];
@@ -236,6 +238,7 @@ struct NetBF16 {
   static constexpr int NT = H / 16, NK = H / 32;
   static constexpr bool W2_LDS = W2_LDS_;
   static constexpr bool SCALED = WT == WT_FP8;
+  static constexpr bool DEC_WIDE = H <= 64;
   static constexpr int LDS_BYTES = W2_LDS ? NT * NK * 64 * 16 : 0;
   bf16x8 a1[NT];
   bf16x8 a2[W2_LDS ? 1 : NT][W2_LDS ? 1 : NK];

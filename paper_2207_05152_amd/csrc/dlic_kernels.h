@@ -16,7 +16,6 @@ struct HeaderFields {
 // Decoder limits: rows per group, and the per-group stream ring in LDS.
 constexpr int DEC_RMAX = 256;
 constexpr int DEC_RING = 4096;
-constexpr int DEC_WAVES = 8;  // wave 0 codes; waves not on its SIMD compute densities
 
 struct DecArgs {
   const uint8_t* bits;

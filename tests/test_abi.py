@@ -112,3 +112,34 @@ def test_quantize_weights_rejects_bad_input():
                                      sc.ctypes.data) == dl.DLIC_ERR_ARG
     assert lib.dlic_quantize_weights(dl.DLIC_FP8_E4M3, np.ones(4, np.float32).ctypes.data, 4,
                                      out.ctypes.data, None) == dl.DLIC_ERR_ARG
+
+
+def test_device_entry_points_reject_bad_arguments_before_any_device_work():
+    # every check below happens on the host, before the library touches a
+    # device pointer (the dummies are never dereferenced)
+    lib = dl.lib()
+    P = 64  # a non-null dummy address
+    m = dl.dlic_model(12, 32, 32, 15, dl.DLIC_FP32, 0, P, P, P, P, P, P, None, 0)
+    c = dl.dlic_coder(1, 32)
+    ctypes_ = ctypes
+    enc = lambda h, w, mm, cc, cap=1 << 30, ws=1 << 30: lib.dlic_encode(
+        ctypes_.byref(mm), ctypes_.byref(cc), P, h, w, P, cap, P, P, ws, None)
+    dec = lambda h, w, mm, cc, n=1 << 20, ws=1 << 30: lib.dlic_decode(
+        ctypes_.byref(mm), ctypes_.byref(cc), P, n, P, h, w, P, P, ws, None)
+    assert enc(0, 5, m, c) == dl.DLIC_ERR_ARG            # empty image
+    assert enc(5, 0, m, c) == dl.DLIC_ERR_ARG
+    assert dec(0, 5, m, c) == dl.DLIC_ERR_ARG
+    assert enc(8, 8, m, dl.dlic_coder(1, 65)) == dl.DLIC_ERR_UNSUPPORTED   # lanes
+    assert enc(8, 8, m, dl.dlic_coder(5, 32)) == dl.DLIC_ERR_UNSUPPORTED   # rows per group < 2
+    assert enc(600, 8, m, dl.dlic_coder(2, 32)) == dl.DLIC_ERR_UNSUPPORTED  # 300 rows per group
+    assert enc(8, 8, m, c, cap=10) == dl.DLIC_ERR_CAPACITY
+    assert enc(8, 8, m, c, ws=10) == dl.DLIC_ERR_CAPACITY
+    assert dec(8, 8, m, c, ws=4) == dl.DLIC_ERR_CAPACITY
+    bad = dl.dlic_model(12, 48, 48, 15, dl.DLIC_FP32, 0, P, P, P, P, P, P, None, 0)
+    assert enc(8, 8, bad, c) == dl.DLIC_ERR_UNSUPPORTED  # width 48
+    bad = dl.dlic_model(12, 32, 32, 15, dl.DLIC_FP8_E4M3, 0, P, P, P, P, P, P, None, 0)
+    assert enc(8, 8, bad, c) == dl.DLIC_ERR_ARG          # FP8 without scales
+    bad = dl.dlic_model(12, 32, 32, 15, 9, 0, P, P, P, P, P, P, None, 0)
+    assert enc(8, 8, bad, c) == dl.DLIC_ERR_UNSUPPORTED  # unknown dtype
+    bad = dl.dlic_model(11, 32, 32, 15, dl.DLIC_FP32, 0, P, P, P, P, P, P, None, 0)
+    assert enc(8, 8, bad, c) == dl.DLIC_ERR_ARG          # window size
