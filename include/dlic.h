@@ -56,8 +56,9 @@ typedef enum {
 typedef enum {
   DLIC_FP32 = 0,
   DLIC_BF16 = 1,
-  DLIC_FP8_E4M3 = 2,
-  DLIC_FP64 = 3 /* training entry points only (gradient checks) */
+  DLIC_FP8_E4M3 = 2, /* e4m3 weights, BF16 activations (W8A16)              */
+  DLIC_FP64 = 3,     /* training entry points only (gradient checks)       */
+  DLIC_FP8_W8A8 = 4  /* e4m3 weights and activations on the FP8 MFMA       */
 } dlic_dtype;
 
 /* Network weights (Section II-B, Neural Network Architecture; the mixture
@@ -76,7 +77,9 @@ typedef struct dlic_model {
   const void *d_w2;      /* [h2][h1]                                        */
   const void *d_w3;      /* [15][h2]                                        */
   const float *d_b1, *d_b2, *d_b3;
-  const float *d_wscale; /* FP8: 3 per-layer scales (device); otherwise NULL */
+  const float *d_wscale; /* FP8_E4M3: 3 per-layer weight scales; FP8_W8A8:
+                            those 3, then the 3 activation multipliers
+                            (device); otherwise NULL                        */
   uint64_t fingerprint;  /* dlic_fnv1a64 over W1,b1,W2,b2,W3,b3 bytes (then
                             the 3 scales for FP8)                          */
 } dlic_model;
@@ -123,6 +126,14 @@ void dlic_host_constants(float *h_S, float *h_D, float *h_beta, float *h_scale);
  * b1, W2, b2, W3, b3 in that order, then for FP8 the three scales. */
 dlic_status dlic_quantize_weights(int32_t dtype, const float *h_w, size_t n, void *h_out,
                                   float *h_scale);
+
+/* Activation multipliers of the W8A8 net: m_l = 2^floor(log2(448 / amax_l))
+ * for each of the 3 layer inputs (1 where amax_l <= 0), so that the largest
+ * input times m_l fits the e4m3 range exactly; the net rounds m_l * a to
+ * e4m3 and rescales the layer's accumulator by s_l / m_l (exact).  The
+ * inputs of layer 1 are the scaled grey levels, amax_1 = 1; amax_2 and
+ * amax_3 come from dlic_activation_range on calibration images.  Host only. */
+dlic_status dlic_w8a8_multipliers(const float *h_amax, float *h_mult);
 
 /* Worst-case stream size in bytes for an h x w image: header, word counts,
  * at most one 16-bit word per pixel and the flushed states. */
@@ -188,6 +199,13 @@ void dlic_set_spin_limit(uint32_t polls);
 dlic_status dlic_density(const dlic_model *model, const uint8_t *d_img, int32_t h, int32_t w,
                          float *d_out15, uint32_t *d_cf, uint32_t *d_tables,
                          hipStream_t stream);
+
+/* Calibration for the W8A8 net: runs the FP32 network (model->dtype must be
+ * DLIC_FP32) on every pixel of an image and folds the largest layer-1 and
+ * layer-2 activations into d_amax[0], d_amax[1] (device FP32, atomic
+ * maximum: clear them before the first image). */
+dlic_status dlic_activation_range(const dlic_model *model, const uint8_t *d_img, int32_t h,
+                                  int32_t w, float *d_amax, hipStream_t stream);
 
 /* rANS-only encode (Section II-B, rANS) of caller-given intervals:
  * d_cf [h][w] u32 holds c | (f - 1) << 16 for each pixel (c + f <= 2^16,

@@ -12,6 +12,9 @@ what those forms compute, in FP64 apart from the roundings that define them:
   * FP8 e4m3 weights with one FP32 scale per layer: scale = max|W| / 448 in
     FP32, codes = e4m3(W / scale) (quotient in FP32, round to nearest even,
     saturating at +-448); activations as for BF16; z = scale (Q a) + b.
+  * W8A8: those weights, and each layer input rounded to e4m3 after
+    multiplying by a power of two m (the largest with max|a| m <= 448 on
+    calibration data); z = (scale / m) (Q a_q) + b.
 
 Readings (listed with the others in the design notes): the scale rule, the
 order scale-then-bias, and e4m3 as the OCP "FN" variant (no infinities,
@@ -97,18 +100,35 @@ def quantize_matrix(W, dtype: str):
     raise ValueError(dtype)
 
 
-def quantize_weights(weights: dict, dtype: str) -> dict:
+def w8a8_multiplier(amax: float) -> np.float32:
+    """Power-of-two multiplier 2^k with the largest k such that amax * 2^k <= 448
+    (1 for amax <= 0)."""
+    if not amax > 0:
+        return np.float32(1.0)
+    k = 0
+    while amax * 2.0 ** k > 448.0:
+        k -= 1
+    while amax * 2.0 ** (k + 1) <= 448.0:
+        k += 1
+    return np.float32(2.0 ** k)
+
+
+def quantize_weights(weights: dict, dtype: str, act_max=None) -> dict:
     """Stored model: {'W1','W2','W3': stored matrices, 'b*': FP32 biases,
-    'scales': three FP32 scales, 'dtype': dtype}."""
+    'scales': three FP32 scales, 'dtype': dtype}; for 'fp8a8' also 'mults',
+    the activation multipliers of the three layer inputs from their largest
+    values act_max (the first is the grey-level range, 1)."""
     out = {"dtype": dtype}
     scales = []
     for k in ("W1", "W2", "W3"):
-        stored, s = quantize_matrix(weights[k], dtype)
+        stored, s = quantize_matrix(weights[k], "fp8" if dtype == "fp8a8" else dtype)
         out[k] = stored
         scales.append(s)
     for k in ("b1", "b2", "b3"):
         out[k] = np.asarray(weights[k], dtype=np.float32)
     out["scales"] = np.array(scales, dtype=np.float32)
+    if dtype == "fp8a8":
+        out["mults"] = np.array([w8a8_multiplier(float(a)) for a in act_max], dtype=np.float32)
     return out
 
 
@@ -125,7 +145,7 @@ def effective_weights(qm: dict) -> dict:
     with its FP32 biases; used to evaluate the dtype's network in FP64."""
     out = {}
     for i, k in enumerate(("W1", "W2", "W3")):
-        out[k] = stored_values(qm, k) * (float(qm["scales"][i]) if qm["dtype"] == "fp8" else 1.0)
+        out[k] = stored_values(qm, k) * (float(qm["scales"][i]) if qm["dtype"] != "bf16" else 1.0)
     for k in ("b1", "b2", "b3"):
         out[k] = qm[k].astype(np.float64)
     return out
@@ -133,8 +153,11 @@ def effective_weights(qm: dict) -> dict:
 
 def mlp_forward_lowp(feats, qm: dict) -> np.ndarray:
     """Network outputs of the reduced-precision form, FP64 apart from the
-    BF16 roundings of inputs and hidden activations.  feats: (n, 12) FP64
-    (or FP32) scaled window values; returns (n, 15) FP64."""
+    roundings of inputs and hidden activations (BF16, or e4m3 after the
+    layer's multiplier for 'fp8a8').  feats: (n, 12) FP64 (or FP32) scaled
+    window values; returns (n, 15) FP64."""
+    if qm["dtype"] == "fp8a8":
+        return _forward_w8a8(feats, qm)
     a = round_bf16(np.asarray(feats, dtype=np.float32)).astype(np.float64)
     fp8 = qm["dtype"] == "fp8"
     layers = (("W1", "b1"), ("W2", "b2"), ("W3", "b3"))
@@ -149,6 +172,22 @@ def mlp_forward_lowp(feats, qm: dict) -> np.ndarray:
     raise AssertionError
 
 
+def _forward_w8a8(feats, qm: dict) -> np.ndarray:
+    """W8A8: layer input a -> e4m3(RN32(a) * m) (m a power of two, so the
+    product is exact), z = (s / m) (Q a_q) + b with FP32 s / m (exact)."""
+    a = np.asarray(feats, dtype=np.float32).astype(np.float64)
+    for li, (wk, bk) in enumerate((("W1", "b1"), ("W2", "b2"), ("W3", "b3"))):
+        m = float(qm["mults"][li])
+        aq = e4m3_value(e4m3_encode((a.astype(np.float32) * np.float32(m)).astype(np.float32)))
+        W = stored_values(qm, wk)
+        d = float(np.float32(qm["scales"][li]) / np.float32(m))
+        z = d * (aq @ W.T) + qm[bk].astype(np.float64)
+        if li == 2:
+            return z
+        a = np.maximum(z, 0.0)
+    raise AssertionError
+
+
 def stored_fingerprint(qm: dict) -> int:
     """Model fingerprint of a stored model: FNV-1a 64 over the bytes of W1,
     b1, W2, b2, W3, b3 as stored, then the three scales for FP8."""
@@ -156,4 +195,6 @@ def stored_fingerprint(qm: dict) -> int:
     arrays = [qm[k] for k in ("W1", "b1", "W2", "b2", "W3", "b3")]
     if qm["dtype"] == "fp8":
         arrays.append(qm["scales"])
+    if qm["dtype"] == "fp8a8":
+        arrays.append(np.concatenate([qm["scales"], qm["mults"]]).astype(np.float32))
     return fingerprint(arrays)

@@ -22,13 +22,14 @@ LIB_PATH = os.environ.get("DLIC_LIB") or os.path.join(_HERE, "libdlic.so")
 
 DLIC_OK, DLIC_ERR_ARG, DLIC_ERR_CAPACITY, DLIC_ERR_CORRUPT = 0, 1, 2, 3
 DLIC_ERR_MODEL_MISMATCH, DLIC_ERR_UNSUPPORTED, DLIC_ERR_HIP, DLIC_ERR_TIMEOUT = 4, 5, 6, 7
-DLIC_FP32, DLIC_BF16, DLIC_FP8_E4M3, DLIC_FP64 = 0, 1, 2, 3
+DLIC_FP32, DLIC_BF16, DLIC_FP8_E4M3, DLIC_FP64, DLIC_FP8_W8A8 = 0, 1, 2, 3, 4
 FNV_OFFSET = 0xCBF29CE484222325
 HEADER_BYTES = 36
 
 # Every symbol include/dlic.h declares.
 EXPORTS = (
     "dlic_status_string", "dlic_fnv1a64", "dlic_host_constants", "dlic_quantize_weights",
+    "dlic_w8a8_multipliers", "dlic_activation_range",
     "dlic_encode_bound",
     "dlic_encode_workspace", "dlic_decode_workspace", "dlic_peek_header", "dlic_init",
     "dlic_encode", "dlic_decode", "dlic_set_spin_limit", "dlic_density",
@@ -74,6 +75,8 @@ def lib():
         "dlic_fnv1a64": (c_uint64, [c_uint64, P, S]),
         "dlic_host_constants": (None, [P, P, P, P]),
         "dlic_quantize_weights": (c_int, [c_int32, P, S, P, P]),
+        "dlic_w8a8_multipliers": (c_int, [P, P]),
+        "dlic_activation_range": (c_int, [POINTER(dlic_model), P, c_int32, c_int32, P, P]),
         "dlic_encode_bound": (S, [c_int32, c_int32, POINTER(dlic_coder)]),
         "dlic_encode_workspace": (S, [c_int32, c_int32, POINTER(dlic_coder)]),
         "dlic_decode_workspace": (S, [c_int32, c_int32, POINTER(dlic_coder)]),
@@ -158,6 +161,18 @@ def dlic_quantize_weights(dtype: int, w) -> tuple:
     _check(lib().dlic_quantize_weights(dtype, a.ctypes.data, a.size, out.ctypes.data,
                                        sc.ctypes.data), "dlic_quantize_weights")
     return out, np.float32(sc[0])
+
+
+def dlic_w8a8_multipliers(amax) -> np.ndarray:
+    a = np.ascontiguousarray(amax, dtype=np.float32)
+    out = np.zeros(3, np.float32)
+    _check(lib().dlic_w8a8_multipliers(a.ctypes.data, out.ctypes.data), "dlic_w8a8_multipliers")
+    return out
+
+
+def dlic_activation_range(model: dlic_model, d_img, h, w, d_amax, stream=None):
+    _check(lib().dlic_activation_range(ctypes.byref(model), _ptr(d_img), h, w, _ptr(d_amax),
+                                       _stream(stream)), "dlic_activation_range")
 
 
 def dlic_host_constants():
@@ -259,7 +274,7 @@ def default_coder(h: int, lanes: int = 32, rows_per_group: int = 192) -> dlic_co
     return dlic_coder(g, lanes)
 
 
-DTYPES = {"fp32": DLIC_FP32, "bf16": DLIC_BF16, "fp8": DLIC_FP8_E4M3}
+DTYPES = {"fp32": DLIC_FP32, "bf16": DLIC_BF16, "fp8": DLIC_FP8_E4M3, "fp8a8": DLIC_FP8_W8A8}
 
 
 class Model:
@@ -268,7 +283,7 @@ class Model:
     dtype 'fp32' keeps the FP32 matrices; 'bf16' and 'fp8' store them as the
     library's dlic_quantize_weights converts them (biases stay FP32)."""
 
-    def __init__(self, weights: dict, device="cuda", dtype: str = "fp32"):
+    def __init__(self, weights: dict, device="cuda", dtype: str = "fp32", calibration=None):
         import torch
         code = DTYPES[dtype]
         self.dtype = dtype
@@ -279,24 +294,39 @@ class Model:
             if code == DLIC_FP32:
                 self.np[k], s = w32, np.float32(1.0)
             else:
-                self.np[k], s = dlic_quantize_weights(code, w32)
+                self.np[k], s = dlic_quantize_weights(
+                    DLIC_FP8_E4M3 if code == DLIC_FP8_W8A8 else code, w32)
             scales.append(s)
         for k in ("b1", "b2", "b3"):
             self.np[k] = np.ascontiguousarray(weights[k], dtype=np.float32)
+        self.act_max = None
+        if code == DLIC_FP8_W8A8:
+            # activation multipliers from the FP32 net's ranges on calibration images
+            if not calibration:
+                raise ValueError("dtype 'fp8a8' needs calibration images")
+            ref = Model(weights, device)
+            amax = torch.zeros(2, dtype=torch.float32, device=device)
+            for im in calibration:
+                t = im if isinstance(im, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(im))
+                t = t.to(device)
+                dlic_activation_range(ref.c, t.contiguous(), t.shape[0], t.shape[1], amax)
+            self.act_max = np.concatenate([[1.0], amax.cpu().numpy()]).astype(np.float32)
+            scales += list(dlic_w8a8_multipliers(self.act_max))
         self.scales = np.array(scales, dtype=np.float32)
         self.t = {k: torch.from_numpy(v).to(device) for k, v in self.np.items()}
         self.t_scales = torch.from_numpy(self.scales).to(device)
         h = FNV_OFFSET
         for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
             h = dlic_fnv1a64(h, self.np[k].tobytes())
-        if code == DLIC_FP8_E4M3:
+        if code in (DLIC_FP8_E4M3, DLIC_FP8_W8A8):
             h = dlic_fnv1a64(h, self.scales.tobytes())
         self.fingerprint = h
         h1, h2 = self.np["W1"].shape[0], self.np["W2"].shape[0]
         self.c = dlic_model(12, h1, h2, 15, code, 0, _ptr(self.t["W1"]), _ptr(self.t["W2"]),
                             _ptr(self.t["W3"]), _ptr(self.t["b1"]), _ptr(self.t["b2"]),
                             _ptr(self.t["b3"]),
-                            _ptr(self.t_scales) if code == DLIC_FP8_E4M3 else None, h)
+                            _ptr(self.t_scales) if code in (DLIC_FP8_E4M3, DLIC_FP8_W8A8)
+                            else None, h)
 
 
 def _empty(n, dtype, device="cuda"):

@@ -145,9 +145,11 @@ dlic_status model_ok(const dlic_model* m) {
   if (!m) return DLIC_ERR_ARG;
   if (m->k_in != K_IN || m->n_out != N_OUT || m->reserved != 0) return DLIC_ERR_ARG;
   if (!m->d_w1 || !m->d_w2 || !m->d_w3 || !m->d_b1 || !m->d_b2 || !m->d_b3) return DLIC_ERR_ARG;
-  if (m->dtype != DLIC_FP32 && m->dtype != DLIC_BF16 && m->dtype != DLIC_FP8_E4M3)
+  if (m->dtype != DLIC_FP32 && m->dtype != DLIC_BF16 && m->dtype != DLIC_FP8_E4M3 &&
+      m->dtype != DLIC_FP8_W8A8)
     return DLIC_ERR_UNSUPPORTED;
-  if (m->dtype == DLIC_FP8_E4M3 && !m->d_wscale) return DLIC_ERR_ARG;
+  if ((m->dtype == DLIC_FP8_E4M3 || m->dtype == DLIC_FP8_W8A8) && !m->d_wscale)
+    return DLIC_ERR_ARG;
   if (m->h1 != m->h2 || (m->h1 != 32 && m->h1 != 64 && m->h1 != 128))
     return DLIC_ERR_UNSUPPORTED;
   return DLIC_OK;
@@ -157,6 +159,7 @@ int weight_type(const dlic_model* m) {
   switch (m->dtype) {
     case DLIC_BF16: return WT_BF16;
     case DLIC_FP8_E4M3: return WT_FP8;
+    case DLIC_FP8_W8A8: return WT_FP8A8;
     default: return WT_F32;
   }
 }
@@ -169,7 +172,7 @@ DevModel dev_model(const dlic_model* m) {
   d.b1 = m->d_b1;
   d.b2 = m->d_b2;
   d.b3 = m->d_b3;
-  d.wscale = m->dtype == DLIC_FP8_E4M3 ? m->d_wscale : nullptr;
+  d.wscale = (m->dtype == DLIC_FP8_E4M3 || m->dtype == DLIC_FP8_W8A8) ? m->d_wscale : nullptr;
   return d;
 }
 
@@ -408,6 +411,25 @@ dlic_status dlic_quantize_weights(int32_t dtype, const float* h_w, size_t n, voi
   return DLIC_OK;
 }
 
+dlic_status dlic_w8a8_multipliers(const float* h_amax, float* h_mult) {
+  if (!h_amax || !h_mult) return DLIC_ERR_ARG;
+  for (int l = 0; l < 3; ++l) {
+    const float a = h_amax[l];
+    if (!(a > 0.0f) || !isfinite(a)) {
+      h_mult[l] = 1.0f;
+      continue;
+    }
+    int k = (int)floor(log2(448.0 / (double)a));
+    // floor(log2) of a quotient can land one off at exact powers of two
+    while (ldexp((double)a, k) > 448.0) --k;
+    while (ldexp((double)a, k + 1) <= 448.0) ++k;
+    if (k > 100) k = 100;
+    if (k < -100) k = -100;
+    h_mult[l] = (float)ldexp(1.0, k);
+  }
+  return DLIC_OK;
+}
+
 size_t dlic_encode_bound(int32_t h, int32_t w, const dlic_coder* coder) {
   if (h <= 0 || w <= 0 || !coder_ok(h, coder)) return 0;
   const size_t G = coder->groups, L = coder->lanes_per_group;
@@ -470,6 +492,23 @@ dlic_status dlic_encode(const dlic_model* model, const dlic_coder* coder, const 
   if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
   HeaderFields hf{model->dtype, model->h1, model->h2, model->fingerprint};
   return run_rans_and_pack(h, w, coder, ws.cf, ws, hf, d_out, d_out_len, stream);
+}
+
+dlic_status dlic_activation_range(const dlic_model* model, const uint8_t* d_img, int32_t h,
+                                  int32_t w, float* d_amax, hipStream_t stream) {
+  timing_reset();
+  if (!d_img || !d_amax || h <= 0 || w <= 0) return DLIC_ERR_ARG;
+  dlic_status rc = model_ok(model);
+  if (rc != DLIC_OK) return rc;
+  if (model->dtype != DLIC_FP32) return DLIC_ERR_ARG;
+  const Consts* K = nullptr;
+  if ((rc = current_consts(&K)) != DLIC_OK) return rc;
+  timing_begin("activation_range_kernel", stream);
+  if (!launch_activation_range(model->h1, K, dev_model(model), d_img, h, w, d_amax,
+                               density_grid((long long)h * w), stream))
+    return DLIC_ERR_UNSUPPORTED;
+  timing_end(stream);
+  return launch_ok();
 }
 
 dlic_status dlic_rans_encode_cf(const dlic_coder* coder, int32_t h, int32_t w,

@@ -671,6 +671,7 @@ static bool launch_batch_decode_h(int wtype, const Consts* K, const DevModel& m,
     case WT_FP8:
       launch_batch_decode_t<NetBF16<H, WT_FP8, (H > 64)>>(K, m, b, split, s);
       return true;
+    case WT_FP8A8: launch_batch_decode_t<NetFP8A<H, (H > 64)>>(K, m, b, split, s); return true;
     default: return false;
   }
 }
@@ -704,6 +705,7 @@ static bool launch_decode_h(int wtype, const Consts* K, const DevModel& m, const
     case WT_F32: launch_decode_t<NetF32<H, (H >= 64)>, false>(K, m, a, s); return true;
     case WT_BF16: launch_decode_t<NetBF16<H, WT_BF16, (H > 64)>, false>(K, m, a, s); return true;
     case WT_FP8: launch_decode_t<NetBF16<H, WT_FP8, (H > 64)>, false>(K, m, a, s); return true;
+    case WT_FP8A8: launch_decode_t<NetFP8A<H, (H > 64)>, false>(K, m, a, s); return true;
     default: return false;
   }
 }

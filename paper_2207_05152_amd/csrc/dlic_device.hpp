@@ -63,6 +63,18 @@ __device__ __forceinline__ f4 mfma_bf16(bf16x8 a, bf16x8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// The same shape with OCP e4m3 operands: byte e of a lane's 64-bit A and B
+// is element 8*(l/16) + e, as for mfma_bf16.
+__device__ __forceinline__ f4 mfma_fp8(long a, long b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+}
+
+// e4m3 codes of two FP32 values (nearest even, saturating at +-448) in the
+// low two bytes.
+__device__ __forceinline__ uint32_t cvt_e4m3x2(float a, float b) {
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xFFFFu;
+}
+
 // Causal window offset of feature k (rows y-2, y-1 at dx -2..2, then (y, x-2), (y, x-1)).
 __device__ __forceinline__ int nb_dy(int k) { return k < 5 ? -2 : (k < 10 ? -1 : 0); }
 __device__ __forceinline__ int nb_dx(int k) { return k < 5 ? k - 2 : (k < 10 ? k - 7 : k - 12); }
@@ -70,7 +82,7 @@ __device__ __forceinline__ int nb_dx(int k) { return k < 5 ? k - 2 : (k < 10 ? k
 __device__ __forceinline__ float relu(float v) { return v > 0.0f ? v : 0.0f; }
 
 // Storage types of the weight matrices.
-enum WeightType { WT_F32 = 0, WT_BF16 = 1, WT_FP8 = 2 };
+enum WeightType { WT_F32 = 0, WT_BF16 = 1, WT_FP8 = 2, WT_FP8A8 = 4 };
 
 // OCP e4m3 (FN) code -> BF16 bit pattern: bias 7, 3 mantissa bits,
 // subnormal step 2^-9; every code is exact in BF16 (exponent bias 127).
@@ -215,6 +227,45 @@ struct NetF32 {
 #pragma unroll
       for (int r = 0; r < 4; ++r) o = mfma_f32(a3[n2 * 4 + r], h2[n2][r], o);
     return o;
+  }
+
+  // Largest hidden activation of each layer among this lane's values (the
+  // ranges that the FP8-activation net's multipliers are chosen from).
+  __device__ __forceinline__ void hidden_max(float f0, float f1, float f2, const void* lds,
+                                             float& mx1, float& mx2) const {
+    f4 h1[NT];
+    mx1 = 0.0f;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      f4 acc = {c1[nt][0], c1[nt][1], c1[nt][2], c1[nt][3]};
+      acc = mfma_f32(a1[nt][0], f0, acc);
+      acc = mfma_f32(a1[nt][1], f1, acc);
+      acc = mfma_f32(a1[nt][2], f2, acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        h1[nt][r] = relu(acc[r]);
+        mx1 = fmaxf(mx1, h1[nt][r]);
+      }
+    }
+    mx2 = 0.0f;
+    const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+#pragma unroll
+    for (int n2 = 0; n2 < NT; ++n2) {
+      f4 acc = {c2[n2][0], c2[n2][1], c2[n2][2], c2[n2][3]};
+#pragma unroll
+      for (int n1 = 0; n1 < NT; ++n1) {
+        f4 w;
+        if constexpr (W2_LDS) {
+          w = ((const f4*)lds)[(n2 * NT + n1) * 64 + lane];
+        } else {
+          w = f4{a2[n2][n1 * 4], a2[n2][n1 * 4 + 1], a2[n2][n1 * 4 + 2], a2[n2][n1 * 4 + 3]};
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc = mfma_f32(w[r], h1[n1][r], acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) mx2 = fmaxf(mx2, relu(acc[r]));
+    }
   }
 };
 
@@ -363,6 +414,139 @@ struct NetBF16 {
     f4 o;
 #pragma unroll
     for (int r = 0; r < 4; ++r) o[r] = finish(acc[r], s3, c3[r]);
+    return o;
+  }
+};
+
+// FP8 weights and FP8 activations (W8A8) on v_mfma_f32_16x16x32_fp8_fp8.
+// Weights are e4m3 codes with one FP32 scale s_l per layer; the input of
+// layer l is multiplied by a power of two m_l (exact) and rounded to e4m3, so
+// z = (s_l / m_l) * (Q_l a_q) + b with s_l / m_l exact as well.  The K slots
+// are those of NetBF16.  wscale holds s_1, s_2, s_3, m_1, m_2, m_3.
+template <int H, bool W2_LDS_>
+struct NetFP8A {
+  static constexpr int NT = H / 16, NK = H / 32;
+  static constexpr bool W2_LDS = W2_LDS_;
+  static constexpr bool DEC_WIDE = H <= 64;
+  static constexpr int LDS_BYTES = W2_LDS ? NT * NK * 64 * 8 : 0;
+  long a1[NT];
+  long a2[W2_LDS ? 1 : NT][W2_LDS ? 1 : NK];
+  long a3[NK];
+  float c1[NT][4], c2[NT][4], c3[4];
+  float d1, d2, d3, m1, m2, m3;
+
+  __device__ __forceinline__ static int slot_neuron(int s, int q, int e) {
+    return 32 * s + 16 * (e >> 2) + 4 * q + (e & 3);
+  }
+  __device__ __forceinline__ static long w8(const void* p, long idx) {
+    return (long)((const uint8_t*)p)[idx];
+  }
+
+  // LDS order: 64-bit word (n2 * NK + s) * 64 + lane.
+  __device__ __forceinline__ static void stage(const DevModel& m, void* lds, int t, int n) {
+    if constexpr (W2_LDS) {
+      uint8_t* d = (uint8_t*)lds;
+      for (int idx = t; idx < NT * NK * 512; idx += n) {
+        const int e = idx & 7, lane = (idx >> 3) & 63, blk = idx >> 9;
+        const int n2 = blk / NK, s = blk - n2 * NK;
+        d[idx] = ((const uint8_t*)m.w2)[(16 * n2 + (lane & 15)) * H + slot_neuron(s, lane >> 4, e)];
+      }
+    }
+  }
+
+  __device__ __forceinline__ void load(const DevModel& m, int lane) {
+    const int i = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      long v = 0;
+#pragma unroll
+      for (int e = 0; e < 3; ++e) v |= w8(m.w1, (16 * nt + i) * K_IN + 4 * e + q) << (8 * e);
+      a1[nt] = v;
+    }
+    if constexpr (!W2_LDS) {
+#pragma unroll
+      for (int n2 = 0; n2 < NT; ++n2)
+#pragma unroll
+        for (int s = 0; s < NK; ++s) {
+          long v = 0;
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            v |= w8(m.w2, (16 * n2 + i) * H + slot_neuron(s, q, e)) << (8 * e);
+          a2[n2][s] = v;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+      long v = 0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (i < N_OUT) v |= w8(m.w3, i * H + slot_neuron(s, q, e)) << (8 * e);
+      a3[s] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        c1[nt][r] = m.b1[16 * nt + 4 * q + r];
+        c2[nt][r] = m.b2[16 * nt + 4 * q + r];
+      }
+      c3[r] = (4 * q + r < N_OUT) ? m.b3[4 * q + r] : 0.0f;
+    }
+    m1 = m.wscale[3];
+    m2 = m.wscale[4];
+    m3 = m.wscale[5];
+    d1 = m.wscale[0] / m1;  // exact: m is a power of two
+    d2 = m.wscale[1] / m2;
+    d3 = m.wscale[2] / m3;
+  }
+
+  // e4m3 codes of 8 activations (two tiles' D registers) times the layer's
+  // power-of-two multiplier, in the K-slot order of slot_neuron.
+  __device__ __forceinline__ static long pack8(const float* lo, const float* hi, float mul) {
+    const uint32_t w0 = cvt_e4m3x2(lo[0] * mul, lo[1] * mul) | (cvt_e4m3x2(lo[2] * mul, lo[3] * mul) << 16);
+    const uint32_t w1 = cvt_e4m3x2(hi[0] * mul, hi[1] * mul) | (cvt_e4m3x2(hi[2] * mul, hi[3] * mul) << 16);
+    return (long)((uint64_t)w0 | ((uint64_t)w1 << 32));
+  }
+
+  __device__ __forceinline__ f4 run(float f0, float f1, float f2, const void* lds) const {
+    const long x = (long)(cvt_e4m3x2(f0 * m1, f1 * m1) | (cvt_e4m3x2(f2 * m1, 0.0f) << 16));
+    float h1[NT][4];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const f4 acc = mfma_fp8(a1[nt], x, f4{0.0f, 0.0f, 0.0f, 0.0f});
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h1[nt][r] = relu(acc[r] * d1 + c1[nt][r]);
+    }
+    long b1[NK];
+#pragma unroll
+    for (int s = 0; s < NK; ++s) b1[s] = pack8(h1[2 * s], h1[2 * s + 1], m2);
+    float h2[NT][4];
+    const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+#pragma unroll
+    for (int n2 = 0; n2 < NT; ++n2) {
+      f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int s = 0; s < NK; ++s) {
+        long w;
+        if constexpr (W2_LDS) {
+          w = ((const long*)lds)[(n2 * NK + s) * 64 + lane];
+        } else {
+          w = a2[n2][s];
+        }
+        acc = mfma_fp8(w, b1[s], acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h2[n2][r] = relu(acc[r] * d2 + c2[n2][r]);
+    }
+    long b2[NK];
+#pragma unroll
+    for (int s = 0; s < NK; ++s) b2[s] = pack8(h2[2 * s], h2[2 * s + 1], m3);
+    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < NK; ++s) acc = mfma_fp8(a3[s], b2[s], acc);
+    f4 o;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[r] = acc[r] * d3 + c3[r];
     return o;
   }
 };

@@ -135,6 +135,64 @@ __global__ __launch_bounds__(256) void batch_density_kernel(const Consts* __rest
   }
 }
 
+// Largest hidden activations of the FP32 net over every pixel of an image:
+// amax[0] (layer 1) and amax[1] (layer 2), non-negative after ReLU, so their
+// bit patterns order like unsigned integers.
+template <int H>
+__global__ __launch_bounds__(256) void activation_range_kernel(const Consts* __restrict__ K,
+                                                               DevModel m,
+                                                               const uint8_t* __restrict__ img,
+                                                               int Hh, int W, float* amax) {
+  using Net = NetF32<H, (H > 64)>;
+  __shared__ DensityLds<Net> S;
+  Net net;
+  density_prologue(K, m, S, net);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4;
+  const long long n = (long long)Hh * W;
+  float mx1 = 0.0f, mx2 = 0.0f;
+  for (long long blk = blockIdx.x; blk * 256 < n; blk += gridDim.x) {
+#pragma unroll 1
+    for (int tile = 0; tile < 4; ++tile) {
+      const long long p = blk * 256 + wave * 64 + tile * 16 + (lane & 15);
+      float fk[3] = {0.0f, 0.0f, 0.0f};
+      if (p < n) {
+        const int y = (int)(p / W), x = (int)(p - (long long)y * W);
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+          const int k = 4 * kk + q;
+          const int yy = y + nb_dy(k), xx = x + nb_dx(k);
+          if (yy >= 0 && xx >= 0 && xx < W) fk[kk] = S.scale[img[(long long)yy * W + xx]];
+        }
+      }
+      float a1, a2;
+      net.hidden_max(fk[0], fk[1], fk[2], S.w2, a1, a2);
+      // lanes past the last pixel ran the all-dummy window: leave them out
+      if (p < n) {
+        mx1 = fmaxf(mx1, a1);
+        mx2 = fmaxf(mx2, a2);
+      }
+    }
+  }
+  atomicMax((unsigned*)&amax[0], __float_as_uint(mx1));
+  atomicMax((unsigned*)&amax[1], __float_as_uint(mx2));
+}
+
+bool launch_activation_range(int width, const Consts* K, const DevModel& m, const uint8_t* img,
+                             int H, int W, float* amax, int grid, hipStream_t s) {
+  switch (width) {
+    case 32:
+      hipLaunchKernelGGL(activation_range_kernel<32>, dim3(grid), dim3(256), 0, s, K, m, img, H, W, amax);
+      return true;
+    case 64:
+      hipLaunchKernelGGL(activation_range_kernel<64>, dim3(grid), dim3(256), 0, s, K, m, img, H, W, amax);
+      return true;
+    case 128:
+      hipLaunchKernelGGL(activation_range_kernel<128>, dim3(grid), dim3(256), 0, s, K, m, img, H, W, amax);
+      return true;
+    default: return false;
+  }
+}
+
 constexpr int ENC_CHUNK = 32;   // wavefront steps staged in LDS per chunk
 constexpr int ENC_BATCH = 8;    // sub-rounds read from LDS ahead of coding
 constexpr int ENC_STAGERS = 192;  // threads of waves 1..3
@@ -355,6 +413,9 @@ static bool launch_density_h(int wtype, const Consts* K, const DevModel& m, cons
     case WT_FP8:
       launch_density_t<NetBF16<H, WT_FP8, false>>(K, m, img, Hh, W, cf, out15, tables, grid, s);
       return true;
+    case WT_FP8A8:
+      launch_density_t<NetFP8A<H, false>>(K, m, img, Hh, W, cf, out15, tables, grid, s);
+      return true;
     default: return false;
   }
 }
@@ -383,6 +444,7 @@ static bool launch_batch_density_h(int wtype, const Consts* K, const DevModel& m
     case WT_F32: launch_batch_density_t<NetF32<H>>(K, m, b, grid, s); return true;
     case WT_BF16: launch_batch_density_t<NetBF16<H, WT_BF16, false>>(K, m, b, grid, s); return true;
     case WT_FP8: launch_batch_density_t<NetBF16<H, WT_FP8, false>>(K, m, b, grid, s); return true;
+    case WT_FP8A8: launch_batch_density_t<NetFP8A<H, false>>(K, m, b, grid, s); return true;
     default: return false;
   }
 }

@@ -76,6 +76,10 @@ struct BatchArgs {
 bool launch_density(int wtype, int width, const Consts* K, const DevModel& m, const uint8_t* img,
                     int H, int W, uint32_t* cf, float* out15, uint32_t* tables, int grid,
                     hipStream_t s);
+// Largest layer-1 and layer-2 activations of the FP32 net over an image,
+// folded into amax[0..1] (atomic maximum; the caller clears them).
+bool launch_activation_range(int width, const Consts* K, const DevModel& m, const uint8_t* img,
+                             int H, int W, float* amax, int grid, hipStream_t s);
 void launch_rans_encode(const uint32_t* cf, int H, int W, int G, int L, uint16_t* words,
                         uint32_t* counts, hipStream_t s);
 void launch_pack(const uint16_t* words, const uint32_t* counts, int H, int W, int G, int L,

@@ -143,3 +143,14 @@ def test_device_entry_points_reject_bad_arguments_before_any_device_work():
     assert enc(8, 8, bad, c) == dl.DLIC_ERR_UNSUPPORTED  # unknown dtype
     bad = dl.dlic_model(11, 32, 32, 15, dl.DLIC_FP32, 0, P, P, P, P, P, P, None, 0)
     assert enc(8, 8, bad, c) == dl.DLIC_ERR_ARG          # window size
+
+
+def test_w8a8_multipliers_match_oracle():
+    from oracle import lowp
+    rng = np.random.default_rng(12)
+    vals = np.concatenate([[1.0, 448.0, 449.0, 224.0, 0.0, -1.0, 1e-6, 3.5e4],
+                           np.exp(rng.uniform(-12, 8, 300))]).astype(np.float32)
+    for i in range(0, len(vals) - 2, 3):
+        got = dl.dlic_w8a8_multipliers(vals[i:i + 3])
+        want = [lowp.w8a8_multiplier(float(v)) for v in vals[i:i + 3]]
+        np.testing.assert_array_equal(got, np.array(want, np.float32))

@@ -141,3 +141,61 @@ def test_lowp_forward_rounds_hidden_activations():
     w["b1"][0] = 0.0
     qm = lowp.quantize_weights(w, "bf16")
     assert lowp.mlp_forward_lowp(f2, qm)[0, 0] == 1.0
+
+
+def test_w8a8_multiplier_hand_values():
+    assert lowp.w8a8_multiplier(1.0) == 256.0      # 256 <= 448 < 512
+    assert lowp.w8a8_multiplier(448.0) == 1.0
+    assert lowp.w8a8_multiplier(449.0) == 0.5
+    assert lowp.w8a8_multiplier(0.001) == 2.0 ** 18  # 262.1 <= 448 < 524.3
+    assert lowp.w8a8_multiplier(0.0) == 1.0
+
+
+def test_w8a8_forward_equals_fp64_when_roundings_are_exact():
+    # one nonzero per row from {+-1, +-0.5} (plus the 1.75 that fixes the
+    # weight scale at 2^-8, on a unit that is always 0 after ReLU), biases in
+    # {0, 1}: every layer input has at most 3 significant bits, so its e4m3
+    # rounding after the power-of-two multiplier is exact and the W8A8 form
+    # must equal the FP64 network; a wrong multiplier or a scale applied the
+    # wrong way round does not survive this.
+    rng = np.random.default_rng(9)
+    h = 16
+
+    def mat(o, i):
+        m = np.zeros((o, i), np.float32)
+        m[0, 0] = 1.75
+        for r in range(1, o):
+            m[r, rng.integers(1, i)] = rng.choice([-1.0, -0.5, 0.5, 1.0])
+        return m
+
+    w = {"W1": mat(h, 12), "W2": mat(h, h), "W3": mat(15, h),
+         "b1": rng.integers(0, 2, h).astype(np.float32), "b2": rng.integers(0, 2, h).astype(np.float32),
+         "b3": rng.integers(-1, 2, 15).astype(np.float32)}
+    w["b1"][0] = -1.75  # unit 0 of layer 1 is 0 for every input in {-1, 0, 1}
+    img = np.where(np.random.default_rng(10).random((7, 9)) < 0.5, 0, 255).astype(np.uint8)
+    f = oracle.causal_features(img).reshape(-1, 12)
+    keys = ("W1", "b1", "W2", "b2", "W3", "b3")
+    h1 = np.maximum(f @ w["W1"].T.astype(np.float64) + w["b1"], 0)
+    h2 = np.maximum(h1 @ w["W2"].T.astype(np.float64) + w["b2"], 0)
+    qm = lowp.quantize_weights(w, "fp8a8", act_max=(1.0, h1.max(), h2.max()))
+    np.testing.assert_array_equal(qm["scales"], np.float32(2.0 ** -8))
+    assert qm["mults"][0] == 256.0
+    want = oracle.mlp_forward(f, *(w[k] for k in keys))
+    np.testing.assert_array_equal(lowp.mlp_forward_lowp(f, qm), want)
+
+
+def test_w8a8_forward_rounds_inputs_to_e4m3():
+    # a single path: output 0 = feature 11 * 1; the feature -1 + 2/255 (grey
+    # level 1) times 256 is -253.99.., whose nearest e4m3 value is -256
+    h = 16
+    w = {k: np.zeros(s, np.float32) for k, s in
+         (("W1", (h, 12)), ("b1", h), ("W2", (h, h)), ("b2", h), ("W3", (15, h)), ("b3", 15))}
+    w["W1"][1, 11] = -1.0
+    w["W2"][1, 1] = 1.0
+    w["W3"][0, 1] = 1.0
+    f = np.zeros((1, 12))
+    f[0, 11] = oracle.scale(1)
+    qm = lowp.quantize_weights(w, "fp8a8", act_max=(1.0, 1.0, 1.0))
+    # (the weight scales 1/448 are not dyadic: products of them stay within
+    # FP32 rounding of 1; without the input rounding the output would be 0.992)
+    assert abs(lowp.mlp_forward_lowp(f, qm)[0, 0] - 1.0) < 1e-6
