@@ -307,9 +307,10 @@ dlic_status batch_enqueue(dlic_batch* b, bool decode, const uint8_t* in, uint8_t
     launch_fill_u32((uint32_t*)status, 0u, b->n_img, s);
     if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
     timing_begin("batch_decode_kernel", s);
-    bool split = true;
-    for (const BatchImage& im : b->images) split = split && im.L <= 32;
-    if (!launch_batch_decode(wtype, b->model.h1, K, dm, a, split, s)) return DLIC_ERR_UNSUPPORTED;
+    int widest = 1;
+    for (const BatchImage& im : b->images) widest = std::max(widest, im.L);
+    if (!launch_batch_decode(wtype, b->model.h1, K, dm, a, coder_lpp(widest), s))
+      return DLIC_ERR_UNSUPPORTED;
     timing_end(s);
   }
   return launch_ok();

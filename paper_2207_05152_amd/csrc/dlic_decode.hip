@@ -46,6 +46,8 @@ constexpr int PAR_STRIDE = 16;               // floats per pixel: pi[5], A[5], B
 constexpr int N_BUCKET = 15;                 // F(16 m), m = 1..15
 constexpr uint32_t LDS_SPIN_LIMIT = 1u << 24;
 constexpr int PROF_SLOTS = 16;               // decode profile counters per group
+constexpr int REC_RING = 64;                 // upstream records kept in LDS, by step
+constexpr int REC_AHEAD = 4;                 // steps ahead that a record is fetched
 
 
 __device__ __forceinline__ int floordiv(int a, int b) {
@@ -101,6 +103,22 @@ __device__ bool receive_record(const uint32_t* up_rec, int s, uint32_t limit, ui
   return true;
 }
 
+// The pixel ring keeps 16 columns per row, so step t overwrites step t - 16.
+// Before step t the coder makes sure the publisher wave has taken every step
+// up to t - PUB_LAG from the ring; pub caches the last value seen.  Returns
+// false if the wait gives up.
+constexpr int PUB_LAG = 13;
+__device__ __forceinline__ bool wait_publisher(const int* s_pub, int t, int& pub) {
+  uint32_t spins = 0;
+  while (pub < t - PUB_LAG) {
+    pub = __hip_atomic_load(s_pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (pub >= t - PUB_LAG) break;
+    if (++spins > LDS_SPIN_LIMIT) return false;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
 // Put the two pixels of upstream record s into ring rows 0 (r0-2) and 1 (r0-1).
 __device__ __forceinline__ void stash_record(uint8_t* ring, uint32_t v, int s, int r0, int W) {
   const int c1 = s - SKEW * (r0 - 1);
@@ -109,9 +127,39 @@ __device__ __forceinline__ void stash_record(uint8_t* ring, uint32_t v, int s, i
   if (c2 >= 0 && c2 < W) ring[0 * 16 + (c2 & 15)] = (uint8_t)((v >> 8) & 0xFF);
 }
 
-// Decode of group g of one stream by the whole workgroup.  SPLIT (L <= 32):
-// the coder's two half-waves share each pixel's symbol search.
-template <class Net, bool TABLES, bool SPLIT>
+// Reductions over the 16 lanes {i, i + 4, ..., i + 60} of pixel i (i < 4):
+// two rotations inside each 16-lane row, then the 16- and 32-lane swaps.
+__device__ __forceinline__ uint32_t px16_max(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false));  // row_ror:8
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xF, 0xF, false));  // row_ror:4
+  const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  v = max(a[0], a[1]);
+  const auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return max(b[0], b[1]);
+}
+__device__ __forceinline__ uint32_t px16_min(uint32_t v) {
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xF, 0xF, false));
+  const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  v = min(a[0], a[1]);
+  const auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return min(b[0], b[1]);
+}
+
+// Bin edge beta_v = RN((2v - 256) / 255) of 0 < v < 256 without the table:
+// one product by RN(1/255) and two fused corrections give the correctly
+// rounded quotient for every integer numerator in [-256, 256].
+__device__ __forceinline__ float bin_edge(int v) {
+  const float xv = (float)(2 * v - 256);
+  const float r = 1.0f / 255.0f;
+  const float q0 = xv * r;
+  const float e = __builtin_fmaf(-q0, 255.0f, xv);
+  return __builtin_fmaf(e, r, q0);
+}
+
+// Decode of group g of one stream by the whole workgroup.  LPP is
+// coder_lpp(L): how many coder lanes share each pixel's symbol search.
+template <class Net, bool TABLES, int LPP>
 __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const DevModel& m,
                                              const DecArgs& a, const int g) {
   __shared__ float2 s_sd[LUT_N];
@@ -122,6 +170,8 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
   __shared__ uint8_t s_ring[(DEC_RMAX + 2) * 16];
   __shared__ uint16_t s_words[DEC_RING];
   __shared__ int s_done[NSLOT][4];
+  __shared__ uint32_t s_rec[REC_RING];  // record | (step mod 2^15) << 16, or 0
+  __shared__ int s_pub;                 // last step handed on by the publisher wave
   __shared__ int s_decoded;
   __shared__ uint32_t s_pw, s_end;  // words consumed by the coder / loaded into the ring
   __shared__ unsigned long long s_total, s_before;
@@ -139,6 +189,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     Net::stage(m, s_w2, tid, NTH);
   }
   if (tid < NSLOT * 4) s_done[tid / 4][tid % 4] = -1;
+  if (tid < REC_RING) s_rec[tid] = 0u;
   if (tid == 0) {
     s_err = check_header(a);
     s_total = 0;
@@ -192,19 +243,210 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
   }
   const uint32_t E0 = bad ? 0u : min(n_words, (uint32_t)DEC_RING);
   for (uint32_t i = tid; i < E0; i += NTH) s_words[i] = gw[i];
-  if (tid == 0) s_end = E0;
+  if (tid == 0) {
+    s_end = E0;
+    s_pub = t_first - 1;
+  }
   __syncthreads();
 
   unsigned long long t_wait = 0, t_busy = 0, t_load = 0, t_search = 0, c_ld = 0, c_sr = 0;
+  unsigned long long t_wait0 = 0;
 
-  if (wave == 0) {
-    // ------------------------------------------------------------------ coder
+  if (!TABLES && LPP == 16 && wave == 0) {
+    // ------------------------------------------ coder, 16 lanes per pixel
+    // The same steps as the general coder below, arranged so that a sub-round
+    // waits on as few LDS round trips as possible: the density flag, the
+    // pixel's parameters and boundary and the next four stream words are read
+    // in one batch (LDS serves a wave's accesses in order, so data read after
+    // the flag was written before it); bin edges are computed, not read; the
+    // renormalising word is picked from the batch.  Lane cl + 4h serves pixel
+    // cl (see the search in the general coder).
+    const int cl = lane & 3, h = lane >> 2;
     uint32_t x = RANS_L;
-    if (lane < L && !bad) x = (uint32_t)gw[2 * lane] | ((uint32_t)gw[2 * lane + 1] << 16);
+    if (cl < L && !bad) x = (uint32_t)gw[2 * cl] | ((uint32_t)gw[2 * cl + 1] << 16);
+    uint32_t Pw = 2u * (uint32_t)L;
+    bool over = false, stuck = false;
+    const bool timeout = s_flag != 0;
+    uint32_t E = E0;
+    int t = t_first, j = -1, pub = t_first - 1;
+    for (int q = 0; q < P; ++q) {
+      if (++j == J) {
+        j = 0;
+        ++t;
+      }
+      if (!bad && E < n_words && Pw + 64u > E && !stuck) {
+        uint32_t spins = 0;
+        while ((E = __hip_atomic_load(&s_end, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) <
+                   min(n_words, Pw + 64u)) {
+          if (++spins > LDS_SPIN_LIMIT) {
+            stuck = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      if (j == 0 && !stuck) stuck = !wait_publisher(&s_pub, t, pub);
+      const int rr = j * L + cl;
+      const int y = r0 + rr;
+      const int xc = t - SKEW * y;
+      const bool act = cl < L && rr < R && xc >= 0 && xc < W;
+      const int slot_i = q & (NSLOT - 1);
+      const unsigned long long c0 = a.prof ? clock64() : 0ull;
+      unsigned long long c1 = c0;
+      if (__ballot(act) != 0ull && !stuck) {
+        const f4* pq = reinterpret_cast<const f4*>(&s_par[slot_i][cl * PAR_STRIDE]);
+        const uint16_t* pb = &s_bk[slot_i][cl * 16 + (h < N_BUCKET ? h : 0)];
+        int d = __hip_atomic_load(&s_done[slot_i][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        asm volatile("" ::: "memory");
+        f4 p0 = pq[0], p1 = pq[1], p2 = pq[2], p3 = pq[3];
+        uint32_t Fb = *pb;
+        uint32_t wd[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) wd[k] = s_words[(Pw + (uint32_t)k) & RING_MASK];
+        if (d != q) {
+          uint32_t spins = 0;
+          while ((d = __hip_atomic_load(&s_done[slot_i][0], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_WORKGROUP)) != q) {
+            if (++spins > LDS_SPIN_LIMIT) {
+              stuck = true;
+              break;
+            }
+          }
+          asm volatile("" ::: "memory");
+          p0 = pq[0];
+          p1 = pq[1];
+          p2 = pq[2];
+          p3 = pq[3];
+          Fb = *pb;
+        }
+        if (a.prof) c1 = clock64();
+        Mix mx;
+        {
+          const float pv[16] = {p0[0], p0[1], p0[2], p0[3], p1[0], p1[1], p1[2], p1[3],
+                                p2[0], p2[1], p2[2], p2[3], p3[0], p3[1], p3[2], p3[3]};
+#pragma unroll
+          for (int k = 0; k < N_MIX; ++k) {
+            mx.pi[k] = pv[k];
+            mx.A[k] = pv[N_MIX + k];
+            mx.B[k] = pv[2 * N_MIX + k];
+          }
+        }
+        const uint32_t slot = x & 0xFFFFu;
+        if (h >= N_BUCKET) Fb = M_TOTAL;
+        const bool le = Fb <= slot;
+        const uint32_t klo = px16_max(le ? (((uint32_t)(h + 1) << 17) | Fb) : 0u);
+        const uint32_t Fhi = px16_min(le ? M_TOTAL : Fb);
+        if (a.prof) c_ld = clock64();
+        const int base = 16 * min((int)(klo >> 17), N_BUCKET);
+        const int lv = base + h + 1;  // <= 255 for h < 15
+        uint32_t Fk = Fhi;
+        if (h < N_BUCKET) Fk = F_of_C(lv, cdf_C(bin_edge(lv), mx, s_sd));
+        const bool le2 = Fk <= slot;
+        const uint32_t k2 = px16_max(le2 ? (((uint32_t)(h + 1) << 17) | Fk) : 0u);
+        const uint32_t F2 = px16_min(le2 ? M_TOTAL : Fk);
+        const int cnt = min((int)(k2 >> 17), N_BUCKET);
+        const int v = base + cnt;
+        const uint32_t c = cnt > 0 ? (k2 & 0x1FFFFu) : (klo & 0x1FFFFu);
+        const uint32_t f = F2 - c;
+        if (a.prof) c_sr = clock64();
+        // f <= 2^16 - 255 and x >> 16 < 2^16: the 24-bit multiplier is exact
+        if (act) x = __umul24(f, x >> 16) + slot - c;
+        const bool ren = act && !bad && x < RANS_L;
+        const uint32_t m4 = (uint32_t)__ballot(ren) & 0xFu;
+        if (ren) {
+          const uint32_t rk = (uint32_t)__popc(m4 & ((1u << cl) - 1u));
+          uint32_t w = rk == 0 ? wd[0] : (rk == 1 ? wd[1] : (rk == 2 ? wd[2] : wd[3]));
+          if (Pw + rk >= n_words) {
+            over = true;
+            w = 0;
+          }
+          x = (x << 16) | w;
+        }
+        Pw += (uint32_t)__popc(m4);
+        if (act && h == 0) s_ring[(rr + 2) * 16 + (xc & 15)] = (uint8_t)v;
+      }
+      if (lane == 0) {
+        // LDS performs this wave's ring store before these two stores
+        asm volatile("" ::: "memory");
+        __hip_atomic_store(&s_pw, Pw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_store(&s_decoded, q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      if (a.prof) {
+        const unsigned long long c2 = clock64();
+        t_wait += c1 - c0;
+        if (j == 0) t_wait0 += c1 - c0;
+        t_busy += c2 - c1;
+        if (c_sr) {
+          t_load += c_ld - c1;
+          t_search += c_sr - c_ld;
+        }
+        c_ld = c_sr = 0;
+      }
+    }
+    const bool lane_bad = (cl < L) && (x != RANS_L);
+    const bool any_bad = __ballot(lane_bad || over || bad) != 0ull;
+    if (lane == 0) {
+      if (any_bad || Pw != n_words || stuck) atomicMax(a.status, 3);
+      if (timeout) atomicMax(a.status, 7);
+      if (a.prof) {
+        a.prof[g * PROF_SLOTS + 0] = t_wait;
+        a.prof[g * PROF_SLOTS + 1] = t_busy;
+        a.prof[g * PROF_SLOTS + 8] = t_load;
+        a.prof[g * PROF_SLOTS + 9] = t_search;
+        a.prof[g * PROF_SLOTS + 10] = (unsigned long long)P;
+        a.prof[g * PROF_SLOTS + 12] = t_wait0;
+      }
+    }
+  } else if (!TABLES && wave == 4) {
+    // ------------------------------------------------------------- publisher
+    // After each step: rows r1-2 and r1-1 go to the next group as one record,
+    // and a row whose last pixel was decoded in this step stores that pixel
+    // to the image (density waves store every other pixel one step later).
+    // The coder waits for this wave only to keep the ring from being
+    // overwritten before it is read.
+    bool stuck = false;
+    for (int t = t_first; t <= t_last && !stuck; ++t) {
+      const int qend = (t - t_first + 1) * J;
+      uint32_t spins = 0;
+      while (lds_acquire(&s_decoded) < qend) {
+        if (++spins > LDS_SPIN_LIMIT) {
+          stuck = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      if (lane == 0 && g + 1 < G) {
+        const int d1 = t - SKEW * (r1 - 1), d2 = t - SKEW * (r1 - 2);
+        uint32_t rv = 0x80000000u;
+        if (d1 >= 0 && d1 < W) rv |= (uint32_t)s_ring[(R - 1 + 2) * 16 + (d1 & 15)];
+        if (d2 >= 0 && d2 < W) rv |= (uint32_t)s_ring[(R - 2 + 2) * 16 + (d2 & 15)] << 8;
+        __hip_atomic_store(my_rec + t, rv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      // row y ends in step t when t - SKEW y = W - 1
+      const int ye = t - (W - 1);
+      if (lane == 1 && ye >= 0 && ye % SKEW == 0) {
+        const int y = ye / SKEW;
+        if (y >= r0 && y < r1)
+          a.img[(long long)y * W + (W - 1)] = s_ring[(y - r0 + 2) * 16 + ((W - 1) & 15)];
+      }
+      if (lane == 0) {
+        asm volatile("" ::: "memory");
+        __hip_atomic_store(&s_pub, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+    if (lane == 0 && stuck) atomicMax(a.status, 3);
+  } else if (wave == 0) {
+    // ------------------------------------------------------------------ coder
+    // cl: the pixel (coder lane) this lane serves.  With 16 lanes per pixel
+    // every lane of pixel cl keeps its own copy of the state and takes the
+    // same decisions, so no broadcast is needed.
+    const int cl = (!TABLES && LPP == 16) ? (lane & 3) : lane;
+    uint32_t x = RANS_L;
+    if (cl < L && !bad) x = (uint32_t)gw[2 * cl] | ((uint32_t)gw[2 * cl + 1] << 16);
     uint32_t Pw = 2u * (uint32_t)L;  // words consumed
     bool over = false, stuck = false, timeout = s_flag != 0;
     uint32_t E = E0;                   // words known to be in the ring
-    int t = t_first, j = -1;
+    int t = t_first, j = -1, pub = t_first - 1;
     for (int q = 0; q < P; ++q) {
       if (++j == J) {
         j = 0;
@@ -236,10 +478,11 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           __builtin_amdgcn_s_sleep(1);
         }
       }
-      const int rr = j * L + lane;
+      if (!TABLES && j == 0 && !stuck) stuck = !wait_publisher(&s_pub, t, pub);
+      const int rr = j * L + cl;
       const int y = r0 + rr;
       const int xc = t - SKEW * y;
-      const bool act = lane < L && rr < R && xc >= 0 && xc < W;
+      const bool act = cl < L && rr < R && xc >= 0 && xc < W;
       const bool any = __ballot(act) != 0ull;
       const int slot_i = q & (NSLOT - 1);
       const unsigned long long c0 = a.prof ? clock64() : 0ull;
@@ -255,11 +498,11 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
             n_ready += (i < NT && d == q) ? 1 : 0;
           }
           if (n_ready == NT) break;
+          // no sleep: the coder has its SIMD to itself
           if (++spins > LDS_SPIN_LIMIT) {
             stuck = true;
             break;
           }
-          __builtin_amdgcn_s_sleep(1);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       }
@@ -276,6 +519,46 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           }
           const uint32_t* tab = a.tables + (long long)ti * 257;
           find_symbol(slot, [&](int lv) { return tab[lv]; }, v, c, f);
+        } else if constexpr (LPP == 16) {
+          // L <= 4: lanes cl + 4h (h = 0..15) serve pixel cl.  Lane h < 15
+          // holds boundary F(16 (h + 1)); one max and one min reduction give
+          // the bucket and its end points.  Lane h < 15 then evaluates the
+          // interior level base + h + 1, and two more reductions give the
+          // symbol, F(v) and F(v + 1).  F rises strictly with the level, so
+          // the levels at or below the slot are a prefix of the lanes and
+          // the packed (count, F) key of the last of them is the maximum.
+          const int h = lane >> 2;
+          const f4* pq = reinterpret_cast<const f4*>(&s_par[slot_i][cl * PAR_STRIDE]);
+          Mix mx;
+          {
+            const f4 q0 = pq[0], q1 = pq[1], q2 = pq[2], q3 = pq[3];
+            const float pv[16] = {q0[0], q0[1], q0[2], q0[3], q1[0], q1[1], q1[2], q1[3],
+                                  q2[0], q2[1], q2[2], q2[3], q3[0], q3[1], q3[2], q3[3]};
+#pragma unroll
+            for (int k = 0; k < N_MIX; ++k) {
+              mx.pi[k] = pv[k];
+              mx.A[k] = pv[N_MIX + k];
+              mx.B[k] = pv[2 * N_MIX + k];
+            }
+          }
+          const uint32_t Fb = h < N_BUCKET ? (uint32_t)s_bk[slot_i][cl * 16 + h] : M_TOTAL;
+          const bool le = Fb <= slot;
+          const uint32_t klo = px16_max(le ? (((uint32_t)(h + 1) << 17) | Fb) : 0u);
+          const uint32_t Fhi = px16_min(le ? M_TOTAL : Fb);
+          if (a.prof) c_ld = clock64();
+          const int nb = min((int)(klo >> 17), N_BUCKET);
+          const int base = 16 * nb;
+          const int lv = base + h + 1;  // <= 255 for h < 15
+          uint32_t Fk = Fhi;
+          if (h < N_BUCKET) Fk = F_of_C(lv, cdf_C(s_beta[lv], mx, s_sd));
+          const bool le2 = Fk <= slot;
+          const uint32_t k2 = px16_max(le2 ? (((uint32_t)(h + 1) << 17) | Fk) : 0u);
+          const uint32_t F2 = px16_min(le2 ? M_TOTAL : Fk);
+          const int cnt = min((int)(k2 >> 17), N_BUCKET);
+          v = base + cnt;
+          c = cnt > 0 ? (k2 & 0x1FFFFu) : (klo & 0x1FFFFu);
+          f = F2 - c;
+          if (a.prof) c_sr = clock64();
         } else {
           // With L <= 32 the two half-waves share the work of each pixel:
           // lanes i and 32 + i both serve pixel i, the low half evaluating
@@ -283,7 +566,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           // a zero-weight pad), joined by one cross-half swap.  With L > 32
           // every lane evaluates both parts.  Either way C is the format's
           // (part 0..2) + (part 3..4), so every lane takes the same decisions.
-          constexpr bool split = SPLIT;
+          constexpr bool split = LPP == 2;
           const int hlf = split ? (lane >> 5) : 0;
           uint32_t sl = slot;
           int px = act ? lane : 0;
@@ -377,13 +660,30 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         }
         // f <= 2^16 - 255 and x >> 16 < 2^16: the 24-bit multiplier is exact
         if (act) x = __umul24(f, x >> 16) + slot - c;
-        Pw = rans_dec_renorm(x, act && !bad, Pw, n_words,
-                             [&](uint32_t pos) { return (uint32_t)s_words[pos & RING_MASK]; }, over);
-        if (act) {
+        if constexpr (!TABLES && LPP == 16) {
+          // every copy of a state reads the same word; lanes 0..3 rank them
+          const bool ren = act && !bad && x < RANS_L;
+          const uint32_t m4 = (uint32_t)__ballot(ren) & 0xFu;
+          if (ren) {
+            const uint32_t pos = Pw + (uint32_t)__popc(m4 & ((1u << cl) - 1u));
+            uint32_t wd = 0;
+            if (pos < n_words)
+              wd = (uint32_t)s_words[pos & RING_MASK];
+            else
+              over = true;
+            x = (x << 16) | wd;
+          }
+          Pw += (uint32_t)__popc(m4);
+        } else {
+          Pw = rans_dec_renorm(x, act && !bad, Pw, n_words,
+                               [&](uint32_t pos) { return (uint32_t)s_words[pos & RING_MASK]; },
+                               over);
+        }
+        if (act && (TABLES || LPP != 16 || lane < 4)) {
           s_ring[(rr + 2) * 16 + (xc & 15)] = (uint8_t)v;
-          // density waves store a pixel to the image one step later; a row's
-          // last pixel has no later step, so the coder stores it
-          if (TABLES || xc == W - 1) a.img[(long long)y * W + xc] = (uint8_t)v;
+          // density waves store a pixel to the image one step later and the
+          // publisher wave a row's last pixel
+          if (TABLES) a.img[(long long)y * W + xc] = (uint8_t)v;
         }
       }
       if (lane == 0) {
@@ -393,6 +693,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       if (a.prof) {
         const unsigned long long c2 = clock64();
         t_wait += c1 - c0;
+        if (j == 0) t_wait0 += c1 - c0;
         t_busy += c2 - c1;
         if (c_sr) {
           t_load += c_ld - c1;
@@ -400,8 +701,9 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         }
         c_ld = c_sr = 0;
       }
-      // after the last block of step t, hand rows r1-2 and r1-1 to the next group
-      if (j == J - 1 && lane == 0 && g + 1 < G) {
+      // after the last block of step t, hand rows r1-2 and r1-1 to the next
+      // group (with density waves the publisher wave does this)
+      if (TABLES && j == J - 1 && lane == 0 && g + 1 < G) {
         const int d1 = t - SKEW * (r1 - 1), d2 = t - SKEW * (r1 - 2);
         uint32_t rv = 0x80000000u;
         if (d1 >= 0 && d1 < W) rv |= (uint32_t)s_ring[(R - 1 + 2) * 16 + (d1 & 15)];
@@ -409,7 +711,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         __hip_atomic_store(my_rec + t, rv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
-    const bool lane_bad = (lane < L) && (x != RANS_L);
+    const bool lane_bad = (cl < L) && (x != RANS_L);
     const bool any_bad = __ballot(lane_bad || over || bad) != 0ull;
     if (lane == 0) {
       if (any_bad || Pw != n_words || stuck) atomicMax(a.status, 3);
@@ -420,6 +722,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         a.prof[g * PROF_SLOTS + 8] = t_load;
         a.prof[g * PROF_SLOTS + 9] = t_search;
         a.prof[g * PROF_SLOTS + 10] = (unsigned long long)P;
+        a.prof[g * PROF_SLOTS + 12] = t_wait0;
       }
     }
   } else if (!TABLES) {
@@ -433,6 +736,11 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     net.load(m, lane);
     const int q4 = lane >> 4;
     unsigned long long t_net = 0, t_head = 0, t_tab = 0, n_tiles = 0, c_net = 0, c_head = 0;
+    unsigned long long t_rec = 0, n_hit = 0, n_miss = 0;
+    // record of step pf_s fetched at the end of this wave's last tile; it is
+    // put into s_rec at the start of the next one, by when it has arrived
+    uint32_t pf_v = 0;
+    int pf_s = -1;
     bool timeout = s_flag != 0;
     bool stuck = false;
     // tile tau = NT * q + ti of sub-round q = (t - t_first) * J + j, every nwork-th
@@ -459,6 +767,11 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         }
       }
       const unsigned long long c1 = a.prof ? clock64() : 0ull;
+      if (lane == 0 && pf_s >= 0) {
+        if (pf_v >> 31) s_rec[pf_s & (REC_RING - 1)] = (pf_v & 0x8000FFFFu) | ((uint32_t)(pf_s & 0x7FFF) << 16);
+        pf_s = -1;
+      }
+      int pf_want = -1;
       // density wave 0 keeps the stream ring ahead of the coder
       if (w == 0 && !bad) {
         const uint32_t end = s_end;
@@ -486,18 +799,37 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       if (__ballot(valid) != 0ull) {
         // the tile holding row r0 takes the upstream record of step t-1
         if (rr == 0 && valid && lane == 0 && g > 0 && t - 1 <= up_last && !timeout) {
-          uint32_t v;
-          timeout = !receive_record(up_rec, t - 1, a.spin_limit, v);
-          stash_record(s_ring, v, t - 1, r0, W);
+          const unsigned long long c5 = a.prof ? clock64() : 0ull;
+          const int sr = t - 1;
+          const uint32_t e = s_rec[sr & (REC_RING - 1)];
+          uint32_t v = e;
+          if (!(e >> 31) || ((e >> 16) & 0x7FFFu) != (uint32_t)(sr & 0x7FFF)) {
+            timeout = !receive_record(up_rec, sr, a.spin_limit, v);
+            ++n_miss;
+          } else {
+            ++n_hit;
+          }
+          stash_record(s_ring, v, sr, r0, W);
+          if (sr + REC_AHEAD <= up_last) pf_want = sr + REC_AHEAD;
+          if (a.prof) t_rec += clock64() - c5;
         }
+        // the three window pixels of this lane: ring reads, then scale reads,
+        // each issued together (a neighbour outside the image reads ring slot 0
+        // and is replaced by 0)
         float fk[3];
+        bool inside[3];
+        uint32_t pv[3];
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) {
           const int k = 4 * kk + q4;
           const int yy = y + nb_dy(k), xx = xc + nb_dx(k);
-          fk[kk] = (valid && yy >= 0 && xx >= 0 && xx < W)
-                       ? s_scale[s_ring[(yy - r0 + 2) * 16 + (xx & 15)]]
-                       : 0.0f;
+          inside[kk] = valid && yy >= 0 && xx >= 0 && xx < W;
+          pv[kk] = s_ring[inside[kk] ? (yy - r0 + 2) * 16 + (xx & 15) : 0];
+        }
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+          const float sv = s_scale[pv[kk]];
+          fk[kk] = inside[kk] ? sv : 0.0f;
         }
         // the left neighbour (decoded last step) goes to the image now
         if (valid && q4 == 0 && xc >= 1)
@@ -524,8 +856,25 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           }
         }
         if (a.prof) c_head = clock64();
-        // table at the bucket boundaries 16, 32, ..., 240: four per lane
-        if (valid) {
+        // table at the bucket boundaries 16, 32, ..., 240
+        if (L <= 4) {
+          // one tile of at most 4 pixels: lane 4 (m - 1) + p computes F(16 m)
+          // of pixel p
+          const int p = lane & 3, mb = (lane >> 2) + 1;
+          const int rp = j * L + p, yp = r0 + rp, xp = t - SKEW * yp;
+          if (p < L && rp < R && xp >= 0 && xp < W && mb <= N_BUCKET) {
+            const float* pp = &par[p * PAR_STRIDE];
+            Mix mx;
+#pragma unroll
+            for (int k = 0; k < N_MIX; ++k) {
+              mx.pi[k] = pp[k];
+              mx.A[k] = pp[N_MIX + k];
+              mx.B[k] = pp[2 * N_MIX + k];
+            }
+            s_bk[slot_i][p * 16 + mb - 1] = (uint16_t)cdf_F(16 * mb, mx, s_sd, s_beta);
+          }
+        } else if (valid) {
+          // four boundaries per lane
           const float* pp = &par[ln * PAR_STRIDE];
           Mix mx;
 #pragma unroll
@@ -543,6 +892,10 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         }
       }
       if (lane == 0) lds_release(&s_done[slot_i][ti], q);
+      if (pf_want >= 0) {
+        pf_s = pf_want;
+        pf_v = __hip_atomic_load(up_rec + pf_s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       if (a.prof) {
         const unsigned long long c2 = clock64();
         t_wait += c1 - c0;
@@ -575,22 +928,25 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         atomicAdd(&a.prof[g * PROF_SLOTS + 5], t_head);
         atomicAdd(&a.prof[g * PROF_SLOTS + 6], t_tab);
         atomicAdd(&a.prof[g * PROF_SLOTS + 7], n_tiles);
+        atomicAdd(&a.prof[g * PROF_SLOTS + 11], t_rec);
+        atomicAdd(&a.prof[g * PROF_SLOTS + 13], n_hit);
+        atomicAdd(&a.prof[g * PROF_SLOTS + 14], n_miss);
       }
     }
   }
 }
 
-template <class Net, bool TABLES, bool SPLIT>
+template <class Net, bool TABLES, int LPP>
 __global__ __launch_bounds__(dec_waves<Net>() * 64) void wavefront_decode_kernel(
     const Consts* __restrict__ K, DevModel m, DecArgs a) {
-  decode_group<Net, TABLES, SPLIT>(K, m, a, blockIdx.x);
+  decode_group<Net, TABLES, LPP>(K, m, a, blockIdx.x);
 }
 
 // Batched decode: every workgroup takes the next work item by ticket.  Items
 // list the groups of an image in order, so the group a workgroup waits for
 // was taken earlier by a workgroup that is resident or done: the waits end.
 // The last group of an image to finish stamps the image's completion time.
-template <class Net, bool SPLIT>
+template <class Net, int LPP>
 __global__ __launch_bounds__(dec_waves<Net>() * 64) void batch_decode_kernel(
     const Consts* __restrict__ K, DevModel m, BatchArgs b) {
   __shared__ int s_item;
@@ -619,7 +975,7 @@ __global__ __launch_bounds__(dec_waves<Net>() * 64) void batch_decode_kernel(
   a.n_tables = 0;
   a.tidx = nullptr;
   a.prof = nullptr;
-  decode_group<Net, false, SPLIT>(K, m, a, it.group);
+  decode_group<Net, false, LPP>(K, m, a, it.group);
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
@@ -651,49 +1007,57 @@ void launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t s) {
 
 template <class Net>
 static void launch_batch_decode_t(const Consts* K, const DevModel& m, const BatchArgs& b,
-                                  bool split, hipStream_t s) {
-  if (split)
-    hipLaunchKernelGGL((batch_decode_kernel<Net, true>), dim3(b.n_items), dim3(dec_waves<Net>() * 64), 0,
-                       s, K, m, b);
+                                  int lpp, hipStream_t s) {
+  const dim3 grid(b.n_items), block(dec_waves<Net>() * 64);
+  if (lpp == 16)
+    hipLaunchKernelGGL((batch_decode_kernel<Net, 16>), grid, block, 0, s, K, m, b);
+  else if (lpp == 2)
+    hipLaunchKernelGGL((batch_decode_kernel<Net, 2>), grid, block, 0, s, K, m, b);
   else
-    hipLaunchKernelGGL((batch_decode_kernel<Net, false>), dim3(b.n_items), dim3(dec_waves<Net>() * 64),
-                       0, s, K, m, b);
+    hipLaunchKernelGGL((batch_decode_kernel<Net, 1>), grid, block, 0, s, K, m, b);
 }
 
 template <int H>
 static bool launch_batch_decode_h(int wtype, const Consts* K, const DevModel& m,
-                                  const BatchArgs& b, bool split, hipStream_t s) {
+                                  const BatchArgs& b, int lpp, hipStream_t s) {
   switch (wtype) {
-    case WT_F32: launch_batch_decode_t<NetF32<H, (H >= 64)>>(K, m, b, split, s); return true;
+    case WT_F32: launch_batch_decode_t<NetF32<H, (H >= 64)>>(K, m, b, lpp, s); return true;
     case WT_BF16:
-      launch_batch_decode_t<NetBF16<H, WT_BF16, (H > 64)>>(K, m, b, split, s);
+      launch_batch_decode_t<NetBF16<H, WT_BF16, (H > 64)>>(K, m, b, lpp, s);
       return true;
     case WT_FP8:
-      launch_batch_decode_t<NetBF16<H, WT_FP8, (H > 64)>>(K, m, b, split, s);
+      launch_batch_decode_t<NetBF16<H, WT_FP8, (H > 64)>>(K, m, b, lpp, s);
       return true;
-    case WT_FP8A8: launch_batch_decode_t<NetFP8A<H, (H > 64)>>(K, m, b, split, s); return true;
+    case WT_FP8A8: launch_batch_decode_t<NetFP8A<H, (H > 64)>>(K, m, b, lpp, s); return true;
     default: return false;
   }
 }
 
 bool launch_batch_decode(int wtype, int width, const Consts* K, const DevModel& m,
-                         const BatchArgs& b, bool split, hipStream_t s) {
+                         const BatchArgs& b, int lpp, hipStream_t s) {
   switch (width) {
-    case 32: return launch_batch_decode_h<32>(wtype, K, m, b, split, s);
-    case 64: return launch_batch_decode_h<64>(wtype, K, m, b, split, s);
-    case 128: return launch_batch_decode_h<128>(wtype, K, m, b, split, s);
+    case 32: return launch_batch_decode_h<32>(wtype, K, m, b, lpp, s);
+    case 64: return launch_batch_decode_h<64>(wtype, K, m, b, lpp, s);
+    case 128: return launch_batch_decode_h<128>(wtype, K, m, b, lpp, s);
     default: return false;
   }
 }
 
+// The table-driven coder (no density waves) runs one lane per pixel.
 template <class Net, bool TB>
 static void launch_decode_t(const Consts* K, const DevModel& m, const DecArgs& a, hipStream_t s) {
-  if (a.L <= 32)
-    hipLaunchKernelGGL((wavefront_decode_kernel<Net, TB, true>), dim3(a.G), dim3(dec_waves<Net>() * 64),
-                       0, s, K, m, a);
-  else
-    hipLaunchKernelGGL((wavefront_decode_kernel<Net, TB, false>), dim3(a.G), dim3(dec_waves<Net>() * 64),
-                       0, s, K, m, a);
+  const dim3 grid(a.G), block(dec_waves<Net>() * 64);
+  if constexpr (TB) {
+    hipLaunchKernelGGL((wavefront_decode_kernel<Net, true, 1>), grid, block, 0, s, K, m, a);
+  } else {
+    const int lpp = coder_lpp(a.L);
+    if (lpp == 16)
+      hipLaunchKernelGGL((wavefront_decode_kernel<Net, false, 16>), grid, block, 0, s, K, m, a);
+    else if (lpp == 2)
+      hipLaunchKernelGGL((wavefront_decode_kernel<Net, false, 2>), grid, block, 0, s, K, m, a);
+    else
+      hipLaunchKernelGGL((wavefront_decode_kernel<Net, false, 1>), grid, block, 0, s, K, m, a);
+  }
 }
 
 // Layer-2 weights of the BF16 nets go to LDS at H = 128: six density waves

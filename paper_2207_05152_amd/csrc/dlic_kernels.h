@@ -95,9 +95,15 @@ bool launch_batch_density(int wtype, int width, const Consts* K, const DevModel&
                           const BatchArgs& b, int grid, hipStream_t s);
 void launch_batch_rans_encode(const BatchArgs& b, hipStream_t s);
 void launch_batch_pack(const BatchArgs& b, int parts, hipStream_t s);
-// split: every image of the batch has L <= 32 (the coder's half-wave split).
+// Lanes of the decoder's coder wave that serve one pixel in its symbol
+// search: 1 for L > 32, 2 for 4 < L <= 32 (two half-waves, mixture
+// components 0..2 and 3..4), 16 for L <= 4 (one interior level of the bucket
+// per lane).
+__host__ __device__ constexpr int coder_lpp(int L) { return L <= 4 ? 16 : (L <= 32 ? 2 : 1); }
+
+// lpp: coder lanes per pixel, coder_lpp(L) of the widest image of the batch.
 bool launch_batch_decode(int wtype, int width, const Consts* K, const DevModel& m,
-                         const BatchArgs& b, bool split, hipStream_t s);
+                         const BatchArgs& b, int lpp, hipStream_t s);
 
 // Training: waves per workgroup of the FP32 / FP64 loss-and-gradient kernel.
 constexpr int TRAIN_WAVES_F32 = 4;

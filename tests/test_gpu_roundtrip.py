@@ -27,7 +27,8 @@ def _roundtrip(dev, img, wts, coder):
 @pytest.mark.parametrize("h,w,width,G,L", [
     (64, 64, 32, 1, 32), (1, 1, 32, 1, 32), (1, 9, 32, 1, 32), (9, 1, 64, 1, 32),
     (2, 3, 32, 1, 32), (5, 7, 64, 2, 4), (33, 4, 32, 2, 32), (100, 37, 64, 3, 32),
-    (31, 70, 64, 1, 64), (50, 20, 32, 5, 3), (256, 256, 64, 2, 32)])
+    (31, 70, 64, 1, 64), (50, 20, 32, 5, 3), (256, 256, 64, 2, 32), (96, 130, 64, 24, 4),
+    (40, 50, 32, 8, 1), (37, 61, 128, 3, 2), (60, 90, 64, 10, 3)])
 def test_lossless_round_trip(dev, h, w, width, G, L):
     img = synth.synth_image(h, w, 3 + h + w)
     wts = synth.xavier_mlp((12, width, width, 15), 3)
