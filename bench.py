@@ -152,12 +152,13 @@ def precision_sweep(dl, torch, img, H, W, coder, hidden=128, reps=3):
     return res
 
 
-def layout_sweep(dl, torch, img, H, W, model, layouts=((8, 32), (8, 64), (16, 32), (24, 64),
-                                                        (48, 32)), reps=3):
+def layout_sweep(dl, torch, img, H, W, model, layouts=((8, 32), (16, 16), (32, 8), (128, 2),
+                                                        (256, 1), (128, 4), (48, 32)), reps=3):
     """The headline image and net coded with other coder layouts (G groups x L
-    lanes; 8 x 32 is the headline's 256 lanes).  More lanes per row cut the
-    sequential sub-rounds per wavefront step, ceil(rows per group / L), and
-    spread one image over more CUs, at the price of 4 flushed bytes per lane."""
+    lanes).  The first five have the headline's 256 lanes; the decoder gives a
+    pixel 16 coder lanes when L <= 4.  More lanes cut the sequential sub-rounds
+    per wavefront step, ceil(rows per group / L), at the price of 4 flushed
+    bytes per lane."""
     out = []
     dl.dlic_set_timing(True)
     for G, L in layouts:
@@ -303,8 +304,8 @@ def main():
     ap.add_argument("--height", type=int, default=1536)
     ap.add_argument("--width", type=int, default=2048)
     ap.add_argument("--hidden", type=int, default=64)
-    ap.add_argument("--groups", type=int, default=8)
-    ap.add_argument("--lanes", type=int, default=32)
+    ap.add_argument("--groups", type=int, default=64)
+    ap.add_argument("--lanes", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed steps, run one plain elementwise copy of MIB MiB "
@@ -391,6 +392,8 @@ def main():
                                    "head": float(pc[:, 5].sum() / tiles),
                                    "buckets_publish": float(pc[:, 6].sum() / tiles),
                                    "tiles": int(tiles)},
+        "shader_clock_mhz": float(pc[:, 13].sum() / max(pc[:, 14].sum(), 1) * 100.0),
+        "coder_loop_cycles_per_sub_round": float(pc[:, 13].sum() / max(pc[:, 10].sum(), 1)),
         "coder_cycles_per_sub_round": {"busy": float(pc[:, 1].sum() / max(pc[:, 10].sum(), 1)),
                                        "to_search": float(pc[:, 8].sum() / max(pc[:, 10].sum(), 1)),
                                        "search": float(pc[:, 9].sum() / max(pc[:, 10].sum(), 1))},
@@ -409,6 +412,9 @@ def main():
     achieved = dom_flops / (avg[dom] * 1e-3) if dom_flops else 0.0
     crit_px = schedule_bound_px(H, W, args.groups)
     sched_ms = crit_px * mlp_flops_per_px(Hd, Hd) / (MI355X_FP32_MFMA / MI355X_CUS) * 1e3
+    steps_T = W + 3 * (H - 1)
+    J = -(-(-(-H // args.groups)) // args.lanes)
+    crit_sub = steps_T * J
 
     res = {
         "metric": "encode/decode MPix/s on 1 MI355X + bpp; BF16 vs FP32 at \u22640.01 bpp \u0394",
@@ -443,12 +449,17 @@ def main():
             "frac": achieved / MI355X_FP32_MFMA,
             "traffic": measured_traffic(dom),
         },
-        "decode_schedule_bound": {
-            "critical_px": crit_px,
-            "bound_ms": sched_ms,
-            "frac": sched_ms / avg["wavefront_decode_kernel"] if "wavefront_decode_kernel" in avg else None,
-            "note": "only one CU per row group can work on a group's step; bound = sum over steps "
-                    "of the busiest group's pixels x FLOP/px at one CU's FP32 MFMA peak",
+        "decode_span": {
+            "wavefront_steps": steps_T,
+            "sub_rounds_per_step": J,
+            "critical_sub_rounds": crit_sub,
+            "ns_per_sub_round": (avg["wavefront_decode_kernel"] * 1e6 / crit_sub
+                                 if "wavefront_decode_kernel" in avg else None),
+            "mfma_bound_ms": sched_ms,
+            "note": "groups move in lock-step on the wavefront step and each step is J sequential "
+                    "coder sub-rounds, so decode time is critical_sub_rounds x the coder's "
+                    "sub-round latency; mfma_bound_ms is the density work on that path at one "
+                    "CU's FP32 MFMA peak per group",
         },
         "decode_profile": decode_profile,
         "host": {"cpu": platform.processor() or platform.machine(), "os_cpus": os.cpu_count()},

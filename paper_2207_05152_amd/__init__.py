@@ -266,8 +266,12 @@ def dlic_kernel_times(max_n: int = 16):
 
 # ---- conveniences (torch-allocated buffers) -------------------------------------
 
-def default_coder(h: int, lanes: int = 32, rows_per_group: int = 192) -> dlic_coder:
-    """G = ceil(h / rows_per_group) row strips of `lanes` interleaved lanes."""
+def default_coder(h: int, lanes: int = 4, rows_per_group: int = 24) -> dlic_coder:
+    """G = ceil(h / rows_per_group) row strips of `lanes` interleaved lanes.
+
+    The default, strips of 24 rows with 4 lanes each (64 x 4 = 256 lanes on a
+    1536-row image), decodes fastest: a decoder workgroup per strip and 16 of
+    its coder lanes per pixel in the symbol search."""
     g = max(1, math.ceil(h / rows_per_group))
     if g > 1 and h < 2 * g:
         g = max(1, h // 2)

@@ -5,8 +5,9 @@ Knobs (all read by the library through dlic_batch_create):
   * rows per group: an image of height h is split into ceil(h / rows) row
     groups (more groups = more workgroups per image and a shorter decode
     span; each group adds 32 or 64 flushed states to the stream);
-  * lanes per group: 32 or 64 interleaved rANS states (a group's sub-round
-    covers that many rows of one wavefront step);
+  * lanes per group: 4, 32 or 64 interleaved rANS states (a group's
+    sub-round covers that many rows of one wavefront step; with at most 4 the
+    decoder gives each pixel 16 coder lanes);
   * density grid: workgroups of the persistent density kernel.
 
 The score is the time of one encode graph plus one decode graph replay,
@@ -25,8 +26,8 @@ import os
 import time
 
 DEFAULT = {"rows_per_group": 192, "lanes": 32, "density_grid": 0}
-ROWS = (192, 96, 64)
-LANES = (32, 64)
+# (rows per group, lanes) pairs, the likeliest first in case the budget ends
+LAYOUTS = ((24, 4), (12, 2), (48, 4), (96, 64), (64, 64), (96, 32), (192, 32), (64, 32))
 GRIDS = (0, 2048)
 
 
@@ -106,7 +107,7 @@ def tune(model, sizes, images, reps: int = 2, budget_s: float = 60.0, use_cache:
     trials = []
     best = None
     t_start = time.perf_counter()
-    for rows, lanes, grid in itertools.product(ROWS, LANES, GRIDS):
+    for (rows, lanes), grid in itertools.product(LAYOUTS, GRIDS):
         if time.perf_counter() - t_start > budget_s:
             break
         knobs = {"rows_per_group": rows, "lanes": lanes, "density_grid": grid}

@@ -46,8 +46,6 @@ constexpr int PAR_STRIDE = 16;               // floats per pixel: pi[5], A[5], B
 constexpr int N_BUCKET = 15;                 // F(16 m), m = 1..15
 constexpr uint32_t LDS_SPIN_LIMIT = 1u << 24;
 constexpr int PROF_SLOTS = 16;               // decode profile counters per group
-constexpr int REC_RING = 64;                 // upstream records kept in LDS, by step
-constexpr int REC_AHEAD = 4;                 // steps ahead that a record is fetched
 
 
 __device__ __forceinline__ int floordiv(int a, int b) {
@@ -127,23 +125,19 @@ __device__ __forceinline__ void stash_record(uint8_t* ring, uint32_t v, int s, i
   if (c2 >= 0 && c2 < W) ring[0 * 16 + (c2 & 15)] = (uint8_t)((v >> 8) & 0xFF);
 }
 
-// Reductions over the 16 lanes {i, i + 4, ..., i + 60} of pixel i (i < 4):
-// two rotations inside each 16-lane row, then the 16- and 32-lane swaps.
-__device__ __forceinline__ uint32_t px16_max(uint32_t v) {
+// Reductions over the 16 lanes of one row of the wave (lanes 16i .. 16i+15
+// serve pixel i): four rotations inside the row.
+__device__ __forceinline__ uint32_t row16_max(uint32_t v) {
   v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false));  // row_ror:8
   v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xF, 0xF, false));  // row_ror:4
-  const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-  v = max(a[0], a[1]);
-  const auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-  return max(b[0], b[1]);
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x122, 0xF, 0xF, false));  // row_ror:2
+  return max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x121, 0xF, 0xF, false));  // row_ror:1
 }
-__device__ __forceinline__ uint32_t px16_min(uint32_t v) {
+__device__ __forceinline__ uint32_t row16_min(uint32_t v) {
   v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false));
   v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xF, 0xF, false));
-  const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-  v = min(a[0], a[1]);
-  const auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-  return min(b[0], b[1]);
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x122, 0xF, 0xF, false));
+  return min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x121, 0xF, 0xF, false));
 }
 
 // Bin edge beta_v = RN((2v - 256) / 255) of 0 < v < 256 without the table:
@@ -170,7 +164,6 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
   __shared__ uint8_t s_ring[(DEC_RMAX + 2) * 16];
   __shared__ uint16_t s_words[DEC_RING];
   __shared__ int s_done[NSLOT][4];
-  __shared__ uint32_t s_rec[REC_RING];  // record | (step mod 2^15) << 16, or 0
   __shared__ int s_pub;                 // last step handed on by the publisher wave
   __shared__ int s_decoded;
   __shared__ uint32_t s_pw, s_end;  // words consumed by the coder / loaded into the ring
@@ -189,7 +182,6 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     Net::stage(m, s_w2, tid, NTH);
   }
   if (tid < NSLOT * 4) s_done[tid / 4][tid % 4] = -1;
-  if (tid < REC_RING) s_rec[tid] = 0u;
   if (tid == 0) {
     s_err = check_header(a);
     s_total = 0;
@@ -254,14 +246,21 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
 
   if (!TABLES && LPP == 16 && wave == 0) {
     // ------------------------------------------ coder, 16 lanes per pixel
-    // The same steps as the general coder below, arranged so that a sub-round
-    // waits on as few LDS round trips as possible: the density flag, the
-    // pixel's parameters and boundary and the next four stream words are read
-    // in one batch (LDS serves a wave's accesses in order, so data read after
-    // the flag was written before it); bin edges are computed, not read; the
-    // renormalising word is picked from the batch.  Lane cl + 4h serves pixel
-    // cl (see the search in the general coder).
-    const int cl = lane & 3, h = lane >> 2;
+    // L <= 4: row cl of the wave (lanes 16 cl + h, h = 0..15) serves pixel
+    // cl, and every lane keeps its own copy of that pixel's state, so all take
+    // the same decisions without a broadcast.  Lane h < 15 holds boundary
+    // F(16 (h + 1)); one max and one min reduction over the row give the
+    // bucket and its end points.  Lane h < 15 then evaluates the interior
+    // level base + h + 1, and two more reductions give the symbol, F(v) and
+    // F(v + 1).  F rises strictly with the level, so the levels at or below
+    // the slot are a prefix of the row and the packed (count, F) key of the
+    // last of them is the maximum.
+    // A sub-round waits on few LDS round trips: the density flag, the pixel's
+    // parameters and boundary and the next four stream words are read in one
+    // batch (LDS serves a wave's accesses in order, so data read after the
+    // flag was written before it); bin edges are computed, not read; the
+    // renormalising word is picked from the batch; the work is branch-free.
+    const int cl = lane >> 4, h = lane & 15;
     uint32_t x = RANS_L;
     if (cl < L && !bad) x = (uint32_t)gw[2 * cl] | ((uint32_t)gw[2 * cl + 1] << 16);
     uint32_t Pw = 2u * (uint32_t)L;
@@ -269,6 +268,10 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     const bool timeout = s_flag != 0;
     uint32_t E = E0;
     int t = t_first, j = -1, pub = t_first - 1;
+    const unsigned long long k0 = a.prof ? clock64() : 0ull;
+    const unsigned long long rt0 = a.prof ? __builtin_amdgcn_s_memrealtime() : 0ull;
+    const uint64_t row_heads = 0x0001000100010001ull;
+    const uint64_t below = (1ull << (16 * cl)) - 1ull;
     for (int q = 0; q < P; ++q) {
       if (++j == J) {
         j = 0;
@@ -295,7 +298,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       unsigned long long c1 = c0;
       if (__ballot(act) != 0ull && !stuck) {
         const f4* pq = reinterpret_cast<const f4*>(&s_par[slot_i][cl * PAR_STRIDE]);
-        const uint16_t* pb = &s_bk[slot_i][cl * 16 + (h < N_BUCKET ? h : 0)];
+        const uint16_t* pb = &s_bk[slot_i][cl * 16 + h];
         int d = __hip_atomic_load(&s_done[slot_i][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         asm volatile("" ::: "memory");
         f4 p0 = pq[0], p1 = pq[1], p2 = pq[2], p3 = pq[3];
@@ -303,6 +306,9 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         uint32_t wd[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) wd[k] = s_words[(Pw + (uint32_t)k) & RING_MASK];
+        // keep the batch together: one wait for all of it, no reload merged
+        // into the rare path below
+        asm volatile("" : "+v"(p0), "+v"(p1), "+v"(p2), "+v"(p3), "+v"(Fb), "+v"(d));
         if (d != q) {
           uint32_t spins = 0;
           while ((d = __hip_atomic_load(&s_done[slot_i][0], __ATOMIC_RELAXED,
@@ -320,49 +326,60 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           Fb = *pb;
         }
         if (a.prof) c1 = clock64();
-        Mix mx;
-        {
-          const float pv[16] = {p0[0], p0[1], p0[2], p0[3], p1[0], p1[1], p1[2], p1[3],
-                                p2[0], p2[1], p2[2], p2[3], p3[0], p3[1], p3[2], p3[3]};
-#pragma unroll
-          for (int k = 0; k < N_MIX; ++k) {
-            mx.pi[k] = pv[k];
-            mx.A[k] = pv[N_MIX + k];
-            mx.B[k] = pv[2 * N_MIX + k];
-          }
-        }
+        const float pv[16] = {p0[0], p0[1], p0[2], p0[3], p1[0], p1[1], p1[2], p1[3],
+                              p2[0], p2[1], p2[2], p2[3], p3[0], p3[1], p3[2], p3[3]};
         const uint32_t slot = x & 0xFFFFu;
-        if (h >= N_BUCKET) Fb = M_TOTAL;
+        // slot 15 of a pixel's boundaries is padding: F(256) = 2^16 there
+        Fb = h < N_BUCKET ? Fb : M_TOTAL;
         const bool le = Fb <= slot;
-        const uint32_t klo = px16_max(le ? (((uint32_t)(h + 1) << 17) | Fb) : 0u);
-        const uint32_t Fhi = px16_min(le ? M_TOTAL : Fb);
+        const uint32_t klo = row16_max(le ? (((uint32_t)(h + 1) << 17) | Fb) : 0u);
+        const uint32_t Fhi = row16_min(le ? M_TOTAL : Fb);
         if (a.prof) c_ld = clock64();
         const int base = 16 * min((int)(klo >> 17), N_BUCKET);
-        const int lv = base + h + 1;  // <= 255 for h < 15
-        uint32_t Fk = Fhi;
-        if (h < N_BUCKET) Fk = F_of_C(lv, cdf_C(bin_edge(lv), mx, s_sd));
+        const int lv = base + h + 1;  // <= 256; lane 15's value is not used
+        // C(beta_lv) in the format's order, the five table reads together
+        const float bq = bin_edge(lv);
+        int ji[N_MIX];
+        float wf[N_MIX];
+#pragma unroll
+        for (int k = 0; k < N_MIX; ++k) {
+          float u = bq * pv[N_MIX + k] + pv[2 * N_MIX + k];
+          u = u > 0.0f ? u : 0.0f;
+          u = fminf(u, 4096.0f);
+          ji[k] = (int)u;
+          wf[k] = __builtin_amdgcn_fractf(u);
+        }
+        float2 e[N_MIX];
+#pragma unroll
+        for (int k = 0; k < N_MIX; ++k) e[k] = s_sd[ji[k]];
+        float sg[N_MIX];
+#pragma unroll
+        for (int k = 0; k < N_MIX; ++k) sg[k] = e[k].x + wf[k] * e[k].y;
+        float clo = pv[0] * sg[0];
+        clo = clo + pv[1] * sg[1];
+        clo = clo + pv[2] * sg[2];
+        float chi = pv[3] * sg[3];
+        chi = chi + pv[4] * sg[4];
+        const uint32_t Fk = h < N_BUCKET ? F_of_C(lv, clo + chi) : Fhi;
         const bool le2 = Fk <= slot;
-        const uint32_t k2 = px16_max(le2 ? (((uint32_t)(h + 1) << 17) | Fk) : 0u);
-        const uint32_t F2 = px16_min(le2 ? M_TOTAL : Fk);
+        const uint32_t k2 = row16_max(le2 ? (((uint32_t)(h + 1) << 17) | Fk) : 0u);
+        const uint32_t F2 = row16_min(le2 ? M_TOTAL : Fk);
         const int cnt = min((int)(k2 >> 17), N_BUCKET);
         const int v = base + cnt;
         const uint32_t c = cnt > 0 ? (k2 & 0x1FFFFu) : (klo & 0x1FFFFu);
         const uint32_t f = F2 - c;
         if (a.prof) c_sr = clock64();
         // f <= 2^16 - 255 and x >> 16 < 2^16: the 24-bit multiplier is exact
-        if (act) x = __umul24(f, x >> 16) + slot - c;
-        const bool ren = act && !bad && x < RANS_L;
-        const uint32_t m4 = (uint32_t)__ballot(ren) & 0xFu;
-        if (ren) {
-          const uint32_t rk = (uint32_t)__popc(m4 & ((1u << cl) - 1u));
-          uint32_t w = rk == 0 ? wd[0] : (rk == 1 ? wd[1] : (rk == 2 ? wd[2] : wd[3]));
-          if (Pw + rk >= n_words) {
-            over = true;
-            w = 0;
-          }
-          x = (x << 16) | w;
-        }
-        Pw += (uint32_t)__popc(m4);
+        const uint32_t xd = __umul24(f, x >> 16) + slot - c;
+        const bool ren = act && !bad && xd < RANS_L;
+        const uint64_t mr = __ballot(ren) & row_heads;
+        const uint32_t rk = (uint32_t)__popcll(mr & below);
+        uint32_t w = rk == 0 ? wd[0] : (rk == 1 ? wd[1] : (rk == 2 ? wd[2] : wd[3]));
+        const bool past = ren && Pw + rk >= n_words;
+        over = over || past;
+        w = past ? 0u : w;
+        x = act ? (ren ? ((xd << 16) | w) : xd) : x;
+        Pw += (uint32_t)__popcll(mr);
         if (act && h == 0) s_ring[(rr + 2) * 16 + (xc & 15)] = (uint8_t)v;
       }
       if (lane == 0) {
@@ -395,6 +412,8 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         a.prof[g * PROF_SLOTS + 9] = t_search;
         a.prof[g * PROF_SLOTS + 10] = (unsigned long long)P;
         a.prof[g * PROF_SLOTS + 12] = t_wait0;
+        a.prof[g * PROF_SLOTS + 13] = clock64() - k0;
+        a.prof[g * PROF_SLOTS + 14] = __builtin_amdgcn_s_memrealtime() - rt0;
       }
     }
   } else if (!TABLES && wave == 4) {
@@ -437,16 +456,15 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     if (lane == 0 && stuck) atomicMax(a.status, 3);
   } else if (wave == 0) {
     // ------------------------------------------------------------------ coder
-    // cl: the pixel (coder lane) this lane serves.  With 16 lanes per pixel
-    // every lane of pixel cl keeps its own copy of the state and takes the
-    // same decisions, so no broadcast is needed.
-    const int cl = (!TABLES && LPP == 16) ? (lane & 3) : lane;
+    const int cl = lane;  // the pixel (coder lane) this lane serves
     uint32_t x = RANS_L;
     if (cl < L && !bad) x = (uint32_t)gw[2 * cl] | ((uint32_t)gw[2 * cl + 1] << 16);
     uint32_t Pw = 2u * (uint32_t)L;  // words consumed
     bool over = false, stuck = false, timeout = s_flag != 0;
     uint32_t E = E0;                   // words known to be in the ring
     int t = t_first, j = -1, pub = t_first - 1;
+    const unsigned long long k0 = a.prof ? clock64() : 0ull;
+    const unsigned long long rt0 = a.prof ? __builtin_amdgcn_s_memrealtime() : 0ull;
     for (int q = 0; q < P; ++q) {
       if (++j == J) {
         j = 0;
@@ -519,46 +537,6 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           }
           const uint32_t* tab = a.tables + (long long)ti * 257;
           find_symbol(slot, [&](int lv) { return tab[lv]; }, v, c, f);
-        } else if constexpr (LPP == 16) {
-          // L <= 4: lanes cl + 4h (h = 0..15) serve pixel cl.  Lane h < 15
-          // holds boundary F(16 (h + 1)); one max and one min reduction give
-          // the bucket and its end points.  Lane h < 15 then evaluates the
-          // interior level base + h + 1, and two more reductions give the
-          // symbol, F(v) and F(v + 1).  F rises strictly with the level, so
-          // the levels at or below the slot are a prefix of the lanes and
-          // the packed (count, F) key of the last of them is the maximum.
-          const int h = lane >> 2;
-          const f4* pq = reinterpret_cast<const f4*>(&s_par[slot_i][cl * PAR_STRIDE]);
-          Mix mx;
-          {
-            const f4 q0 = pq[0], q1 = pq[1], q2 = pq[2], q3 = pq[3];
-            const float pv[16] = {q0[0], q0[1], q0[2], q0[3], q1[0], q1[1], q1[2], q1[3],
-                                  q2[0], q2[1], q2[2], q2[3], q3[0], q3[1], q3[2], q3[3]};
-#pragma unroll
-            for (int k = 0; k < N_MIX; ++k) {
-              mx.pi[k] = pv[k];
-              mx.A[k] = pv[N_MIX + k];
-              mx.B[k] = pv[2 * N_MIX + k];
-            }
-          }
-          const uint32_t Fb = h < N_BUCKET ? (uint32_t)s_bk[slot_i][cl * 16 + h] : M_TOTAL;
-          const bool le = Fb <= slot;
-          const uint32_t klo = px16_max(le ? (((uint32_t)(h + 1) << 17) | Fb) : 0u);
-          const uint32_t Fhi = px16_min(le ? M_TOTAL : Fb);
-          if (a.prof) c_ld = clock64();
-          const int nb = min((int)(klo >> 17), N_BUCKET);
-          const int base = 16 * nb;
-          const int lv = base + h + 1;  // <= 255 for h < 15
-          uint32_t Fk = Fhi;
-          if (h < N_BUCKET) Fk = F_of_C(lv, cdf_C(s_beta[lv], mx, s_sd));
-          const bool le2 = Fk <= slot;
-          const uint32_t k2 = px16_max(le2 ? (((uint32_t)(h + 1) << 17) | Fk) : 0u);
-          const uint32_t F2 = px16_min(le2 ? M_TOTAL : Fk);
-          const int cnt = min((int)(k2 >> 17), N_BUCKET);
-          v = base + cnt;
-          c = cnt > 0 ? (k2 & 0x1FFFFu) : (klo & 0x1FFFFu);
-          f = F2 - c;
-          if (a.prof) c_sr = clock64();
         } else {
           // With L <= 32 the two half-waves share the work of each pixel:
           // lanes i and 32 + i both serve pixel i, the low half evaluating
@@ -660,26 +638,9 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         }
         // f <= 2^16 - 255 and x >> 16 < 2^16: the 24-bit multiplier is exact
         if (act) x = __umul24(f, x >> 16) + slot - c;
-        if constexpr (!TABLES && LPP == 16) {
-          // every copy of a state reads the same word; lanes 0..3 rank them
-          const bool ren = act && !bad && x < RANS_L;
-          const uint32_t m4 = (uint32_t)__ballot(ren) & 0xFu;
-          if (ren) {
-            const uint32_t pos = Pw + (uint32_t)__popc(m4 & ((1u << cl) - 1u));
-            uint32_t wd = 0;
-            if (pos < n_words)
-              wd = (uint32_t)s_words[pos & RING_MASK];
-            else
-              over = true;
-            x = (x << 16) | wd;
-          }
-          Pw += (uint32_t)__popc(m4);
-        } else {
-          Pw = rans_dec_renorm(x, act && !bad, Pw, n_words,
-                               [&](uint32_t pos) { return (uint32_t)s_words[pos & RING_MASK]; },
-                               over);
-        }
-        if (act && (TABLES || LPP != 16 || lane < 4)) {
+        Pw = rans_dec_renorm(x, act && !bad, Pw, n_words,
+                             [&](uint32_t pos) { return (uint32_t)s_words[pos & RING_MASK]; }, over);
+        if (act) {
           s_ring[(rr + 2) * 16 + (xc & 15)] = (uint8_t)v;
           // density waves store a pixel to the image one step later and the
           // publisher wave a row's last pixel
@@ -723,6 +684,8 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         a.prof[g * PROF_SLOTS + 9] = t_search;
         a.prof[g * PROF_SLOTS + 10] = (unsigned long long)P;
         a.prof[g * PROF_SLOTS + 12] = t_wait0;
+        a.prof[g * PROF_SLOTS + 13] = clock64() - k0;
+        a.prof[g * PROF_SLOTS + 14] = __builtin_amdgcn_s_memrealtime() - rt0;
       }
     }
   } else if (!TABLES) {
@@ -736,11 +699,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     net.load(m, lane);
     const int q4 = lane >> 4;
     unsigned long long t_net = 0, t_head = 0, t_tab = 0, n_tiles = 0, c_net = 0, c_head = 0;
-    unsigned long long t_rec = 0, n_hit = 0, n_miss = 0;
-    // record of step pf_s fetched at the end of this wave's last tile; it is
-    // put into s_rec at the start of the next one, by when it has arrived
-    uint32_t pf_v = 0;
-    int pf_s = -1;
+    unsigned long long t_rec = 0;
     bool timeout = s_flag != 0;
     bool stuck = false;
     // tile tau = NT * q + ti of sub-round q = (t - t_first) * J + j, every nwork-th
@@ -767,11 +726,6 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         }
       }
       const unsigned long long c1 = a.prof ? clock64() : 0ull;
-      if (lane == 0 && pf_s >= 0) {
-        if (pf_v >> 31) s_rec[pf_s & (REC_RING - 1)] = (pf_v & 0x8000FFFFu) | ((uint32_t)(pf_s & 0x7FFF) << 16);
-        pf_s = -1;
-      }
-      int pf_want = -1;
       // density wave 0 keeps the stream ring ahead of the coder
       if (w == 0 && !bad) {
         const uint32_t end = s_end;
@@ -800,17 +754,9 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         // the tile holding row r0 takes the upstream record of step t-1
         if (rr == 0 && valid && lane == 0 && g > 0 && t - 1 <= up_last && !timeout) {
           const unsigned long long c5 = a.prof ? clock64() : 0ull;
-          const int sr = t - 1;
-          const uint32_t e = s_rec[sr & (REC_RING - 1)];
-          uint32_t v = e;
-          if (!(e >> 31) || ((e >> 16) & 0x7FFFu) != (uint32_t)(sr & 0x7FFF)) {
-            timeout = !receive_record(up_rec, sr, a.spin_limit, v);
-            ++n_miss;
-          } else {
-            ++n_hit;
-          }
-          stash_record(s_ring, v, sr, r0, W);
-          if (sr + REC_AHEAD <= up_last) pf_want = sr + REC_AHEAD;
+          uint32_t v;
+          timeout = !receive_record(up_rec, t - 1, a.spin_limit, v);
+          stash_record(s_ring, v, t - 1, r0, W);
           if (a.prof) t_rec += clock64() - c5;
         }
         // the three window pixels of this lane: ring reads, then scale reads,
@@ -892,10 +838,6 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         }
       }
       if (lane == 0) lds_release(&s_done[slot_i][ti], q);
-      if (pf_want >= 0) {
-        pf_s = pf_want;
-        pf_v = __hip_atomic_load(up_rec + pf_s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
       if (a.prof) {
         const unsigned long long c2 = clock64();
         t_wait += c1 - c0;
@@ -929,8 +871,6 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         atomicAdd(&a.prof[g * PROF_SLOTS + 6], t_tab);
         atomicAdd(&a.prof[g * PROF_SLOTS + 7], n_tiles);
         atomicAdd(&a.prof[g * PROF_SLOTS + 11], t_rec);
-        atomicAdd(&a.prof[g * PROF_SLOTS + 13], n_hit);
-        atomicAdd(&a.prof[g * PROF_SLOTS + 14], n_miss);
       }
     }
   }

@@ -79,10 +79,11 @@ def test_decode_oracle_stream_with_tables(dev, h, w, G, L):
     assert np.array_equal(got, sym.astype(np.uint8))
 
 
-def test_full_size_layout_sampled_groups(dev):
-    # The 2048x1536 / 8 x 32-lane layout: GPU stream of the first and the last
-    # group byte-identical to the oracle's; every group decodes back.
-    h, w, G, L = 1536, 2048, 8, 32
+@pytest.mark.parametrize("G,L", [(8, 32), (64, 4)])
+def test_full_size_layout_sampled_groups(dev, G, L):
+    # The 2048x1536 image in 256-lane layouts: GPU stream of the first and the
+    # last group byte-identical to the oracle's; every group decodes back.
+    h, w = 1536, 2048
     tabs, tidx, sym, c, f = _inputs(h, w, 77)
     say("rans_encode_cf full size", h, w, G, L)
     got = _gpu_encode_cf(dev, h, w, dl.dlic_coder(G, L), c, f)

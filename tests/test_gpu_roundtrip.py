@@ -66,10 +66,11 @@ def test_c0_stream_structure_and_rate(dev, c0_inputs):
     assert cost - 1 <= payload <= cost + 32 * 32 + 0.02 * img.size
 
 
-def test_full_size_round_trip(dev):
+@pytest.mark.parametrize("G,L", [(8, 32), (64, 4)])
+def test_full_size_round_trip(dev, G, L):
     img = synth.synth_image(1536, 2048, 1)
     wts = synth.xavier_mlp((12, 64, 64, 15), 3)
-    _, _, bits, dec, st = _roundtrip(dev, img, wts, dl.dlic_coder(8, 32))
+    _, _, bits, dec, st = _roundtrip(dev, img, wts, dl.dlic_coder(G, L))
     assert st == 0
     assert np.array_equal(dec, img)
 
