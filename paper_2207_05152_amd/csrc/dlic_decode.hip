@@ -9,12 +9,16 @@
 //
 // Inside the workgroup the work is split by wave and synchronised through
 // LDS counters instead of barriers:
-//   * wave 0, the coder, walks the sub-rounds in order: for each active lane
+//   * wave 0, the coder, walks the sub-rounds in order: for each active pixel
 //     it locates the symbol from the slot of its state (16-level bucket from
-//     precomputed boundaries, then 4 halvings on the FP32 table rule), updates
-//     the state, renormalises by ballot from an LDS ring of the stream, writes
-//     the pixel, and publishes the sub-rounds done;
-//   * waves 1..7 compute densities ahead of the coder, one 16-pixel tile of
+//     precomputed boundaries, then the level inside the bucket on the FP32
+//     table rule: 4 halvings with one or two lanes per pixel, or one level per
+//     lane with 16 lanes per pixel when L <= 4), updates the state,
+//     renormalises by ballot from an LDS ring of the stream, writes the pixel
+//     to the ring, and publishes the sub-rounds done;
+//   * wave 4, the publisher, hands each finished step's last two rows to the
+//     next group and stores rows' last pixels to the image;
+//   * the other waves compute densities ahead of the coder, one 16-pixel tile of
 //     one sub-round at a time: gather from the LDS pixel ring, network on
 //     MFMA, mixture head, and the table at the 15 bucket boundaries.  Sub-round
 //     (t, j) only needs (t-1, j) and (t-1, j-1) decoded, so densities run up
@@ -34,8 +38,8 @@ constexpr int REFILL_WORDS = 1024;           // one coder-wave refill: 16 words 
 // Waves per decoder workgroup: 12 where a density wave's registers allow
 // three waves per SIMD (nets up to 64 wide, the FP32 net's layer-2 weights
 // then in LDS), else 8.  Waves are placed on the four SIMDs round-robin, so
-// waves 4, 8, ... share the coder's SIMD; they stay idle and leave that SIMD
-// to the coder.  The others compute densities.
+// waves 4, 8, ... share the coder's SIMD: wave 4 is the publisher (light and
+// mostly asleep), wave 8 stays idle.  The others compute densities.
 template <class Net>
 constexpr int dec_waves() { return Net::DEC_WIDE ? 12 : 8; }
 template <class Net>
@@ -690,8 +694,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     }
   } else if (!TABLES) {
     // -------------------------------------------------------- density waves
-    // density waves: waves are placed on SIMDs round-robin, so wave 4 would
-    // share the coder's SIMD; it stays idle and the coder keeps its SIMD
+    // waves 4, 8, ... share the coder's SIMD and compute no densities
     if ((wave & 3) == 0) return;
     constexpr int nwork = dec_workers<Net>();
     const int w = wave - 1 - (wave >> 2);
