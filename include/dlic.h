@@ -340,9 +340,12 @@ int dlic_kernel_times(float *h_ms, const char **h_names, int max_n);
  * coder's busy time [8] from the densities' arrival to the start of the
  * symbol search, [9] the search itself, and [10] the group's sub-rounds;
  * [11] density waves waiting for the group above's records, [12] the coder's
- * wait at the first block of each step, [13] the coder loop's shader-clock
- * cycles and [14] its duration in 100 MHz real-time ticks.  NULL turns it
- * off. */
+ * wait at the first block of each step (with 16 lanes per pixel: its cycles
+ * waiting for densities not ready when first read), [13] the coder loop's
+ * shader-clock cycles and [14] its duration in 100 MHz real-time ticks, [15]
+ * (16 lanes per pixel) the sub-rounds whose densities were not ready when
+ * first read, low 32 bits, and of them those at block 0, high 32 bits.  NULL
+ * turns it off. */
 void dlic_set_decode_profile(unsigned long long *d_counters);
 
 #ifdef __cplusplus

@@ -110,6 +110,7 @@ __device__ bool receive_record(const uint32_t* up_rec, int s, uint32_t limit, ui
 // up to t - PUB_LAG from the ring; pub caches the last value seen.  Returns
 // false if the wait gives up.
 constexpr int PUB_LAG = 13;
+constexpr int RCV_AHEAD = 6;  // upstream records stored at most this many steps ahead
 __device__ __forceinline__ bool wait_publisher(const int* s_pub, int t, int& pub) {
   uint32_t spins = 0;
   while (pub < t - PUB_LAG) {
@@ -168,7 +169,8 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
   __shared__ uint8_t s_ring[(DEC_RMAX + 2) * 16];
   __shared__ uint16_t s_words[DEC_RING];
   __shared__ int s_done[NSLOT][4];
-  __shared__ int s_pub;                 // last step handed on by the publisher wave
+  __shared__ int s_pub;                 // last step handed on by the courier wave
+  __shared__ int s_rcv;                 // last upstream step in the ring (courier)
   __shared__ int s_decoded;
   __shared__ uint32_t s_pw, s_end;  // words consumed by the coder / loaded into the ring
   __shared__ unsigned long long s_total, s_before;
@@ -242,6 +244,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
   if (tid == 0) {
     s_end = E0;
     s_pub = t_first - 1;
+    s_rcv = t_first - 2;
   }
   __syncthreads();
 
@@ -275,6 +278,9 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     const unsigned long long k0 = a.prof ? clock64() : 0ull;
     const unsigned long long rt0 = a.prof ? __builtin_amdgcn_s_memrealtime() : 0ull;
     const uint64_t row_heads = 0x0001000100010001ull;
+    // sub-rounds whose densities were not there yet (high half: of them at
+    // block 0) and the cycles spent waiting for them
+    unsigned long long n_late = 0, t_late = 0;
     const uint64_t below = (1ull << (16 * cl)) - 1ull;
     for (int q = 0; q < P; ++q) {
       if (++j == J) {
@@ -313,7 +319,10 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         // keep the batch together: one wait for all of it, no reload merged
         // into the rare path below
         asm volatile("" : "+v"(p0), "+v"(p1), "+v"(p2), "+v"(p3), "+v"(Fb), "+v"(d));
-        if (d != q) {
+        // the flag is one LDS word read by every lane: decide on lane 0's copy
+        if (__builtin_amdgcn_readfirstlane(d) != q) {
+          n_late += j == 0 ? (1ull << 32) + 1ull : 1ull;
+          const unsigned long long cw = a.prof ? clock64() : 0ull;
           uint32_t spins = 0;
           while ((d = __hip_atomic_load(&s_done[slot_i][0], __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_WORKGROUP)) != q) {
@@ -328,6 +337,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           p2 = pq[2];
           p3 = pq[3];
           Fb = *pb;
+          if (a.prof) t_late += clock64() - cw;
         }
         if (a.prof) c1 = clock64();
         const float pv[16] = {p0[0], p0[1], p0[2], p0[3], p1[0], p1[1], p1[2], p1[3],
@@ -415,49 +425,92 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         a.prof[g * PROF_SLOTS + 8] = t_load;
         a.prof[g * PROF_SLOTS + 9] = t_search;
         a.prof[g * PROF_SLOTS + 10] = (unsigned long long)P;
-        a.prof[g * PROF_SLOTS + 12] = t_wait0;
+        a.prof[g * PROF_SLOTS + 12] = t_late;
         a.prof[g * PROF_SLOTS + 13] = clock64() - k0;
         a.prof[g * PROF_SLOTS + 14] = __builtin_amdgcn_s_memrealtime() - rt0;
+        a.prof[g * PROF_SLOTS + 15] = n_late;
       }
     }
   } else if (!TABLES && wave == 4) {
-    // ------------------------------------------------------------- publisher
-    // After each step: rows r1-2 and r1-1 go to the next group as one record,
-    // and a row whose last pixel was decoded in this step stores that pixel
-    // to the image (density waves store every other pixel one step later).
-    // The coder waits for this wave only to keep the ring from being
-    // overwritten before it is read.
-    bool stuck = false;
-    for (int t = t_first; t <= t_last && !stuck; ++t) {
-      const int qend = (t - t_first + 1) * J;
-      uint32_t spins = 0;
-      while (lds_acquire(&s_decoded) < qend) {
-        if (++spins > LDS_SPIN_LIMIT) {
-          stuck = true;
-          break;
+    // --------------------------------------------------------------- courier
+    // Carries rows between groups, both ways:
+    //  * after each finished step, rows r1-2 and r1-1 go to the next group as
+    //    one record, and a row whose last pixel was decoded in this step
+    //    stores that pixel to the image (density waves store every other
+    //    pixel one step later);
+    //  * records of the group above are polled ahead of need, eight steps per
+    //    vector load, and put into ring rows 0 and 1, up to RCV_AHEAD steps
+    //    beyond the coder's step, so no density wave waits on global memory.
+    // The ring keeps 16 columns: record s shares its columns with s + 16, and
+    // a density wave of step t reads records t-8 .. t-1, so storing at most 7
+    // steps ahead of the coder never overwrites a column still to be read.
+    // The coder waits for this wave only to keep its own rows from being
+    // overwritten before they are published.
+    int pub_t = t_first;      // next own step to publish
+    int rcv = t_first - 1;    // next upstream record to receive
+    const int rcv_last = g > 0 ? up_last : rcv - 1;
+    bool stuck = false, timeout = s_flag != 0;
+    uint32_t idle = 0, rspins = 0;
+    while ((pub_t <= t_last || (rcv <= rcv_last && !timeout)) && !stuck) {
+      bool progress = false;
+      const int done_q = lds_acquire(&s_decoded);
+      while (pub_t <= t_last && done_q >= (pub_t - t_first + 1) * J) {
+        if (lane == 0 && g + 1 < G) {
+          const int d1 = pub_t - SKEW * (r1 - 1), d2 = pub_t - SKEW * (r1 - 2);
+          uint32_t rv = 0x80000000u;
+          if (d1 >= 0 && d1 < W) rv |= (uint32_t)s_ring[(R - 1 + 2) * 16 + (d1 & 15)];
+          if (d2 >= 0 && d2 < W) rv |= (uint32_t)s_ring[(R - 2 + 2) * 16 + (d2 & 15)] << 8;
+          __hip_atomic_store(my_rec + pub_t, rv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        // row y ends in step pub_t when pub_t - SKEW y = W - 1
+        const int ye = pub_t - (W - 1);
+        if (lane == 1 && ye >= 0 && ye % SKEW == 0) {
+          const int y = ye / SKEW;
+          if (y >= r0 && y < r1)
+            a.img[(long long)y * W + (W - 1)] = s_ring[(y - r0 + 2) * 16 + ((W - 1) & 15)];
+        }
+        if (lane == 0) {
+          asm volatile("" ::: "memory");
+          __hip_atomic_store(&s_pub, pub_t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        ++pub_t;
+        progress = true;
+      }
+      const int lim = min(rcv_last, t_first + done_q / J + RCV_AHEAD);
+      if (rcv <= lim && !timeout) {
+        const int sr = rcv + lane;
+        uint32_t v = 0;
+        if (lane < 8 && sr <= lim)
+          v = __hip_atomic_load(up_rec + sr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t okm = __ballot((v >> 31) != 0u);
+        const int n = (int)__builtin_ctzll(~okm);  // leading run of valid records
+        if (lane < n) stash_record(s_ring, v, sr, r0, W);
+        if (n > 0) {
+          rcv += n;
+          if (lane == 0) {
+            asm volatile("" ::: "memory");
+            __hip_atomic_store(&s_rcv, rcv - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+          progress = true;
+          rspins = 0;
+        } else if (++rspins > a.spin_limit) {
+          timeout = true;
+        }
+      }
+      if (progress) {
+        idle = 0;
+      } else {
+        if (++idle > LDS_SPIN_LIMIT) stuck = true;
         __builtin_amdgcn_s_sleep(1);
       }
-      if (lane == 0 && g + 1 < G) {
-        const int d1 = t - SKEW * (r1 - 1), d2 = t - SKEW * (r1 - 2);
-        uint32_t rv = 0x80000000u;
-        if (d1 >= 0 && d1 < W) rv |= (uint32_t)s_ring[(R - 1 + 2) * 16 + (d1 & 15)];
-        if (d2 >= 0 && d2 < W) rv |= (uint32_t)s_ring[(R - 2 + 2) * 16 + (d2 & 15)] << 8;
-        __hip_atomic_store(my_rec + t, rv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      // row y ends in step t when t - SKEW y = W - 1
-      const int ye = t - (W - 1);
-      if (lane == 1 && ye >= 0 && ye % SKEW == 0) {
-        const int y = ye / SKEW;
-        if (y >= r0 && y < r1)
-          a.img[(long long)y * W + (W - 1)] = s_ring[(y - r0 + 2) * 16 + ((W - 1) & 15)];
-      }
-      if (lane == 0) {
-        asm volatile("" ::: "memory");
-        __hip_atomic_store(&s_pub, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
     }
-    if (lane == 0 && stuck) atomicMax(a.status, 3);
+    if (lane == 0) {
+      // density waves stop waiting for records that will not come
+      if (timeout || stuck)
+        __hip_atomic_store(&s_rcv, 0x7FFFFFFF, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (stuck) atomicMax(a.status, 3);
+      if (timeout) atomicMax(a.status, 7);
+    }
   } else if (wave == 0) {
     // ------------------------------------------------------------------ coder
     const int cl = lane;  // the pixel (coder lane) this lane serves
@@ -754,12 +807,18 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       const int xc = t - SKEW * y;
       const bool valid = ln < L && rr < R && xc >= 0 && xc < W;
       if (__ballot(valid) != 0ull) {
-        // the tile holding row r0 takes the upstream record of step t-1
-        if (rr == 0 && valid && lane == 0 && g > 0 && t - 1 <= up_last && !timeout) {
+        // the tile holding row r0 needs the group above's step t-1 in the
+        // ring; the courier has usually put it there already
+        if (rr == 0 && valid && lane == 0 && g > 0 && t - 1 <= up_last && !stuck) {
           const unsigned long long c5 = a.prof ? clock64() : 0ull;
-          uint32_t v;
-          timeout = !receive_record(up_rec, t - 1, a.spin_limit, v);
-          stash_record(s_ring, v, t - 1, r0, W);
+          uint32_t spins = 0;
+          while (lds_acquire(&s_rcv) < t - 1) {
+            if (++spins > LDS_SPIN_LIMIT) {
+              stuck = true;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
           if (a.prof) t_rec += clock64() - c5;
         }
         // the three window pixels of this lane: ring reads, then scale reads,
@@ -790,6 +849,53 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           ++n_tiles;
         }
         if (valid) *reinterpret_cast<f4*>(&par[ln * PAR_STRIDE + 4 * q4]) = o;
+        if (L <= 4) {
+          // At most 4 pixels: row p of the wave (lanes 16 p + k) serves pixel
+          // p.  Lane k < 5 evaluates mixture component k (the head's two
+          // exponentials), lane 0 the softmax sum in the head's order, and lane
+          // h < 15 the boundary F(16 (h + 1)); every value equals the one
+          // mixture_head and cdf_F give.  LDS serves the wave's reads and
+          // writes in program order.
+          const int p = lane >> 4, k = lane & 15;
+          const int rp = j * L + p, yp = r0 + rp, xp = t - SKEW * yp;
+          const bool pv = p < L && rp < R && xp >= 0 && xp < W;
+          float* pp = &par[p * PAR_STRIDE];
+          if (pv && k < N_MIX) {
+            float lg[N_MIX];
+#pragma unroll
+            for (int i = 0; i < N_MIX; ++i) lg[i] = pp[i];
+            const float mu = pp[N_MIX + k], ls = pp[2 * N_MIX + k], ok = pp[k];
+            float m = lg[0];
+#pragma unroll
+            for (int i = 1; i < N_MIX; ++i) m = fmaxf(m, lg[i]);
+            const float e = expf(ok - m);
+            const float inv_s = expf(-fmaxf(ls, LOG_SCALE_MIN));
+            const float A = inv_s * 128.0f;
+            const float B = 2048.0f - mu * A;
+            pp[k] = e;
+            pp[N_MIX + k] = A;
+            pp[2 * N_MIX + k] = B;
+          }
+          if (pv && k < N_MIX) {
+            float sm = 0.0f;
+#pragma unroll
+            for (int i = 0; i < N_MIX; ++i) sm = sm + pp[i];
+            const float rs = 1.0f / sm;
+            const float e = pp[k];
+            pp[k] = e * rs;
+          }
+          if (a.prof) c_head = clock64();
+          if (pv && k < N_BUCKET) {
+            Mix mx;
+#pragma unroll
+            for (int i = 0; i < N_MIX; ++i) {
+              mx.pi[i] = pp[i];
+              mx.A[i] = pp[N_MIX + i];
+              mx.B[i] = pp[2 * N_MIX + i];
+            }
+            s_bk[slot_i][p * 16 + k] = (uint16_t)cdf_F(16 * (k + 1), mx, s_sd, s_beta);
+          }
+        } else {
         // mixture head, one lane per pixel
         if (lane < 16 && valid) {
           float* pp = &par[ln * PAR_STRIDE];
@@ -806,23 +912,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         }
         if (a.prof) c_head = clock64();
         // table at the bucket boundaries 16, 32, ..., 240
-        if (L <= 4) {
-          // one tile of at most 4 pixels: lane 4 (m - 1) + p computes F(16 m)
-          // of pixel p
-          const int p = lane & 3, mb = (lane >> 2) + 1;
-          const int rp = j * L + p, yp = r0 + rp, xp = t - SKEW * yp;
-          if (p < L && rp < R && xp >= 0 && xp < W && mb <= N_BUCKET) {
-            const float* pp = &par[p * PAR_STRIDE];
-            Mix mx;
-#pragma unroll
-            for (int k = 0; k < N_MIX; ++k) {
-              mx.pi[k] = pp[k];
-              mx.A[k] = pp[N_MIX + k];
-              mx.B[k] = pp[2 * N_MIX + k];
-            }
-            s_bk[slot_i][p * 16 + mb - 1] = (uint16_t)cdf_F(16 * mb, mx, s_sd, s_beta);
-          }
-        } else if (valid) {
+        if (valid) {
           // four boundaries per lane
           const float* pp = &par[ln * PAR_STRIDE];
           Mix mx;
@@ -838,6 +928,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
             const int mb = q4 + 4 * i + 1;
             if (mb <= N_BUCKET) bk[mb - 1] = (uint16_t)cdf_F(16 * mb, mx, s_sd, s_beta);
           }
+        }
         }
       }
       if (lane == 0) lds_release(&s_done[slot_i][ti], q);
