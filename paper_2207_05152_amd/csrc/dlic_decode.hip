@@ -1100,7 +1100,15 @@ template <int H>
 static bool launch_decode_h(int wtype, const Consts* K, const DevModel& m, const DecArgs& a,
                             hipStream_t s) {
   switch (wtype) {
-    case WT_F32: launch_decode_t<NetF32<H, (H >= 64)>, false>(K, m, a, s); return true;
+    case WT_F32:
+      // at H = 64, layouts of at most 4 lanes (one 16-pixel tile per
+      // sub-round, latency-bound) keep layer 2 in registers on 8 waves; wider
+      // ones need the 9 density waves of the 12-wave form
+      if (H == 64 && a.L <= 4)
+        launch_decode_t<NetF32<64, false>, false>(K, m, a, s);
+      else
+        launch_decode_t<NetF32<H, (H >= 64)>, false>(K, m, a, s);
+      return true;
     case WT_BF16: launch_decode_t<NetBF16<H, WT_BF16, (H > 64)>, false>(K, m, a, s); return true;
     case WT_FP8: launch_decode_t<NetBF16<H, WT_FP8, (H > 64)>, false>(K, m, a, s); return true;
     case WT_FP8A8: launch_decode_t<NetFP8A<H, (H > 64)>, false>(K, m, a, s); return true;
