@@ -43,6 +43,26 @@ def test_batch_streams_equal_single_image_streams(dev, dtype, width):
     b.close()
 
 
+@pytest.mark.parametrize("dtype,width", [("fp32", 64), ("bf16", 64), ("fp32", 32)])
+def test_batch_small_lane_layouts(dev, dtype, width):
+    # 1 to 4 lanes per group: the decoder's coder gives each pixel 16 lanes
+    model = dl.Model(synth.xavier_mlp((12, width, width, 15), 5), dev, dtype=dtype)
+    coders = [(max(1, min(h // 8, 6)), 1 + i % 4) for i, (h, w) in enumerate(SIZES)]
+    imgs = _images(SIZES, 700)
+    say("batch small lanes", dtype, width)
+    b = dl.Batch(model, SIZES, coders=coders)
+    b.load(imgs)
+    b.encode()
+    b.decode()
+    torch.cuda.synchronize()
+    assert np.array_equal(b.status.cpu().numpy(), np.zeros(len(SIZES)))
+    for i, img in enumerate(imgs):
+        want = _single(img, model, dl.dlic_coder(*coders[i]), dev)
+        assert np.array_equal(b.stream(i).cpu().numpy(), want), i
+        assert np.array_equal(b.image(i).cpu().numpy(), img), i
+    b.close()
+
+
 def test_batch_default_layout_and_work_order(dev):
     model = dl.Model(synth.xavier_mlp((12, 32, 32, 15), 7), dev)
     sizes = [(300, 40), (16, 16), (193, 20), (385, 12)]

@@ -20,9 +20,10 @@ def _roundtrip(dev, img, width, coder):
     return m, bits, out.cpu().numpy(), st
 
 
-def test_timeout_of_upstream_wait_is_reported_and_recoverable(dev):
+@pytest.mark.parametrize("L", [8, 4])
+def test_timeout_of_upstream_wait_is_reported_and_recoverable(dev, L):
     img = synth.synth_image(96, 300, 5)
-    coder = dl.dlic_coder(4, 8)
+    coder = dl.dlic_coder(4, L)
     m = dl.Model(synth.xavier_mlp((12, 32, 32, 15), 3), dev)
     bits = dl.encode(to_dev(img, dev), m, coder)
     torch.cuda.synchronize()
