@@ -145,6 +145,14 @@ __device__ __forceinline__ uint32_t row16_min(uint32_t v) {
   return min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x121, 0xF, 0xF, false));
 }
 
+// Shader clock, waited for at once: a clock read left in flight would make
+// later LDS waits wait for everything (the scalar read completes out of order).
+__device__ __forceinline__ unsigned long long clk_now() {
+  const unsigned long long c = clock64();
+  asm volatile("" ::"s"(c));
+  return c;
+}
+
 // Bin edge beta_v = RN((2v - 256) / 255) of 0 < v < 256 without the table:
 // one product by RN(1/255) and two fused corrections give the correctly
 // rounded quotient for every integer numerator in [-256, 256].
@@ -262,11 +270,13 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     // F(v + 1).  F rises strictly with the level, so the levels at or below
     // the slot are a prefix of the row and the packed (count, F) key of the
     // last of them is the maximum.
-    // A sub-round waits on few LDS round trips: the density flag, the pixel's
-    // parameters and boundary and the next four stream words are read in one
-    // batch (LDS serves a wave's accesses in order, so data read after the
-    // flag was written before it); bin edges are computed, not read; the
-    // renormalising word is picked from the batch; the work is branch-free.
+    // A sub-round waits on few LDS round trips: the density flag and the
+    // pixel's parameters and boundary are read in one batch (LDS serves a
+    // wave's accesses in order, so data read after the flag was written
+    // before it), and the batch of sub-round q + 1 is issued while sub-round q
+    // waits for its table reads; bin edges are computed, not read; stream
+    // words come from a 64-word register window (lane i holds word base + i);
+    // the work is branch-free.
     const int cl = lane >> 4, h = lane & 15;
     uint32_t x = RANS_L;
     if (cl < L && !bad) x = (uint32_t)gw[2 * cl] | ((uint32_t)gw[2 * cl + 1] << 16);
@@ -275,13 +285,21 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     const bool timeout = s_flag != 0;
     uint32_t E = E0;
     int t = t_first, j = -1, pub = t_first - 1;
-    const unsigned long long k0 = a.prof ? clock64() : 0ull;
+    const unsigned long long k0 = a.prof ? clk_now() : 0ull;
     const unsigned long long rt0 = a.prof ? __builtin_amdgcn_s_memrealtime() : 0ull;
     const uint64_t row_heads = 0x0001000100010001ull;
     // sub-rounds whose densities were not there yet (high half: of them at
     // block 0) and the cycles spent waiting for them
     unsigned long long n_late = 0, t_late = 0;
     const uint64_t below = (1ull << (16 * cl)) - 1ull;
+    // stream words wbase .. wbase + 63, one per lane (the ring holds at least
+    // min(n_words, 4096) words at the start)
+    uint32_t wbase = Pw;
+    uint32_t wwin = s_words[(wbase + (uint32_t)lane) & RING_MASK];
+    // the batch of sub-round pre_q, issued during the sub-round before it
+    int pre_q = -1, nd = 0;
+    f4 n0 = {0.0f, 0.0f, 0.0f, 0.0f}, n1 = n0, n2 = n0, n3 = n0;
+    uint32_t nFb = 0;
     for (int q = 0; q < P; ++q) {
       if (++j == J) {
         j = 0;
@@ -299,30 +317,47 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         }
       }
       if (j == 0 && !stuck) stuck = !wait_publisher(&s_pub, t, pub);
+      if (Pw + 4u > wbase + 64u) {
+        // the ring holds min(n_words, Pw + 64) words by now
+        wbase = Pw;
+        wwin = s_words[(wbase + (uint32_t)lane) & RING_MASK];
+      }
       const int rr = j * L + cl;
       const int y = r0 + rr;
       const int xc = t - SKEW * y;
       const bool act = cl < L && rr < R && xc >= 0 && xc < W;
       const int slot_i = q & (NSLOT - 1);
-      const unsigned long long c0 = a.prof ? clock64() : 0ull;
+      const unsigned long long c0 = a.prof ? clk_now() : 0ull;
       unsigned long long c1 = c0;
       if (__ballot(act) != 0ull && !stuck) {
         const f4* pq = reinterpret_cast<const f4*>(&s_par[slot_i][cl * PAR_STRIDE]);
         const uint16_t* pb = &s_bk[slot_i][cl * 16 + h];
-        int d = __hip_atomic_load(&s_done[slot_i][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        asm volatile("" ::: "memory");
-        f4 p0 = pq[0], p1 = pq[1], p2 = pq[2], p3 = pq[3];
-        uint32_t Fb = *pb;
-        uint32_t wd[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) wd[k] = s_words[(Pw + (uint32_t)k) & RING_MASK];
+        int d;
+        f4 p0, p1, p2, p3;
+        uint32_t Fb;
+        if (pre_q == q) {
+          d = nd;
+          p0 = n0;
+          p1 = n1;
+          p2 = n2;
+          p3 = n3;
+          Fb = nFb;
+        } else {
+          d = __hip_atomic_load(&s_done[slot_i][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          asm volatile("" ::: "memory");
+          p0 = pq[0];
+          p1 = pq[1];
+          p2 = pq[2];
+          p3 = pq[3];
+          Fb = *pb;
+        }
         // keep the batch together: one wait for all of it, no reload merged
         // into the rare path below
         asm volatile("" : "+v"(p0), "+v"(p1), "+v"(p2), "+v"(p3), "+v"(Fb), "+v"(d));
         // the flag is one LDS word read by every lane: decide on lane 0's copy
         if (__builtin_amdgcn_readfirstlane(d) != q) {
           n_late += j == 0 ? (1ull << 32) + 1ull : 1ull;
-          const unsigned long long cw = a.prof ? clock64() : 0ull;
+          const unsigned long long cw = a.prof ? clk_now() : 0ull;
           uint32_t spins = 0;
           while ((d = __hip_atomic_load(&s_done[slot_i][0], __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_WORKGROUP)) != q) {
@@ -337,9 +372,9 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           p2 = pq[2];
           p3 = pq[3];
           Fb = *pb;
-          if (a.prof) t_late += clock64() - cw;
+          if (a.prof) t_late += clk_now() - cw;
         }
-        if (a.prof) c1 = clock64();
+        if (a.prof) c1 = clk_now();
         const float pv[16] = {p0[0], p0[1], p0[2], p0[3], p1[0], p1[1], p1[2], p1[3],
                               p2[0], p2[1], p2[2], p2[3], p3[0], p3[1], p3[2], p3[3]};
         const uint32_t slot = x & 0xFFFFu;
@@ -348,7 +383,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         const bool le = Fb <= slot;
         const uint32_t klo = row16_max(le ? (((uint32_t)(h + 1) << 17) | Fb) : 0u);
         const uint32_t Fhi = row16_min(le ? M_TOTAL : Fb);
-        if (a.prof) c_ld = clock64();
+        if (a.prof) c_ld = clk_now();
         const int base = 16 * min((int)(klo >> 17), N_BUCKET);
         const int lv = base + h + 1;  // <= 256; lane 15's value is not used
         // C(beta_lv) in the format's order, the five table reads together
@@ -366,6 +401,24 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         float2 e[N_MIX];
 #pragma unroll
         for (int k = 0; k < N_MIX; ++k) e[k] = s_sd[ji[k]];
+        // the batch of the next sub-round goes out behind the table reads
+        // (unconditionally, so that the wait for the table reads can leave it
+        // in flight; past the last sub-round it is not used)
+        {
+          const int sn = (q + 1) & (NSLOT - 1);
+          __builtin_amdgcn_sched_barrier(0);
+          nd = __hip_atomic_load(&s_done[sn][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          __builtin_amdgcn_sched_barrier(0);
+          const f4* nq = reinterpret_cast<const f4*>(&s_par[sn][cl * PAR_STRIDE]);
+          n0 = nq[0];
+          n1 = nq[1];
+          n2 = nq[2];
+          n3 = nq[3];
+          nFb = s_bk[sn][cl * 16 + h];
+          pre_q = q + 1;
+        }
+        // the table values are used only from here on, with the batch in flight
+        __builtin_amdgcn_sched_barrier(0);
         float sg[N_MIX];
 #pragma unroll
         for (int k = 0; k < N_MIX; ++k) sg[k] = e[k].x + wf[k] * e[k].y;
@@ -374,7 +427,11 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         clo = clo + pv[2] * sg[2];
         float chi = pv[3] * sg[3];
         chi = chi + pv[4] * sg[4];
-        const uint32_t Fk = h < N_BUCKET ? F_of_C(lv, clo + chi) : Fhi;
+        // every lane evaluates (lane 15's value is dropped), so that no
+        // branch makes the wait for the table reads also wait for the batch
+        uint32_t Fe = F_of_C(lv, clo + chi);
+        __builtin_amdgcn_sched_barrier(0);
+        const uint32_t Fk = h < N_BUCKET ? Fe : Fhi;
         const bool le2 = Fk <= slot;
         const uint32_t k2 = row16_max(le2 ? (((uint32_t)(h + 1) << 17) | Fk) : 0u);
         const uint32_t F2 = row16_min(le2 ? M_TOTAL : Fk);
@@ -382,13 +439,18 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         const int v = base + cnt;
         const uint32_t c = cnt > 0 ? (k2 & 0x1FFFFu) : (klo & 0x1FFFFu);
         const uint32_t f = F2 - c;
-        if (a.prof) c_sr = clock64();
+        if (a.prof) c_sr = clk_now();
         // f <= 2^16 - 255 and x >> 16 < 2^16: the 24-bit multiplier is exact
         const uint32_t xd = __umul24(f, x >> 16) + slot - c;
         const bool ren = act && !bad && xd < RANS_L;
         const uint64_t mr = __ballot(ren) & row_heads;
         const uint32_t rk = (uint32_t)__popcll(mr & below);
-        uint32_t w = rk == 0 ? wd[0] : (rk == 1 ? wd[1] : (rk == 2 ? wd[2] : wd[3]));
+        const int wo = (int)(Pw - wbase);  // <= 60
+        const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)wwin, wo);
+        const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)wwin, wo + 1);
+        const uint32_t w2 = (uint32_t)__builtin_amdgcn_readlane((int)wwin, wo + 2);
+        const uint32_t w3 = (uint32_t)__builtin_amdgcn_readlane((int)wwin, wo + 3);
+        uint32_t w = rk == 0 ? w0 : (rk == 1 ? w1 : (rk == 2 ? w2 : w3));
         const bool past = ren && Pw + rk >= n_words;
         over = over || past;
         w = past ? 0u : w;
@@ -403,7 +465,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         __hip_atomic_store(&s_decoded, q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
       if (a.prof) {
-        const unsigned long long c2 = clock64();
+        const unsigned long long c2 = clk_now();
         t_wait += c1 - c0;
         if (j == 0) t_wait0 += c1 - c0;
         t_busy += c2 - c1;
@@ -426,7 +488,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         a.prof[g * PROF_SLOTS + 9] = t_search;
         a.prof[g * PROF_SLOTS + 10] = (unsigned long long)P;
         a.prof[g * PROF_SLOTS + 12] = t_late;
-        a.prof[g * PROF_SLOTS + 13] = clock64() - k0;
+        a.prof[g * PROF_SLOTS + 13] = clk_now() - k0;
         a.prof[g * PROF_SLOTS + 14] = __builtin_amdgcn_s_memrealtime() - rt0;
         a.prof[g * PROF_SLOTS + 15] = n_late;
       }
