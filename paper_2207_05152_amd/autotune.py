@@ -27,7 +27,8 @@ import time
 
 DEFAULT = {"rows_per_group": 192, "lanes": 32, "density_grid": 0}
 # (rows per group, lanes) pairs, the likeliest first in case the budget ends
-LAYOUTS = ((24, 4), (12, 2), (48, 4), (96, 64), (64, 64), (96, 32), (192, 32), (64, 32))
+LAYOUTS = ((96, 32), (12, 4), (16, 4), (24, 4), (96, 64), (64, 64), (64, 32), (192, 32),
+           (12, 2))
 GRIDS = (0, 2048)
 
 
