@@ -196,15 +196,20 @@ bool launch_activation_range(int width, const Consts* K, const DevModel& m, cons
 constexpr int ENC_CHUNK = 32;   // wavefront steps staged in LDS per chunk
 constexpr int ENC_BATCH = 8;    // sub-rounds read from LDS ahead of coding
 constexpr int ENC_STAGERS = 192;  // threads of waves 1..3
-constexpr int ENC_PER_STAGER = (ENC_CHUNK * DEC_RMAX + ENC_STAGERS - 1) / ENC_STAGERS;
+constexpr int ENC_ROWS = DEC_RMAX + 64;  // J * L <= rows + L - 1 rows per step, padded
+constexpr int ENC_SLOTS = ENC_CHUNK * ENC_ROWS;
+constexpr int ENC_PER_STAGER = (ENC_SLOTS + ENC_STAGERS - 1) / ENC_STAGERS;
 
 // One group's rANS walk (one workgroup of 4 waves).  Wave 0 codes; while it
 // walks one chunk of 32 steps in reverse canonical order from LDS, waves 1..3
 // stage the next chunk's intervals, all of a thread's loads issued before any
-// LDS store so their latencies overlap.  Words go below the top of the
+// LDS store so their latencies overlap.  They store them in the order the
+// coder reads them: sub-round i of the chunk's reverse walk at [i * L, i * L
+// + L), inactive slots (rows past the group, steps before its first) marked,
+// so the coder's reads are one running index.  Words go below the top of the
 // group's scratch slice (cap_g = R*W + 2L words, the worst case), so a stream
 // is contiguous at [cap_g - count, cap_g).
-__device__ __forceinline__ void rans_encode_group(uint32_t (*s_cf)[ENC_CHUNK * DEC_RMAX],
+__device__ __forceinline__ void rans_encode_group(uint32_t (*s_cf)[ENC_SLOTS],
                                                   const uint32_t* __restrict__ cf, int H, int W,
                                                   int G, int L, int g,
                                                   uint16_t* __restrict__ words,
@@ -218,7 +223,10 @@ __device__ __forceinline__ void rans_encode_group(uint32_t (*s_cf)[ENC_CHUNK * D
   const int t_first = SKEW * r0, t_last = SKEW * (r1 - 1) + W - 1;
   const int n_chunks = R > 0 ? (t_last - t_first + ENC_CHUNK) / ENC_CHUNK : 0;
 
-  // chunk c holds steps [t_last - 32c - 31, t_last - 32c] as [k][row], k = t - t_lo
+  // chunk c holds steps [t_last - 32c - 31, t_last - 32c]; the interval of
+  // step t_lo + k, row j * L + l of the group goes to slot i * L + l with
+  // i = (31 - k) * J + (J - 1 - j), its sub-round in the reverse walk
+  const int JL = J * L;  // <= R + L - 1 <= ENC_ROWS - 1
   auto stage = [&](int c, uint32_t* buf, int first, int stride) {
     const int t_lo = t_last - ENC_CHUNK * c - (ENC_CHUNK - 1);
     uint32_t v[ENC_PER_STAGER];
@@ -227,16 +235,17 @@ __device__ __forceinline__ void rans_encode_group(uint32_t (*s_cf)[ENC_CHUNK * D
       const int idx = first + i * stride;
       const int rr = idx / ENC_CHUNK, k = idx - rr * ENC_CHUNK;
       const int y = r0 + rr, t = t_lo + k, x = t - SKEW * y;
-      v[i] = (idx < R * ENC_CHUNK && t >= t_first && x >= 0 && x < W)
+      v[i] = (idx < JL * ENC_CHUNK && rr < R && t >= t_first && x >= 0 && x < W)
                  ? cf[(long long)y * W + x]
                  : INACTIVE;
     }
 #pragma unroll
     for (int i = 0; i < ENC_PER_STAGER; ++i) {
       const int idx = first + i * stride;
-      if (idx < R * ENC_CHUNK) {
+      if (idx < JL * ENC_CHUNK) {
         const int rr = idx / ENC_CHUNK, k = idx - rr * ENC_CHUNK;
-        buf[k * DEC_RMAX + rr] = v[i];
+        const int jb = rr / L, l = rr - jb * L;
+        buf[((ENC_CHUNK - 1 - k) * J + (J - 1 - jb)) * L + l] = v[i];
       }
     }
   };
@@ -250,22 +259,14 @@ __device__ __forceinline__ void rans_encode_group(uint32_t (*s_cf)[ENC_CHUNK * D
       if (c + 1 < n_chunks) stage(c + 1, s_cf[(c + 1) & 1], tid - 64, ENC_STAGERS);
     } else {
       const uint32_t* buf = s_cf[c & 1];
-      const int t_lo = t_last - ENC_CHUNK * c - (ENC_CHUNK - 1);
-      int k = ENC_CHUNK - 1, j = J - 1;
-      const int n_sub = ENC_CHUNK * J;
+      const int n_sub = ENC_CHUNK * J;  // a multiple of ENC_BATCH
       for (int s0 = 0; s0 < n_sub; s0 += ENC_BATCH) {
         uint32_t v[ENC_BATCH];
 #pragma unroll
         for (int i = 0; i < ENC_BATCH; ++i) {
-          const int rr = j * L + lane;
-          const bool ok = s0 + i < n_sub && t_lo + k >= t_first && lane < L && rr < R;
           // read an in-bounds slot unconditionally, then select
-          const uint32_t w = buf[max(k, 0) * DEC_RMAX + min(rr, DEC_RMAX - 1)];
-          v[i] = ok ? w : INACTIVE;
-          if (--j < 0) {
-            j = J - 1;
-            --k;
-          }
+          const uint32_t w = buf[min((s0 + i) * L + lane, ENC_SLOTS - 1)];
+          v[i] = lane < L ? w : INACTIVE;
         }
 #pragma unroll
         for (int i = 0; i < ENC_BATCH; ++i) {
@@ -291,13 +292,13 @@ __global__ __launch_bounds__(256) void rans_encode_kernel(const uint32_t* __rest
                                                           int W, int G, int L,
                                                           uint16_t* __restrict__ words,
                                                           uint32_t* __restrict__ counts) {
-  __shared__ uint32_t s_cf[2][ENC_CHUNK * DEC_RMAX];
+  __shared__ uint32_t s_cf[2][ENC_SLOTS];
   rans_encode_group(s_cf, cf, H, W, G, L, blockIdx.x, words, counts);
 }
 
 // Batched form: workgroup i codes work item i (image, group).
 __global__ __launch_bounds__(256) void batch_rans_encode_kernel(BatchArgs b) {
-  __shared__ uint32_t s_cf[2][ENC_CHUNK * DEC_RMAX];
+  __shared__ uint32_t s_cf[2][ENC_SLOTS];
   const BatchItem it = b.items[blockIdx.x];
   const BatchImage im = b.images[it.image];
   rans_encode_group(s_cf, b.cf + im.px_off, im.H, im.W, im.G, im.L, it.group,
