@@ -310,6 +310,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed steps, run one plain elementwise copy of MIB MiB "
                          "(FP32 negation) so that counter runs can scale FETCH_SIZE/WRITE_SIZE")
+    ap.add_argument("--no-decode-profile", action="store_true",
+                    help="skip the extra decode with the in-kernel cycle counters (so that a "
+                         "profiler's kernel averages cover the timed launches only)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision, batch and training sweeps after the headline step")
     args = ap.parse_args()
@@ -377,10 +380,11 @@ def main():
 
     # one more decode with the in-kernel cycle counters on (outside the timed region)
     prof = torch.zeros(16 * args.groups, dtype=torch.int64, device="cuda")
-    dl.dlic_set_decode_profile(prof)
-    dl.dlic_decode(model.c, coder, out, n_bytes, dec, H, W, st, dws, dws.numel(), stream)
-    torch.cuda.synchronize()
-    dl.dlic_set_decode_profile(None)
+    if not args.no_decode_profile:
+        dl.dlic_set_decode_profile(prof)
+        dl.dlic_decode(model.c, coder, out, n_bytes, dec, H, W, st, dws, dws.numel(), stream)
+        torch.cuda.synchronize()
+        dl.dlic_set_decode_profile(None)
     pc = prof.view(args.groups, 16).cpu().numpy().astype(np.float64)
     busy = pc[:, 0] + pc[:, 1]
     tiles = max(pc[:, 7].sum(), 1)
