@@ -339,7 +339,7 @@ int dlic_kernel_times(float *h_ms, const char **h_names, int max_n);
  * [6] bucket boundaries + publish, then [7] the number of tiles; of the
  * coder's busy time [8] from the densities' arrival to the start of the
  * symbol search, [9] the search itself, and [10] the group's sub-rounds;
- * [11] density waves waiting for the group above's records, [12] the coder's
+ * [11] unused (0), [12] the coder's
  * wait at the first block of each step (with 16 lanes per pixel: its cycles
  * waiting for densities not ready when first read), [13] the coder loop's
  * shader-clock cycles and [14] its duration in 100 MHz real-time ticks, [15]

@@ -153,16 +153,18 @@ __device__ __forceinline__ unsigned long long clk_now() {
   return c;
 }
 
-// Bin edge beta_v = RN((2v - 256) / 255) of 0 < v < 256 without the table:
-// one product by RN(1/255) and two fused corrections give the correctly
-// rounded quotient for every integer numerator in [-256, 256].
-__device__ __forceinline__ float bin_edge(int v) {
-  const float xv = (float)(2 * v - 256);
+// RN(n / 255) for an integer n in [-256, 256] without a table: one product
+// by RN(1/255) and two fused corrections give the correctly rounded quotient
+// for every such n.  Bin edges beta_v = RN((2v - 256) / 255) and scaled grey
+// levels RN((2v - 255) / 255) (the host's tables) are both of this form.
+__device__ __forceinline__ float div255(int n) {
+  const float xv = (float)n;
   const float r = 1.0f / 255.0f;
   const float q0 = xv * r;
   const float e = __builtin_fmaf(-q0, 255.0f, xv);
   return __builtin_fmaf(e, r, q0);
 }
+__device__ __forceinline__ float bin_edge(int v) { return div255(2 * v - 256); }
 
 // Decode of group g of one stream by the whole workgroup.  LPP is
 // coder_lpp(L): how many coder lanes share each pixel's symbol search.
@@ -171,7 +173,6 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
                                              const DecArgs& a, const int g) {
   __shared__ float2 s_sd[LUT_N];
   __shared__ __attribute__((aligned(16))) float s_beta[260];
-  __shared__ float s_scale[256];
   __shared__ __attribute__((aligned(16))) float s_par[NSLOT][SLOT_PX * PAR_STRIDE];
   __shared__ __attribute__((aligned(16))) uint16_t s_bk[NSLOT][SLOT_PX * 16];
   __shared__ uint8_t s_ring[(DEC_RMAX + 2) * 16];
@@ -192,7 +193,6 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
   if (!TABLES) {
     for (int i = tid; i < LUT_N; i += NTH) s_sd[i] = K->sd[i];
     for (int i = tid; i < 257; i += NTH) s_beta[i] = K->beta[i];
-    for (int i = tid; i < 256; i += NTH) s_scale[i] = K->scale[i];
     Net::stage(m, s_w2, tid, NTH);
   }
   if (tid < NSLOT * 4) s_done[tid / 4][tid % 4] = -1;
@@ -582,7 +582,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     bool over = false, stuck = false, timeout = s_flag != 0;
     uint32_t E = E0;                   // words known to be in the ring
     int t = t_first, j = -1, pub = t_first - 1;
-    const unsigned long long k0 = a.prof ? clock64() : 0ull;
+    const unsigned long long k0 = a.prof ? clk_now() : 0ull;
     const unsigned long long rt0 = a.prof ? __builtin_amdgcn_s_memrealtime() : 0ull;
     for (int q = 0; q < P; ++q) {
       if (++j == J) {
@@ -622,7 +622,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       const bool act = cl < L && rr < R && xc >= 0 && xc < W;
       const bool any = __ballot(act) != 0ull;
       const int slot_i = q & (NSLOT - 1);
-      const unsigned long long c0 = a.prof ? clock64() : 0ull;
+      const unsigned long long c0 = a.prof ? clk_now() : 0ull;
       if (!TABLES && any && !stuck) {
         // all tiles' flags in one round of relaxed loads, then one acquire
         uint32_t spins = 0;
@@ -643,7 +643,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       }
-      const unsigned long long c1 = a.prof ? clock64() : 0ull;
+      const unsigned long long c1 = a.prof ? clk_now() : 0ull;
       if (any) {
         const uint32_t slot = x & 0xFFFFu;
         int v = 0;
@@ -721,7 +721,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
             be[4 * i + 2] = v4[2];
             be[4 * i + 3] = v4[3];
           }
-          if (a.prof) c_ld = clock64();
+          if (a.prof) c_ld = clk_now();
           int off = 0;
 #pragma unroll
           for (int it = 0; it < 4; ++it) {
@@ -753,7 +753,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           v = lo;
           c = Flo;
           f = Fhi - Flo;
-          if (a.prof) c_sr = clock64();
+          if (a.prof) c_sr = clk_now();
         }
         // f <= 2^16 - 255 and x >> 16 < 2^16: the 24-bit multiplier is exact
         if (act) x = __umul24(f, x >> 16) + slot - c;
@@ -771,7 +771,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         lds_release(&s_decoded, q + 1);
       }
       if (a.prof) {
-        const unsigned long long c2 = clock64();
+        const unsigned long long c2 = clk_now();
         t_wait += c1 - c0;
         if (j == 0) t_wait0 += c1 - c0;
         t_busy += c2 - c1;
@@ -803,7 +803,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         a.prof[g * PROF_SLOTS + 9] = t_search;
         a.prof[g * PROF_SLOTS + 10] = (unsigned long long)P;
         a.prof[g * PROF_SLOTS + 12] = t_wait0;
-        a.prof[g * PROF_SLOTS + 13] = clock64() - k0;
+        a.prof[g * PROF_SLOTS + 13] = clk_now() - k0;
         a.prof[g * PROF_SLOTS + 14] = __builtin_amdgcn_s_memrealtime() - rt0;
       }
     }
@@ -817,7 +817,6 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     net.load(m, lane);
     const int q4 = lane >> 4;
     unsigned long long t_net = 0, t_head = 0, t_tab = 0, n_tiles = 0, c_net = 0, c_head = 0;
-    unsigned long long t_rec = 0;
     bool timeout = s_flag != 0;
     bool stuck = false;
     // tile tau = NT * q + ti of sub-round q = (t - t_first) * J + j, every nwork-th
@@ -832,7 +831,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       if (q >= P) break;
       const int slot_i = q & (NSLOT - 1);
       const int need = max(q - J + 1, q - NSLOT + 1);
-      const unsigned long long c0 = a.prof ? clock64() : 0ull;
+      const unsigned long long c0 = a.prof ? clk_now() : 0ull;
       if (!stuck) {
         uint32_t spins = 0;
         while (lds_acquire(&s_decoded) < need) {
@@ -843,7 +842,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           __builtin_amdgcn_s_sleep(1);
         }
       }
-      const unsigned long long c1 = a.prof ? clock64() : 0ull;
+      const unsigned long long c1 = a.prof ? clk_now() : 0ull;
       // density wave 0 keeps the stream ring ahead of the coder
       if (w == 0 && !bad) {
         const uint32_t end = s_end;
@@ -872,7 +871,6 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         // the tile holding row r0 needs the group above's step t-1 in the
         // ring; the courier has usually put it there already
         if (rr == 0 && valid && lane == 0 && g > 0 && t - 1 <= up_last && !stuck) {
-          const unsigned long long c5 = a.prof ? clock64() : 0ull;
           uint32_t spins = 0;
           while (lds_acquire(&s_rcv) < t - 1) {
             if (++spins > LDS_SPIN_LIMIT) {
@@ -881,11 +879,10 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
             }
             __builtin_amdgcn_s_sleep(1);
           }
-          if (a.prof) t_rec += clock64() - c5;
         }
-        // the three window pixels of this lane: ring reads, then scale reads,
-        // each issued together (a neighbour outside the image reads ring slot 0
-        // and is replaced by 0)
+        // the three window pixels of this lane, read together (a neighbour
+        // outside the image reads ring slot 0 and is replaced by 0), scaled
+        // arithmetically to the table's value
         float fk[3];
         bool inside[3];
         uint32_t pv[3];
@@ -898,16 +895,16 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         }
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) {
-          const float sv = s_scale[pv[kk]];
+          const float sv = div255((int)(2 * pv[kk]) - 255);
           fk[kk] = inside[kk] ? sv : 0.0f;
         }
-        // the left neighbour (decoded last step) goes to the image now
+        const f4 o = net.run(fk[0], fk[1], fk[2], s_w2);
+        // the left neighbour (decoded last step) goes to the image
         if (valid && q4 == 0 && xc >= 1)
           a.img[(long long)y * W + xc - 1] = s_ring[(rr + 2) * 16 + ((xc - 1) & 15)];
-        const f4 o = net.run(fk[0], fk[1], fk[2], s_w2);
         float* par = &s_par[slot_i][0];
         if (a.prof) {
-          c_net = clock64();
+          c_net = clk_now();
           ++n_tiles;
         }
         if (valid) *reinterpret_cast<f4*>(&par[ln * PAR_STRIDE + 4 * q4]) = o;
@@ -946,7 +943,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
             const float e = pp[k];
             pp[k] = e * rs;
           }
-          if (a.prof) c_head = clock64();
+          if (a.prof) c_head = clk_now();
           if (pv && k < N_BUCKET) {
             Mix mx;
 #pragma unroll
@@ -972,7 +969,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
             pp[2 * N_MIX + k] = mx.B[k];
           }
         }
-        if (a.prof) c_head = clock64();
+        if (a.prof) c_head = clk_now();
         // table at the bucket boundaries 16, 32, ..., 240
         if (valid) {
           // four boundaries per lane
@@ -995,7 +992,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       }
       if (lane == 0) lds_release(&s_done[slot_i][ti], q);
       if (a.prof) {
-        const unsigned long long c2 = clock64();
+        const unsigned long long c2 = clk_now();
         t_wait += c1 - c0;
         t_busy += c2 - c1;
         if (c_net) {
@@ -1026,7 +1023,6 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         atomicAdd(&a.prof[g * PROF_SLOTS + 5], t_head);
         atomicAdd(&a.prof[g * PROF_SLOTS + 6], t_tab);
         atomicAdd(&a.prof[g * PROF_SLOTS + 7], n_tiles);
-        atomicAdd(&a.prof[g * PROF_SLOTS + 11], t_rec);
       }
     }
   }
