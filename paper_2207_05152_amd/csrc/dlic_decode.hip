@@ -898,10 +898,10 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           const float sv = div255((int)(2 * pv[kk]) - 255);
           fk[kk] = inside[kk] ? sv : 0.0f;
         }
-        const f4 o = net.run(fk[0], fk[1], fk[2], s_w2);
         // the left neighbour (decoded last step) goes to the image
         if (valid && q4 == 0 && xc >= 1)
           a.img[(long long)y * W + xc - 1] = s_ring[(rr + 2) * 16 + ((xc - 1) & 15)];
+        const f4 o = net.run(fk[0], fk[1], fk[2], s_w2);
         float* par = &s_par[slot_i][0];
         if (a.prof) {
           c_net = clk_now();
