@@ -24,6 +24,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MI355X_FP32_MFMA = 157.3e12
+
+# The paper's own timings, printed beside ours as context only: other hardware,
+# other (trained, larger) networks, a softmax head and other images.
+_MRI_PX = 256 * 256 * 35
+_MRI_COMPLETE_S = [0.3374, 0.3946, 0.5997, 1.4250, 7.1203]
+PAPER_CONTEXT = {
+    "note": "context only, not a target: other hardware, networks, output head and data",
+    "image_coding": {
+        "hardware": "Ryzen 5 2600 CPU + GTX 1070 Ti GPU",
+        "encode_s_per_image": "< 1 (smallest net, about 1e5 parameters; mean of 10 runs)",
+        "decode_vs_encode": "within 4%",
+        "source": "Section III-B, Fig. 3 (image and network sizes only in the figure)",
+    },
+    "mri_estimated": {
+        "scan": "256x256x35, 12-bit",
+        "params": [3.5e5, 1.35e6, 5.33e6, 1.75e7, 9.2e7],
+        "first_frame_s": [0.2799, 0.3273, 0.4975, 1.1821, 5.9286],
+        "complete_s": _MRI_COMPLETE_S,
+        "complete_mpix_s": [round(_MRI_PX / t / 1e6, 3) for t in _MRI_COMPLETE_S],
+        "hardware": "not named for these estimates",
+        "source": "Section IV-D, Table III",
+    },
+}
 MI355X_CUS = 256
 
 
@@ -318,7 +341,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the DLIC hot path here runs on a single MI355X "
-              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+              "(no multi-GPU path is built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -467,6 +490,7 @@ def main():
         },
         "decode_profile": decode_profile,
         "host": {"cpu": platform.processor() or platform.machine(), "os_cpus": os.cpu_count()},
+        "paper_context": PAPER_CONTEXT,
     }
     if not args.no_extras:
         res["layouts"] = layout_sweep(dl, torch, img, H, W, model)

@@ -48,7 +48,7 @@ typedef enum {
   DLIC_ERR_CAPACITY = 2,       /* output or workspace buffer too small           */
   DLIC_ERR_CORRUPT = 3,        /* stream malformed or inconsistent (device)      */
   DLIC_ERR_MODEL_MISMATCH = 4, /* stream coded with another model (device)       */
-  DLIC_ERR_UNSUPPORTED = 5,    /* dims, dtype or layout this build does not run  */
+  DLIC_ERR_UNSUPPORTED = 5,    /* dims, dtype or layout the library does not run */
   DLIC_ERR_HIP = 6,            /* HIP runtime error or no usable device          */
   DLIC_ERR_TIMEOUT = 7         /* a decode wait exceeded its spin limit (device) */
 } dlic_status;

@@ -6,7 +6,7 @@ Paper passages followed:
     (encoder and decoder must evaluate the same network), not of the stream.
   * Section III-A: rates are quoted excluding header information.
 
-The paper defines no container.  Reading, little-endian:
+The paper defines no container.  Our reading, little-endian:
   36-byte header  "DLIC" | u16 version=1 | u16 flags=0 | u32 H | u32 W |
                   u8 k_in=12 | u8 n_mix=5 | u8 dtype | u8 skew=3 |
                   u16 h1 | u16 h2 | u8 prob_bits=16 | u8 lanes per group |

@@ -8,7 +8,7 @@ Paper passages followed:
     floating-point results, so the table rule must be evaluated the same
     way on both sides.
 
-The paper does not state the quantisation.  Reading:
+The paper does not state the quantisation.  Our reading:
 M = 2^16, M' = M - 256 = 65280, and for the cumulative table
     F(0) = 0, F(256) = M,  F(v) = v + min(M', floor(C(beta_v) * M'))  (v = 1..255)
 so every symbol gets frequency f_v = F(v+1) - F(v) >= 1 and the table sums

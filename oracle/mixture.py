@@ -8,7 +8,7 @@ Paper passages followed:
   * Section III-A: the validation loss in bits per pixel measures the rate
     excluding header information.
 
-Readings: level v owns the interval [beta_v, beta_{v+1}) with
+Readings where the paper is silent: level v owns the interval [beta_v, beta_{v+1}) with
 beta_v = (2v - 1)/255 - 1 for v = 1..255, beta_0 = -inf, beta_256 = +inf,
 so the two end bins are open and the 256 masses sum to one exactly.
 

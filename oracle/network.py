@@ -10,7 +10,7 @@ Paper passages followed:
   * Section I and Section IV-B/IV-C (Higher Bit Depth): the alternative
     output is a (discretised) mixture of logistics as in PixelCNN++.
 
-Readings: outputs are ordered [5 mixture logits, 5 means,
+Readings where the paper is silent: outputs are ordered [5 mixture logits, 5 means,
 5 log-scales]; means live in the scaled [-1, 1] domain; log-scales are
 clamped below at -7; inverse scale = exp(-log_scale).
 

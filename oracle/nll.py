@@ -5,7 +5,7 @@ Paper passages followed:
     value in bits per pixel indicates the rate without header.
   * Section IV: the network can be retrained on domain data (MRI).
 
-Readings: the loss is the mean over sampled pixels of
+Readings where the paper is silent: the loss is the mean over sampled pixels of
 -log2 P(target | window) under the discretised logistic mixture; windows
 are taken inside each slice with the same dummy rule as coding; the
 optimiser is Adam (Kingma and Ba, 2015) with lr 1e-3, betas (0.9, 0.999),

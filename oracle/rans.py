@@ -17,7 +17,7 @@ renormalisation words:
                          x = f_s * (x >> 16) + slot - c_s
                          if x < 2^16: x = (x << 16) | next word
 
-Layout readings, all explicit in the arguments:
+Layout readings (the paper fixes none of this), all explicit in the arguments:
   * G groups; group g owns rows [floor(gH/G), floor((g+1)H/G)) and one
     stream shared by its L lanes (interleaved rANS).
   * Row y of group g belongs to lane (y - r_g) mod L, block j = (y - r_g) div L.

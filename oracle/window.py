@@ -9,7 +9,7 @@ Paper passages followed:
   * Section II-B (Preprocessor): wavefront order similar to HEVC WPP; in
     each coding step every pixel whose window is already coded is coded.
 
-Readings where the paper is silent (listed in the design doc): the window is the
+Readings where the paper is silent: the window is the
 12 causal neighbours of rows y-2 and y-1 at dx = -2..+2 plus (y, x-2) and
 (y, x-1), in that row-major order; pixel values are scaled to [-1, 1] by
 s(v) = (2v - 255)/255; the dummy value is 0.0 in the scaled domain; the
