@@ -173,8 +173,11 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
                                              const DecArgs& a, const int g) {
   __shared__ float2 s_sd[LUT_N];
   __shared__ __attribute__((aligned(16))) float s_beta[260];
-  __shared__ __attribute__((aligned(16))) float s_par[NSLOT][SLOT_PX * PAR_STRIDE];
-  __shared__ __attribute__((aligned(16))) uint16_t s_bk[NSLOT][SLOT_PX * 16];
+  // nets for tiles of at most 4 pixels run only with the 16-lane coder,
+  // which serves at most 4 pixels per sub-round
+  constexpr int SPX = Net::SCRATCH_FLOATS > 0 ? 4 : SLOT_PX;
+  __shared__ __attribute__((aligned(16))) float s_par[NSLOT][SPX * PAR_STRIDE];
+  __shared__ __attribute__((aligned(16))) uint16_t s_bk[NSLOT][SPX * 16];
   __shared__ uint8_t s_ring[(DEC_RMAX + 2) * 16];
   __shared__ uint16_t s_words[DEC_RING];
   __shared__ int s_done[NSLOT][4];
@@ -185,6 +188,8 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
   __shared__ unsigned long long s_total, s_before;
   __shared__ int s_err, s_flag;
   __shared__ __attribute__((aligned(16))) char s_w2[Net::LDS_BYTES > 0 ? Net::LDS_BYTES : 16];
+  __shared__ __attribute__((aligned(16)))
+  float s_xs[Net::SCRATCH_FLOATS > 0 ? dec_workers<Net>() * Net::SCRATCH_FLOATS : 4];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int H = a.H, W = a.W, G = a.G, L = a.L;
@@ -815,6 +820,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     const int w = wave - 1 - (wave >> 2);
     Net net;
     net.load(m, lane);
+    if constexpr (Net::SCRATCH_FLOATS > 0) net.xs = &s_xs[w * Net::SCRATCH_FLOATS];
     const int q4 = lane >> 4;
     unsigned long long t_net = 0, t_head = 0, t_tab = 0, n_tiles = 0, c_net = 0, c_head = 0;
     bool timeout = s_flag != 0;
@@ -908,7 +914,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           ++n_tiles;
         }
         if (valid) *reinterpret_cast<f4*>(&par[ln * PAR_STRIDE + 4 * q4]) = o;
-        if (L <= 4) {
+        if (SPX == 4 || L <= 4) {
           // At most 4 pixels: row p of the wave (lanes 16 p + k) serves pixel
           // p.  Lane k < 5 evaluates mixture component k (the head's two
           // exponentials), lane 0 the softmax sum in the head's order, and lane
@@ -1152,6 +1158,14 @@ static void launch_decode_t(const Consts* K, const DevModel& m, const DecArgs& a
   }
 }
 
+// Nets for tiles of at most 4 pixels run only with the 16-lane coder (L <= 4).
+template <class Net>
+static void launch_decode_lpp16(const Consts* K, const DevModel& m, const DecArgs& a,
+                                hipStream_t s) {
+  const dim3 grid(a.G), block(dec_waves<Net>() * 64);
+  hipLaunchKernelGGL((wavefront_decode_kernel<Net, false, 16>), grid, block, 0, s, K, m, a);
+}
+
 // Layer-2 weights of the BF16 nets go to LDS at H = 128: six density waves
 // share one copy instead of holding 128 VGPRs each.
 template <int H>
@@ -1159,11 +1173,14 @@ static bool launch_decode_h(int wtype, const Consts* K, const DevModel& m, const
                             hipStream_t s) {
   switch (wtype) {
     case WT_F32:
-      // at H = 64, layouts of at most 4 lanes (one 16-pixel tile per
-      // sub-round, latency-bound) keep layer 2 in registers on 8 waves; wider
-      // ones need the 9 density waves of the 12-wave form
+      // layouts of at most 4 lanes (one tile of at most 4 pixels per
+      // sub-round, latency-bound): at H = 64 layer 2 stays in registers on 8
+      // waves, at H = 128 it runs on the 4x4 MFMA form; wider layouts need
+      // the 9 density waves of the 12-wave form at H = 64
       if (H == 64 && a.L <= 4)
         launch_decode_t<NetF32<64, false>, false>(K, m, a, s);
+      else if (H == 128 && a.L <= 4)
+        launch_decode_lpp16<NetF32x4>(K, m, a, s);
       else
         launch_decode_t<NetF32<H, (H >= 64)>, false>(K, m, a, s);
       return true;

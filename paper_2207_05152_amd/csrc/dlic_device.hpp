@@ -127,6 +127,8 @@ __device__ __forceinline__ bf16x8 pack_bf16x8(const uint32_t* h) {
 //   load(m, lane)        per-lane weights and biases into registers
 //   run(f0, f1, f2, lds) features 4e + l/16 (e = 0, 1, 2) of pixel l%16 in,
 //                        outputs 4*(l/16) .. 4*(l/16)+3 of that pixel out.
+//   SCRATCH_FLOATS       LDS floats each decoder density wave lends the net
+//                        (xs points there before run)
 // -----------------------------------------------------------------------------
 
 // FP32 weights, v_mfma_f32_16x16x4f32, biases seed the accumulators.
@@ -139,6 +141,7 @@ struct NetF32 {
   // few enough VGPRs for three decoder waves per SIMD
   static constexpr bool DEC_WIDE = H <= 32 || (H == 64 && W2L);
   static constexpr int LDS_BYTES = W2_LDS ? NT * NT * 64 * 16 : 0;
+  static constexpr int SCRATCH_FLOATS = 0;  // per-wave LDS scratch of the decoder
   float a1[NT][3];
   float a2[W2_LDS ? 1 : NT][W2_LDS ? 1 : NT * 4];
   float a3[NT * 4];
@@ -269,6 +272,133 @@ struct NetF32 {
   }
 };
 
+// The 12-128-128-15 FP32 net for decoder tiles of at most 4 pixels, with
+// results bit-identical to NetF32<128> (the encoder's form).
+//
+// The FP32 MFMAs compute each output as a chain of correctly rounded fused
+// multiply-adds in K order: v_mfma_f32_16x16x4f32 takes its four K slots in
+// order, v_mfma_f32_4x4x1f32 one product (checked on the MI355X for 512 000
+// results of each form against scalar fma chains, operands from 2^-8 to 2^8
+// with both signs).  Layer 2 therefore runs as 128 one-product steps of the
+// 4x4 form in NetF32's K order, on the 4 pixels a tile has, where the 16x16
+// form computes 16 pixels: a quarter of the MFMA time.  The 16 blocks of the
+// 4x4 form are 16 groups of 4 output neurons (lane 4b + i is neuron 4b + i of
+// the A operand, lane 4b + j pixel j of the B operand and of D), two
+// accumulators cover neurons 0-63 and 64-127.  Layers 1 and 3 keep the 16x16
+// form; activations change layout through the wave's own LDS scratch (one row
+// of ROW floats per pixel).
+//
+// NetF32's layer-2 order: MFMA (n1, r) takes slots q = 0..3, i.e. layer-1
+// neurons 16 n1 + 4 q + r, so chain step c takes neuron kc(c).
+__device__ __forceinline__ f4 mfma_f32_4x4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
+struct NetF32x4 {
+  static constexpr int H = 128, NT = H / 16;
+  static constexpr bool DEC_WIDE = false;             // 8 waves per decoder workgroup
+  static constexpr int LDS_BYTES = H * H * 4;         // W2 in chain order, 64 KB
+  static constexpr int ROW = H + 4;                   // scratch floats per pixel row
+  static constexpr int SCRATCH_FLOATS = 2 * 4 * ROW;  // layer-1 rows, then layer-2 rows
+  float a1[NT][3];
+  float a3[NT * 4];
+  float c1[NT][4], c2[2][4], c3[4];
+  float* xs = nullptr;
+
+  __host__ __device__ static constexpr int kc(int c) {
+    return 16 * (c / 16) + 4 * (c % 4) + (c % 16) / 4;
+  }
+
+  // f4 index cp * 64 + lane holds, for steps c = 2 cp and 2 cp + 1 in turn,
+  // W2[lane][kc(c)] and W2[64 + lane][kc(c)].
+  __device__ __forceinline__ static void stage(const DevModel& m, void* lds, int t, int n) {
+    const float* w2 = (const float*)m.w2;
+    float* d = (float*)lds;
+    for (int idx = t; idx < H * H; idx += n) {
+      const int e = idx & 3, lane = (idx >> 2) & 63, cp = idx >> 8;
+      const int c = 2 * cp + (e >> 1), half = e & 1;
+      d[idx] = w2[(64 * half + lane) * H + kc(c)];
+    }
+  }
+
+  __device__ __forceinline__ void load(const DevModel& m, int lane) {
+    const float* w1 = (const float*)m.w1;
+    const float* w3 = (const float*)m.w3;
+    const int i = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) a1[nt][kk] = w1[(16 * nt + i) * K_IN + 4 * kk + q];
+#pragma unroll
+    for (int n2 = 0; n2 < NT; ++n2)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        a3[n2 * 4 + r] = (i < N_OUT) ? w3[i * H + 16 * n2 + 4 * q + r] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) c1[nt][r] = m.b1[16 * nt + 4 * q + r];
+      c2[0][r] = m.b2[4 * (lane >> 2) + r];
+      c2[1][r] = m.b2[64 + 4 * (lane >> 2) + r];
+      c3[r] = (4 * q + r < N_OUT) ? m.b3[4 * q + r] : 0.0f;
+    }
+  }
+
+  // Features as NetF32::run; the outputs of pixels 0..3 (lanes l % 16 < 4)
+  // are NetF32<128>'s, the other lanes' are unspecified.
+  __device__ __forceinline__ f4 run(float f0, float f1, float f2, const void* lds) const {
+    const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    const int p = lane & 15, q = lane >> 4, j = lane & 3;
+    float* h1t = xs;            // [pixel][chain step]
+    float* h2t = xs + 4 * ROW;  // [pixel][neuron]
+    // layer 1: neuron 16 nt + 4 q + r of pixel p goes to chain step 16 nt + 4 r + q
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      f4 acc = {c1[nt][0], c1[nt][1], c1[nt][2], c1[nt][3]};
+      acc = mfma_f32(a1[nt][0], f0, acc);
+      acc = mfma_f32(a1[nt][1], f1, acc);
+      acc = mfma_f32(a1[nt][2], f2, acc);
+      if (p < 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h1t[p * ROW + 16 * nt + 4 * r + q] = relu(acc[r]);
+      }
+    }
+    // layer 2: four chain steps per pass, both neuron halves
+    const f4* w = reinterpret_cast<const f4*>(lds);
+    f4 lo = {c2[0][0], c2[0][1], c2[0][2], c2[0][3]};
+    f4 hi = {c2[1][0], c2[1][1], c2[1][2], c2[1][3]};
+#pragma unroll
+    for (int c4 = 0; c4 < H / 4; ++c4) {
+      const f4 hv = *reinterpret_cast<const f4*>(&h1t[j * ROW + 4 * c4]);
+      const f4 wa = w[(2 * c4) * 64 + lane];
+      const f4 wb = w[(2 * c4 + 1) * 64 + lane];
+      lo = mfma_f32_4x4(wa[0], hv[0], lo);
+      hi = mfma_f32_4x4(wa[1], hv[0], hi);
+      lo = mfma_f32_4x4(wa[2], hv[1], lo);
+      hi = mfma_f32_4x4(wa[3], hv[1], hi);
+      lo = mfma_f32_4x4(wb[0], hv[2], lo);
+      hi = mfma_f32_4x4(wb[1], hv[2], hi);
+      lo = mfma_f32_4x4(wb[2], hv[3], lo);
+      hi = mfma_f32_4x4(wb[3], hv[3], hi);
+    }
+    // lane 4 b + j holds neurons 4 b + i and 64 + 4 b + i of pixel j
+    *reinterpret_cast<f4*>(&h2t[j * ROW + 4 * (lane >> 2)]) =
+        f4{relu(lo[0]), relu(lo[1]), relu(lo[2]), relu(lo[3])};
+    *reinterpret_cast<f4*>(&h2t[j * ROW + 64 + 4 * (lane >> 2)]) =
+        f4{relu(hi[0]), relu(hi[1]), relu(hi[2]), relu(hi[3])};
+    // layer 3: slot q of MFMA (n2, r) is neuron 16 n2 + 4 q + r
+    f4 o = {c3[0], c3[1], c3[2], c3[3]};
+#pragma unroll
+    for (int n2 = 0; n2 < NT; ++n2) {
+      f4 hv = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (p < 4) hv = *reinterpret_cast<const f4*>(&h2t[p * ROW + 16 * n2 + 4 * q]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) o = mfma_f32(a3[n2 * 4 + r], hv[r], o);
+    }
+    return o;
+  }
+};
+
 // BF16 operands with FP32 accumulation on v_mfma_f32_16x16x32_bf16.  Inputs
 // and hidden activations are rounded to BF16 (round to nearest even) before
 // each product; biases and accumulators stay FP32.
@@ -291,6 +421,7 @@ struct NetBF16 {
   static constexpr bool SCALED = WT == WT_FP8;
   static constexpr bool DEC_WIDE = H <= 64;
   static constexpr int LDS_BYTES = W2_LDS ? NT * NK * 64 * 16 : 0;
+  static constexpr int SCRATCH_FLOATS = 0;  // per-wave LDS scratch of the decoder
   bf16x8 a1[NT];
   bf16x8 a2[W2_LDS ? 1 : NT][W2_LDS ? 1 : NK];
   bf16x8 a3[NK];
@@ -429,6 +560,7 @@ struct NetFP8A {
   static constexpr bool W2_LDS = W2_LDS_;
   static constexpr bool DEC_WIDE = H <= 64;
   static constexpr int LDS_BYTES = W2_LDS ? NT * NK * 64 * 8 : 0;
+  static constexpr int SCRATCH_FLOATS = 0;  // per-wave LDS scratch of the decoder
   long a1[NT];
   long a2[W2_LDS ? 1 : NT][W2_LDS ? 1 : NK];
   long a3[NK];

@@ -75,6 +75,16 @@ def test_full_size_round_trip(dev, G, L):
     assert np.array_equal(dec, img)
 
 
+def test_full_size_round_trip_width128(dev):
+    # the 128-wide FP32 net at the headline layout: the decoder's 4-pixel form
+    # of layer 2 must reproduce the encoder's 16-pixel form bit for bit
+    img = synth.synth_image(1536, 2048, 1)
+    wts = synth.xavier_mlp((12, 128, 128, 15), 3)
+    _, _, bits, dec, st = _roundtrip(dev, img, wts, dl.dlic_coder(64, 4))
+    assert st == 0
+    assert np.array_equal(dec, img)
+
+
 def test_model_mismatch_and_corruption(dev, c0_inputs):
     img, wts = c0_inputs
     m, d_img, bits, dec, st = _roundtrip(dev, img, wts, dl.dlic_coder(1, 32))
