@@ -1119,7 +1119,15 @@ template <int H>
 static bool launch_batch_decode_h(int wtype, const Consts* K, const DevModel& m,
                                   const BatchArgs& b, int lpp, hipStream_t s) {
   switch (wtype) {
-    case WT_F32: launch_batch_decode_t<NetF32<H, (H >= 64)>>(K, m, b, lpp, s); return true;
+    case WT_F32:
+      // as for one image: the 128-wide net on tiles of at most 4 pixels
+      if (H == 128 && lpp == 16) {
+        hipLaunchKernelGGL((batch_decode_kernel<NetF32x4, 16>), dim3(b.n_items),
+                           dim3(dec_waves<NetF32x4>() * 64), 0, s, K, m, b);
+      } else {
+        launch_batch_decode_t<NetF32<H, (H >= 64)>>(K, m, b, lpp, s);
+      }
+      return true;
     case WT_BF16:
       launch_batch_decode_t<NetBF16<H, WT_BF16, (H > 64)>>(K, m, b, lpp, s);
       return true;

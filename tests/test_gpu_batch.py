@@ -43,7 +43,7 @@ def test_batch_streams_equal_single_image_streams(dev, dtype, width):
     b.close()
 
 
-@pytest.mark.parametrize("dtype,width", [("fp32", 64), ("bf16", 64), ("fp32", 32)])
+@pytest.mark.parametrize("dtype,width", [("fp32", 64), ("bf16", 64), ("fp32", 32), ("fp32", 128)])
 def test_batch_small_lane_layouts(dev, dtype, width):
     # 1 to 4 lanes per group: the decoder's coder gives each pixel 16 lanes
     model = dl.Model(synth.xavier_mlp((12, width, width, 15), 5), dev, dtype=dtype)
