@@ -300,9 +300,9 @@ struct NetF32x4 {
   static constexpr int LDS_BYTES = H * H * 4;         // W2 in chain order, 64 KB
   static constexpr int ROW = H + 4;                   // scratch floats per pixel row
   static constexpr int SCRATCH_FLOATS = 2 * 4 * ROW;  // layer-1 rows, then layer-2 rows
-  float a1[NT][3];
+  float a1[2][K_IN];  // W1[64 h + lane][k]
   float a3[NT * 4];
-  float c1[NT][4], c2[2][4], c3[4];
+  float c1[2][4], c2[2][4], c3[4];
   float* xs = nullptr;
 
   __host__ __device__ static constexpr int kc(int c) {
@@ -326,9 +326,9 @@ struct NetF32x4 {
     const float* w3 = (const float*)m.w3;
     const int i = lane & 15, q = lane >> 4;
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int kk = 0; kk < 3; ++kk) a1[nt][kk] = w1[(16 * nt + i) * K_IN + 4 * kk + q];
+      for (int k = 0; k < K_IN; ++k) a1[h][k] = w1[(64 * h + lane) * K_IN + k];
 #pragma unroll
     for (int n2 = 0; n2 < NT; ++n2)
 #pragma unroll
@@ -336,8 +336,8 @@ struct NetF32x4 {
         a3[n2 * 4 + r] = (i < N_OUT) ? w3[i * H + 16 * n2 + 4 * q + r] : 0.0f;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) c1[nt][r] = m.b1[16 * nt + 4 * q + r];
+      c1[0][r] = m.b1[4 * (lane >> 2) + r];
+      c1[1][r] = m.b1[64 + 4 * (lane >> 2) + r];
       c2[0][r] = m.b2[4 * (lane >> 2) + r];
       c2[1][r] = m.b2[64 + 4 * (lane >> 2) + r];
       c3[r] = (4 * q + r < N_OUT) ? m.b3[4 * q + r] : 0.0f;
@@ -351,16 +351,35 @@ struct NetF32x4 {
     const int p = lane & 15, q = lane >> 4, j = lane & 3;
     float* h1t = xs;            // [pixel][chain step]
     float* h2t = xs + 4 * ROW;  // [pixel][neuron]
-    // layer 1: neuron 16 nt + 4 q + r of pixel p goes to chain step 16 nt + 4 r + q
+    // layer 1 on the 4x4 form too: the 12 features of pixel j in every lane
+    // 4 b + j (K order 0..11, as the 16x16 form's slots take them), then
+    // neuron n = 16 n1 + 4 q + r goes to chain step 16 n1 + 4 r + q
+    float* ft = h2t;  // free until layer 2 ends
+    if (p < 4) {
+      ft[p * ROW + q] = f0;
+      ft[p * ROW + 4 + q] = f1;
+      ft[p * ROW + 8 + q] = f2;
+    }
+    {
+      const f4 fa = *reinterpret_cast<const f4*>(&ft[j * ROW]);
+      const f4 fb = *reinterpret_cast<const f4*>(&ft[j * ROW + 4]);
+      const f4 fc = *reinterpret_cast<const f4*>(&ft[j * ROW + 8]);
+      const float fv[K_IN] = {fa[0], fa[1], fa[2], fa[3], fb[0], fb[1],
+                              fb[2], fb[3], fc[0], fc[1], fc[2], fc[3]};
+      f4 l1 = {c1[0][0], c1[0][1], c1[0][2], c1[0][3]};
+      f4 h1 = {c1[1][0], c1[1][1], c1[1][2], c1[1][3]};
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      f4 acc = {c1[nt][0], c1[nt][1], c1[nt][2], c1[nt][3]};
-      acc = mfma_f32(a1[nt][0], f0, acc);
-      acc = mfma_f32(a1[nt][1], f1, acc);
-      acc = mfma_f32(a1[nt][2], f2, acc);
-      if (p < 4) {
+      for (int k = 0; k < K_IN; ++k) {
+        l1 = mfma_f32_4x4(a1[0][k], fv[k], l1);
+        h1 = mfma_f32_4x4(a1[1][k], fv[k], h1);
+      }
+      // lane 4 b + j holds neurons 4 b + i and 64 + 4 b + i of pixel j
+      const int b = lane >> 2;
+      const int c0 = 16 * (b >> 2) + (b & 3);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) h1t[p * ROW + 16 * nt + 4 * r + q] = relu(acc[r]);
+      for (int i = 0; i < 4; ++i) {
+        h1t[j * ROW + c0 + 4 * i] = relu(l1[i]);
+        h1t[j * ROW + 64 + c0 + 4 * i] = relu(h1[i]);
       }
     }
     // layer 2: four chain steps per pass, both neuron halves
