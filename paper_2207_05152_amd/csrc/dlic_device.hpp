@@ -224,6 +224,20 @@ struct NetF32 {
 #pragma unroll
       for (int r = 0; r < 4; ++r) h2[n2][r] = relu(acc[r]);
     }
+    if constexpr (H == 128) {
+      // four K quarters (neuron tiles 2g and 2g + 1), each its own chain, the
+      // first seeded with the bias; summed as ((q0 + q1) + q2) + q3
+      f4 oq[4] = {{c3[0], c3[1], c3[2], c3[3]}, {0.0f, 0.0f, 0.0f, 0.0f},
+                  {0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+#pragma unroll
+      for (int n2 = 0; n2 < NT; ++n2)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) oq[n2 / 2] = mfma_f32(a3[n2 * 4 + r], h2[n2][r], oq[n2 / 2]);
+      f4 o;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) o[e] = ((oq[0][e] + oq[1][e]) + oq[2][e]) + oq[3][e];
+      return o;
+    }
     f4 o = {c3[0], c3[1], c3[2], c3[3]};
 #pragma unroll
     for (int n2 = 0; n2 < NT; ++n2)
@@ -301,7 +315,7 @@ struct NetF32x4 {
   static constexpr int ROW = H + 4;                   // scratch floats per pixel row
   static constexpr int SCRATCH_FLOATS = 2 * 4 * ROW;  // layer-1 rows, then layer-2 rows
   float a1[2][K_IN];  // W1[64 h + lane][k]
-  float a3[NT * 4];
+  float a3[32];       // W3[lane % 16][k] along quarter lane / 16 of layer 3's chain
   float c1[2][4], c2[2][4], c3[4];
   float* xs = nullptr;
 
@@ -330,18 +344,28 @@ struct NetF32x4 {
 #pragma unroll
       for (int k = 0; k < K_IN; ++k) a1[h][k] = w1[(64 * h + lane) * K_IN + k];
 #pragma unroll
-    for (int n2 = 0; n2 < NT; ++n2)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        a3[n2 * 4 + r] = (i < N_OUT) ? w3[i * H + 16 * n2 + 4 * q + r] : 0.0f;
+    for (int st = 0; st < 32; ++st)
+      a3[st] = (i < N_OUT) ? w3[i * H + k3(q, st)] : 0.0f;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       c1[0][r] = m.b1[4 * (lane >> 2) + r];
       c1[1][r] = m.b1[64 + 4 * (lane >> 2) + r];
       c2[0][r] = m.b2[4 * (lane >> 2) + r];
       c2[1][r] = m.b2[64 + 4 * (lane >> 2) + r];
-      c3[r] = (4 * q + r < N_OUT) ? m.b3[4 * q + r] : 0.0f;
+      const int o3 = 4 * ((lane >> 2) & 3) + r;  // output of D register r
+      c3[r] = (q == 0 && o3 < N_OUT) ? m.b3[o3] : 0.0f;
     }
+  }
+
+  // Layer 3 (15 outputs) in NetF32<128>'s four K quarters: step st of
+  // quarter g takes neuron k3(g, st) (MFMA (n2, r) of the 16x16 form, n2 =
+  // 2g, 2g + 1, takes slots q = 0..3, neurons 16 n2 + 4 q + r), and l3pos
+  // is where neuron n sits in the quarters' chains (32 g + st).
+  __host__ __device__ static constexpr int k3(int g, int st) {
+    return 16 * (2 * g + (st >> 4)) + 4 * (st & 3) + ((st >> 2) & 3);
+  }
+  __host__ __device__ static constexpr int l3pos(int n) {
+    return 32 * (n >> 5) + 16 * ((n >> 4) & 1) + 4 * (n & 3) + ((n >> 2) & 3);
   }
 
   // Features as NetF32::run; the outputs of pixels 0..3 (lanes l % 16 < 4)
@@ -400,19 +424,34 @@ struct NetF32x4 {
       lo = mfma_f32_4x4(wb[2], hv[3], lo);
       hi = mfma_f32_4x4(wb[3], hv[3], hi);
     }
-    // lane 4 b + j holds neurons 4 b + i and 64 + 4 b + i of pixel j
-    *reinterpret_cast<f4*>(&h2t[j * ROW + 4 * (lane >> 2)]) =
-        f4{relu(lo[0]), relu(lo[1]), relu(lo[2]), relu(lo[3])};
-    *reinterpret_cast<f4*>(&h2t[j * ROW + 64 + 4 * (lane >> 2)]) =
-        f4{relu(hi[0]), relu(hi[1]), relu(hi[2]), relu(hi[3])};
-    // layer 3: slot q of MFMA (n2, r) is neuron 16 n2 + 4 q + r
-    f4 o = {c3[0], c3[1], c3[2], c3[3]};
+    // lane 4 b + j holds neurons 4 b + i and 64 + 4 b + i of pixel j; they go
+    // to their places in layer 3's chains
 #pragma unroll
-    for (int n2 = 0; n2 < NT; ++n2) {
-      f4 hv = {0.0f, 0.0f, 0.0f, 0.0f};
-      if (p < 4) hv = *reinterpret_cast<const f4*>(&h2t[p * ROW + 16 * n2 + 4 * q]);
+    for (int i = 0; i < 4; ++i) {
+      const int n = 4 * (lane >> 2) + i;
+      h2t[j * ROW + l3pos(n)] = relu(lo[i]);
+      h2t[j * ROW + l3pos(64 + n)] = relu(hi[i]);
+    }
+    // layer 3 on the 4x4 form: block b = 4 g + og is quarter g of outputs
+    // 4 og .. 4 og + 3, so lane 16 g + 4 og + j accumulates that quarter for
+    // pixel j; the quarters then meet in the 16x16 layout
+    f4 o3 = {c3[0], c3[1], c3[2], c3[3]};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) o = mfma_f32(a3[n2 * 4 + r], hv[r], o);
+    for (int s4 = 0; s4 < 8; ++s4) {
+      const f4 hv = *reinterpret_cast<const f4*>(&h2t[j * ROW + 32 * q + 4 * s4]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) o3 = mfma_f32_4x4(a3[4 * s4 + e], hv[e], o3);
+    }
+    float* part = h1t;  // free once layer 2 has read it
+    *reinterpret_cast<f4*>(&part[4 * lane]) = o3;
+    f4 o = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (p < 4) {
+      // outputs 4 q .. 4 q + 3 of pixel p: quarter g sits at lane 16 g + 4 q + p
+      f4 v[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) v[g] = *reinterpret_cast<const f4*>(&part[4 * (16 * g + 4 * q + p)]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) o[e] = ((v[0][e] + v[1][e]) + v[2][e]) + v[3][e];
     }
     return o;
   }
