@@ -11,9 +11,16 @@ are taken inside each slice with the same dummy rule as coding; the
 optimiser is Adam (Kingma and Ba, 2015) with lr 1e-3, betas (0.9, 0.999),
 eps 1e-8.
 
-Parity: the loss reuses the pinned mixture log-mass; its gradient is
-pinned against FP64 central differences of the loss itself and against
-the softmax gauge identity; Adam is pinned against torch.optim.Adam.
+Parity (CPU tests in tests/test_oracle_nll.py):
+  * sample_features: equal, pixel by pixel, to the whole-slice window
+    matrix (itself pinned by hand-derived golden windows) and to the
+    one-pixel window reader;
+  * nll_bits: equal to a per-sample loop over CDF differences (not the log
+    form the loss uses);
+  * nll_and_grad_fd: equal to hand-derived derivatives of a single
+    logistic (five identical components, weights zero), to the chain rule
+    through the last layer, and to the softmax shift invariance;
+  * adam_update: equal to torch.optim.Adam over five steps.
 """
 from __future__ import annotations
 

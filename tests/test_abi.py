@@ -71,6 +71,18 @@ def test_peek_header_reads_oracle_header():
         dl.dlic_peek_header(raw[:20])
 
 
+def test_peek_header_reads_golden_bytes(golden):
+    for ln in golden("header_v1.txt"):
+        left, right = ln.split(":")
+        f = left.split()
+        if f[0] == "container":
+            continue
+        h, w, g, l, dt, h1, h2 = (int(v) for v in f[:7])
+        p = dl.dlic_peek_header(bytes.fromhex(right.replace(" ", "")))
+        assert (p["h"], p["w"], p["coder"].groups, p["coder"].lanes_per_group, p["dtype"],
+                p["h1"], p["h2"], p["fingerprint"]) == (h, w, g, l, dt, h1, h2, int(f[7], 16))
+
+
 def _quant_inputs():
     import synth
     from oracle import lowp

@@ -24,6 +24,34 @@ def test_header_round_trip():
     assert p["fingerprint"] == 0x0123456789ABCDEF and p["skew"] == 3 and p["prob_bits"] == 16
 
 
+def _header_cases(golden):
+    cases, container = [], None
+    for ln in golden("header_v1.txt"):
+        left, right = ln.split(":")
+        raw = bytes.fromhex(right.replace(" ", ""))
+        f = left.split()
+        if f[0] == "container":
+            container = ([int(v, 16) for v in f[1:]], raw)
+        else:
+            h, w, g, l, dt, h1, h2 = (int(v) for v in f[:7])
+            cases.append(((h, w, g, l, dt, h1, h2, int(f[7], 16)), raw))
+    return cases, container
+
+
+def test_header_bytes_match_hand_written_golden(golden):
+    cases, (words, tail) = _header_cases(golden)
+    assert len(cases) == 3
+    for (h, w, g, l, dt, h1, h2, fp), raw in cases:
+        assert oracle.pack_header(h, w, g, l, dtype=dt, h1=h1, h2=h2, fp=fp) == raw
+        p = oracle.parse_header(raw)
+        assert (p["h"], p["w"], p["groups"], p["lanes"], p["dtype"], p["h1"], p["h2"],
+                p["fingerprint"]) == (h, w, g, l, dt, h1, h2, fp)
+    hdr = cases[1][1]
+    full = oracle.assemble(hdr, [words])
+    assert full == hdr + tail
+    assert oracle.split_streams(full, 1) == [words]
+
+
 def test_c0_round_trip_and_rate(c0_inputs):
     img, w = c0_inputs
     bits = oracle.encode_image(img, w, oracle.OracleCoder(1, 32))
