@@ -6,7 +6,8 @@ fetch the stream length, decode it (wavefront kernel).  The input image is
 resident in HBM before the timed region.  Prints one JSON line.
 
 Workload (default): a 2048x1536 synthetic greyscale image (seed 1), network
-12-64-64-15 FP32 (Glorot, seed 3), 8 row groups x 32 interleaved rANS lanes.
+12-64-64-15 FP32 (Glorot, seed 3), 64 row groups x 4 interleaved rANS lanes
+(256 lanes).
 """
 from __future__ import annotations
 
@@ -176,12 +177,14 @@ def precision_sweep(dl, torch, img, H, W, coder, hidden=128, reps=3):
 
 
 def layout_sweep(dl, torch, img, H, W, model, layouts=((8, 32), (16, 16), (32, 8), (128, 2),
-                                                        (256, 1), (128, 4), (48, 32)), reps=3):
+                                                        (256, 1), (128, 4), (192, 4), (384, 4),
+                                                        (48, 32)), reps=3):
     """The headline image and net coded with other coder layouts (G groups x L
     lanes).  The first five have the headline's 256 lanes; the decoder gives a
     pixel 16 coder lanes when L <= 4.  More lanes cut the sequential sub-rounds
     per wavefront step, ceil(rows per group / L), at the price of 4 flushed
-    bytes per lane."""
+    bytes per lane; 384 x 4 and 48 x 32 give every row its own lane (one
+    sub-round per step)."""
     out = []
     dl.dlic_set_timing(True)
     for G, L in layouts:
@@ -230,7 +233,9 @@ def batch_sweep(dl, torch, reps=3, tune_budget_s=60.0):
     def run(knobs):
         b = dl.Batch(model, sizes, coders=autotune.coders_for(sizes, knobs["rows_per_group"],
                                                                 knobs["lanes"]),
-                     density_grid=knobs["density_grid"])
+                     density_grid=knobs["density_grid"],
+                     search_lanes=knobs.get("search_lanes", 0),
+                     decode_grid=knobs.get("decode_grid", 0))
         b.load(images)
         b.capture()
         s = torch.cuda.current_stream()

@@ -184,6 +184,27 @@ dlic_status dlic_decode(const dlic_model *model, const dlic_coder *coder,
                         int32_t h, int32_t w, int32_t *d_status,
                         void *d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* dlic_decode for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same stream format, kernels, results and device status as dlic_decode,
+ * without d_ws: the decode's progress records and group ticket live in a
+ * fixed array of dlic_decode_noalloc_limit() bytes (8 MiB) that the library
+ * keeps on every device it runs on until the process ends.  The call makes
+ * no allocation, creates no timing events, and clears the part of the array
+ * it uses with a kernel before its decode kernel runs.  Needs dlic_init on
+ * the current device first (DLIC_ERR_ARG otherwise: set-up allocates).
+ * Returns DLIC_ERR_CAPACITY when dlic_decode_workspace(h, w, coder) exceeds
+ * the limit (G * (W + 3H - 3) + 1 four-byte words; 2048x1536 with 64 groups
+ * takes 1.7 MB).  Every call on one device shares its array: calls whose
+ * kernels overlap on one GPU (several streams, several host threads) race
+ * and must be serialised by the caller. */
+dlic_status dlic_decode_noalloc(const dlic_model *model, const dlic_coder *coder,
+                                const uint8_t *d_bits, size_t n_bytes, uint8_t *d_img,
+                                int32_t h, int32_t w, int32_t *d_status, hipStream_t stream);
+
+/* Bytes of the fixed workspace array of dlic_decode_noalloc. */
+size_t dlic_decode_noalloc_limit(void);
+
 /* Spin limit of one decode wait (polls of an upstream record, each followed
  * by a short sleep); a wait that exceeds it reports DLIC_ERR_TIMEOUT and the
  * workgroup continues without waiting again.  Default 2^22.  For tests of the
@@ -199,6 +220,19 @@ void dlic_set_spin_limit(uint32_t polls);
 dlic_status dlic_density(const dlic_model *model, const uint8_t *d_img, int32_t h, int32_t w,
                          float *d_out15, uint32_t *d_cf, uint32_t *d_tables,
                          hipStream_t stream);
+
+/* Test hook for the rule that encoder and decoder evaluate the network
+ * identically (Section II-B, Preprocessor: the same arithmetic on both sides
+ * makes the rounding errors equal).  At 12-128-128-15 in FP32 the encoder's
+ * density kernel runs 16-pixel tiles on the 16x16x4 MFMA and the decoder
+ * (with at most 4 lanes per group) 4-pixel tiles on the 4x4x1 MFMA in the
+ * same summation order.  This runs both forms on n caller-given feature rows
+ * (d_feats: [n][12] FP32, n a multiple of 16) and writes their outputs to
+ * d_out16 and d_out4 ([n][15] FP32).  In the 4-pixel form, rows 4s + j with
+ * j >= lanes (1..4) are replaced by zero features, as the decoder's unused
+ * tile rows; their d_out4 entries are unspecified.  model: FP32, h1 = 128. */
+dlic_status dlic_net_forms(const dlic_model *model, const float *d_feats, int64_t n,
+                           int32_t lanes, float *d_out16, float *d_out4, hipStream_t stream);
 
 /* Calibration for the W8A8 net: runs the FP32 network (model->dtype must be
  * DLIC_FP32) on every pixel of an image and folds the largest layer-1 and
@@ -249,6 +283,18 @@ dlic_status dlic_batch_create(const dlic_model *model, int32_t n_img, const int3
                               dlic_batch **out);
 void dlic_batch_destroy(dlic_batch *b);
 
+/* Decode knobs of a plan, for the autotuner (Section II-B, Preprocessor: the
+ * wavefront's work per step spread over the GPU).  search_lanes: coder lanes
+ * that share one pixel's symbol search: 16 (one level of a 16-level bucket
+ * per lane; every image at most 4 lanes per group), 2 (binary halvings with
+ * the mixture split over two half-waves; at most 32 lanes per group), 1 (one
+ * lane per pixel), or 0 for the default (16 / 2 / 1 by the widest layout).
+ * decode_grid: workgroups of the persistent decode kernel, 0 for as many as
+ * stay resident on the device (capped at the number of work items).
+ * DLIC_ERR_UNSUPPORTED when a layout of the plan is too wide for the fan-out.
+ * The streams and decoded pixels do not depend on either knob. */
+dlic_status dlic_batch_tune(dlic_batch *b, int32_t search_lanes, int32_t decode_grid);
+
 /* Bytes of the concatenated pixel buffer (images back to back, raster
  * order), of the stream regions (one per image, dlic_encode_bound bytes,
  * 256-aligned), of the workspace both directions need, and the number of
@@ -262,7 +308,10 @@ dlic_status dlic_batch_layout(const dlic_batch *b, uint64_t *h_px_off, uint64_t 
                               int32_t *h_coders);
 
 /* Encode every image: image i's stream (the same bytes dlic_encode writes
- * for it) goes to its region of d_out, its length to d_out_len[i].
+ * for it) goes to its region of d_out, its length to d_out_len[i].  After
+ * the call, and until the workspace is used again, its first 4 * pixels
+ * bytes hold every pixel's packed interval c | (f - 1) << 16 (u32, at the
+ * pixel's index in the concatenated buffer) that the streams code.
  * d_t_done, if not NULL, has n_img + 1 entries: the device realtime counter
  * when image i's stream was complete, and at [n_img] the start of the call
  * (dlic_wallclock_hz gives the counter's rate). */
@@ -272,7 +321,8 @@ dlic_status dlic_encode_batch(dlic_batch *b, const uint8_t *d_pixels, uint8_t *d
 
 /* Decode every image from its region of d_bits (d_len[i] bytes) into its
  * place in d_pixels; d_status[i] as dlic_decode's status; d_t_done as for
- * dlic_encode_batch. */
+ * dlic_encode_batch.  One launch of a persistent grid: each workgroup takes
+ * (image, group) items by ticket until none is left. */
 dlic_status dlic_decode_batch(dlic_batch *b, const uint8_t *d_bits, const uint64_t *d_len,
                               uint8_t *d_pixels, int32_t *d_status, uint64_t *d_t_done,
                               void *d_ws, size_t ws_bytes, hipStream_t stream);

@@ -37,7 +37,8 @@ EXPORTS = (
     "dlic_set_decode_profile", "dlic_nll_workspace", "dlic_nll_fwd_bwd", "dlic_adam_step",
     "dlic_batch_create", "dlic_batch_destroy", "dlic_batch_sizes", "dlic_batch_layout",
     "dlic_encode_batch", "dlic_decode_batch", "dlic_batch_capture", "dlic_batch_replay",
-    "dlic_wallclock_hz",
+    "dlic_wallclock_hz", "dlic_decode_noalloc", "dlic_decode_noalloc_limit", "dlic_batch_tune",
+    "dlic_net_forms",
 )
 
 
@@ -88,7 +89,11 @@ def lib():
                                 P, P, S, P]),
         "dlic_decode": (c_int, [POINTER(dlic_model), POINTER(dlic_coder), P, S, P, c_int32, c_int32,
                                 P, P, S, P]),
+        "dlic_decode_noalloc": (c_int, [POINTER(dlic_model), POINTER(dlic_coder), P, S, P, c_int32,
+                                        c_int32, P, P]),
+        "dlic_decode_noalloc_limit": (S, []),
         "dlic_set_spin_limit": (None, [c_uint32]),
+        "dlic_net_forms": (c_int, [POINTER(dlic_model), P, ctypes.c_int64, c_int32, P, P, P]),
         "dlic_density": (c_int, [POINTER(dlic_model), P, c_int32, c_int32, P, P, P, P]),
         "dlic_rans_encode_cf": (c_int, [POINTER(dlic_coder), c_int32, c_int32, P, P, S, P, P, S, P]),
         "dlic_rans_decode_tables": (c_int, [POINTER(dlic_coder), c_int32, c_int32, P, c_int32, P, P,
@@ -103,6 +108,7 @@ def lib():
                                    c_float, P]),
         "dlic_batch_create": (c_int, [POINTER(dlic_model), c_int32, P, P, c_int32, POINTER(P)]),
         "dlic_batch_destroy": (None, [P]),
+        "dlic_batch_tune": (c_int, [P, c_int32, c_int32]),
         "dlic_batch_sizes": (c_int, [P, POINTER(S), POINTER(S), POINTER(S), POINTER(c_int32)]),
         "dlic_batch_layout": (c_int, [P, P, P, P]),
         "dlic_encode_batch": (c_int, [P, P, P, P, P, P, S, P]),
@@ -222,6 +228,22 @@ def dlic_decode(model: dlic_model, coder: dlic_coder, d_bits, n_bytes, d_img, h,
     _check(lib().dlic_decode(ctypes.byref(model), ctypes.byref(coder), _ptr(d_bits), n_bytes,
                              _ptr(d_img), h, w, _ptr(d_status), _ptr(d_ws), ws_bytes,
                              _stream(stream)), "dlic_decode")
+
+
+def dlic_decode_noalloc(model: dlic_model, coder: dlic_coder, d_bits, n_bytes, d_img, h, w,
+                        d_status, stream=None):
+    _check(lib().dlic_decode_noalloc(ctypes.byref(model), ctypes.byref(coder), _ptr(d_bits),
+                                     n_bytes, _ptr(d_img), h, w, _ptr(d_status), _stream(stream)),
+           "dlic_decode_noalloc")
+
+
+def dlic_decode_noalloc_limit() -> int:
+    return int(lib().dlic_decode_noalloc_limit())
+
+
+def dlic_net_forms(model: dlic_model, d_feats, n, lanes, d_out16, d_out4, stream=None):
+    _check(lib().dlic_net_forms(ctypes.byref(model), _ptr(d_feats), int(n), int(lanes),
+                                _ptr(d_out16), _ptr(d_out4), _stream(stream)), "dlic_net_forms")
 
 
 def dlic_set_spin_limit(polls: int):
@@ -516,6 +538,10 @@ def dlic_batch_create(model: dlic_model, sizes, coders=None, density_grid: int =
     return out.value
 
 
+def dlic_batch_tune(b: int, search_lanes: int = 0, decode_grid: int = 0):
+    _check(lib().dlic_batch_tune(b, int(search_lanes), int(decode_grid)), "dlic_batch_tune")
+
+
 def dlic_batch_destroy(b: int):
     lib().dlic_batch_destroy(b)
 
@@ -565,15 +591,23 @@ class Batch:
     """A batch plan with its torch-allocated buffers: images in, streams,
     decoded images out, lengths, statuses, completion stamps, workspace."""
 
-    def __init__(self, model: Model, sizes, coders=None, density_grid: int = 0, device="cuda"):
+    def __init__(self, model: Model, sizes, coders=None, density_grid: int = 0, device="cuda",
+                 search_lanes: int = 0, decode_grid: int = 0):
         import torch
         self.model = model  # keeps the weights alive for the plan
         self.sizes = [(int(h), int(w)) for h, w in sizes]
         self.n = len(self.sizes)
         self.plan = dlic_batch_create(model.c, self.sizes, coders, density_grid)
+        if search_lanes or decode_grid:
+            try:
+                dlic_batch_tune(self.plan, search_lanes, decode_grid)
+            except DlicError:
+                self.close()
+                raise
         sz = dlic_batch_sizes(self.plan)
         self.n_items = sz["n_items"]
         self.px_off, self.out_off, self.coders = dlic_batch_layout(self.plan, self.n)
+        self.n_pixels = sz["pixels"]
         self.pixels = torch.zeros(max(sz["pixels"], 1), dtype=torch.uint8, device=device)
         self.decoded = torch.zeros_like(self.pixels)
         self.out = torch.zeros(max(sz["out_bytes"], 1), dtype=torch.uint8, device=device)
@@ -596,6 +630,13 @@ class Batch:
         h, w = self.sizes[i]
         o = int(self.px_off[i])
         return (self.decoded if decoded else self.pixels)[o:o + h * w].view(h, w)
+
+    def intervals(self, i):
+        """Packed intervals c | (f - 1) << 16 of image i from the last encode ([h, w] int32)."""
+        import torch
+        h, w = self.sizes[i]
+        o = int(self.px_off[i])
+        return self.ws[:4 * self.n_pixels].view(torch.int32)[o:o + h * w].view(h, w)
 
     def stream(self, i):
         o = int(self.out_off[i])

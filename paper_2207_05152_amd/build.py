@@ -1,5 +1,8 @@
 """Build libdlic.so for gfx950 in-tree with hipcc.
 
+Each source compiles to its own object in parallel, then one hipcc line links
+them into the shared library.
+
 Usage: python -m paper_2207_05152_amd.build   (or build() from Python)
 """
 from __future__ import annotations
@@ -7,6 +10,8 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -20,7 +25,6 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # encoder and decoder must round identically: no contraction into FMA
     "-ffp-contract=off",
     # packed FP32 ops stay off (only scalar VALU FP32 and MFMA are used)
@@ -29,17 +33,28 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", INCLUDE, *[os.path.join(CSRC, s) for s in SOURCES],
-           "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libdlic.so")
+    return res.returncode
+
+
+def build(verbose: bool = False) -> str:
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    with tempfile.TemporaryDirectory(prefix="dlic_build_") as tmpd:
+        objs = [os.path.join(tmpd, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        cmds = [[hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-c", os.path.join(CSRC, s), "-o", o]
+                for s, o in zip(SOURCES, objs)]
+        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+            rcs = list(ex.map(lambda c: _run(c, verbose), cmds))
+        if any(rcs):
+            raise RuntimeError("hipcc failed compiling libdlic sources")
+        tmp = LIB + ".tmp"
+        if _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose):
+            raise RuntimeError("hipcc failed linking libdlic.so")
     os.replace(tmp, LIB)
     return LIB
 

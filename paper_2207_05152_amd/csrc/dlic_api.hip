@@ -24,7 +24,15 @@ constexpr int MAX_TIMED = 16;
 struct DeviceState {
   bool ready = false;
   Consts* consts = nullptr;
+  void* scratch = nullptr;  // this device's address of `scratch` below
 };
+
+// Decode workspace of dlic_decode_noalloc: a fixed array in the code
+// object, one copy per device, reserved until the process ends.  Host code
+// never passes this name to a kernel (on the host it is only a stand-in for
+// the symbol); it uses the device address that ensure_device looks up.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)8 << 20;
+__device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
 
 std::mutex g_mu;
 DeviceState g_dev[MAX_DEVICES];
@@ -72,13 +80,19 @@ dlic_status ensure_device(int device, const Consts** out) {
     Consts host;
     build_consts(&host);
     Consts* d = nullptr;
+    void* sp = nullptr;
     dlic_status rc = DLIC_OK;
     if (hipMalloc((void**)&d, sizeof(Consts)) != hipSuccess ||
         hipMemcpy(d, &host, sizeof(Consts), hipMemcpyHostToDevice) != hipSuccess)
       rc = DLIC_ERR_HIP;
+    // the no-alloc decode's workspace on this device (device current here)
+    if (rc == DLIC_OK &&
+        (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || sp == nullptr))
+      rc = DLIC_ERR_HIP;
     (void)hipSetDevice(prev);
     if (rc != DLIC_OK) return rc;
     st.consts = d;
+    st.scratch = sp;
     st.ready = true;
   }
   if (out) *out = st.consts;
@@ -94,8 +108,16 @@ dlic_status current_consts(const Consts** out) {
 // --- timing -----------------------------------------------------------------
 void timing_reset() { g_n_timed = 0; }
 
+// Timing stays off while one of these lives (calls that must not allocate).
+bool g_timing_off = false;
+struct NoTiming {
+  bool prev;
+  NoTiming() : prev(g_timing_off) { g_timing_off = true; }
+  ~NoTiming() { g_timing_off = prev; }
+};
+
 void timing_begin(const char* name, hipStream_t s) {
-  if (!g_timing) return;
+  if (!g_timing || g_timing_off) return;
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_n_timed >= MAX_TIMED) return;
   if ((int)g_events.size() <= g_n_timed) {
@@ -109,7 +131,7 @@ void timing_begin(const char* name, hipStream_t s) {
 }
 
 void timing_end(hipStream_t s) {
-  if (!g_timing) return;
+  if (!g_timing || g_timing_off) return;
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_n_timed >= MAX_TIMED) return;
   (void)hipEventRecord(g_events[g_n_timed].stop, s);
@@ -237,6 +259,9 @@ struct dlic_batch {
   int device = 0;
   dlic_model model{};
   int n_img = 0, n_blk = 0, density_grid = 0, pack_parts = 1;
+  int widest = 1;       // largest lanes per group of any image
+  int search_lpp = 0;   // coder lanes per pixel in decode; 0: coder_lpp(widest)
+  int decode_grid = 0;  // cap on the persistent decode grid; 0: resident capacity
   std::vector<BatchImage> images;
   std::vector<BatchItem> items;
   BatchImage* d_images = nullptr;
@@ -307,9 +332,8 @@ dlic_status batch_enqueue(dlic_batch* b, bool decode, const uint8_t* in, uint8_t
     launch_fill_u32((uint32_t*)status, 0u, b->n_img, s);
     if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
     timing_begin("batch_decode_kernel", s);
-    int widest = 1;
-    for (const BatchImage& im : b->images) widest = std::max(widest, im.L);
-    if (!launch_batch_decode(wtype, b->model.h1, K, dm, a, coder_lpp(widest), s))
+    const int lpp = b->search_lpp > 0 ? b->search_lpp : coder_lpp(b->widest);
+    if (!launch_batch_decode(wtype, b->model.h1, K, dm, a, lpp, b->decode_grid, s))
       return DLIC_ERR_UNSUPPORTED;
     timing_end(s);
   }
@@ -444,7 +468,8 @@ size_t dlic_encode_workspace(int32_t h, int32_t w, const dlic_coder* coder) {
 
 size_t dlic_decode_workspace(int32_t h, int32_t w, const dlic_coder* coder) {
   if (h <= 0 || w <= 0 || !coder_ok(h, coder)) return 0;
-  return align256(4 * (size_t)coder->groups * (size_t)n_steps(h, w));
+  // records [G][T], then the group ticket
+  return align256(4 * ((size_t)coder->groups * (size_t)n_steps(h, w) + 1));
 }
 
 dlic_status dlic_peek_header(const uint8_t* b, size_t n, int32_t* h, int32_t* w,
@@ -556,6 +581,7 @@ static dlic_status decode_common(const dlic_model* model, bool tables_mode,
   a.L = coder->lanes_per_group;
   a.rec = (uint32_t*)d_ws;
   a.T = n_steps(h, w);
+  a.ticket = (unsigned*)(a.rec + (long long)a.G * a.T);
   a.status = d_status;
   a.spin_limit = g_spin_limit;
   a.prof = tables_mode ? nullptr : g_prof;
@@ -576,7 +602,7 @@ static dlic_status decode_common(const dlic_model* model, bool tables_mode,
     wtype = weight_type(model);
   }
   timing_begin("fill_u32_kernel", stream);
-  launch_fill_u32(a.rec, 0u, (long long)a.G * a.T, stream);
+  launch_fill_u32(a.rec, 0u, (long long)a.G * a.T + 1, stream);
   launch_fill_u32((uint32_t*)d_status, 0u, 1, stream);
   timing_end(stream);
   if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
@@ -594,6 +620,29 @@ dlic_status dlic_decode(const dlic_model* model, const dlic_coder* coder,
   return decode_common(model, false, coder, nullptr, 0, nullptr, d_bits, n_bytes, d_img, h, w,
                        d_status, d_ws, ws_bytes, stream);
 }
+
+dlic_status dlic_decode_noalloc(const dlic_model* model, const dlic_coder* coder,
+                                const uint8_t* d_bits, size_t n_bytes, uint8_t* d_img, int32_t h,
+                                int32_t w, int32_t* d_status, hipStream_t stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return DLIC_ERR_HIP;
+  void* sp = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_dev[dev].ready) sp = g_dev[dev].scratch;
+  }
+  // set-up (constant tables, workspace address) allocates: dlic_init first
+  if (sp == nullptr) return DLIC_ERR_ARG;
+  if (!d_bits || !d_img || !d_status || h <= 0 || w <= 0) return DLIC_ERR_ARG;
+  if (!coder_ok(h, coder)) return DLIC_ERR_UNSUPPORTED;
+  if (dlic_decode_workspace(h, w, coder) > NOALLOC_SCRATCH_BYTES) return DLIC_ERR_CAPACITY;
+  // no timing events either: creating one may allocate
+  const NoTiming quiet;
+  return decode_common(model, false, coder, nullptr, 0, nullptr, d_bits, n_bytes, d_img, h, w,
+                       d_status, sp, NOALLOC_SCRATCH_BYTES, stream);
+}
+
+size_t dlic_decode_noalloc_limit(void) { return NOALLOC_SCRATCH_BYTES; }
 
 dlic_status dlic_rans_decode_tables(const dlic_coder* coder, int32_t h, int32_t w,
                                     const uint32_t* d_tables, int32_t n_tables,
@@ -615,6 +664,21 @@ dlic_status dlic_density(const dlic_model* model, const uint8_t* d_img, int32_t 
   timing_begin("density_kernel", stream);
   launch_density(weight_type(model), model->h1, K, dev_model(model), d_img, h, w, d_cf, d_out15, d_tables,
                  density_grid((long long)h * w), stream);
+  timing_end(stream);
+  return launch_ok();
+}
+
+dlic_status dlic_net_forms(const dlic_model* model, const float* d_feats, int64_t n,
+                           int32_t lanes, float* d_out16, float* d_out4, hipStream_t stream) {
+  timing_reset();
+  if (!d_feats || !d_out16 || !d_out4 || n <= 0 || n % 16 != 0 || lanes < 1 || lanes > 4)
+    return DLIC_ERR_ARG;
+  dlic_status rc = model_ok(model);
+  if (rc != DLIC_OK) return rc;
+  if (model->dtype != DLIC_FP32 || model->h1 != 128) return DLIC_ERR_UNSUPPORTED;
+  if ((rc = current_consts(nullptr)) != DLIC_OK) return rc;
+  timing_begin("net_forms_kernel", stream);
+  launch_net_forms(dev_model(model), d_feats, n, lanes, d_out16, d_out4, stream);
   timing_end(stream);
   return launch_ok();
 }
@@ -753,6 +817,7 @@ dlic_status dlic_batch_create(const dlic_model* model, int32_t n_img, const int3
   });
   for (int i : order)
     for (int g = 0; g < b->images[i].G; ++g) b->items.push_back(BatchItem{i, g});
+  for (const BatchImage& im : b->images) b->widest = std::max(b->widest, im.L);
   b->n_blk = (int)blk;
   b->density_grid = density_grid > 0 ? density_grid : (int)std::min<long long>(blk, 1024);
   b->pack_parts = (int)std::min<long long>(64, maxper / 4096 + 1);
@@ -776,6 +841,19 @@ dlic_status dlic_batch_create(const dlic_model* model, int32_t n_img, const int3
     return DLIC_ERR_HIP;
   }
   *out = b;
+  return DLIC_OK;
+}
+
+dlic_status dlic_batch_tune(dlic_batch* b, int32_t search_lanes, int32_t decode_grid) {
+  if (!b || decode_grid < 0) return DLIC_ERR_ARG;
+  // 16 lanes per pixel serve at most 4 pixels per sub-round; the split
+  // binary search at most 32
+  if (search_lanes != 0 && search_lanes != 1 && search_lanes != 2 && search_lanes != 16)
+    return DLIC_ERR_ARG;
+  if ((search_lanes == 16 && b->widest > 4) || (search_lanes == 2 && b->widest > 32))
+    return DLIC_ERR_UNSUPPORTED;
+  b->search_lpp = search_lanes;
+  b->decode_grid = decode_grid;
   return DLIC_OK;
 }
 

@@ -26,8 +26,9 @@
 // Rows r0-2 and r0-1 come from the group above through 32-bit records that
 // carry validity and both pixels in one word (bit 31 valid, bits 8..15 row
 // r1-2, bits 0..7 row r1-1), written and read with agent-scope atomics.  A
-// group only waits for the one before it, which the dispatcher started
-// earlier, and every wait is bounded, so the grid always drains.
+// group only waits for the one before it, whose workgroup took its ticket
+// earlier and is running or done, and every wait is bounded, so the grid
+// always drains.
 #include "dlic_device.hpp"
 #include "dlic_kernels.h"
 
@@ -413,6 +414,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           const int sn = (q + 1) & (NSLOT - 1);
           __builtin_amdgcn_sched_barrier(0);
           nd = __hip_atomic_load(&s_done[sn][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          asm volatile("" ::: "memory");
           __builtin_amdgcn_sched_barrier(0);
           const f4* nq = reinterpret_cast<const f4*>(&s_par[sn][cl * PAR_STRIDE]);
           n0 = nq[0];
@@ -914,6 +916,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
           ++n_tiles;
         }
         if (valid) *reinterpret_cast<f4*>(&par[ln * PAR_STRIDE + 4 * q4]) = o;
+        wave_lds_handover();
         if (SPX == 4 || L <= 4) {
           // At most 4 pixels: row p of the wave (lanes 16 p + k) serves pixel
           // p.  Lane k < 5 evaluates mixture component k (the head's two
@@ -941,6 +944,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
             pp[N_MIX + k] = A;
             pp[2 * N_MIX + k] = B;
           }
+          wave_lds_handover();
           if (pv && k < N_MIX) {
             float sm = 0.0f;
 #pragma unroll
@@ -949,6 +953,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
             const float e = pp[k];
             pp[k] = e * rs;
           }
+          wave_lds_handover();
           if (a.prof) c_head = clk_now();
           if (pv && k < N_BUCKET) {
             Mix mx;
@@ -975,6 +980,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
             pp[2 * N_MIX + k] = mx.B[k];
           }
         }
+        wave_lds_handover();
         if (a.prof) c_head = clk_now();
         // table at the bucket boundaries 16, 32, ..., 240
         if (valid) {
@@ -1034,52 +1040,90 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
   }
 }
 
+// One image: each workgroup takes its group by ticket, so group g - 1 was
+// taken by a workgroup that is running or done before group g waits on it,
+// whatever order the dispatcher starts workgroups in.
 template <class Net, bool TABLES, int LPP>
 __global__ __launch_bounds__(dec_waves<Net>() * 64) void wavefront_decode_kernel(
     const Consts* __restrict__ K, DevModel m, DecArgs a) {
-  decode_group<Net, TABLES, LPP>(K, m, a, blockIdx.x);
+  __shared__ int s_group;
+  if (threadIdx.x == 0) s_group = (int)atomicAdd(a.ticket, 1u);
+  __syncthreads();
+  const int g = s_group;
+  if (g >= a.G) return;
+  decode_group<Net, TABLES, LPP>(K, m, a, g);
 }
 
-// Batched decode: every workgroup takes the next work item by ticket.  Items
-// list the groups of an image in order, so the group a workgroup waits for
-// was taken earlier by a workgroup that is resident or done: the waits end.
-// The last group of an image to finish stamps the image's completion time.
+// Batched decode, persistent: a grid of resident workgroups, each taking the
+// next work item by ticket until the list is empty.  Items list the groups
+// of an image in order, and a workgroup finishes its item before it takes
+// another, so the group an item waits for was taken earlier by a workgroup
+// that is running or done: the waits end.  The last group of an image to
+// finish stamps the image's completion time.
 template <class Net, int LPP>
 __global__ __launch_bounds__(dec_waves<Net>() * 64) void batch_decode_kernel(
     const Consts* __restrict__ K, DevModel m, BatchArgs b) {
   __shared__ int s_item;
-  if (threadIdx.x == 0) s_item = (int)atomicAdd(b.ticket, 1u);
-  __syncthreads();
-  const int item = s_item;
-  if (item >= b.n_items) return;
-  const BatchItem it = b.items[item];
-  const BatchImage im = b.images[it.image];
-  DecArgs a;
-  a.bits = b.bits + im.out_off;
-  // a length beyond the region is corrupt; 0 makes the header check say so
-  a.n_bytes = b.len[it.image] <= (unsigned long long)im.out_cap ? b.len[it.image] : 0ull;
-  a.img = b.pix_out + im.px_off;
-  a.H = im.H;
-  a.W = im.W;
-  a.G = im.G;
-  a.L = im.L;
-  a.rec = b.rec + im.rec_off;
-  a.T = im.T;
-  a.status = b.status + it.image;
-  a.spin_limit = b.spin_limit;
-  a.check_model = 1;
-  a.hf = b.hf;
-  a.tables = nullptr;
-  a.n_tables = 0;
-  a.tidx = nullptr;
-  a.prof = nullptr;
-  decode_group<Net, false, LPP>(K, m, a, it.group);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    if (atomicAdd(b.done + it.image, 1u) + 1u == (unsigned)im.G && b.t_done)
-      b.t_done[it.image] = __builtin_amdgcn_s_memrealtime();
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(b.ticket, 1u);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= b.n_items) return;
+    const BatchItem it = b.items[item];
+    const BatchImage im = b.images[it.image];
+    DecArgs a;
+    a.bits = b.bits + im.out_off;
+    // a length beyond the region is corrupt; 0 makes the header check say so
+    a.n_bytes = b.len[it.image] <= (unsigned long long)im.out_cap ? b.len[it.image] : 0ull;
+    a.img = b.pix_out + im.px_off;
+    a.H = im.H;
+    a.W = im.W;
+    a.G = im.G;
+    a.L = im.L;
+    a.rec = b.rec + im.rec_off;
+    a.ticket = nullptr;
+    a.T = im.T;
+    a.status = b.status + it.image;
+    a.spin_limit = b.spin_limit;
+    a.check_model = 1;
+    a.hf = b.hf;
+    a.tables = nullptr;
+    a.n_tables = 0;
+    a.tidx = nullptr;
+    a.prof = nullptr;
+    decode_group<Net, false, LPP>(K, m, a, it.group);
+    // every thread is past decode_group (and has read s_item) before the
+    // next ticket overwrites it
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      if (atomicAdd(b.done + it.image, 1u) + 1u == (unsigned)im.G && b.t_done)
+        b.t_done[it.image] = __builtin_amdgcn_s_memrealtime();
+    }
   }
+}
+
+// Workgroups of a persistent batch decode: as many as stay resident at once,
+// at most one per work item.
+template <class Kern>
+static int persistent_grid(Kern kern, int threads, int n_items) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) != hipSuccess)
+    per_cu = 0;
+  long long g = (long long)(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+  if (g > n_items) g = n_items;
+  return (int)(g > 0 ? g : 1);
+}
+
+template <class Net, int LPP>
+static void launch_batch_decode_k(const Consts* K, const DevModel& m, const BatchArgs& b,
+                                  int grid_cap, hipStream_t s) {
+  const int threads = dec_waves<Net>() * 64;
+  int grid = persistent_grid(batch_decode_kernel<Net, LPP>, threads, b.n_items);
+  if (grid_cap > 0 && grid_cap < grid) grid = grid_cap;
+  hipLaunchKernelGGL((batch_decode_kernel<Net, LPP>), dim3(grid), dim3(threads), 0, s, K, m, b);
 }
 
 __global__ void stamp_kernel(unsigned long long* t) {
@@ -1105,46 +1149,46 @@ void launch_fill_u32(uint32_t* p, uint32_t v, long long n, hipStream_t s) {
 
 template <class Net>
 static void launch_batch_decode_t(const Consts* K, const DevModel& m, const BatchArgs& b,
-                                  int lpp, hipStream_t s) {
-  const dim3 grid(b.n_items), block(dec_waves<Net>() * 64);
+                                  int lpp, int cap, hipStream_t s) {
   if (lpp == 16)
-    hipLaunchKernelGGL((batch_decode_kernel<Net, 16>), grid, block, 0, s, K, m, b);
+    launch_batch_decode_k<Net, 16>(K, m, b, cap, s);
   else if (lpp == 2)
-    hipLaunchKernelGGL((batch_decode_kernel<Net, 2>), grid, block, 0, s, K, m, b);
+    launch_batch_decode_k<Net, 2>(K, m, b, cap, s);
   else
-    hipLaunchKernelGGL((batch_decode_kernel<Net, 1>), grid, block, 0, s, K, m, b);
+    launch_batch_decode_k<Net, 1>(K, m, b, cap, s);
 }
 
 template <int H>
 static bool launch_batch_decode_h(int wtype, const Consts* K, const DevModel& m,
-                                  const BatchArgs& b, int lpp, hipStream_t s) {
+                                  const BatchArgs& b, int lpp, int cap, hipStream_t s) {
   switch (wtype) {
     case WT_F32:
       // as for one image: the 128-wide net on tiles of at most 4 pixels
       if (H == 128 && lpp == 16) {
-        hipLaunchKernelGGL((batch_decode_kernel<NetF32x4, 16>), dim3(b.n_items),
-                           dim3(dec_waves<NetF32x4>() * 64), 0, s, K, m, b);
+        launch_batch_decode_k<NetF32x4, 16>(K, m, b, cap, s);
       } else {
-        launch_batch_decode_t<NetF32<H, (H >= 64)>>(K, m, b, lpp, s);
+        launch_batch_decode_t<NetF32<H, (H >= 64)>>(K, m, b, lpp, cap, s);
       }
       return true;
     case WT_BF16:
-      launch_batch_decode_t<NetBF16<H, WT_BF16, (H > 64)>>(K, m, b, lpp, s);
+      launch_batch_decode_t<NetBF16<H, WT_BF16, (H > 64)>>(K, m, b, lpp, cap, s);
       return true;
     case WT_FP8:
-      launch_batch_decode_t<NetBF16<H, WT_FP8, (H > 64)>>(K, m, b, lpp, s);
+      launch_batch_decode_t<NetBF16<H, WT_FP8, (H > 64)>>(K, m, b, lpp, cap, s);
       return true;
-    case WT_FP8A8: launch_batch_decode_t<NetFP8A<H, (H > 64)>>(K, m, b, lpp, s); return true;
+    case WT_FP8A8:
+      launch_batch_decode_t<NetFP8A<H, (H > 64)>>(K, m, b, lpp, cap, s);
+      return true;
     default: return false;
   }
 }
 
 bool launch_batch_decode(int wtype, int width, const Consts* K, const DevModel& m,
-                         const BatchArgs& b, int lpp, hipStream_t s) {
+                         const BatchArgs& b, int lpp, int grid_cap, hipStream_t s) {
   switch (width) {
-    case 32: return launch_batch_decode_h<32>(wtype, K, m, b, lpp, s);
-    case 64: return launch_batch_decode_h<64>(wtype, K, m, b, lpp, s);
-    case 128: return launch_batch_decode_h<128>(wtype, K, m, b, lpp, s);
+    case 32: return launch_batch_decode_h<32>(wtype, K, m, b, lpp, grid_cap, s);
+    case 64: return launch_batch_decode_h<64>(wtype, K, m, b, lpp, grid_cap, s);
+    case 128: return launch_batch_decode_h<128>(wtype, K, m, b, lpp, grid_cap, s);
     default: return false;
   }
 }

@@ -81,6 +81,14 @@ __device__ __forceinline__ int nb_dx(int k) { return k < 5 ? k - 2 : (k < 10 ? k
 
 __device__ __forceinline__ float relu(float v) { return v > 0.0f ? v : 0.0f; }
 
+// Hand-over of LDS data between lanes of one wave: a wave-scope release and
+// acquire keep the compiler from moving the reads above the writes (the
+// hardware already serves one wave's LDS accesses in order; no wait is added).
+__device__ __forceinline__ void wave_lds_handover() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Storage types of the weight matrices.
 enum WeightType { WT_F32 = 0, WT_BF16 = 1, WT_FP8 = 2, WT_FP8A8 = 4 };
 
@@ -384,6 +392,7 @@ struct NetF32x4 {
       ft[p * ROW + 4 + q] = f1;
       ft[p * ROW + 8 + q] = f2;
     }
+    wave_lds_handover();
     {
       const f4 fa = *reinterpret_cast<const f4*>(&ft[j * ROW]);
       const f4 fb = *reinterpret_cast<const f4*>(&ft[j * ROW + 4]);
@@ -406,6 +415,7 @@ struct NetF32x4 {
         h1t[j * ROW + 64 + c0 + 4 * i] = relu(h1[i]);
       }
     }
+    wave_lds_handover();
     // layer 2: four chain steps per pass, both neuron halves
     const f4* w = reinterpret_cast<const f4*>(lds);
     f4 lo = {c2[0][0], c2[0][1], c2[0][2], c2[0][3]};
@@ -432,6 +442,7 @@ struct NetF32x4 {
       h2t[j * ROW + l3pos(n)] = relu(lo[i]);
       h2t[j * ROW + l3pos(64 + n)] = relu(hi[i]);
     }
+    wave_lds_handover();
     // layer 3 on the 4x4 form: block b = 4 g + og is quarter g of outputs
     // 4 og .. 4 og + 3, so lane 16 g + 4 og + j accumulates that quarter for
     // pixel j; the quarters then meet in the 16x16 layout
@@ -444,6 +455,7 @@ struct NetF32x4 {
     }
     float* part = h1t;  // free once layer 2 has read it
     *reinterpret_cast<f4*>(&part[4 * lane]) = o3;
+    wave_lds_handover();
     f4 o = {0.0f, 0.0f, 0.0f, 0.0f};
     if (p < 4) {
       // outputs 4 q .. 4 q + 3 of pixel p: quarter g sits at lane 16 g + 4 q + p

@@ -193,6 +193,61 @@ bool launch_activation_range(int width, const Consts* K, const DevModel& m, cons
   }
 }
 
+// Test hook: the encoder's 16-pixel FP32 form of the 12-128-128-15 net and
+// the decoder's 4-pixel form (NetF32x4) on the same caller-given feature rows.
+// One wave per block, 16 rows per tile.  In the 4-pixel form, rows 4s + j
+// with j >= lanes get all-zero features (the decoder's idle tile rows).
+__global__ __launch_bounds__(64) void net_forms_kernel(DevModel m, const float* __restrict__ feats,
+                                                      long long n, int lanes,
+                                                      float* __restrict__ out16,
+                                                      float* __restrict__ out4) {
+  using Net16 = NetF32<128>;
+  __shared__ __attribute__((aligned(16))) char w16[Net16::LDS_BYTES];
+  __shared__ __attribute__((aligned(16))) char w4[NetF32x4::LDS_BYTES];
+  __shared__ __attribute__((aligned(16))) float xs[NetF32x4::SCRATCH_FLOATS];
+  const int lane = threadIdx.x, q = lane >> 4, p = lane & 15;
+  Net16::stage(m, w16, lane, 64);
+  NetF32x4::stage(m, w4, lane, 64);
+  __syncthreads();
+  Net16 a;
+  a.load(m, lane);
+  NetF32x4 b;
+  b.load(m, lane);
+  b.xs = xs;
+  for (long long tile = blockIdx.x; tile * 16 < n; tile += gridDim.x) {
+    const long long r16 = tile * 16 + p;
+    float f[3];
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) f[kk] = feats[r16 * K_IN + 4 * kk + q];
+    const f4 o = a.run(f[0], f[1], f[2], w16);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (4 * q + r < N_OUT) out16[r16 * N_OUT + 4 * q + r] = o[r];
+#pragma unroll 1
+    for (int sub = 0; sub < 4; ++sub) {
+      const long long r4 = tile * 16 + 4 * sub + (p & 3);
+      const bool live = p < 4 && p < lanes;
+      float g[3];
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) g[kk] = live ? feats[r4 * K_IN + 4 * kk + q] : 0.0f;
+      const f4 o4 = b.run(g[0], g[1], g[2], w4);
+      if (p < 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (4 * q + r < N_OUT) out4[r4 * N_OUT + 4 * q + r] = o4[r];
+      }
+    }
+  }
+}
+
+void launch_net_forms(const DevModel& m, const float* feats, long long n, int lanes, float* out16,
+                      float* out4, hipStream_t s) {
+  long long tiles = n / 16;
+  const int grid = (int)(tiles < 1024 ? (tiles > 0 ? tiles : 1) : 1024);
+  hipLaunchKernelGGL(net_forms_kernel, dim3(grid), dim3(64), 0, s, m, feats, n, lanes, out16,
+                     out4);
+}
+
 constexpr int ENC_CHUNK = 32;   // wavefront steps staged in LDS per chunk
 constexpr int ENC_BATCH = 8;    // sub-rounds read from LDS ahead of coding
 constexpr int ENC_STAGERS = 192;  // threads of waves 1..3

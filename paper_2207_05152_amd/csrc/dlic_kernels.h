@@ -23,6 +23,7 @@ struct DecArgs {
   uint8_t* img;
   int H, W, G, L;
   uint32_t* rec;          // [G][T] progress records, cleared before launch
+  unsigned* ticket;       // one-image decode: next group to take, cleared before launch
   long long T;            // wavefront steps W + 3H - 3
   int* status;
   uint32_t spin_limit;
@@ -80,6 +81,10 @@ bool launch_density(int wtype, int width, const Consts* K, const DevModel& m, co
 // folded into amax[0..1] (atomic maximum; the caller clears them).
 bool launch_activation_range(int width, const Consts* K, const DevModel& m, const uint8_t* img,
                              int H, int W, float* amax, int grid, hipStream_t s);
+// Test hook: both FP32 forms of the 12-128-128-15 net on n (a multiple of 16)
+// feature rows; out16 / out4: [n][15].
+void launch_net_forms(const DevModel& m, const float* feats, long long n, int lanes, float* out16,
+                      float* out4, hipStream_t s);
 void launch_rans_encode(const uint32_t* cf, int H, int W, int G, int L, uint16_t* words,
                         uint32_t* counts, hipStream_t s);
 void launch_pack(const uint16_t* words, const uint32_t* counts, int H, int W, int G, int L,
@@ -101,9 +106,11 @@ void launch_batch_pack(const BatchArgs& b, int parts, hipStream_t s);
 // per lane).
 __host__ __device__ constexpr int coder_lpp(int L) { return L <= 4 ? 16 : (L <= 32 ? 2 : 1); }
 
-// lpp: coder lanes per pixel, coder_lpp(L) of the widest image of the batch.
+// lpp: coder lanes per pixel, coder_lpp(L) of the widest image of the batch
+// or a smaller fan-out the plan asks for.  grid_cap > 0 caps the persistent
+// grid below the number of workgroups that stay resident.
 bool launch_batch_decode(int wtype, int width, const Consts* K, const DevModel& m,
-                         const BatchArgs& b, int lpp, hipStream_t s);
+                         const BatchArgs& b, int lpp, int grid_cap, hipStream_t s);
 
 // Training: waves per workgroup of the FP32 / FP64 loss-and-gradient kernel.
 constexpr int TRAIN_WAVES_F32 = 4;
