@@ -1049,7 +1049,7 @@ __global__ __launch_bounds__(dec_waves<Net>() * 64) void wavefront_decode_kernel
   __shared__ int s_group;
   if (threadIdx.x == 0) s_group = (int)atomicAdd(a.ticket, 1u);
   __syncthreads();
-  const int g = s_group;
+  const int g = __builtin_amdgcn_readfirstlane(s_group);
   if (g >= a.G) return;
   decode_group<Net, TABLES, LPP>(K, m, a, g);
 }
@@ -1064,11 +1064,14 @@ template <class Net, int LPP>
 __global__ __launch_bounds__(dec_waves<Net>() * 64) void batch_decode_kernel(
     const Consts* __restrict__ K, DevModel m, BatchArgs b) {
   __shared__ int s_item;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = (int)atomicAdd(b.ticket, 1u);
-    __syncthreads();
-    const int item = s_item;
-    if (item >= b.n_items) return;
+  if (threadIdx.x == 0) s_item = (int)atomicAdd(b.ticket, 1u);
+  __syncthreads();
+  // The item is read as a wave-uniform value, so every wave leaves or repeats
+  // the loop as a whole.  Read per lane, the loop's exit would be divergent,
+  // and the compiler may then send lanes 1..63 of wave 0 back to the top
+  // barrier ahead of lane 0, before it has taken the next ticket.
+  int item = __builtin_amdgcn_readfirstlane(s_item);
+  while (item < b.n_items) {
     const BatchItem it = b.items[item];
     const BatchImage im = b.images[it.image];
     DecArgs a;
@@ -1092,14 +1095,17 @@ __global__ __launch_bounds__(dec_waves<Net>() * 64) void batch_decode_kernel(
     a.tidx = nullptr;
     a.prof = nullptr;
     decode_group<Net, false, LPP>(K, m, a, it.group);
-    // every thread is past decode_group (and has read s_item) before the
-    // next ticket overwrites it
+    // every wave is done with the item (and with the LDS of decode_group)
+    // before thread 0 counts it and takes the next ticket
     __syncthreads();
     if (threadIdx.x == 0) {
       __threadfence();
       if (atomicAdd(b.done + it.image, 1u) + 1u == (unsigned)im.G && b.t_done)
         b.t_done[it.image] = __builtin_amdgcn_s_memrealtime();
+      s_item = (int)atomicAdd(b.ticket, 1u);
     }
+    __syncthreads();
+    item = __builtin_amdgcn_readfirstlane(s_item);
   }
 }
 
