@@ -184,12 +184,15 @@ dlic_status dlic_decode(const dlic_model *model, const dlic_coder *coder,
                         int32_t h, int32_t w, int32_t *d_status,
                         void *d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* Bytes of the fixed workspace array of dlic_decode_noalloc. */
+#define DLIC_DECODE_NOALLOC_BYTES ((size_t)8 << 20)
+
 /* dlic_decode for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
  * Same stream format, kernels, results and device status as dlic_decode,
  * without d_ws: the decode's progress records and group ticket live in a
- * fixed array of dlic_decode_noalloc_limit() bytes (8 MiB) that the library
- * keeps on every device it runs on until the process ends.  The call makes
+ * fixed array of DLIC_DECODE_NOALLOC_BYTES (8 MiB) that the library keeps on
+ * every device it runs on until the process ends.  The call makes
  * no allocation, creates no timing events, and clears the part of the array
  * it uses with a kernel before its decode kernel runs.  Needs dlic_init on
  * the current device first (DLIC_ERR_ARG otherwise: set-up allocates).
@@ -202,8 +205,6 @@ dlic_status dlic_decode_noalloc(const dlic_model *model, const dlic_coder *coder
                                 const uint8_t *d_bits, size_t n_bytes, uint8_t *d_img,
                                 int32_t h, int32_t w, int32_t *d_status, hipStream_t stream);
 
-/* Bytes of the fixed workspace array of dlic_decode_noalloc. */
-size_t dlic_decode_noalloc_limit(void);
 
 /* Spin limit of one decode wait (polls of an upstream record, each followed
  * by a short sleep); a wait that exceeds it reports DLIC_ERR_TIMEOUT and the

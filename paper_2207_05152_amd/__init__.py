@@ -25,6 +25,7 @@ DLIC_ERR_MODEL_MISMATCH, DLIC_ERR_UNSUPPORTED, DLIC_ERR_HIP, DLIC_ERR_TIMEOUT = 
 DLIC_FP32, DLIC_BF16, DLIC_FP8_E4M3, DLIC_FP64, DLIC_FP8_W8A8 = 0, 1, 2, 3, 4
 FNV_OFFSET = 0xCBF29CE484222325
 HEADER_BYTES = 36
+DECODE_NOALLOC_BYTES = 8 << 20  # DLIC_DECODE_NOALLOC_BYTES of dlic.h
 
 # Every symbol include/dlic.h declares.
 EXPORTS = (
@@ -37,7 +38,7 @@ EXPORTS = (
     "dlic_set_decode_profile", "dlic_nll_workspace", "dlic_nll_fwd_bwd", "dlic_adam_step",
     "dlic_batch_create", "dlic_batch_destroy", "dlic_batch_sizes", "dlic_batch_layout",
     "dlic_encode_batch", "dlic_decode_batch", "dlic_batch_capture", "dlic_batch_replay",
-    "dlic_wallclock_hz", "dlic_decode_noalloc", "dlic_decode_noalloc_limit", "dlic_batch_tune",
+    "dlic_wallclock_hz", "dlic_decode_noalloc", "dlic_batch_tune",
     "dlic_net_forms",
 )
 
@@ -91,7 +92,6 @@ def lib():
                                 P, P, S, P]),
         "dlic_decode_noalloc": (c_int, [POINTER(dlic_model), POINTER(dlic_coder), P, S, P, c_int32,
                                         c_int32, P, P]),
-        "dlic_decode_noalloc_limit": (S, []),
         "dlic_set_spin_limit": (None, [c_uint32]),
         "dlic_net_forms": (c_int, [POINTER(dlic_model), P, ctypes.c_int64, c_int32, P, P, P]),
         "dlic_density": (c_int, [POINTER(dlic_model), P, c_int32, c_int32, P, P, P, P]),
@@ -238,7 +238,8 @@ def dlic_decode_noalloc(model: dlic_model, coder: dlic_coder, d_bits, n_bytes, d
 
 
 def dlic_decode_noalloc_limit() -> int:
-    return int(lib().dlic_decode_noalloc_limit())
+    """DLIC_DECODE_NOALLOC_BYTES of dlic.h: the no-alloc decode's fixed workspace."""
+    return DECODE_NOALLOC_BYTES
 
 
 def dlic_net_forms(model: dlic_model, d_feats, n, lanes, d_out16, d_out4, stream=None):

@@ -31,7 +31,7 @@ struct DeviceState {
 // object, one copy per device, reserved until the process ends.  Host code
 // never passes this name to a kernel (on the host it is only a stand-in for
 // the symbol); it uses the device address that ensure_device looks up.
-constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)8 << 20;
+constexpr size_t NOALLOC_SCRATCH_BYTES = DLIC_DECODE_NOALLOC_BYTES;
 __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
 
 std::mutex g_mu;
@@ -641,8 +641,6 @@ dlic_status dlic_decode_noalloc(const dlic_model* model, const dlic_coder* coder
   return decode_common(model, false, coder, nullptr, 0, nullptr, d_bits, n_bytes, d_img, h, w,
                        d_status, sp, NOALLOC_SCRATCH_BYTES, stream);
 }
-
-size_t dlic_decode_noalloc_limit(void) { return NOALLOC_SCRATCH_BYTES; }
 
 dlic_status dlic_rans_decode_tables(const dlic_coder* coder, int32_t h, int32_t w,
                                     const uint32_t* d_tables, int32_t n_tables,

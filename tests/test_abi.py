@@ -27,6 +27,13 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(dl.EXPORTS)
 
 
+def test_noalloc_limit_macro_matches_binding():
+    src = open(os.path.join(ROOT, "include", "dlic.h")).read()
+    m = re.search(r"#define DLIC_DECODE_NOALLOC_BYTES \(\(size_t\)(\d+) << (\d+)\)", src)
+    assert m, "DLIC_DECODE_NOALLOC_BYTES not found"
+    assert int(m.group(1)) << int(m.group(2)) == dl.DECODE_NOALLOC_BYTES == 8 << 20
+
+
 def test_constant_tables_match_oracle_bit_for_bit():
     S, D, beta, scale = dl.dlic_host_constants()
     So, Do = oracle.sigma_lut32()

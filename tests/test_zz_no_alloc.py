@@ -55,7 +55,7 @@ def test_noalloc_decode_reports_corruption_like_decode(dev):
 
 def test_noalloc_decode_limit(dev):
     model = dl.Model(synth.xavier_mlp((12, 32, 32, 15), 7), dev)
-    limit = dl.dlic_decode_noalloc_limit()
+    limit = dl.DECODE_NOALLOC_BYTES
     assert limit == 8 << 20
     # 1024 groups of 4 rows over a 4096 x 8192 image: far beyond the array
     coder = dl.dlic_coder(1024, 4)
