@@ -66,7 +66,8 @@ def test_c0_stream_structure_and_rate(dev, c0_inputs):
     assert cost - 1 <= payload <= cost + 32 * 32 + 0.02 * img.size
 
 
-@pytest.mark.parametrize("G,L", [(8, 32), (64, 4)])
+# 8 x 32 and 64 x 4: 256 lanes; 384 x 4 and 48 x 32: one lane per row (one sub-round per step)
+@pytest.mark.parametrize("G,L", [(8, 32), (64, 4), (384, 4), (48, 32)])
 def test_full_size_round_trip(dev, G, L):
     img = synth.synth_image(1536, 2048, 1)
     wts = synth.xavier_mlp((12, 64, 64, 15), 3)
