@@ -224,14 +224,15 @@ dlic_status dlic_density(const dlic_model *model, const uint8_t *d_img, int32_t 
 
 /* Test hook for the rule that encoder and decoder evaluate the network
  * identically (Section II-B, Preprocessor: the same arithmetic on both sides
- * makes the rounding errors equal).  At 12-128-128-15 in FP32 the encoder's
- * density kernel runs 16-pixel tiles on the 16x16x4 MFMA and the decoder
- * (with at most 4 lanes per group) 4-pixel tiles on the 4x4x1 MFMA in the
- * same summation order.  This runs both forms on n caller-given feature rows
- * (d_feats: [n][12] FP32, n a multiple of 16) and writes their outputs to
- * d_out16 and d_out4 ([n][15] FP32).  In the 4-pixel form, rows 4s + j with
- * j >= lanes (1..4) are replaced by zero features, as the decoder's unused
- * tile rows; their d_out4 entries are unspecified.  model: FP32, h1 = 128. */
+ * makes the rounding errors equal).  At 12-H-H-15 in FP32 with H = 64 or 128
+ * the encoder's density kernel runs 16-pixel tiles on the 16x16x4 MFMA and
+ * the decoder (with at most 4 lanes per group) 4-pixel tiles on the 4x4x1
+ * MFMA in the same summation order.  This runs both forms on n caller-given
+ * feature rows (d_feats: [n][12] FP32, n a multiple of 16) and writes their
+ * outputs to d_out16 and d_out4 ([n][15] FP32).  In the 4-pixel form, rows
+ * 4s + j with j >= lanes (1..4) are replaced by zero features, as the
+ * decoder's unused tile rows; their d_out4 entries are unspecified.
+ * model: FP32, h1 = h2 = 64 or 128 (DLIC_ERR_UNSUPPORTED otherwise). */
 dlic_status dlic_net_forms(const dlic_model *model, const float *d_feats, int64_t n,
                            int32_t lanes, float *d_out16, float *d_out4, hipStream_t stream);
 
@@ -343,6 +344,24 @@ dlic_status dlic_batch_replay(dlic_batch *b, int32_t decode, hipStream_t stream)
 
 /* Rate (Hz) of the device realtime counter behind the d_t_done stamps. */
 double dlic_wallclock_hz(void);
+
+/* Measurement hook for the decode bound (Section II-B, Preprocessor and rANS:
+ * each wavefront step waits for the previous one, so the decode takes at least
+ * the steps times the latency of the dependent operations one step needs).
+ * Runs one dependent chain per primitive on the current device and writes
+ * shader cycles per link to h_out[0..11]:
+ *   0 v_fma_f32, 1 4x4x1 FP32 MFMA, 2 16x16x4 FP32 MFMA (accumulator chains),
+ *   3 LDS store then load by one wave, 4 LDS load (address chase),
+ *   5 LDS flag hand-off between two waves (one way), 6 DPP reduction over 16
+ *   lanes, 7 expf, 8 one rANS decode update, 9 ballot + popcount,
+ *   10 flag hand-off between two workgroups through device memory (one way),
+ *   11 v_readlane;
+ * and h_out[12] = the shader clock in MHz over probe 0.  n >= DLIC_PROBE_COUNT.
+ * d_ws: at least 256 bytes of device memory.  Synchronous: returns after the
+ * probes ran (DLIC_ERR_TIMEOUT if a hand-off probe's bounded wait gave up). */
+#define DLIC_PROBE_COUNT 13
+dlic_status dlic_latency_probe(double *h_out, int32_t n, void *d_ws, size_t ws_bytes,
+                               hipStream_t stream);
 
 /* ---- retraining ------------------------------------------------------------ */
 

@@ -38,7 +38,7 @@ EXPORTS = (
     "dlic_set_decode_profile", "dlic_nll_workspace", "dlic_nll_fwd_bwd", "dlic_adam_step",
     "dlic_batch_create", "dlic_batch_destroy", "dlic_batch_sizes", "dlic_batch_layout",
     "dlic_encode_batch", "dlic_decode_batch", "dlic_batch_capture", "dlic_batch_replay",
-    "dlic_wallclock_hz", "dlic_decode_noalloc", "dlic_batch_tune",
+    "dlic_wallclock_hz", "dlic_decode_noalloc", "dlic_batch_tune", "dlic_latency_probe",
     "dlic_net_forms",
 )
 
@@ -116,6 +116,7 @@ def lib():
         "dlic_batch_capture": (c_int, [P, c_int32, P, P, P, P, P, P, S]),
         "dlic_batch_replay": (c_int, [P, c_int32, P]),
         "dlic_wallclock_hz": (ctypes.c_double, []),
+        "dlic_latency_probe": (c_int, [P, c_int32, P, S, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -586,6 +587,22 @@ def dlic_batch_replay(b, decode, stream=None):
 
 def dlic_wallclock_hz() -> float:
     return float(lib().dlic_wallclock_hz())
+
+
+PROBE_NAMES = ("fma_f32", "mfma_4x4x1_f32", "mfma_16x16x4_f32", "lds_store_load", "lds_load",
+               "lds_flag_handoff", "dpp_reduce16", "expf", "rans_update", "ballot_popcount",
+               "global_flag_handoff", "readlane")
+
+
+def dlic_latency_probe(stream=None) -> dict:
+    """Shader cycles per link of each primitive's dependent chain, and the shader clock."""
+    import torch
+    out = (ctypes.c_double * 13)()
+    ws = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    _check(lib().dlic_latency_probe(out, 13, _ptr(ws), 256, _stream(stream)), "dlic_latency_probe")
+    res = {n: float(out[i]) for i, n in enumerate(PROBE_NAMES)}
+    res["shader_clock_mhz"] = float(out[12])
+    return res
 
 
 class Batch:

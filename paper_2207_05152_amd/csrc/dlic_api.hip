@@ -673,10 +673,11 @@ dlic_status dlic_net_forms(const dlic_model* model, const float* d_feats, int64_
     return DLIC_ERR_ARG;
   dlic_status rc = model_ok(model);
   if (rc != DLIC_OK) return rc;
-  if (model->dtype != DLIC_FP32 || model->h1 != 128) return DLIC_ERR_UNSUPPORTED;
+  if (model->dtype != DLIC_FP32 || (model->h1 != 64 && model->h1 != 128))
+    return DLIC_ERR_UNSUPPORTED;
   if ((rc = current_consts(nullptr)) != DLIC_OK) return rc;
   timing_begin("net_forms_kernel", stream);
-  launch_net_forms(dev_model(model), d_feats, n, lanes, d_out16, d_out4, stream);
+  launch_net_forms(model->h1, dev_model(model), d_feats, n, lanes, d_out16, d_out4, stream);
   timing_end(stream);
   return launch_ok();
 }
@@ -952,6 +953,31 @@ dlic_status dlic_batch_replay(dlic_batch* b, int32_t decode, hipStream_t stream)
   const hipError_t e = hipGraphLaunch(b->exec[d], stream);
   timing_end(stream);
   return e == hipSuccess ? DLIC_OK : DLIC_ERR_HIP;
+}
+
+dlic_status dlic_latency_probe(double* h_out, int32_t n, void* d_ws, size_t ws_bytes,
+                               hipStream_t stream) {
+  if (!h_out || n < DLIC_PROBE_COUNT || !d_ws || ws_bytes < 256) return DLIC_ERR_ARG;
+  dlic_status rc = current_consts(nullptr);
+  if (rc != DLIC_OK) return rc;
+  unsigned long long* out = (unsigned long long*)d_ws;
+  uint32_t* gflags = (uint32_t*)((uint8_t*)d_ws + 128);
+  unsigned long long hv[4];
+  bool all_ok = true;
+  double mhz = 0.0;
+  for (int p = 0; p + 1 < DLIC_PROBE_COUNT; ++p) {
+    launch_fill_u32(gflags, 0u, 32, stream);
+    launch_latency_probe(p, out, gflags, stream);
+    if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
+    if (hipMemcpyAsync(hv, out, sizeof(hv), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return DLIC_ERR_HIP;
+    all_ok = all_ok && hv[2] == 1ull;
+    h_out[p] = (double)hv[0] / (double)probe_links(p);
+    if (p == 0 && hv[1] > 0) mhz = (double)hv[0] / (double)hv[1] * 100.0;
+  }
+  h_out[DLIC_PROBE_COUNT - 1] = mhz;
+  return all_ok ? DLIC_OK : DLIC_ERR_TIMEOUT;
 }
 
 double dlic_wallclock_hz(void) {

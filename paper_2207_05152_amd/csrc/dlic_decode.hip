@@ -1169,9 +1169,9 @@ static bool launch_batch_decode_h(int wtype, const Consts* K, const DevModel& m,
                                   const BatchArgs& b, int lpp, int cap, hipStream_t s) {
   switch (wtype) {
     case WT_F32:
-      // as for one image: the 128-wide net on tiles of at most 4 pixels
-      if (H == 128 && lpp == 16) {
-        launch_batch_decode_k<NetF32x4, 16>(K, m, b, cap, s);
+      // as for one image: nets of 64 or 128 neurons on tiles of at most 4 pixels
+      if (H >= 64 && lpp == 16) {
+        launch_batch_decode_k<NetF32x4<(H >= 64 ? H : 64)>, 16>(K, m, b, cap, s);
       } else {
         launch_batch_decode_t<NetF32<H, (H >= 64)>>(K, m, b, lpp, cap, s);
       }
@@ -1232,13 +1232,11 @@ static bool launch_decode_h(int wtype, const Consts* K, const DevModel& m, const
   switch (wtype) {
     case WT_F32:
       // layouts of at most 4 lanes (one tile of at most 4 pixels per
-      // sub-round, latency-bound): at H = 64 layer 2 stays in registers on 8
-      // waves, at H = 128 it runs on the 4x4 MFMA form; wider layouts need
-      // the 9 density waves of the 12-wave form at H = 64
-      if (H == 64 && a.L <= 4)
-        launch_decode_t<NetF32<64, false>, false>(K, m, a, s);
-      else if (H == 128 && a.L <= 4)
-        launch_decode_lpp16<NetF32x4>(K, m, a, s);
+      // sub-round, latency-bound): the 4-pixel 4x4 MFMA form at H = 64 and
+      // 128; wider layouts need the 9 density waves of the 12-wave form at
+      // H = 64
+      if (H >= 64 && a.L <= 4)
+        launch_decode_lpp16<NetF32x4<(H >= 64 ? H : 64)>>(K, m, a, s);
       else
         launch_decode_t<NetF32<H, (H >= 64)>, false>(K, m, a, s);
       return true;

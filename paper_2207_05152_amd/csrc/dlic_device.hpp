@@ -232,15 +232,18 @@ struct NetF32 {
 #pragma unroll
       for (int r = 0; r < 4; ++r) h2[n2][r] = relu(acc[r]);
     }
-    if constexpr (H == 128) {
-      // four K quarters (neuron tiles 2g and 2g + 1), each its own chain, the
-      // first seeded with the bias; summed as ((q0 + q1) + q2) + q3
+    if constexpr (H >= 64) {
+      // four K quarters (neuron tiles NT/4 g .. NT/4 g + NT/4 - 1), each its
+      // own chain, the first seeded with the bias; summed as
+      // ((q0 + q1) + q2) + q3
+      constexpr int TQ = NT / 4;
       f4 oq[4] = {{c3[0], c3[1], c3[2], c3[3]}, {0.0f, 0.0f, 0.0f, 0.0f},
                   {0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
 #pragma unroll
       for (int n2 = 0; n2 < NT; ++n2)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) oq[n2 / 2] = mfma_f32(a3[n2 * 4 + r], h2[n2][r], oq[n2 / 2]);
+        for (int r = 0; r < 4; ++r)
+          oq[n2 / TQ] = mfma_f32(a3[n2 * 4 + r], h2[n2][r], oq[n2 / TQ]);
       f4 o;
 #pragma unroll
       for (int e = 0; e < 4; ++e) o[e] = ((oq[0][e] + oq[1][e]) + oq[2][e]) + oq[3][e];
@@ -294,52 +297,61 @@ struct NetF32 {
   }
 };
 
-// The 12-128-128-15 FP32 net for decoder tiles of at most 4 pixels, with
-// results bit-identical to NetF32<128> (the encoder's form).
+// The 12-H-H-15 FP32 net (H = 64 or 128) for decoder tiles of at most 4
+// pixels, with results bit-identical to NetF32<H> (the encoder's form).
 //
 // The FP32 MFMAs compute each output as a chain of correctly rounded fused
 // multiply-adds in K order: v_mfma_f32_16x16x4f32 takes its four K slots in
 // order, v_mfma_f32_4x4x1f32 one product (checked on the MI355X for 512 000
 // results of each form against scalar fma chains, operands from 2^-8 to 2^8
-// with both signs).  Layer 2 therefore runs as 128 one-product steps of the
-// 4x4 form in NetF32's K order, on the 4 pixels a tile has, where the 16x16
-// form computes 16 pixels: a quarter of the MFMA time.  The 16 blocks of the
-// 4x4 form are 16 groups of 4 output neurons (lane 4b + i is neuron 4b + i of
-// the A operand, lane 4b + j pixel j of the B operand and of D), two
-// accumulators cover neurons 0-63 and 64-127.  Layers 1 and 3 keep the 16x16
-// form; activations change layout through the wave's own LDS scratch (one row
-// of ROW floats per pixel).
+// with both signs).  All three layers therefore run as one-product steps of
+// the 4x4 form in NetF32's K order, on the 4 pixels a tile has, where the
+// 16x16 form computes 16 pixels: a quarter of the MFMA time.  The 16 blocks of
+// the 4x4 form are 16 groups of 4 output neurons (lane 4b + i is neuron 4b + i
+// of the A operand, lane 4b + j pixel j of the B operand and of D); one
+// accumulator covers 64 neurons (two at H = 128).  Activations change layout
+// through the wave's own LDS scratch (one row of ROW floats per pixel).
 //
 // NetF32's layer-2 order: MFMA (n1, r) takes slots q = 0..3, i.e. layer-1
-// neurons 16 n1 + 4 q + r, so chain step c takes neuron kc(c).
+// neurons 16 n1 + 4 q + r, so chain step c takes neuron kc(c).  Layer 3 (15
+// outputs) is summed in four K quarters of H/4 neurons on both sides.
 __device__ __forceinline__ f4 mfma_f32_4x4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
 }
 
+template <int H_>
 struct NetF32x4 {
-  static constexpr int H = 128, NT = H / 16;
+  static_assert(H_ == 64 || H_ == 128, "4-pixel form for 64 or 128 neurons");
+  static constexpr int H = H_, NT = H / 16;
+  static constexpr int HALVES = H / 64;               // accumulators of 64 neurons
+  static constexpr int QS = H / 4;                    // chain steps of a layer-3 quarter
   static constexpr bool DEC_WIDE = false;             // 8 waves per decoder workgroup
-  static constexpr int LDS_BYTES = H * H * 4;         // W2 in chain order, 64 KB
+  static constexpr int LDS_BYTES = H * H * 4;         // W2 in chain order
   static constexpr int ROW = H + 4;                   // scratch floats per pixel row
   static constexpr int SCRATCH_FLOATS = 2 * 4 * ROW;  // layer-1 rows, then layer-2 rows
-  float a1[2][K_IN];  // W1[64 h + lane][k]
-  float a3[32];       // W3[lane % 16][k] along quarter lane / 16 of layer 3's chain
-  float c1[2][4], c2[2][4], c3[4];
+  float a1[HALVES][K_IN];  // W1[64 h + lane][k]
+  float a3[QS];            // W3[lane % 16][k] along quarter lane / 16 of layer 3's chain
+  float c1[HALVES][4], c2[HALVES][4], c3[4];
   float* xs = nullptr;
 
   __host__ __device__ static constexpr int kc(int c) {
     return 16 * (c / 16) + 4 * (c % 4) + (c % 16) / 4;
   }
 
-  // f4 index cp * 64 + lane holds, for steps c = 2 cp and 2 cp + 1 in turn,
-  // W2[lane][kc(c)] and W2[64 + lane][kc(c)].
+  // H = 128: f4 index cp * 64 + lane holds, for steps c = 2 cp and 2 cp + 1
+  // in turn, W2[lane][kc(c)] and W2[64 + lane][kc(c)].  H = 64: f4 index
+  // cq * 64 + lane holds W2[lane][kc(c)] for steps c = 4 cq .. 4 cq + 3.
   __device__ __forceinline__ static void stage(const DevModel& m, void* lds, int t, int n) {
     const float* w2 = (const float*)m.w2;
     float* d = (float*)lds;
     for (int idx = t; idx < H * H; idx += n) {
       const int e = idx & 3, lane = (idx >> 2) & 63, cp = idx >> 8;
-      const int c = 2 * cp + (e >> 1), half = e & 1;
-      d[idx] = w2[(64 * half + lane) * H + kc(c)];
+      if constexpr (HALVES == 2) {
+        const int c = 2 * cp + (e >> 1), half = e & 1;
+        d[idx] = w2[(64 * half + lane) * H + kc(c)];
+      } else {
+        d[idx] = w2[lane * H + kc(4 * cp + e)];
+      }
     }
   }
 
@@ -348,36 +360,37 @@ struct NetF32x4 {
     const float* w3 = (const float*)m.w3;
     const int i = lane & 15, q = lane >> 4;
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < HALVES; ++h)
 #pragma unroll
       for (int k = 0; k < K_IN; ++k) a1[h][k] = w1[(64 * h + lane) * K_IN + k];
 #pragma unroll
-    for (int st = 0; st < 32; ++st)
+    for (int st = 0; st < QS; ++st)
       a3[st] = (i < N_OUT) ? w3[i * H + k3(q, st)] : 0.0f;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      c1[0][r] = m.b1[4 * (lane >> 2) + r];
-      c1[1][r] = m.b1[64 + 4 * (lane >> 2) + r];
-      c2[0][r] = m.b2[4 * (lane >> 2) + r];
-      c2[1][r] = m.b2[64 + 4 * (lane >> 2) + r];
+#pragma unroll
+      for (int h = 0; h < HALVES; ++h) {
+        c1[h][r] = m.b1[64 * h + 4 * (lane >> 2) + r];
+        c2[h][r] = m.b2[64 * h + 4 * (lane >> 2) + r];
+      }
       const int o3 = 4 * ((lane >> 2) & 3) + r;  // output of D register r
       c3[r] = (q == 0 && o3 < N_OUT) ? m.b3[o3] : 0.0f;
     }
   }
 
-  // Layer 3 (15 outputs) in NetF32<128>'s four K quarters: step st of
-  // quarter g takes neuron k3(g, st) (MFMA (n2, r) of the 16x16 form, n2 =
-  // 2g, 2g + 1, takes slots q = 0..3, neurons 16 n2 + 4 q + r), and l3pos
-  // is where neuron n sits in the quarters' chains (32 g + st).
+  // Layer 3 in NetF32<H>'s four K quarters: step st of quarter g takes neuron
+  // k3(g, st) (MFMA (n2, r) of the 16x16 form, n2 in quarter g, takes slots
+  // q = 0..3, neurons 16 n2 + 4 q + r), and l3pos is where neuron n sits in
+  // the quarters' chains (QS g + st).
   __host__ __device__ static constexpr int k3(int g, int st) {
-    return 16 * (2 * g + (st >> 4)) + 4 * (st & 3) + ((st >> 2) & 3);
+    return 16 * ((QS / 16) * g + st / 16) + 4 * (st & 3) + ((st >> 2) & 3);
   }
   __host__ __device__ static constexpr int l3pos(int n) {
-    return 32 * (n >> 5) + 16 * ((n >> 4) & 1) + 4 * (n & 3) + ((n >> 2) & 3);
+    return 16 * (n >> 4) + 4 * (n & 3) + ((n >> 2) & 3);
   }
 
   // Features as NetF32::run; the outputs of pixels 0..3 (lanes l % 16 < 4)
-  // are NetF32<128>'s, the other lanes' are unspecified.
+  // are NetF32<H>'s, the other lanes' are unspecified.
   __device__ __forceinline__ f4 run(float f0, float f1, float f2, const void* lds) const {
     const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
     const int p = lane & 15, q = lane >> 4, j = lane & 3;
@@ -399,48 +412,55 @@ struct NetF32x4 {
       const f4 fc = *reinterpret_cast<const f4*>(&ft[j * ROW + 8]);
       const float fv[K_IN] = {fa[0], fa[1], fa[2], fa[3], fb[0], fb[1],
                               fb[2], fb[3], fc[0], fc[1], fc[2], fc[3]};
-      f4 l1 = {c1[0][0], c1[0][1], c1[0][2], c1[0][3]};
-      f4 h1 = {c1[1][0], c1[1][1], c1[1][2], c1[1][3]};
+      f4 acc[HALVES];
 #pragma unroll
-      for (int k = 0; k < K_IN; ++k) {
-        l1 = mfma_f32_4x4(a1[0][k], fv[k], l1);
-        h1 = mfma_f32_4x4(a1[1][k], fv[k], h1);
-      }
-      // lane 4 b + j holds neurons 4 b + i and 64 + 4 b + i of pixel j
+      for (int h = 0; h < HALVES; ++h) acc[h] = f4{c1[h][0], c1[h][1], c1[h][2], c1[h][3]};
+#pragma unroll
+      for (int k = 0; k < K_IN; ++k)
+#pragma unroll
+        for (int h = 0; h < HALVES; ++h) acc[h] = mfma_f32_4x4(a1[h][k], fv[k], acc[h]);
+      // lane 4 b + j holds neurons 64 h + 4 b + i of pixel j
       const int b = lane >> 2;
       const int c0 = 16 * (b >> 2) + (b & 3);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        h1t[j * ROW + c0 + 4 * i] = relu(l1[i]);
-        h1t[j * ROW + 64 + c0 + 4 * i] = relu(h1[i]);
-      }
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int h = 0; h < HALVES; ++h) h1t[j * ROW + 64 * h + c0 + 4 * i] = relu(acc[h][i]);
     }
     wave_lds_handover();
-    // layer 2: four chain steps per pass, both neuron halves
+    // layer 2: the chain of H steps, both neuron halves at H = 128
     const f4* w = reinterpret_cast<const f4*>(lds);
     f4 lo = {c2[0][0], c2[0][1], c2[0][2], c2[0][3]};
-    f4 hi = {c2[1][0], c2[1][1], c2[1][2], c2[1][3]};
+    f4 hi = {c2[HALVES - 1][0], c2[HALVES - 1][1], c2[HALVES - 1][2], c2[HALVES - 1][3]};
 #pragma unroll
     for (int c4 = 0; c4 < H / 4; ++c4) {
       const f4 hv = *reinterpret_cast<const f4*>(&h1t[j * ROW + 4 * c4]);
-      const f4 wa = w[(2 * c4) * 64 + lane];
-      const f4 wb = w[(2 * c4 + 1) * 64 + lane];
-      lo = mfma_f32_4x4(wa[0], hv[0], lo);
-      hi = mfma_f32_4x4(wa[1], hv[0], hi);
-      lo = mfma_f32_4x4(wa[2], hv[1], lo);
-      hi = mfma_f32_4x4(wa[3], hv[1], hi);
-      lo = mfma_f32_4x4(wb[0], hv[2], lo);
-      hi = mfma_f32_4x4(wb[1], hv[2], hi);
-      lo = mfma_f32_4x4(wb[2], hv[3], lo);
-      hi = mfma_f32_4x4(wb[3], hv[3], hi);
+      if constexpr (HALVES == 2) {
+        const f4 wa = w[(2 * c4) * 64 + lane];
+        const f4 wb = w[(2 * c4 + 1) * 64 + lane];
+        lo = mfma_f32_4x4(wa[0], hv[0], lo);
+        hi = mfma_f32_4x4(wa[1], hv[0], hi);
+        lo = mfma_f32_4x4(wa[2], hv[1], lo);
+        hi = mfma_f32_4x4(wa[3], hv[1], hi);
+        lo = mfma_f32_4x4(wb[0], hv[2], lo);
+        hi = mfma_f32_4x4(wb[1], hv[2], hi);
+        lo = mfma_f32_4x4(wb[2], hv[3], lo);
+        hi = mfma_f32_4x4(wb[3], hv[3], hi);
+      } else {
+        const f4 wa = w[c4 * 64 + lane];
+        lo = mfma_f32_4x4(wa[0], hv[0], lo);
+        lo = mfma_f32_4x4(wa[1], hv[1], lo);
+        lo = mfma_f32_4x4(wa[2], hv[2], lo);
+        lo = mfma_f32_4x4(wa[3], hv[3], lo);
+      }
     }
-    // lane 4 b + j holds neurons 4 b + i and 64 + 4 b + i of pixel j; they go
-    // to their places in layer 3's chains
+    // lane 4 b + j holds neurons 64 h + 4 b + i of pixel j; they go to their
+    // places in layer 3's chains
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int n = 4 * (lane >> 2) + i;
       h2t[j * ROW + l3pos(n)] = relu(lo[i]);
-      h2t[j * ROW + l3pos(64 + n)] = relu(hi[i]);
+      if constexpr (HALVES == 2) h2t[j * ROW + l3pos(64 + n)] = relu(hi[i]);
     }
     wave_lds_handover();
     // layer 3 on the 4x4 form: block b = 4 g + og is quarter g of outputs
@@ -448,8 +468,8 @@ struct NetF32x4 {
     // pixel j; the quarters then meet in the 16x16 layout
     f4 o3 = {c3[0], c3[1], c3[2], c3[3]};
 #pragma unroll
-    for (int s4 = 0; s4 < 8; ++s4) {
-      const f4 hv = *reinterpret_cast<const f4*>(&h2t[j * ROW + 32 * q + 4 * s4]);
+    for (int s4 = 0; s4 < QS / 4; ++s4) {
+      const f4 hv = *reinterpret_cast<const f4*>(&h2t[j * ROW + QS * q + 4 * s4]);
 #pragma unroll
       for (int e = 0; e < 4; ++e) o3 = mfma_f32_4x4(a3[4 * s4 + e], hv[e], o3);
     }

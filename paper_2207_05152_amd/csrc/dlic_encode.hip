@@ -193,25 +193,28 @@ bool launch_activation_range(int width, const Consts* K, const DevModel& m, cons
   }
 }
 
-// Test hook: the encoder's 16-pixel FP32 form of the 12-128-128-15 net and
-// the decoder's 4-pixel form (NetF32x4) on the same caller-given feature rows.
-// One wave per block, 16 rows per tile.  In the 4-pixel form, rows 4s + j
-// with j >= lanes get all-zero features (the decoder's idle tile rows).
+// Test hook: the encoder's 16-pixel FP32 form of the 12-H-H-15 net (H = 64
+// or 128) and the decoder's 4-pixel form (NetF32x4) on the same caller-given
+// feature rows.  One wave per block, 16 rows per tile.  In the 4-pixel form,
+// rows 4s + j with j >= lanes get all-zero features (the decoder's idle tile
+// rows).
+template <int H>
 __global__ __launch_bounds__(64) void net_forms_kernel(DevModel m, const float* __restrict__ feats,
                                                       long long n, int lanes,
                                                       float* __restrict__ out16,
                                                       float* __restrict__ out4) {
-  using Net16 = NetF32<128>;
-  __shared__ __attribute__((aligned(16))) char w16[Net16::LDS_BYTES];
-  __shared__ __attribute__((aligned(16))) char w4[NetF32x4::LDS_BYTES];
-  __shared__ __attribute__((aligned(16))) float xs[NetF32x4::SCRATCH_FLOATS];
+  using Net16 = NetF32<H>;
+  using Net4 = NetF32x4<H>;
+  __shared__ __attribute__((aligned(16))) char w16[Net16::LDS_BYTES > 0 ? Net16::LDS_BYTES : 16];
+  __shared__ __attribute__((aligned(16))) char w4[Net4::LDS_BYTES];
+  __shared__ __attribute__((aligned(16))) float xs[Net4::SCRATCH_FLOATS];
   const int lane = threadIdx.x, q = lane >> 4, p = lane & 15;
   Net16::stage(m, w16, lane, 64);
-  NetF32x4::stage(m, w4, lane, 64);
+  Net4::stage(m, w4, lane, 64);
   __syncthreads();
   Net16 a;
   a.load(m, lane);
-  NetF32x4 b;
+  Net4 b;
   b.load(m, lane);
   b.xs = xs;
   for (long long tile = blockIdx.x; tile * 16 < n; tile += gridDim.x) {
@@ -240,12 +243,19 @@ __global__ __launch_bounds__(64) void net_forms_kernel(DevModel m, const float* 
   }
 }
 
-void launch_net_forms(const DevModel& m, const float* feats, long long n, int lanes, float* out16,
-                      float* out4, hipStream_t s) {
+bool launch_net_forms(int width, const DevModel& m, const float* feats, long long n, int lanes,
+                      float* out16, float* out4, hipStream_t s) {
   long long tiles = n / 16;
   const int grid = (int)(tiles < 1024 ? (tiles > 0 ? tiles : 1) : 1024);
-  hipLaunchKernelGGL(net_forms_kernel, dim3(grid), dim3(64), 0, s, m, feats, n, lanes, out16,
-                     out4);
+  if (width == 64)
+    hipLaunchKernelGGL(net_forms_kernel<64>, dim3(grid), dim3(64), 0, s, m, feats, n, lanes, out16,
+                       out4);
+  else if (width == 128)
+    hipLaunchKernelGGL(net_forms_kernel<128>, dim3(grid), dim3(64), 0, s, m, feats, n, lanes,
+                       out16, out4);
+  else
+    return false;
+  return true;
 }
 
 constexpr int ENC_CHUNK = 32;   // wavefront steps staged in LDS per chunk

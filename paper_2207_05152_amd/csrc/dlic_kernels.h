@@ -81,10 +81,10 @@ bool launch_density(int wtype, int width, const Consts* K, const DevModel& m, co
 // folded into amax[0..1] (atomic maximum; the caller clears them).
 bool launch_activation_range(int width, const Consts* K, const DevModel& m, const uint8_t* img,
                              int H, int W, float* amax, int grid, hipStream_t s);
-// Test hook: both FP32 forms of the 12-128-128-15 net on n (a multiple of 16)
-// feature rows; out16 / out4: [n][15].
-void launch_net_forms(const DevModel& m, const float* feats, long long n, int lanes, float* out16,
-                      float* out4, hipStream_t s);
+// Test hook: both FP32 forms of the 12-H-H-15 net (H = width, 64 or 128) on n
+// (a multiple of 16) feature rows; out16 / out4: [n][15].  False for another width.
+bool launch_net_forms(int width, const DevModel& m, const float* feats, long long n, int lanes,
+                      float* out16, float* out4, hipStream_t s);
 void launch_rans_encode(const uint32_t* cf, int H, int W, int G, int L, uint16_t* words,
                         uint32_t* counts, hipStream_t s);
 void launch_pack(const uint16_t* words, const uint32_t* counts, int H, int W, int G, int L,
@@ -111,6 +111,12 @@ __host__ __device__ constexpr int coder_lpp(int L) { return L <= 4 ? 16 : (L <= 
 // grid below the number of workgroups that stay resident.
 bool launch_batch_decode(int wtype, int width, const Consts* K, const DevModel& m,
                          const BatchArgs& b, int lpp, int grid_cap, hipStream_t s);
+
+// Latency probes of the decode's critical path (one chain per probe; see
+// dlic_probe.hip): out[0] shader cycles, out[1] real-time ticks, out[2] 1 if
+// every hand-off completed.  gflags: 32 cleared words.
+void launch_latency_probe(int probe, unsigned long long* out, uint32_t* gflags, hipStream_t s);
+int probe_links(int probe);
 
 // Training: waves per workgroup of the FP32 / FP64 loss-and-gradient kernel.
 constexpr int TRAIN_WAVES_F32 = 4;

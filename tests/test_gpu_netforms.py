@@ -1,4 +1,4 @@
-"""The two FP32 forms of the 12-128-128-15 network, on the GPU through the C-ABI test hook:
+"""The two FP32 forms of the 12-H-H-15 network (H = 64, 128), on the GPU through the C-ABI test hook:
 the encoder's 16-pixel tiles (16x16x4 MFMA) and the decoder's 4-pixel tiles (4x4x1 MFMA),
 bit for bit on the same features, and both against a CPU statement of the summation order
 they share: every output a chain of correctly rounded FP32 fused multiply-adds, layer by
@@ -52,20 +52,21 @@ def kc(c):   # input of layer-2 chain step c
     return 16 * (c // 16) + 4 * (c % 4) + (c % 16) // 4
 
 
-def k3(g, st):   # input of step st of layer-3 quarter g
-    return 16 * (2 * g + (st >> 4)) + 4 * (st & 3) + ((st >> 2) & 3)
+def k3(g, st, H=128):   # input of step st of layer-3 quarter g (H / 4 steps per quarter)
+    return 16 * ((H // 64) * g + (st >> 4)) + 4 * (st & 3) + ((st >> 2) & 3)
 
 
 def net_chain32(f, w):
-    """12-128-128-15 FP32 in the shared order, every step one correctly rounded FMA."""
+    """12-H-H-15 FP32 in the shared order, every step one correctly rounded FMA."""
     f = f.astype(np.float32)
     W1, W2, W3 = (w[k].astype(np.float32) for k in ("W1", "W2", "W3"))
-    acc = np.broadcast_to(w["b1"].astype(np.float32), (f.shape[0], 128)).copy()
+    H = W1.shape[0]
+    acc = np.broadcast_to(w["b1"].astype(np.float32), (f.shape[0], H)).copy()
     for k in range(12):
         acc = fma32(W1[None, :, k], f[:, k:k + 1], acc)
     h1 = np.where(acc > 0, acc, np.float32(0))
-    acc = np.broadcast_to(w["b2"].astype(np.float32), (f.shape[0], 128)).copy()
-    for c in range(128):
+    acc = np.broadcast_to(w["b2"].astype(np.float32), (f.shape[0], H)).copy()
+    for c in range(H):
         k = kc(c)
         acc = fma32(W2[None, :, k], h1[:, k:k + 1], acc)
     h2 = np.where(acc > 0, acc, np.float32(0))
@@ -73,16 +74,17 @@ def net_chain32(f, w):
     for g in range(4):
         q = np.broadcast_to(w["b3"].astype(np.float32) if g == 0 else np.zeros(15, np.float32),
                             (f.shape[0], 15)).copy()
-        for st in range(32):
-            k = k3(g, st)
+        for st in range(H // 4):
+            k = k3(g, st, H)
             q = fma32(W3[None, :, k], h2[:, k:k + 1], q)
         quarters.append(q)
     return ((quarters[0] + quarters[1]) + quarters[2]) + quarters[3]
 
 
-def test_layer_orders_are_permutations():
-    assert sorted(kc(c) for c in range(128)) == list(range(128))
-    assert sorted(k3(g, s) for g in range(4) for s in range(32)) == list(range(128))
+@pytest.mark.parametrize("H", [64, 128])
+def test_layer_orders_are_permutations(H):
+    assert sorted(kc(c) for c in range(H)) == list(range(H))
+    assert sorted(k3(g, s, H) for g in range(4) for s in range(H // 4)) == list(range(H))
 
 
 def _features(n, seed):
@@ -99,8 +101,8 @@ def _features(n, seed):
     return f.astype(np.float32)
 
 
-def _weights(seed, scale):
-    w = synth.xavier_mlp((12, 128, 128, 15), seed)
+def _weights(seed, scale, H=128):
+    w = synth.xavier_mlp((12, H, H, 15), seed)
     rng = np.random.default_rng(seed + 1)
     for k in ("W1", "W2", "W3"):
         w[k] = (w[k] * scale).astype(np.float32)
@@ -109,9 +111,10 @@ def _weights(seed, scale):
     return w
 
 
-@pytest.mark.parametrize("seed,scale", [(3, 1.0), (11, 4.0)])
-def test_four_pixel_form_equals_sixteen_pixel_form(dev, seed, scale):
-    w = _weights(seed, scale)
+@pytest.mark.parametrize("H,seed,scale", [(128, 3, 1.0), (128, 11, 4.0), (64, 3, 1.0),
+                                          (64, 11, 4.0)])
+def test_four_pixel_form_equals_sixteen_pixel_form(dev, H, seed, scale):
+    w = _weights(seed, scale, H)
     m = dl.Model(w, dev)
     n = 4096
     feats = _features(n, seed)
@@ -119,7 +122,7 @@ def test_four_pixel_form_equals_sixteen_pixel_form(dev, seed, scale):
     o16 = torch.empty((n, 15), dtype=torch.float32, device=dev)
     o4 = torch.empty((n, 15), dtype=torch.float32, device=dev)
     for lanes in (4, 3, 2, 1):
-        say("net forms", seed, scale, lanes)
+        say("net forms", H, seed, scale, lanes)
         o4.fill_(float("nan"))
         dl.dlic_net_forms(m.c, d_f, n, lanes, o16, o4)
         torch.cuda.synchronize()
@@ -133,7 +136,7 @@ def test_four_pixel_form_equals_sixteen_pixel_form(dev, seed, scale):
 
 
 def test_net_forms_rejects_other_models(dev):
-    m = dl.Model(synth.xavier_mlp((12, 64, 64, 15), 3), dev)
+    m = dl.Model(synth.xavier_mlp((12, 32, 32, 15), 3), dev)
     x = torch.zeros((16, 15), dtype=torch.float32, device=dev)
     with pytest.raises(dl.DlicError):
         dl.dlic_net_forms(m.c, x, 16, 4, x, x)
