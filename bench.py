@@ -69,6 +69,66 @@ def schedule_bound_px(h, w, G):
     return int(worst.sum())
 
 
+def step_chain_cycles(probe, hidden):
+    """Shader cycles of the dependent operations one wavefront step needs for one
+    row, each at its measured latency (probe: dlic_latency_probe's cycles per
+    link), with every independent operation assumed in parallel and no hand-off
+    between waves.  Returns (density part, coder part, breakdown).
+
+    density: the left neighbour, decoded in the step before, is read back from
+    LDS (store then load) and scaled (3 ops); layer 1's chain ends with the up-right
+    neighbour and the two left ones (3 FMAs) and a ReLU; layer 1's outputs reach
+    layer 2's lanes through LDS; layer 2 is one FMA chain over all H inputs in the
+    format's order, then ReLU and LDS again; layer 3 is a chain over one K quarter
+    (H / 4 inputs; the whole H at 32 wide) and three adds joining the quarters;
+    the head takes a maximum over 5 logits (4 ops), one exponential, a 5-term sum
+    (4 adds), a reciprocal (2 ops) and a product; its parameters reach the
+    table lanes through LDS; a bucket boundary is the table rule at one level:
+    u = beta A + B, clamp, integer and fraction (6 ops), one table load from LDS,
+    the interpolation (2), the 5-component sum (4 deep) and F (3).
+    coder: the slot against the boundaries (1) and a 16-lane reduction, the
+    table rule at the level inside the bucket as above, a second comparison and
+    reduction, the rANS update, and the renormalisation (ballot, popcount,
+    readlane and a select)."""
+    fma, lsl, ld = probe["fma_f32"], probe["lds_store_load"], probe["lds_load"]
+    layer3 = hidden // 4 + 3 if hidden >= 64 else hidden
+    table = 6 * fma + ld + 2 * fma + 4 * fma + 3 * fma
+    parts = {
+        "window": lsl + 3 * fma,
+        "layer1_tail": 3 * fma + fma,
+        "layer2": lsl + hidden * fma + fma,
+        "layer3": lsl + layer3 * fma,
+        "head": 4 * fma + probe["expf"] + 4 * fma + 2 * fma + fma,
+        "boundaries": lsl + table,
+    }
+    coder = {
+        "bucket": fma + probe["dpp_reduce16"],
+        "level": table,
+        "symbol": fma + probe["dpp_reduce16"],
+        "update": probe["rans_update"] + probe["ballot_popcount"] + probe["readlane"] + fma,
+    }
+    return sum(parts.values()), sum(coder.values()), {**parts, **{"coder_" + k: v for k, v in coder.items()}}
+
+
+def decode_latency_bound_ms(probe, H, W, G, L, hidden):
+    """Lower bound on the decode time from dependent latencies: every one of the
+    T = W + 3H - 3 wavefront steps waits for the step before it (left and up-right
+    neighbours), a lane decodes its J = ceil(rows per group / L) rows of a step one
+    after another (its state carries from row to row), and each of the G - 1
+    group boundaries on the critical path passes a pixel between workgroups
+    through device memory instead of LDS."""
+    dens, coder, parts = step_chain_cycles(probe, hidden)
+    T = W + 3 * H - 3
+    J = -(-(-(-H // G)) // L)
+    per_step = max(J * coder, dens + coder)
+    cross = (G - 1) * max(0.0, probe["global_flag_handoff"] - probe["lds_store_load"])
+    cycles = T * per_step + cross
+    return cycles / (probe["shader_clock_mhz"] * 1e3), {
+        "steps": T, "rows_per_lane_per_step": J, "density_chain_cycles": dens,
+        "coder_chain_cycles": coder, "per_step_cycles": per_step,
+        "group_crossing_cycles": cross, "chain_cycles": parts}
+
+
 def host_info():
     """CPU model, core counts and the BLAS the oracle's matrix products use."""
     from threadpoolctl import threadpool_info
@@ -209,9 +269,9 @@ def precision_sweep(dl, torch, img, H, W, coder, hidden=128, reps=3):
     return res
 
 
-def layout_sweep(dl, torch, img, H, W, model, layouts=((8, 32), (16, 16), (32, 8), (128, 2),
-                                                        (256, 1), (128, 4), (192, 4), (384, 4),
-                                                        (48, 32)), reps=3):
+def layout_sweep(dl, torch, img, H, W, model, probe, hidden,
+                 layouts=((8, 32), (16, 16), (32, 8), (128, 2), (256, 1), (128, 4), (192, 4),
+                          (384, 4), (48, 32)), reps=3):
     """The headline image and net coded with other coder layouts (G groups x L
     lanes).  The first five have the headline's 256 lanes; the decoder gives a
     pixel 16 coder lanes when L <= 4.  More lanes cut the sequential sub-rounds
@@ -234,8 +294,10 @@ def layout_sweep(dl, torch, img, H, W, model, layouts=((8, 32), (16, 16), (32, 8
         torch.cuda.synchronize()
         assert int(st.item()) == 0 and torch.equal(dec, img), f"layout {G}x{L} round trip"
         rows = -(-H // G)
+        bound_ms, _ = decode_latency_bound_ms(probe, H, W, G, L, hidden)
         out.append({"groups": G, "lanes": L, "sub_rounds_per_step": -(-rows // L),
                     "decode_ms": float(np.mean(ms)), "decode_mpix_s": H * W / np.mean(ms) / 1e3,
+                    "latency_bound_ms": bound_ms, "frac_latency": bound_ms / float(np.mean(ms)),
                     "bpp_total": 8.0 * bits.numel() / (H * W)})
     dl.dlic_set_timing(False)
     return out
@@ -481,6 +543,10 @@ def main():
     J = -(-(-(-H // args.groups)) // args.lanes)
     crit_sub = steps_T * J
 
+    probe = dl.dlic_latency_probe()
+    lat_ms, lat_detail = decode_latency_bound_ms(probe, H, W, args.groups, args.lanes, Hd)
+    dec_kernel_ms = avg.get("wavefront_decode_kernel")
+
     res = {
         "metric": "encode/decode MPix/s on 1 MI355X + bpp; BF16 vs FP32 at \u22640.01 bpp \u0394",
         "value": n_px / (ms_step * 1e-3) / 1e6,
@@ -513,7 +579,14 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / MI355X_FP32_MFMA,
             "traffic": measured_traffic(dom),
+            "latency_bound_ms": lat_ms,
+            "frac_latency": (lat_ms / dec_kernel_ms) if dec_kernel_ms else None,
+            "note": "bound/peak/frac: the chip's FP32 MFMA peak; the decode is latency-bound, "
+                    "and frac_latency is the decode bound built from the measured latencies of "
+                    "its dependent operations (latency_probe, decode_latency) over the measured "
+                    "decode kernel time",
         },
+        "decode_latency": lat_detail,
         "decode_span": {
             "wavefront_steps": steps_T,
             "sub_rounds_per_step": J,
@@ -527,11 +600,12 @@ def main():
                     "CU's FP32 MFMA peak per group",
         },
         "decode_profile": decode_profile,
+        "latency_probe": probe,
         "host": host_info(),
         "paper_context": PAPER_CONTEXT,
     }
     if not args.no_extras:
-        res["layouts"] = layout_sweep(dl, torch, img, H, W, model)
+        res["layouts"] = layout_sweep(dl, torch, img, H, W, model, probe, Hd)
         res["precision"] = precision_sweep(dl, torch, img, H, W, coder)
         res["batch"] = batch_sweep(dl, torch)
         res["training"] = training_sweep(dl, torch)

@@ -34,3 +34,38 @@ def test_paper_context_rates():
 def test_source_digest_is_stable():
     a, b = bench.kernel_sources_sha256(), bench.kernel_sources_sha256()
     assert a == b and len(a) == 64
+
+
+PROBE = {"fma_f32": 5.6, "mfma_4x4x1_f32": 12.6, "mfma_16x16x4_f32": 32.4, "lds_store_load": 118.0,
+         "lds_load": 72.0, "lds_flag_handoff": 234.0, "dpp_reduce16": 54.0, "expf": 75.0,
+         "rans_update": 39.0, "ballot_popcount": 34.0, "global_flag_handoff": 1760.0,
+         "readlane": 31.0, "shader_clock_mhz": 2400.0}
+
+
+def test_step_chain_by_hand():
+    dens, coder, parts = bench.step_chain_cycles(PROBE, 64)
+    f = 5.6
+    table = 15 * f + 72.0
+    want_dens = ((118 + 3 * f) + 4 * f + (118 + 64 * f + f) + (118 + 19 * f)
+                 + (11 * f + 75) + (118 + table))
+    want_coder = (f + 54) + table + (f + 54) + (39 + 34 + 31 + f)
+    assert dens == pytest.approx(want_dens)
+    assert coder == pytest.approx(want_coder)
+    assert sum(parts.values()) == pytest.approx(dens + coder)
+    # 32 wide: layer 3 is one chain over all 32 inputs
+    d32, _, _ = bench.step_chain_cycles(PROBE, 32)
+    assert d32 == pytest.approx(want_dens - 64 * f + 32 * f - 19 * f + 32 * f)
+
+
+def test_latency_bound_takes_the_longer_chain():
+    dens, coder, _ = bench.step_chain_cycles(PROBE, 64)
+    T = 2048 + 3 * 1536 - 3
+    # 64 groups of 4 lanes: 24 rows per group, 6 rows per lane and step
+    ms, d = bench.decode_latency_bound_ms(PROBE, 1536, 2048, 64, 4, 64)
+    assert d["rows_per_lane_per_step"] == 6 and d["steps"] == T
+    assert d["per_step_cycles"] == pytest.approx(max(6 * coder, dens + coder))
+    assert ms == pytest.approx((T * d["per_step_cycles"] + 63 * (1760 - 118)) / 2.4e6)
+    # one lane per row: the density-coder loop of one step bounds it
+    ms1, d1 = bench.decode_latency_bound_ms(PROBE, 1536, 2048, 384, 4, 64)
+    assert d1["rows_per_lane_per_step"] == 1
+    assert d1["per_step_cycles"] == pytest.approx(dens + coder)
