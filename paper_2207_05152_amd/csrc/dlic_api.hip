@@ -686,7 +686,9 @@ size_t dlic_nll_workspace(int64_t n, const dlic_model* model) {
   if (!model || n <= 0) return 0;
   const bool f64 = model->dtype == DLIC_FP64;
   const size_t rows = (size_t)TRAIN_GRID * (f64 ? TRAIN_WAVES_F64 : TRAIN_WAVES_F32);
-  return align256(rows * (size_t)(train_n_params(model->h1, model->h2) + 1) *
+  // per-wave partial rows, then one sum row per block of 32 rows
+  const size_t sums = rows + (rows + 31) / 32;
+  return align256(sums * (size_t)(train_n_params(model->h1, model->h2) + 1) *
                   (f64 ? sizeof(double) : sizeof(float)));
 }
 

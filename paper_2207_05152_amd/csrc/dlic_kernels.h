@@ -119,7 +119,7 @@ void launch_latency_probe(int probe, unsigned long long* out, uint32_t* gflags, 
 int probe_links(int probe);
 
 // Training: waves per workgroup of the FP32 / FP64 loss-and-gradient kernel.
-constexpr int TRAIN_WAVES_F32 = 4;
+constexpr int TRAIN_WAVES_F32 = 8;
 constexpr int TRAIN_WAVES_F64 = 1;
 constexpr int TRAIN_GRID = 256;
 int train_n_params(int h1, int h2);

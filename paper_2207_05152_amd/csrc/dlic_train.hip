@@ -153,9 +153,11 @@ __global__ __launch_bounds__(WAVES * 64) void nll_fwd_bwd_kernel(TrainArgs<T> a)
   __shared__ T s_f[WAVES][16 * 16];
   __shared__ T s_o[WAVES][16 * 16];
   __shared__ T s_h1[WAVES][H1 * 16];
+  // s_h2 holds layer 2's outputs until the layer-3 weight gradient has read
+  // them, then layer 1's input gradients (H1 == H2)
   __shared__ T s_h2[WAVES][H2 * 16];
   __shared__ T s_d2[WAVES][H2 * 16];
-  __shared__ T s_d1[WAVES][H1 * 16];
+  static_assert(H1 == H2, "layer-1 gradients reuse layer 2's output buffer");
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4, i16 = lane & 15;
   constexpr int NTH = WAVES * 64;
@@ -214,7 +216,7 @@ __global__ __launch_bounds__(WAVES * 64) void nll_fwd_bwd_kernel(TrainArgs<T> a)
   T* sh1 = s_h1[wave];
   T* sh2 = s_h2[wave];
   T* sd2 = s_d2[wave];
-  T* sd1 = s_d1[wave];
+  T* sd1 = s_h2[wave];
   const long long row = (long long)blockIdx.x * WAVES + wave;
   const long long n_rows = (long long)gridDim.x * WAVES;
   const long long plane = (long long)a.sh * a.sw;
@@ -303,6 +305,7 @@ __global__ __launch_bounds__(WAVES * 64) void nll_fwd_bwd_kernel(TrainArgs<T> a)
       so[lane * 16 + 15] = T(0);
     }
     if (!a.want_grad) continue;
+    wave_lds_handover();
     // ---- backward through the network
     T d2[NT2][4];
 #pragma unroll
@@ -319,6 +322,18 @@ __global__ __launch_bounds__(WAVES * 64) void nll_fwd_bwd_kernel(TrainArgs<T> a)
         sd2[(16 * n2 + Mma<T>::row(q, r)) * 16 + i16] = dv;
       }
     }
+    // ---- weight gradients: contractions over the 16 samples of the tile.
+    // Layer 3's first, which frees layer 2's outputs for layer 1's gradients.
+    wave_lds_handover();
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int s_ = 4 * kk + q;  // sample index of this k-step
+      const T ao = so[s_ * 16 + i16];
+#pragma unroll
+      for (int n2 = 0; n2 < NT2; ++n2)
+        g3[n2] = Mma<T>::op(ao, sh2[(16 * n2 + i16) * 16 + s_], g3[n2]);
+    }
+    wave_lds_handover();
 #pragma unroll
     for (int mt = 0; mt < NT1; ++mt) {
       V acc = {0, 0, 0, 0};
@@ -334,18 +349,14 @@ __global__ __launch_bounds__(WAVES * 64) void nll_fwd_bwd_kernel(TrainArgs<T> a)
         sd1[(16 * mt + Mma<T>::row(q, r)) * 16 + i16] = dv;
       }
     }
-    // ---- weight gradients: contractions over the 16 samples of the tile
+    wave_lds_handover();
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int s_ = 4 * kk + q;  // sample index of this k-step
-      const T ao = so[s_ * 16 + i16];
       const T bf = sf[s_ * 16 + i16];
       T a2v[NT2], b1v[NT1], a1v[NT1];
 #pragma unroll
-      for (int n2 = 0; n2 < NT2; ++n2) {
-        a2v[n2] = sd2[(16 * n2 + i16) * 16 + s_];
-        g3[n2] = Mma<T>::op(ao, sh2[(16 * n2 + i16) * 16 + s_], g3[n2]);
-      }
+      for (int n2 = 0; n2 < NT2; ++n2) a2v[n2] = sd2[(16 * n2 + i16) * 16 + s_];
 #pragma unroll
       for (int mt = 0; mt < NT1; ++mt) {
         b1v[mt] = sh1[(16 * mt + i16) * 16 + s_];
@@ -358,6 +369,8 @@ __global__ __launch_bounds__(WAVES * 64) void nll_fwd_bwd_kernel(TrainArgs<T> a)
 #pragma unroll
       for (int mt = 0; mt < NT1; ++mt) g1[mt] = Mma<T>::op(a1v[mt], bf, g1[mt]);
     }
+    // the next tile's forward pass overwrites these buffers
+    wave_lds_handover();
   }
 
   // ---- this wave's partial sums, one row of [P + 1]
@@ -406,24 +419,52 @@ __global__ __launch_bounds__(WAVES * 64) void nll_fwd_bwd_kernel(TrainArgs<T> a)
 }
 
 // Sum the partial rows in a fixed order: blocks of 32 rows, then the blocks.
+// Stage 1 gives every block of 32 rows (and every 256 columns) its own
+// workgroup, each thread summing one column's 32 rows in row order; stage 2
+// sums the block sums of a column in block order.  The result is the same
+// sequence of additions as one thread walking all rows block by block.
+constexpr int RED_BLOCK = 32;
+
 template <typename T>
-__global__ void nll_reduce_kernel(const T* __restrict__ partials, long long rows, int np,
-                                  T* __restrict__ grad, T* __restrict__ loss, long long n,
-                                  int want_grad) {
+__global__ __launch_bounds__(256) void nll_reduce_rows_kernel(const T* __restrict__ partials,
+                                                              long long rows, int np,
+                                                              T* __restrict__ blocks) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e > np) return;
+  const long long r0 = (long long)blockIdx.y * RED_BLOCK;
+  const long long r1 = r0 + RED_BLOCK < rows ? r0 + RED_BLOCK : rows;
+  T s = T(0);
+  for (long long r = r0; r < r1; ++r) s += partials[r * (np + 1) + e];
+  blocks[(long long)blockIdx.y * (np + 1) + e] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void nll_reduce_blocks_kernel(const T* __restrict__ blocks,
+                                                                long long n_blocks, int np,
+                                                                T* __restrict__ grad,
+                                                                T* __restrict__ loss, long long n,
+                                                                int want_grad) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e > np) return;
   if (e < np && !want_grad) return;
   T total = T(0);
-  for (long long r0 = 0; r0 < rows; r0 += 32) {
-    T s = T(0);
-    const long long r1 = r0 + 32 < rows ? r0 + 32 : rows;
-    for (long long r = r0; r < r1; ++r) s += partials[r * (np + 1) + e];
-    total += s;
-  }
+  for (long long b = 0; b < n_blocks; ++b) total += blocks[b * (np + 1) + e];
   if (e < np)
     grad[e] = total;
   else
     *loss = total / T(n);
+}
+
+template <typename T>
+static void launch_reduce(const T* partials, long long rows, int np, T* grad, T* loss, long long n,
+                          bool want_grad, hipStream_t s) {
+  const unsigned cgrid = (unsigned)((np + 1 + 255) / 256);
+  const long long n_blocks = (rows + RED_BLOCK - 1) / RED_BLOCK;
+  T* blocks = const_cast<T*>(partials) + rows * (np + 1);  // after the partial rows
+  hipLaunchKernelGGL(nll_reduce_rows_kernel<T>, dim3(cgrid, (unsigned)n_blocks), dim3(256), 0, s,
+                     partials, rows, np, blocks);
+  hipLaunchKernelGGL(nll_reduce_blocks_kernel<T>, dim3(cgrid), dim3(256), 0, s,
+                     (const T*)blocks, n_blocks, np, grad, loss, n, want_grad ? 1 : 0);
 }
 
 // step_size = lr / (1 - b1^t) and bc2_sqrt = sqrt(1 - b2^t) come from the
@@ -458,7 +499,6 @@ bool launch_nll(bool fp64, int width, const void* w1, const void* b1, const void
                 int grid, bool want_grad, void* grad, void* loss, hipStream_t s) {
   const long long rows = (long long)grid * (fp64 ? TRAIN_WAVES_F64 : TRAIN_WAVES_F32);
   const int np = train_n_params(width, width);
-  const int rgrid = (np + 1 + 255) / 256;
   if (fp64) {
     TrainArgs<double> a{(const double*)w1, (const double*)b1, (const double*)w2, (const double*)b2,
                         (const double*)w3, (const double*)b3, slices, n_slices, sh, sw, idx, n,
@@ -469,9 +509,7 @@ bool launch_nll(bool fp64, int width, const void* w1, const void* b1, const void
       case 64: launch_nll_t<double, 64, TRAIN_WAVES_F64>(a, grid, s); break;
       default: return false;
     }
-    hipLaunchKernelGGL(nll_reduce_kernel<double>, dim3(rgrid), dim3(256), 0, s,
-                       (const double*)partials, rows, np, (double*)grad, (double*)loss, n,
-                       want_grad ? 1 : 0);
+    launch_reduce((const double*)partials, rows, np, (double*)grad, (double*)loss, n, want_grad, s);
   } else {
     TrainArgs<float> a{(const float*)w1, (const float*)b1, (const float*)w2, (const float*)b2,
                        (const float*)w3, (const float*)b3, slices, n_slices, sh, sw, idx, n,
@@ -482,9 +520,7 @@ bool launch_nll(bool fp64, int width, const void* w1, const void* b1, const void
       case 64: launch_nll_t<float, 64, TRAIN_WAVES_F32>(a, grid, s); break;
       default: return false;
     }
-    hipLaunchKernelGGL(nll_reduce_kernel<float>, dim3(rgrid), dim3(256), 0, s,
-                       (const float*)partials, rows, np, (float*)grad, (float*)loss, n,
-                       want_grad ? 1 : 0);
+    launch_reduce((const float*)partials, rows, np, (float*)grad, (float*)loss, n, want_grad, s);
   }
   return true;
 }
