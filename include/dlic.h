@@ -206,6 +206,17 @@ dlic_status dlic_decode_noalloc(const dlic_model *model, const dlic_coder *coder
                                 int32_t h, int32_t w, int32_t *d_status, hipStream_t stream);
 
 
+/* Test hook for the decoder's synchronisation (Section II-B, Preprocessor:
+ * decode follows the wavefront, so every wave waits for the ones producing
+ * its inputs).  With max_cycles > 0 every later decode (single images and
+ * batches) pauses each wave at fixed points (the coder before each
+ * sub-round, the density waves before each tile and before publishing it,
+ * the courier in each round of its loop) for a seeded pseudo-random time
+ * below max_cycles shader cycles (at most 2^20), so that the waves' hand-offs
+ * meet in other orders; decoded pixels must not change.  0 turns it off
+ * (the default).  Host-side setting, not thread-safe. */
+void dlic_set_decode_delays(uint32_t seed, uint32_t max_cycles);
+
 /* Spin limit of one decode wait (polls of an upstream record, each followed
  * by a short sleep); a wait that exceeds it reports DLIC_ERR_TIMEOUT and the
  * workgroup continues without waiting again.  Default 2^22.  For tests of the

@@ -39,6 +39,7 @@ EXPORTS = (
     "dlic_batch_create", "dlic_batch_destroy", "dlic_batch_sizes", "dlic_batch_layout",
     "dlic_encode_batch", "dlic_decode_batch", "dlic_batch_capture", "dlic_batch_replay",
     "dlic_wallclock_hz", "dlic_decode_noalloc", "dlic_batch_tune", "dlic_latency_probe",
+    "dlic_set_decode_delays",
     "dlic_net_forms",
 )
 
@@ -93,6 +94,7 @@ def lib():
         "dlic_decode_noalloc": (c_int, [POINTER(dlic_model), POINTER(dlic_coder), P, S, P, c_int32,
                                         c_int32, P, P]),
         "dlic_set_spin_limit": (None, [c_uint32]),
+        "dlic_set_decode_delays": (None, [c_uint32, c_uint32]),
         "dlic_net_forms": (c_int, [POINTER(dlic_model), P, ctypes.c_int64, c_int32, P, P, P]),
         "dlic_density": (c_int, [POINTER(dlic_model), P, c_int32, c_int32, P, P, P, P]),
         "dlic_rans_encode_cf": (c_int, [POINTER(dlic_coder), c_int32, c_int32, P, P, S, P, P, S, P]),
@@ -250,6 +252,10 @@ def dlic_net_forms(model: dlic_model, d_feats, n, lanes, d_out16, d_out4, stream
 
 def dlic_set_spin_limit(polls: int):
     lib().dlic_set_spin_limit(int(polls))
+
+
+def dlic_set_decode_delays(seed: int, max_cycles: int):
+    lib().dlic_set_decode_delays(int(seed), int(max_cycles))
 
 
 def dlic_density(model: dlic_model, d_img, h, w, d_out15=None, d_cf=None, d_tables=None,

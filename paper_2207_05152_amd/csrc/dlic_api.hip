@@ -37,6 +37,7 @@ __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
 std::mutex g_mu;
 DeviceState g_dev[MAX_DEVICES];
 uint32_t g_spin_limit = 1u << 22;
+uint32_t g_delay_seed = 0, g_delay_max = 0;  // decoder delay injection (test hook)
 unsigned long long* g_prof = nullptr;
 
 struct TimedLaunch {
@@ -293,6 +294,8 @@ BatchArgs batch_args(const dlic_batch* b, void* d_ws) {
   a.done = a.ticket + 1;
   a.hf = HeaderFields{b->model.dtype, b->model.h1, b->model.h2, b->model.fingerprint};
   a.spin_limit = g_spin_limit;
+  a.delay_seed = g_delay_seed;
+  a.delay_max = g_delay_max;
   return a;
 }
 
@@ -584,6 +587,8 @@ static dlic_status decode_common(const dlic_model* model, bool tables_mode,
   a.ticket = (unsigned*)(a.rec + (long long)a.G * a.T);
   a.status = d_status;
   a.spin_limit = g_spin_limit;
+  a.delay_seed = g_delay_seed;
+  a.delay_max = g_delay_max;
   a.prof = tables_mode ? nullptr : g_prof;
   DevModel dm;
   memset(&dm, 0, sizeof(dm));
@@ -729,6 +734,11 @@ dlic_status dlic_adam_step(int64_t n_params, float* d_params, const float* d_gra
 }
 
 void dlic_set_spin_limit(uint32_t polls) { g_spin_limit = polls ? polls : 1u; }
+
+void dlic_set_decode_delays(uint32_t seed, uint32_t max_cycles) {
+  g_delay_seed = seed;
+  g_delay_max = max_cycles > (1u << 20) ? (1u << 20) : max_cycles;
+}
 
 void dlic_set_decode_profile(unsigned long long* d_counters) { g_prof = d_counters; }
 

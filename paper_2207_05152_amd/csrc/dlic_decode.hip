@@ -106,6 +106,22 @@ __device__ bool receive_record(const uint32_t* up_rec, int s, uint32_t limit, ui
   return true;
 }
 
+// Test hook: a seeded pause of up to delay_max shader cycles (in 64-cycle
+// sleeps) at one point of one wave, the same for every lane, so that the
+// waves' hand-offs meet in other orders.  No-op when delay_max is 0.
+__device__ __forceinline__ void inject_delay(const DecArgs& a, uint32_t site, uint32_t g,
+                                             uint32_t step) {
+  if (a.delay_max == 0) return;
+  uint32_t h = a.delay_seed ^ (site * 0x9E3779B1u) ^ (g * 0x85EBCA77u) ^ (step * 0xC2B2AE3Du);
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  h *= 0x297A2D39u;
+  h ^= h >> 15;
+  const uint32_t n = (h % a.delay_max) >> 6;
+  for (uint32_t i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(1);
+}
+
 // The pixel ring keeps 16 columns per row, so step t overwrites step t - 16.
 // Before step t the coder makes sure the publisher wave has taken every step
 // up to t - PUB_LAG from the ring; pub caches the last value seen.  Returns
@@ -169,7 +185,7 @@ __device__ __forceinline__ float bin_edge(int v) { return div255(2 * v - 256); }
 
 // Decode of group g of one stream by the whole workgroup.  LPP is
 // coder_lpp(L): how many coder lanes share each pixel's symbol search.
-template <class Net, bool TABLES, int LPP>
+template <class Net, bool TABLES, int LPP, bool DELAY = false>
 __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const DevModel& m,
                                              const DecArgs& a, const int g) {
   __shared__ float2 s_sd[LUT_N];
@@ -307,6 +323,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     f4 n0 = {0.0f, 0.0f, 0.0f, 0.0f}, n1 = n0, n2 = n0, n3 = n0;
     uint32_t nFb = 0;
     for (int q = 0; q < P; ++q) {
+      if constexpr (DELAY) inject_delay(a, 2u, (uint32_t)g, (uint32_t)q);
       if (++j == J) {
         j = 0;
         ++t;
@@ -521,6 +538,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     bool stuck = false, timeout = s_flag != 0;
     uint32_t idle = 0, rspins = 0;
     while ((pub_t <= t_last || (rcv <= rcv_last && !timeout)) && !stuck) {
+      if constexpr (DELAY) inject_delay(a, 4u, (uint32_t)g, (uint32_t)(pub_t * 8 + rcv));
       bool progress = false;
       const int done_q = lds_acquire(&s_decoded);
       while (pub_t <= t_last && done_q >= (pub_t - t_first + 1) * J) {
@@ -592,6 +610,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     const unsigned long long k0 = a.prof ? clk_now() : 0ull;
     const unsigned long long rt0 = a.prof ? __builtin_amdgcn_s_memrealtime() : 0ull;
     for (int q = 0; q < P; ++q) {
+      if constexpr (DELAY) inject_delay(a, 3u, (uint32_t)g, (uint32_t)q);
       if (++j == J) {
         j = 0;
         ++t;
@@ -839,6 +858,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       if (q >= P) break;
       const int slot_i = q & (NSLOT - 1);
       const int need = max(q - J + 1, q - NSLOT + 1);
+      if constexpr (DELAY) inject_delay(a, 8u + (uint32_t)wave, (uint32_t)g, (uint32_t)q);
       const unsigned long long c0 = a.prof ? clk_now() : 0ull;
       if (!stuck) {
         uint32_t spins = 0;
@@ -1002,6 +1022,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         }
         }
       }
+      if constexpr (DELAY) inject_delay(a, 32u + (uint32_t)wave, (uint32_t)g, (uint32_t)q);
       if (lane == 0) lds_release(&s_done[slot_i][ti], q);
       if (a.prof) {
         const unsigned long long c2 = clk_now();
@@ -1043,7 +1064,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
 // One image: each workgroup takes its group by ticket, so group g - 1 was
 // taken by a workgroup that is running or done before group g waits on it,
 // whatever order the dispatcher starts workgroups in.
-template <class Net, bool TABLES, int LPP>
+template <class Net, bool TABLES, int LPP, bool DELAY = false>
 __global__ __launch_bounds__(dec_waves<Net>() * 64) void wavefront_decode_kernel(
     const Consts* __restrict__ K, DevModel m, DecArgs a) {
   __shared__ int s_group;
@@ -1051,7 +1072,7 @@ __global__ __launch_bounds__(dec_waves<Net>() * 64) void wavefront_decode_kernel
   __syncthreads();
   const int g = __builtin_amdgcn_readfirstlane(s_group);
   if (g >= a.G) return;
-  decode_group<Net, TABLES, LPP>(K, m, a, g);
+  decode_group<Net, TABLES, LPP, DELAY>(K, m, a, g);
 }
 
 // Batched decode, persistent: a grid of resident workgroups, each taking the
@@ -1060,7 +1081,7 @@ __global__ __launch_bounds__(dec_waves<Net>() * 64) void wavefront_decode_kernel
 // another, so the group an item waits for was taken earlier by a workgroup
 // that is running or done: the waits end.  The last group of an image to
 // finish stamps the image's completion time.
-template <class Net, int LPP>
+template <class Net, int LPP, bool DELAY = false>
 __global__ __launch_bounds__(dec_waves<Net>() * 64) void batch_decode_kernel(
     const Consts* __restrict__ K, DevModel m, BatchArgs b) {
   __shared__ int s_item;
@@ -1088,13 +1109,15 @@ __global__ __launch_bounds__(dec_waves<Net>() * 64) void batch_decode_kernel(
     a.T = im.T;
     a.status = b.status + it.image;
     a.spin_limit = b.spin_limit;
+    a.delay_seed = b.delay_seed;
+    a.delay_max = b.delay_max;
     a.check_model = 1;
     a.hf = b.hf;
     a.tables = nullptr;
     a.n_tables = 0;
     a.tidx = nullptr;
     a.prof = nullptr;
-    decode_group<Net, false, LPP>(K, m, a, it.group);
+    decode_group<Net, false, LPP, DELAY>(K, m, a, it.group);
     // every wave is done with the item (and with the LDS of decode_group)
     // before thread 0 counts it and takes the next ticket
     __syncthreads();
@@ -1123,13 +1146,25 @@ static int persistent_grid(Kern kern, int threads, int n_items) {
   return (int)(g > 0 ? g : 1);
 }
 
+template <class Net, int LPP, bool DELAY>
+static void launch_batch_decode_d(const Consts* K, const DevModel& m, const BatchArgs& b,
+                                  int grid_cap, hipStream_t s) {
+  const int threads = dec_waves<Net>() * 64;
+  int grid = persistent_grid(batch_decode_kernel<Net, LPP, DELAY>, threads, b.n_items);
+  if (grid_cap > 0 && grid_cap < grid) grid = grid_cap;
+  hipLaunchKernelGGL((batch_decode_kernel<Net, LPP, DELAY>), dim3(grid), dim3(threads), 0, s, K,
+                     m, b);
+}
+
+// The delay-injecting form (a test hook) is a separate kernel, so that the
+// production kernel carries no trace of it.
 template <class Net, int LPP>
 static void launch_batch_decode_k(const Consts* K, const DevModel& m, const BatchArgs& b,
                                   int grid_cap, hipStream_t s) {
-  const int threads = dec_waves<Net>() * 64;
-  int grid = persistent_grid(batch_decode_kernel<Net, LPP>, threads, b.n_items);
-  if (grid_cap > 0 && grid_cap < grid) grid = grid_cap;
-  hipLaunchKernelGGL((batch_decode_kernel<Net, LPP>), dim3(grid), dim3(threads), 0, s, K, m, b);
+  if (b.delay_max > 0)
+    launch_batch_decode_d<Net, LPP, true>(K, m, b, grid_cap, s);
+  else
+    launch_batch_decode_d<Net, LPP, false>(K, m, b, grid_cap, s);
 }
 
 __global__ void stamp_kernel(unsigned long long* t) {
@@ -1199,20 +1234,32 @@ bool launch_batch_decode(int wtype, int width, const Consts* K, const DevModel& 
   }
 }
 
+template <class Net, bool TABLES, int LPP>
+static void launch_wavefront(const Consts* K, const DevModel& m, const DecArgs& a, hipStream_t s) {
+  const dim3 grid(a.G), block(dec_waves<Net>() * 64);
+  // the delay-injecting form (a test hook) is a separate kernel, so that the
+  // production kernel carries no trace of it
+  if (a.delay_max > 0)
+    hipLaunchKernelGGL((wavefront_decode_kernel<Net, TABLES, LPP, true>), grid, block, 0, s, K, m,
+                       a);
+  else
+    hipLaunchKernelGGL((wavefront_decode_kernel<Net, TABLES, LPP, false>), grid, block, 0, s, K,
+                       m, a);
+}
+
 // The table-driven coder (no density waves) runs one lane per pixel.
 template <class Net, bool TB>
 static void launch_decode_t(const Consts* K, const DevModel& m, const DecArgs& a, hipStream_t s) {
-  const dim3 grid(a.G), block(dec_waves<Net>() * 64);
   if constexpr (TB) {
-    hipLaunchKernelGGL((wavefront_decode_kernel<Net, true, 1>), grid, block, 0, s, K, m, a);
+    launch_wavefront<Net, true, 1>(K, m, a, s);
   } else {
     const int lpp = coder_lpp(a.L);
     if (lpp == 16)
-      hipLaunchKernelGGL((wavefront_decode_kernel<Net, false, 16>), grid, block, 0, s, K, m, a);
+      launch_wavefront<Net, false, 16>(K, m, a, s);
     else if (lpp == 2)
-      hipLaunchKernelGGL((wavefront_decode_kernel<Net, false, 2>), grid, block, 0, s, K, m, a);
+      launch_wavefront<Net, false, 2>(K, m, a, s);
     else
-      hipLaunchKernelGGL((wavefront_decode_kernel<Net, false, 1>), grid, block, 0, s, K, m, a);
+      launch_wavefront<Net, false, 1>(K, m, a, s);
   }
 }
 
@@ -1220,8 +1267,7 @@ static void launch_decode_t(const Consts* K, const DevModel& m, const DecArgs& a
 template <class Net>
 static void launch_decode_lpp16(const Consts* K, const DevModel& m, const DecArgs& a,
                                 hipStream_t s) {
-  const dim3 grid(a.G), block(dec_waves<Net>() * 64);
-  hipLaunchKernelGGL((wavefront_decode_kernel<Net, false, 16>), grid, block, 0, s, K, m, a);
+  launch_wavefront<Net, false, 16>(K, m, a, s);
 }
 
 // Layer-2 weights of the BF16 nets go to LDS at H = 128: six density waves

@@ -27,6 +27,7 @@ struct DecArgs {
   long long T;            // wavefront steps W + 3H - 3
   int* status;
   uint32_t spin_limit;
+  uint32_t delay_seed, delay_max;  // injected wave delays (test hook), 0: none
   int check_model;        // compare header model fields with the ones below
   HeaderFields hf;
   const uint32_t* tables;  // table mode: [n_tables][257]
@@ -72,6 +73,7 @@ struct BatchArgs {
   unsigned long long* t_done;  // optional per-image completion times (realtime counter)
   HeaderFields hf;
   uint32_t spin_limit;
+  uint32_t delay_seed, delay_max;  // injected wave delays (test hook), 0: none
 };
 
 bool launch_density(int wtype, int width, const Consts* K, const DevModel& m, const uint8_t* img,
