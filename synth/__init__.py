@@ -143,6 +143,20 @@ def xavier_mlp(dims, seed: int) -> dict:
     return out
 
 
+def xavier_deep(hidden: int, seed: int, depth: int = 6, k_in: int = 12, n_out: int = 256) -> list:
+    """Glorot-uniform weights of a dense net k_in -> hidden x (depth - 1) -> n_out, FP32,
+    biases zero: [(W, b)] per layer, W of shape [out, in], drawn in layer order from
+    numpy's PCG64 as for xavier_mlp."""
+    dims = [k_in] + [hidden] * (depth - 1) + [n_out]
+    rng = np.random.default_rng(seed)
+    out = []
+    for fi, fo in zip(dims[:-1], dims[1:]):
+        lim = np.sqrt(6.0 / (fi + fo))
+        out.append((rng.uniform(-lim, lim, size=(fo, fi)).astype(np.float32),
+                    np.zeros(fo, np.float32)))
+    return out
+
+
 def batch_sizes(seeds) -> list:
     """(h, w) per image of the batch workload: one uniform draw from C3_SIZES per seed."""
     return [C3_SIZES[int(np.random.default_rng(s).integers(0, 4))] for s in seeds]
