@@ -356,6 +356,62 @@ dlic_status dlic_batch_replay(dlic_batch *b, int32_t decode, hipStream_t stream)
 /* Rate (Hz) of the device realtime counter behind the d_t_done stamps. */
 double dlic_wallclock_hz(void);
 
+/* ---- The paper's own network and head (Section II-B, Neural Network
+ * Architecture: six dense layers, the output layer 256 neurons with a
+ * softmax, one probability per grey level). -------------------------------
+ * Layers 12 -> H -> H -> H -> H -> H -> 256 (H = 64 or 128), ReLU after the
+ * first five; BF16 weights and layer inputs with FP32 accumulation on the
+ * BF16 MFMA, FP32 biases.  The coder's table is the format's FP32 rule on
+ * the logits: e_v = expf(o_v - max), the sum over four blocks of 64 levels
+ * (each in level order, the blocks added left to right), p_v = e_v / sum,
+ * the cumulative sum C_v by blocks (running sums inside a block, offsets the
+ * running sum of block totals), F(v) = v + min(65280, floor(C_v 65280)),
+ * F(0) = 0, F(256) = 2^16.  Streams use the container, rANS layout and
+ * wavefront order of dlic_encode; the header's mixture count is 0 and its
+ * dtype DLIC_BF16, h1 = h2 = H.
+ *
+ * Decoding follows the paper's GPU scheme (Section II-B, Preprocessor: the
+ * pixels of one wavefront step enter the network together as a matrix): one
+ * cooperative launch walks the W + 3H - 3 steps, the whole grid evaluating
+ * the step's pixels, then every group decoding its rows' pixels of the step,
+ * with a grid barrier after each phase.  It needs every group's wave
+ * resident: G <= 256 (DLIC_ERR_UNSUPPORTED otherwise). */
+#define DLIC_DEEP_LAYERS 6
+typedef struct {
+  int32_t hidden;                          /* H: 64 or 128 */
+  const uint16_t *d_w[DLIC_DEEP_LAYERS];   /* BF16 bit patterns, row-major [out][in] */
+  const float *d_b[DLIC_DEEP_LAYERS];      /* FP32 biases */
+  uint64_t fingerprint; /* FNV-1a 64 over W1, b1, ..., W6, b6 as stored (BF16 / FP32) */
+} dlic_deep_model;
+
+/* Device workspace bytes: decode = 0 for dlic_deep_encode, 1 for
+ * dlic_deep_decode, -1 for dlic_deep_density (coder may be NULL then).  0 for
+ * an unsupported size, width or layout. */
+size_t dlic_deep_workspace(int32_t h, int32_t w, const dlic_coder *coder, int32_t hidden,
+                           int32_t decode);
+
+/* Encode one image with the softmax network: as dlic_encode (same bound,
+ * output and length conventions). */
+dlic_status dlic_deep_encode(const dlic_deep_model *model, const dlic_coder *coder,
+                             const uint8_t *d_img, int32_t h, int32_t w, uint8_t *d_out,
+                             size_t out_cap, uint64_t *d_out_len, void *d_ws, size_t ws_bytes,
+                             hipStream_t stream);
+
+/* Decode a stream of dlic_deep_encode: as dlic_decode (d_status 0, 3 corrupt,
+ * 4 other model, 7 a bounded wait gave up). */
+dlic_status dlic_deep_decode(const dlic_deep_model *model, const dlic_coder *coder,
+                             const uint8_t *d_bits, size_t n_bytes, uint8_t *d_img, int32_t h,
+                             int32_t w, int32_t *d_status, void *d_ws, size_t ws_bytes,
+                             hipStream_t stream);
+
+/* Test hook: the encoder's network and table rule on every pixel of an image
+ * (raster order): FP32 logits [n][256], packed intervals c | (f - 1) << 16
+ * [n] of each pixel's own value, tables F(0..255) [n][256] (u16); each output
+ * optional (NULL), at least one. */
+dlic_status dlic_deep_density(const dlic_deep_model *model, const uint8_t *d_img, int32_t h,
+                              int32_t w, float *d_logits, uint32_t *d_cf, uint16_t *d_tables,
+                              void *d_ws, size_t ws_bytes, hipStream_t stream);
+
 /* Measurement hook for the decode bound (Section II-B, Preprocessor and rANS:
  * each wavefront step waits for the previous one, so the decode takes at least
  * the steps times the latency of the dependent operations one step needs).

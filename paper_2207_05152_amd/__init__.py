@@ -39,7 +39,8 @@ EXPORTS = (
     "dlic_batch_create", "dlic_batch_destroy", "dlic_batch_sizes", "dlic_batch_layout",
     "dlic_encode_batch", "dlic_decode_batch", "dlic_batch_capture", "dlic_batch_replay",
     "dlic_wallclock_hz", "dlic_decode_noalloc", "dlic_batch_tune", "dlic_latency_probe",
-    "dlic_set_decode_delays",
+    "dlic_set_decode_delays", "dlic_deep_workspace", "dlic_deep_encode", "dlic_deep_decode",
+    "dlic_deep_density",
     "dlic_net_forms",
 )
 
@@ -59,6 +60,14 @@ class dlic_model(ctypes.Structure):
 
 class dlic_coder(ctypes.Structure):
     _fields_ = [("groups", c_int32), ("lanes_per_group", c_int32)]
+
+
+DEEP_LAYERS = 6
+
+
+class dlic_deep_model(ctypes.Structure):
+    _fields_ = [("hidden", c_int32), ("d_w", c_void_p * DEEP_LAYERS),
+                ("d_b", c_void_p * DEEP_LAYERS), ("fingerprint", c_uint64)]
 
 
 _lib = None
@@ -119,6 +128,13 @@ def lib():
         "dlic_batch_replay": (c_int, [P, c_int32, P]),
         "dlic_wallclock_hz": (ctypes.c_double, []),
         "dlic_latency_probe": (c_int, [P, c_int32, P, S, P]),
+        "dlic_deep_workspace": (S, [c_int32, c_int32, P, c_int32, c_int32]),
+        "dlic_deep_encode": (c_int, [POINTER(dlic_deep_model), POINTER(dlic_coder), P, c_int32,
+                                     c_int32, P, S, P, P, S, P]),
+        "dlic_deep_decode": (c_int, [POINTER(dlic_deep_model), POINTER(dlic_coder), P, S, P,
+                                     c_int32, c_int32, P, P, S, P]),
+        "dlic_deep_density": (c_int, [POINTER(dlic_deep_model), P, c_int32, c_int32, P, P, P, P,
+                                      S, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -410,6 +426,88 @@ def density(img, model: Model, tables=False, stream=None):
     tab = torch.empty((n, 257), dtype=torch.int32, device=img.device) if tables else None
     dlic_density(model.c, img.contiguous(), h, w, out15, cf, tab, stream)
     return out15, cf, tab
+
+
+# ---- the six-layer softmax-256 network ----------------------------------------------
+
+class DeepModel:
+    """The paper's six-layer network with the softmax head, resident on a device:
+    layers = [(W, b)] * 6 (FP32, W [out, in]: 12 -> H, H -> H x 4, H -> 256).  The
+    library's dlic_quantize_weights stores the matrices as BF16; biases stay FP32."""
+
+    def __init__(self, layers, device="cuda"):
+        import torch
+        if len(layers) != DEEP_LAYERS:
+            raise ValueError("six layers")
+        self.hidden = int(np.asarray(layers[0][0]).shape[0])
+        self.w, self.b = [], []
+        h = FNV_OFFSET
+        for W, b in layers:
+            wq, _ = dlic_quantize_weights(DLIC_BF16, np.ascontiguousarray(W, dtype=np.float32))
+            bb = np.ascontiguousarray(b, dtype=np.float32)
+            h = dlic_fnv1a64(h, wq.tobytes())
+            h = dlic_fnv1a64(h, bb.tobytes())
+            self.w.append(torch.from_numpy(wq.view(np.int16)).to(device))
+            self.b.append(torch.from_numpy(bb).to(device))
+        self.fingerprint = h
+        self.c = dlic_deep_model(self.hidden, (c_void_p * DEEP_LAYERS)(*[_ptr(t) for t in self.w]),
+                                 (c_void_p * DEEP_LAYERS)(*[_ptr(t) for t in self.b]), h)
+
+
+def dlic_deep_workspace(h, w, coder, hidden, decode) -> int:
+    return int(lib().dlic_deep_workspace(h, w, ctypes.byref(coder) if coder is not None else None,
+                                         hidden, decode))
+
+
+def deep_encode(img, model: DeepModel, coder: dlic_coder, stream=None):
+    """Encode a [h, w] uint8 device tensor with the softmax network."""
+    import torch
+    h, w = img.shape
+    cap = dlic_encode_bound(h, w, coder)
+    out = _empty(cap, torch.uint8, img.device)
+    olen = _empty(1, torch.int64, img.device)
+    wsb = dlic_deep_workspace(h, w, coder, model.hidden, 0)
+    ws = _empty(wsb, torch.uint8, img.device)
+    _check(lib().dlic_deep_encode(ctypes.byref(model.c), ctypes.byref(coder),
+                                  _ptr(img.contiguous()), h, w, _ptr(out), cap, _ptr(olen),
+                                  _ptr(ws), wsb, _stream(stream)), "dlic_deep_encode")
+    return out[:int(olen.item())]
+
+
+def deep_decode(bits, model: DeepModel, stream=None, check=True):
+    """Decode a stream of deep_encode; returns ([h, w] uint8 tensor, status)."""
+    import torch
+    hd = dlic_peek_header(bits[:HEADER_BYTES].cpu().numpy().tobytes())
+    h, w, coder = hd["h"], hd["w"], hd["coder"]
+    img = torch.empty((h, w), dtype=torch.uint8, device=bits.device)
+    st = torch.zeros(1, dtype=torch.int32, device=bits.device)
+    wsb = dlic_deep_workspace(h, w, coder, model.hidden, 1)
+    ws = _empty(wsb, torch.uint8, bits.device)
+    _check(lib().dlic_deep_decode(ctypes.byref(model.c), ctypes.byref(coder),
+                                  _ptr(bits.contiguous()), bits.numel(), _ptr(img), h, w,
+                                  _ptr(st), _ptr(ws), wsb, _stream(stream)), "dlic_deep_decode")
+    status = int(st.item())
+    if check and status != DLIC_OK:
+        raise DlicError(status, "dlic_deep_decode (device status)")
+    return img, status
+
+
+def deep_density(img, model: DeepModel, logits=True, tables=False, stream=None):
+    """Logits [n, 256] FP32, packed intervals [n] and optionally tables F(0..255)
+    [n, 256] (u16 in int16 storage) of every pixel of an image."""
+    import torch
+    h, w = img.shape
+    n = h * w
+    lg = torch.empty((n, 256), dtype=torch.float32, device=img.device) if logits else None
+    cf = torch.empty(n, dtype=torch.int32, device=img.device)
+    tab = torch.empty((n, 256), dtype=torch.int16, device=img.device) if tables else None
+    wsb = dlic_deep_workspace(h, w, None, model.hidden, -1)
+    ws = _empty(wsb, torch.uint8, img.device)
+    _check(lib().dlic_deep_density(ctypes.byref(model.c), _ptr(img.contiguous()), h, w,
+                                   _ptr(lg) if lg is not None else None, _ptr(cf),
+                                   _ptr(tab) if tab is not None else None, _ptr(ws), wsb,
+                                   _stream(stream)), "dlic_deep_density")
+    return lg, cf, tab
 
 
 # ---- retraining -------------------------------------------------------------------

@@ -21,7 +21,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libdlic.so")
 
-SOURCES = ["dlic_api.hip", "dlic_encode.hip", "dlic_decode.hip", "dlic_train.hip", "dlic_probe.hip"]
+SOURCES = ["dlic_api.hip", "dlic_encode.hip", "dlic_decode.hip", "dlic_train.hip", "dlic_probe.hip",
+           "dlic_deep.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -252,6 +252,35 @@ dlic_status run_rans_and_pack(int h, int w, const dlic_coder* coder, const uint3
   return launch_ok();
 }
 
+// ---- the six-layer softmax-256 network -----------------------------------
+dlic_status deep_model_ok(const dlic_deep_model* m) {
+  if (!m) return DLIC_ERR_ARG;
+  if (m->hidden != 64 && m->hidden != 128) return DLIC_ERR_UNSUPPORTED;
+  for (int i = 0; i < DLIC_DEEP_LAYERS; ++i)
+    if (!m->d_w[i] || !m->d_b[i]) return DLIC_ERR_ARG;
+  return DLIC_OK;
+}
+
+DeepNetArgs deep_net(const dlic_deep_model* m, void* wop) {
+  DeepNetArgs n;
+  n.H = m->hidden;
+  n.wop = wop;
+  for (int i = 0; i < DLIC_DEEP_LAYERS; ++i) n.b[i] = m->d_b[i];
+  return n;
+}
+
+// Operand-order weights at the head of every deep workspace.
+dlic_status deep_stage(const dlic_deep_model* m, void* wop, hipStream_t s) {
+  launch_deep_pack(m->hidden, m->d_w, wop, s);
+  return launch_ok();
+}
+
+HeaderFields deep_header(const dlic_deep_model* m) {
+  HeaderFields hf{DLIC_BF16, m->hidden, m->hidden, m->fingerprint};
+  hf.n_mix = 0;
+  return hf;
+}
+
 }  // namespace
 
 // A batch plan: per-image layout, the work items in longest-wavefront-first
@@ -990,6 +1019,106 @@ dlic_status dlic_latency_probe(double* h_out, int32_t n, void* d_ws, size_t ws_b
   }
   h_out[DLIC_PROBE_COUNT - 1] = mhz;
   return all_ok ? DLIC_OK : DLIC_ERR_TIMEOUT;
+}
+
+size_t dlic_deep_workspace(int32_t h, int32_t w, const dlic_coder* coder, int32_t hidden,
+                           int32_t decode) {
+  if (h <= 0 || w <= 0 || (hidden != 64 && hidden != 128)) return 0;
+  const size_t wop = align256(deep_wop_bytes(hidden));
+  if (decode < 0) return wop;  // density hook
+  if (!coder_ok(h, coder)) return 0;
+  if (decode) return wop + align256((size_t)h * DEEP_OUT * 2) + 256;
+  return wop + enc_ws_layout(h, w, coder->groups, coder->lanes_per_group, nullptr, nullptr);
+}
+
+dlic_status dlic_deep_density(const dlic_deep_model* model, const uint8_t* d_img, int32_t h,
+                              int32_t w, float* d_logits, uint32_t* d_cf, uint16_t* d_tables,
+                              void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  timing_reset();
+  if (!d_img || !d_ws || h <= 0 || w <= 0 || (!d_logits && !d_cf && !d_tables))
+    return DLIC_ERR_ARG;
+  dlic_status rc = deep_model_ok(model);
+  if (rc != DLIC_OK) return rc;
+  if (ws_bytes < dlic_deep_workspace(h, w, nullptr, model->hidden, -1)) return DLIC_ERR_CAPACITY;
+  const Consts* K = nullptr;
+  if ((rc = current_consts(&K)) != DLIC_OK) return rc;
+  if ((rc = deep_stage(model, d_ws, stream)) != DLIC_OK) return rc;
+  timing_begin("deep_density_kernel", stream);
+  launch_deep_density(K, deep_net(model, d_ws), d_img, h, w, d_cf, d_logits, d_tables, stream);
+  timing_end(stream);
+  return launch_ok();
+}
+
+dlic_status dlic_deep_encode(const dlic_deep_model* model, const dlic_coder* coder,
+                             const uint8_t* d_img, int32_t h, int32_t w, uint8_t* d_out,
+                             size_t out_cap, uint64_t* d_out_len, void* d_ws, size_t ws_bytes,
+                             hipStream_t stream) {
+  timing_reset();
+  if (!d_img || !d_out || !d_out_len || !d_ws || h <= 0 || w <= 0) return DLIC_ERR_ARG;
+  if (!coder_ok(h, coder)) return DLIC_ERR_UNSUPPORTED;
+  dlic_status rc = deep_model_ok(model);
+  if (rc != DLIC_OK) return rc;
+  if (out_cap < dlic_encode_bound(h, w, coder)) return DLIC_ERR_CAPACITY;
+  if (ws_bytes < dlic_deep_workspace(h, w, coder, model->hidden, 0)) return DLIC_ERR_CAPACITY;
+  const Consts* K = nullptr;
+  if ((rc = current_consts(&K)) != DLIC_OK) return rc;
+  const size_t wop = align256(deep_wop_bytes(model->hidden));
+  EncWs ws;
+  enc_ws_layout(h, w, coder->groups, coder->lanes_per_group, (uint8_t*)d_ws + wop, &ws);
+  if ((rc = deep_stage(model, d_ws, stream)) != DLIC_OK) return rc;
+  timing_begin("deep_density_kernel", stream);
+  launch_deep_density(K, deep_net(model, d_ws), d_img, h, w, ws.cf, nullptr, nullptr, stream);
+  timing_end(stream);
+  if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
+  return run_rans_and_pack(h, w, coder, ws.cf, ws, deep_header(model), d_out, d_out_len, stream);
+}
+
+dlic_status dlic_deep_decode(const dlic_deep_model* model, const dlic_coder* coder,
+                             const uint8_t* d_bits, size_t n_bytes, uint8_t* d_img, int32_t h,
+                             int32_t w, int32_t* d_status, void* d_ws, size_t ws_bytes,
+                             hipStream_t stream) {
+  timing_reset();
+  if (!d_bits || !d_img || !d_status || !d_ws || h <= 0 || w <= 0) return DLIC_ERR_ARG;
+  if (!coder_ok(h, coder)) return DLIC_ERR_UNSUPPORTED;
+  dlic_status rc = deep_model_ok(model);
+  if (rc != DLIC_OK) return rc;
+  if (ws_bytes < dlic_deep_workspace(h, w, coder, model->hidden, 1)) return DLIC_ERR_CAPACITY;
+  const Consts* K = nullptr;
+  if ((rc = current_consts(&K)) != DLIC_OK) return rc;
+  // one wave per group, all workgroups resident (cooperative launch)
+  int grid = deep_decode_max_grid(model->hidden);
+  if (grid > 64) grid = 64;
+  if (grid <= 0) return DLIC_ERR_HIP;
+  if (coder->groups > grid * DEEP_WAVES) return DLIC_ERR_UNSUPPORTED;
+  const size_t wop = align256(deep_wop_bytes(model->hidden));
+  uint8_t* base = (uint8_t*)d_ws;
+  DeepDecArgs a;
+  memset(&a, 0, sizeof(a));
+  a.net = deep_net(model, d_ws);
+  a.K = K;
+  a.bits = d_bits;
+  a.n_bytes = n_bytes;
+  a.img = d_img;
+  a.H = h;
+  a.W = w;
+  a.G = coder->groups;
+  a.L = coder->lanes_per_group;
+  a.T = n_steps(h, w);
+  a.tables = (uint16_t*)(base + wop);
+  uint32_t* ctl = (uint32_t*)(base + wop + align256((size_t)h * DEEP_OUT * 2));
+  a.bar = ctl;
+  a.abort_flag = (int*)(ctl + 16);
+  a.status = d_status;
+  a.spin_limit = g_spin_limit;
+  a.hf = deep_header(model);
+  if ((rc = deep_stage(model, d_ws, stream)) != DLIC_OK) return rc;
+  launch_fill_u32(ctl, 0u, 64, stream);
+  launch_fill_u32((uint32_t*)d_status, 0u, 1, stream);
+  if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
+  timing_begin("deep_decode_kernel", stream);
+  if (launch_deep_decode(a, grid, stream) != hipSuccess) return DLIC_ERR_HIP;
+  timing_end(stream);
+  return launch_ok();
 }
 
 double dlic_wallclock_hz(void) {

@@ -1,0 +1,479 @@
+// The paper's own density network and head (Section II-B, Neural Network
+// Architecture): six dense layers, 12 -> H -> H -> H -> H -> H -> 256 with
+// ReLU, and a softmax over the 256 grey levels; the PMF becomes the coder's
+// cumulative table by a prefix sum (Section II-B, rANS).
+//
+// Arithmetic (the format; encoder and decoder run these same functions):
+//  * BF16 weights and layer inputs, FP32 accumulation on
+//    v_mfma_f32_16x16x32_bf16 (16-pixel tiles, the layout of NetBF16: slot e
+//    of lane group q of k-step s is input neuron 32 s + 16 (e / 4) + 4 q + e % 4,
+//    layer 1 takes feature 4 e + q in slot e < 3); the bias seeds the
+//    accumulator;
+//  * table rule in FP32: m = max logit, e_v = expf(o_v - m), S = ((S0 + S1) +
+//    S2) + S3 over four blocks of 64 levels each summed in level order,
+//    r = 1 / S, p_v = e_v r, block totals T_b in level order, offsets O_0 = 0,
+//    O_b+1 = O_b + T_b, running sum L inside a block, C_v = O_b + L_v,
+//    F(v) = v + min(M', floor(C_v M')), F(0) = 0, F(256) = 2^16.
+//
+// Decoding follows the paper's GPU scheme (Section II-B, Preprocessor: all
+// pixels of one wavefront step enter the network as one matrix): one
+// cooperative launch walks the steps; in each, the whole grid evaluates the
+// network for the step's pixels (one 16-pixel tile per wave) and writes their
+// tables, a grid barrier, every group's wave decodes its rows' pixels of the
+// step from those tables, a grid barrier.  Weights do not fit a CU's LDS
+// (200 KB at H = 128), so every tile reads them from the L2 in operand order.
+#include "dlic_device.hpp"
+#include "dlic_kernels.h"
+
+namespace dlic {
+
+constexpr int SM_ROW = DEEP_OUT + 4;  // floats per pixel row of the softmax scratch
+
+__host__ __device__ constexpr int deep_in(int i, int H) { return i == 0 ? 32 : H; }
+__host__ __device__ constexpr int deep_out(int i, int H) { return i == DEEP_LAYERS - 1 ? DEEP_OUT : H; }
+// bf16x8 operands (64 per (tile, k-step)) before layer i
+__host__ __device__ constexpr long long deep_off(int i, int H) {
+  long long o = 0;
+  for (int l = 0; l < i; ++l) o += (long long)(deep_out(l, H) / 16) * (deep_in(l, H) / 32) * 64;
+  return o;
+}
+
+size_t deep_wop_bytes(int H) { return (size_t)deep_off(DEEP_LAYERS, H) * 16; }
+
+// Input index of slot e of lane group q in k-step s of layer i (-1: zero slot).
+__device__ __forceinline__ int deep_slot_input(int i, int s, int q, int e) {
+  if (i == 0) return e < 3 ? 4 * e + q : -1;
+  return 32 * s + 16 * (e >> 2) + 4 * q + (e & 3);
+}
+
+struct DeepPackArgs {
+  const uint16_t* w[DEEP_LAYERS];
+};
+
+__global__ __launch_bounds__(256) void deep_pack_kernel(int H, DeepPackArgs p, uint16_t* wop) {
+  const long long total = deep_off(DEEP_LAYERS, H);
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int i = 0;
+    while (idx >= deep_off(i + 1, H)) ++i;
+    const long long r = idx - deep_off(i, H);
+    const int lane = (int)(r & 63), blk = (int)(r >> 6);
+    const int NK = deep_in(i, H) / 32;
+    const int nt = blk / NK, s = blk - nt * NK;
+    const int row = 16 * nt + (lane & 15), q = lane >> 4;
+    const int fan_in = i == 0 ? K_IN : H;
+    for (int e = 0; e < 8; ++e) {
+      const int k = deep_slot_input(i, s, q, e);
+      wop[idx * 8 + e] = k >= 0 ? p.w[i][(long long)row * fan_in + k] : (uint16_t)0;
+    }
+  }
+}
+
+void launch_deep_pack(int H, const uint16_t* const* w, void* wop, hipStream_t s) {
+  DeepPackArgs p;
+  for (int i = 0; i < DEEP_LAYERS; ++i) p.w[i] = w[i];
+  const long long total = deep_off(DEEP_LAYERS, H);
+  const int grid = (int)((total + 255) / 256);
+  hipLaunchKernelGGL(deep_pack_kernel, dim3(grid), dim3(256), 0, s, H, p, (uint16_t*)wop);
+}
+
+// One 16-pixel tile through the six layers.  Lane l holds features 4e + l/16
+// (e = 0..2) of pixel l % 16 and gets logits 16 nt + 4 (l / 16) + r of that
+// pixel in o[nt][r].
+template <int H>
+__device__ __forceinline__ void deep_run(const DeepNetArgs& d, float f0, float f1, float f2,
+                                         float (&o)[DEEP_OUT / 16][4]) {
+  constexpr int NT = H / 16, NK = H / 32;
+  const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+  const int q = lane >> 4;
+  const bf16x8* w = reinterpret_cast<const bf16x8*>(d.wop);
+  const __bf16 z = (__bf16)0.0f;
+  const bf16x8 x = {(__bf16)f0, (__bf16)f1, (__bf16)f2, z, z, z, z, z};
+  float h[NT][4];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const float* b = d.b[0] + 16 * nt + 4 * q;
+    f4 acc = {b[0], b[1], b[2], b[3]};
+    acc = mfma_bf16(w[nt * 64 + lane], x, acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[nt][r] = relu(acc[r]);
+  }
+  w += NT * 64;
+#pragma unroll 1
+  for (int li = 1; li < DEEP_LAYERS - 1; ++li) {
+    bf16x8 a[NK];
+#pragma unroll
+    for (int s = 0; s < NK; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) a[s][e] = (__bf16)h[2 * s + (e >> 2)][e & 3];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const float* b = d.b[li] + 16 * nt + 4 * q;
+      f4 acc = {b[0], b[1], b[2], b[3]};
+#pragma unroll
+      for (int s = 0; s < NK; ++s) acc = mfma_bf16(w[(nt * NK + s) * 64 + lane], a[s], acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h[nt][r] = relu(acc[r]);
+    }
+    w += NT * NK * 64;
+  }
+  bf16x8 a[NK];
+#pragma unroll
+  for (int s = 0; s < NK; ++s)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) a[s][e] = (__bf16)h[2 * s + (e >> 2)][e & 3];
+#pragma unroll
+  for (int nt = 0; nt < DEEP_OUT / 16; ++nt) {
+    const float* b = d.b[DEEP_LAYERS - 1] + 16 * nt + 4 * q;
+    f4 acc = {b[0], b[1], b[2], b[3]};
+#pragma unroll
+    for (int s = 0; s < NK; ++s) acc = mfma_bf16(w[(nt * NK + s) * 64 + lane], a[s], acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[nt][r] = acc[r];
+  }
+}
+
+// The table rule for the 16 pixels of a tile.  sm: the wave's [16][SM_ROW]
+// scratch.  Afterwards lane (b, p) = (l / 16, l % 16) holds block b of pixel
+// p: its offset O_b and, in sm[p][64 b + k], the probabilities p_v.
+struct DeepBlock {
+  float off;
+};
+
+__device__ __forceinline__ DeepBlock deep_softmax(float (&o)[DEEP_OUT / 16][4], float* sm) {
+  const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+  const int p = lane & 15, q = lane >> 4;
+  float m = o[0][0];
+#pragma unroll
+  for (int nt = 0; nt < DEEP_OUT / 16; ++nt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) m = fmaxf(m, o[nt][r]);
+  m = fmaxf(m, __shfl_xor(m, 16));
+  m = fmaxf(m, __shfl_xor(m, 32));
+#pragma unroll
+  for (int nt = 0; nt < DEEP_OUT / 16; ++nt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sm[p * SM_ROW + 16 * nt + 4 * q + r] = expf(o[nt][r] - m);
+  wave_lds_handover();
+  // block b = q of pixel p, in level order
+  float* row = sm + p * SM_ROW + 64 * q;
+  float sb = 0.0f;
+#pragma unroll 8
+  for (int k = 0; k < 64; ++k) sb = sb + row[k];
+  const float s0 = __shfl(sb, p), s1 = __shfl(sb, p + 16), s2 = __shfl(sb, p + 32),
+              s3 = __shfl(sb, p + 48);
+  const float S = ((s0 + s1) + s2) + s3;
+  const float rr = 1.0f / S;
+  float tb = 0.0f;
+#pragma unroll 8
+  for (int k = 0; k < 64; ++k) {
+    const float pv = row[k] * rr;
+    row[k] = pv;
+    tb = tb + pv;
+  }
+  const float t0 = __shfl(tb, p), t1 = __shfl(tb, p + 16), t2 = __shfl(tb, p + 32);
+  const float o1 = t0, o2 = o1 + t1, o3 = o2 + t2;
+  DeepBlock blk;
+  blk.off = q == 0 ? 0.0f : (q == 1 ? o1 : (q == 2 ? o2 : o3));
+  return blk;
+}
+
+__device__ __forceinline__ uint32_t deep_F(int v, float C) {
+  const float t = floorf(C * (float)M_PRIME);
+  const uint32_t qv = t >= (float)M_PRIME ? M_PRIME : (uint32_t)t;
+  return (uint32_t)v + qv;
+}
+
+// Features 4e + q (e = 0..2) of pixel (y, x): scaled window values, 0 outside.
+__device__ __forceinline__ void deep_features(const Consts* __restrict__ K, const uint8_t* img,
+                                              int H, int W, int y, int x, bool valid, int q,
+                                              float& f0, float& f1, float& f2) {
+  float f[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int k = 4 * e + q;
+    const int yy = y + nb_dy(k), xx = x + nb_dx(k);
+    const bool in = valid && yy >= 0 && xx >= 0 && xx < W;
+    f[e] = in ? K->scale[img[(long long)yy * W + xx]] : 0.0f;
+  }
+  f0 = f[0];
+  f1 = f[1];
+  f2 = f[2];
+}
+
+// Encoder side: every pixel's interval (and optionally logits / tables).
+template <int H>
+__global__ __launch_bounds__(DEEP_WAVES * 64) void deep_density_kernel(
+    const Consts* __restrict__ K, DeepNetArgs net, const uint8_t* __restrict__ img, int Hh, int W,
+    uint32_t* __restrict__ cf, float* __restrict__ logits, uint16_t* __restrict__ tables) {
+  __shared__ float s_sm[DEEP_WAVES][16 * SM_ROW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = lane & 15, q = lane >> 4;
+  float* sm = s_sm[wave];
+  const long long n = (long long)Hh * W;
+  const long long n_tiles = (n + 15) / 16;
+  for (long long tile = (long long)blockIdx.x * DEEP_WAVES + wave; tile < n_tiles;
+       tile += (long long)gridDim.x * DEEP_WAVES) {
+    const long long px = tile * 16 + p;
+    const bool valid = px < n;
+    const int y = valid ? (int)(px / W) : 0, x = valid ? (int)(px - (long long)y * W) : 0;
+    float f0, f1, f2;
+    deep_features(K, img, Hh, W, y, x, valid, q, f0, f1, f2);
+    float o[DEEP_OUT / 16][4];
+    deep_run<H>(net, f0, f1, f2, o);
+    if (logits && valid) {
+#pragma unroll
+      for (int nt = 0; nt < DEEP_OUT / 16; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) logits[px * DEEP_OUT + 16 * nt + 4 * q + r] = o[nt][r];
+    }
+    const DeepBlock blk = deep_softmax(o, sm);
+    const float* row = sm + p * SM_ROW + 64 * q;
+    const int xv = valid ? (int)img[px] : 0;
+    const bool mine = (xv >> 6) == q;  // this lane's block holds the pixel's level
+    float L = 0.0f;
+    uint32_t c = 0, fnext = 0;
+#pragma unroll 4
+    for (int k = 0; k < 64; ++k) {
+      const int v = 64 * q + k;
+      const uint32_t Fv = v == 0 ? 0u : deep_F(v, blk.off + L);
+      if (tables && valid) tables[px * DEEP_OUT + v] = (uint16_t)Fv;
+      if (v == xv) c = Fv;
+      L = L + row[k];
+      if (v == xv) fnext = v == DEEP_OUT - 1 ? M_TOTAL : deep_F(v + 1, blk.off + L);
+    }
+    if (valid && mine && cf) cf[px] = c | ((fnext - c - 1u) << 16);
+    wave_lds_handover();
+  }
+}
+
+bool launch_deep_density(const Consts* K, const DeepNetArgs& net, const uint8_t* img, int H,
+                         int W, uint32_t* cf, float* logits, uint16_t* tables, hipStream_t s) {
+  const long long tiles = ((long long)H * W + 15) / 16;
+  long long grid = (tiles + DEEP_WAVES - 1) / DEEP_WAVES;
+  if (grid > 2048) grid = 2048;
+  if (grid < 1) grid = 1;
+  if (net.H == 64)
+    hipLaunchKernelGGL(deep_density_kernel<64>, dim3((unsigned)grid), dim3(DEEP_WAVES * 64), 0, s,
+                       K, net, img, H, W, cf, logits, tables);
+  else if (net.H == 128)
+    hipLaunchKernelGGL(deep_density_kernel<128>, dim3((unsigned)grid), dim3(DEEP_WAVES * 64), 0,
+                       s, K, net, img, H, W, cf, logits, tables);
+  else
+    return false;
+  return true;
+}
+
+// ---- decoder ----------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t rd32(const uint8_t* p) {
+  return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+}
+__device__ __forceinline__ uint32_t rd16(const uint8_t* p) {
+  return (uint32_t)p[0] | ((uint32_t)p[1] << 8);
+}
+
+// Grid barrier over a cooperative launch: a counter that only grows (barrier
+// k completes when it reaches k * gridDim.x).  The wait is bounded; giving up
+// sets the abort flag, which ends every workgroup's walk.
+__device__ __forceinline__ bool grid_sync(unsigned* bar, int* abort_flag, unsigned& k,
+                                          uint32_t limit) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ++k;
+    const unsigned target = k * gridDim.x;
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t spins = 0;
+    int ok = 1;
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+          ++spins > limit) {
+        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return s_ok != 0;
+}
+
+__device__ int deep_check_header(const DeepDecArgs& a) {
+  if (a.n_bytes < (unsigned long long)(HEADER_BYTES + 4LL * a.G)) return 3;
+  const uint8_t* b = a.bits;
+  if (b[0] != 'D' || b[1] != 'L' || b[2] != 'I' || b[3] != 'C') return 3;
+  if (rd16(b + 4) != 1u) return 3;
+  if (rd32(b + 8) != (uint32_t)a.H || rd32(b + 12) != (uint32_t)a.W) return 3;
+  if (b[16] != K_IN || b[19] != SKEW || b[24] != PROB_BITS) return 3;
+  if (b[25] != (uint8_t)a.L || rd16(b + 26) != (uint32_t)a.G) return 3;
+  const uint64_t fp = (uint64_t)rd32(b + 28) | ((uint64_t)rd32(b + 32) << 32);
+  if (b[17] != 0 || b[18] != (uint8_t)a.hf.dtype || rd16(b + 20) != (uint32_t)a.hf.h1 ||
+      rd16(b + 22) != (uint32_t)a.hf.h2 || fp != a.hf.fingerprint)
+    return 4;
+  return 0;
+}
+
+template <int H>
+__global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArgs a) {
+  __shared__ float s_sm[DEEP_WAVES][16 * SM_ROW];
+  __shared__ int s_err;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = lane & 15, q = lane >> 4;
+  float* sm = s_sm[wave];
+  const int gw = blockIdx.x * DEEP_WAVES + wave;
+  const int NW = gridDim.x * DEEP_WAVES;
+  if (threadIdx.x == 0) s_err = deep_check_header(a);
+  __syncthreads();
+  const int err = s_err;
+  // the group this wave decodes, if any: its lanes' states live in registers
+  const int g = gw;
+  const bool coder = err == 0 && g < a.G;
+  int r0 = 0, R = 0, J = 0;
+  uint32_t n_words = 0, Pw = 0, x = RANS_L;
+  const uint16_t* gw16 = nullptr;
+  bool bad = false;
+  if (coder) {
+    r0 = (int)(((long long)g * a.H) / a.G);
+    R = (int)(((long long)(g + 1) * a.H) / a.G) - r0;
+    J = (R + a.L - 1) / a.L;
+    unsigned long long before = 0, total = 0;
+    for (int i = lane; i < a.G; i += 64) {
+      const uint32_t c = rd32(a.bits + HEADER_BYTES + 4 * i);
+      total += c;
+      if (i < g) before += c;
+    }
+    for (int sh = 32; sh >= 1; sh >>= 1) {
+      total += __shfl_xor(total, sh);
+      before += __shfl_xor(before, sh);
+    }
+    n_words = rd32(a.bits + HEADER_BYTES + 4 * g);
+    bad = (unsigned long long)(HEADER_BYTES + 4LL * a.G) + 2ull * total != a.n_bytes ||
+          n_words < 2u * (uint32_t)a.L;
+    gw16 = reinterpret_cast<const uint16_t*>(a.bits + HEADER_BYTES + 4LL * a.G + 2ull * before);
+    if (!bad && lane < a.L) x = (uint32_t)gw16[2 * lane] | ((uint32_t)gw16[2 * lane + 1] << 16);
+    Pw = 2u * (uint32_t)a.L;
+  }
+  bool over = false;
+  unsigned k_bar = 0;
+  bool alive = err == 0;
+  for (long long t = 0; t < a.T && alive; ++t) {
+    // ---- the step's pixels through the network, one 16-row tile per wave
+    const int y_lo = (int)(t - a.W + 1 > 0 ? (t - a.W + 1 + SKEW - 1) / SKEW : 0);
+    const int y_hi = (int)(t / SKEW < a.H - 1 ? t / SKEW : a.H - 1);
+    const int n_act = y_hi - y_lo + 1;
+    for (int tile = gw; tile * 16 < n_act; tile += NW) {
+      const int y = y_lo + 16 * tile + p;
+      const bool valid = y <= y_hi;
+      const int xx = valid ? (int)(t - (long long)SKEW * y) : 0;
+      float f0, f1, f2;
+      deep_features(a.K, a.img, a.H, a.W, valid ? y : 0, xx, valid, q, f0, f1, f2);
+      float o[DEEP_OUT / 16][4];
+      deep_run<H>(a.net, f0, f1, f2, o);
+      const DeepBlock blk = deep_softmax(o, sm);
+      const float* row = sm + p * SM_ROW + 64 * q;
+      float L = 0.0f;
+      uint16_t* tab = a.tables + (long long)(valid ? y : 0) * DEEP_OUT;
+#pragma unroll 4
+      for (int k = 0; k < 64; ++k) {
+        const int v = 64 * q + k;
+        if (valid) tab[v] = (uint16_t)(v == 0 ? 0u : deep_F(v, blk.off + L));
+        L = L + row[k];
+      }
+      wave_lds_handover();
+    }
+    alive = grid_sync(a.bar, a.abort_flag, k_bar, a.spin_limit);
+    if (!alive) break;
+    // ---- each group decodes its rows' pixels of the step
+    if (coder && !bad) {
+      for (int j = 0; j < J; ++j) {
+        const int rr = j * a.L + lane;
+        const int y = r0 + rr;
+        const long long xc = t - (long long)SKEW * y;
+        const bool act = lane < a.L && rr < R && xc >= 0 && xc < a.W;
+        if (__ballot(act) == 0ull) continue;
+        const uint32_t slot = x & 0xFFFFu;
+        const uint16_t* tab = a.tables + (long long)(act ? y : 0) * DEEP_OUT;
+        // bucket of 16 levels from the boundaries F(16 k), then the level in it
+        int nb = 0;
+#pragma unroll
+        for (int k = 1; k < 16; ++k) nb += ((uint32_t)tab[16 * k] <= slot) ? 1 : 0;
+        uint32_t Fl[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Fl[i] = tab[16 * nb + i];
+        int cnt = 0;
+#pragma unroll
+        for (int i = 1; i < 16; ++i) cnt += (Fl[i] <= slot) ? 1 : 0;
+        const int v = 16 * nb + cnt;
+        uint32_t c = Fl[0], fn = nb < 15 ? (uint32_t)tab[16 * (nb + 1)] : M_TOTAL;
+#pragma unroll
+        for (int i = 1; i < 16; ++i) {
+          if (i == cnt) c = Fl[i];
+          if (i == cnt + 1) fn = Fl[i];
+        }
+        const uint32_t f = fn - c;
+        const uint32_t xd = __umul24(f, x >> 16) + slot - c;
+        const bool ren = act && xd < RANS_L;
+        const uint64_t m = __ballot(ren);
+        const uint32_t rk = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        const uint32_t pos = Pw + rk;
+        uint32_t wv = 0;
+        if (ren) {
+          if (pos < n_words)
+            wv = gw16[pos];
+          else
+            over = true;
+        }
+        if (act) x = ren ? ((xd << 16) | wv) : xd;
+        Pw += (uint32_t)__popcll(m);
+        if (act) a.img[(long long)y * a.W + xc] = (uint8_t)v;
+      }
+    }
+    alive = grid_sync(a.bar, a.abort_flag, k_bar, a.spin_limit);
+  }
+  if (err != 0) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) atomicMax(a.status, err);
+    return;
+  }
+  if (!alive) {
+    if (threadIdx.x == 0) atomicMax(a.status, 7);
+    return;
+  }
+  if (coder) {
+    const bool lane_bad = lane < a.L && x != RANS_L;
+    if (__ballot(lane_bad || over || bad) != 0ull || Pw != n_words) {
+      if (lane == 0) atomicMax(a.status, 3);
+    }
+  }
+}
+
+int deep_decode_max_grid(int H) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const hipError_t e =
+      H == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, deep_decode_kernel<64>,
+                                                             DEEP_WAVES * 64, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, deep_decode_kernel<128>,
+                                                             DEEP_WAVES * 64, 0);
+  if (e != hipSuccess) return 0;
+  return cus * per_cu;
+}
+
+hipError_t launch_deep_decode(const DeepDecArgs& a, int grid, hipStream_t s) {
+  DeepDecArgs args = a;
+  void* kargs[] = {&args};
+  if (a.net.H == 64)
+    return hipLaunchCooperativeKernel((const void*)deep_decode_kernel<64>, dim3(grid),
+                                      dim3(DEEP_WAVES * 64), kargs, 0, s);
+  if (a.net.H == 128)
+    return hipLaunchCooperativeKernel((const void*)deep_decode_kernel<128>, dim3(grid),
+                                      dim3(DEEP_WAVES * 64), kargs, 0, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dlic

@@ -406,7 +406,7 @@ __device__ __forceinline__ void pack_group_part(const uint16_t* __restrict__ wor
       put_u32(out + 8, (uint32_t)H);
       put_u32(out + 12, (uint32_t)W);
       out[16] = (uint8_t)K_IN;
-      out[17] = (uint8_t)N_MIX;
+      out[17] = (uint8_t)hf.n_mix;
       out[18] = (uint8_t)hf.dtype;
       out[19] = (uint8_t)SKEW;
       put_u16(out + 20, (uint32_t)hf.h1);

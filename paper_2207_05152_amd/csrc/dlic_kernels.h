@@ -11,6 +11,7 @@ namespace dlic {
 struct HeaderFields {
   int dtype, h1, h2;
   uint64_t fingerprint;
+  int n_mix = N_MIX;  // 0: the six-layer softmax-256 network
 };
 
 // Decoder limits: rows per group, and the per-group stream ring in LDS.
@@ -119,6 +120,43 @@ bool launch_batch_decode(int wtype, int width, const Consts* K, const DevModel& 
 // every hand-off completed.  gflags: 32 cleared words.
 void launch_latency_probe(int probe, unsigned long long* out, uint32_t* gflags, hipStream_t s);
 int probe_links(int probe);
+
+// ---- six-layer softmax-256 network (the paper's own head) -----------------
+constexpr int DEEP_LAYERS = 6;
+constexpr int DEEP_OUT = 256;
+struct DeepNetArgs {
+  int H;                        // hidden width (64 or 128)
+  const void* wop;              // weights in MFMA operand order (deep_pack_weights)
+  const float* b[DEEP_LAYERS];  // FP32 biases
+};
+// Bytes of the operand-order weights of a 12 -> H x 5 -> 256 net.
+size_t deep_wop_bytes(int H);
+// Rearrange row-major BF16 weights (w[i]: [out][in]) into operand order at wop.
+void launch_deep_pack(int H, const uint16_t* const* w, void* wop, hipStream_t s);
+// Encoder density: packed interval c | (f - 1) << 16 of every pixel (raster
+// order) by the softmax table rule; optionally the FP32 logits [n][256] and the
+// tables F(0..255) [n][256] (u16).  False for an unsupported width.
+bool launch_deep_density(const Consts* K, const DeepNetArgs& net, const uint8_t* img, int H,
+                         int W, uint32_t* cf, float* logits, uint16_t* tables, hipStream_t s);
+struct DeepDecArgs {
+  DeepNetArgs net;
+  const Consts* K;
+  const uint8_t* bits;
+  unsigned long long n_bytes;
+  uint8_t* img;
+  int H, W, G, L;
+  long long T;
+  uint16_t* tables;   // [H][256]: F(0..255) of each row's pixel of the current step
+  unsigned* bar;      // grid barrier counter, cleared before launch
+  int* abort_flag;    // cleared before launch
+  int* status;
+  uint32_t spin_limit;
+  HeaderFields hf;
+};
+// Cooperative launch of the per-step decoder; returns the hipError of the launch.
+hipError_t launch_deep_decode(const DeepDecArgs& a, int grid, hipStream_t s);
+int deep_decode_max_grid(int H);
+constexpr int DEEP_WAVES = 4;  // waves per workgroup of the deep kernels
 
 // Training: waves per workgroup of the FP32 / FP64 loss-and-gradient kernel.
 constexpr int TRAIN_WAVES_F32 = 8;
