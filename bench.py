@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MI355X_FP32_MFMA = 157.3e12
+MI355X_BF16_MFMA = 2.5e15  # dense
 
 # The paper's own timings, printed beside ours as context only: other hardware,
 # other (trained, larger) networks, a softmax head and other images.
@@ -372,6 +373,47 @@ def batch_sweep(dl, torch, reps=3, tune_budget_s=60.0):
     return res
 
 
+def deep_flops_per_px(hidden):
+    """FLOP per pixel of the six-layer 12 -> H x 5 -> 256 network (2 per MAC)."""
+    return 2 * (12 * hidden + 4 * hidden * hidden + hidden * 256)
+
+
+def deep_sweep(dl, torch, img, H, W, hidden=128, layout=(48, 32), reps=2):
+    """The paper's own network and head (six dense layers, softmax over 256 levels), BF16
+    weights, on the same image: encode and decode kernel times, MPix/s, bpp and the
+    encoder density kernel's MFMA rate (outside the timed region of the headline step)."""
+    import synth
+    m = dl.DeepModel(synth.xavier_deep(hidden, 3), "cuda:0")
+    coder = dl.dlic_coder(*layout)
+    dl.dlic_set_timing(True)
+    kt = {}
+    for r in range(reps + 1):
+        bits = dl.deep_encode(img, m, coder)
+        ke = dict(dl.dlic_kernel_times())
+        dec, st = dl.deep_decode(bits, m, check=False)
+        kd = dict(dl.dlic_kernel_times())
+        if r:
+            for k, v in list(ke.items()) + list(kd.items()):
+                kt.setdefault(k, []).append(v)
+    torch.cuda.synchronize()
+    dl.dlic_set_timing(False)
+    assert st == 0 and torch.equal(dec, img), "softmax-network round trip"
+    avg = {k: float(np.mean(v)) for k, v in kt.items()}
+    enc = avg["deep_density_kernel"] + avg["rans_encode_kernel"] + avg["pack_kernel"]
+    dcd = avg["deep_decode_kernel"]
+    n_px = H * W
+    flop = n_px * deep_flops_per_px(hidden)
+    return {"workload": f"{W}x{H} image (seed 1), six dense layers 12-{hidden}x5-256 with a "
+                        f"softmax over 256 levels, BF16 weights (Glorot seed 3), "
+                        f"{layout[0]}x{layout[1]} lanes",
+            "params": int(sum(W_.size + b.size for W_, b in synth.xavier_deep(hidden, 3))),
+            "kernel_ms": avg, "encode_mpix_s": n_px / enc / 1e3, "decode_mpix_s": n_px / dcd / 1e3,
+            "bpp_total": 8.0 * bits.numel() / n_px,
+            "density_tflops": flop / (avg["deep_density_kernel"] * 1e-3) / 1e12,
+            "density_frac_bf16_mfma": flop / (avg["deep_density_kernel"] * 1e-3) / MI355X_BF16_MFMA,
+            "decode_us_per_step": dcd * 1e3 / (W + 3 * H - 3)}
+
+
 def _phantom_job(seed):
     import synth
     return synth.mri_phantom(seed, 256)
@@ -609,6 +651,7 @@ def main():
         res["precision"] = precision_sweep(dl, torch, img, H, W, coder)
         res["batch"] = batch_sweep(dl, torch)
         res["training"] = training_sweep(dl, torch)
+        res["softmax_net"] = deep_sweep(dl, torch, img, H, W)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(img_np, weights, args.groups, args.lanes)
     print(json.dumps(res))
