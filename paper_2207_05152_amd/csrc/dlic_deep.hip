@@ -18,10 +18,11 @@
 // Decoding follows the paper's GPU scheme (Section II-B, Preprocessor: all
 // pixels of one wavefront step enter the network as one matrix): one
 // cooperative launch walks the steps; in each, the whole grid evaluates the
-// network for the step's pixels (one 16-pixel tile per wave) and writes their
-// tables, a grid barrier, every group's wave decodes its rows' pixels of the
-// step from those tables, a grid barrier.  Weights do not fit a CU's LDS
-// (200 KB at H = 128), so every tile reads them from the L2 in operand order.
+// network for the step's pixels (one 16-pixel tile per workgroup, its layers
+// split over the four waves) and writes their tables, a grid barrier, every
+// group's wave decodes its rows' pixels of the step from those tables, a grid
+// barrier.  Weights do not fit a CU's LDS (200 KB at H = 128), so every tile
+// reads them from the L2 in operand order.
 #include "dlic_device.hpp"
 #include "dlic_kernels.h"
 
@@ -133,6 +134,94 @@ __device__ __forceinline__ void deep_run(const DeepNetArgs& d, float f0, float f
   }
 }
 
+// The same network evaluated by the four waves of a workgroup on one tile:
+// wave w computes the neuron tiles nt = w, w + 4, ... of every layer, so it
+// needs a quarter of the weights, all of one layer loaded at once and the next
+// layer's loads issued before this layer's products.  Layer outputs go through
+// LDS as the next layer's BF16 operands (act: two buffers of NK * 64 bf16x8);
+// the logits land in sm[p][v].  Each output tile's accumulation is the same
+// chain of the same MFMAs as in deep_run, so the results are identical.
+template <int H>
+__device__ __forceinline__ void deep_run_wg(const DeepNetArgs& d, float f0, float f1, float f2,
+                                            bf16x8* act, float* sm) {
+  constexpr int NT = H / 16, NK = H / 32;
+  constexpr int TW = NT / DEEP_WAVES;            // hidden tiles per wave (1 or 2)
+  constexpr int TO = DEEP_OUT / 16 / DEEP_WAVES;  // output tiles per wave (4)
+  constexpr int MAXT = TO > TW ? TO : TW;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, p = lane & 15;
+  const bf16x8* w = reinterpret_cast<const bf16x8*>(d.wop);
+  const __bf16 z = (__bf16)0.0f;
+  const bf16x8 x = {(__bf16)f0, (__bf16)f1, (__bf16)f2, z, z, z, z, z};
+  bf16x8 wc[MAXT][NK], wn[MAXT][NK];
+  // layer 0 weights, then layer 1's in flight
+#pragma unroll
+  for (int i = 0; i < TW; ++i) wc[i][0] = w[(wave + DEEP_WAVES * i) * 64 + lane];
+  const bf16x8* wl = w + NT * 64;  // layer 1
+#pragma unroll
+  for (int i = 0; i < TW; ++i)
+#pragma unroll
+    for (int s = 0; s < NK; ++s) wn[i][s] = wl[((wave + DEEP_WAVES * i) * NK + s) * 64 + lane];
+  // layer 0
+#pragma unroll
+  for (int i = 0; i < TW; ++i) {
+    const int nt = wave + DEEP_WAVES * i;
+    const float* b = d.b[0] + 16 * nt + 4 * q;
+    f4 acc = {b[0], b[1], b[2], b[3]};
+    acc = mfma_bf16(wc[i][0], x, acc);
+    // neuron 16 nt + 4 q + r goes to slot e = 4 (nt % 2) + r of lane group q, k-step nt / 2
+    __bf16* dst = reinterpret_cast<__bf16*>(&act[(nt >> 1) * 64 + 16 * q + p]) + 4 * (nt & 1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dst[r] = (__bf16)relu(acc[r]);
+  }
+  __syncthreads();
+  int cur = 0;
+#pragma unroll 1
+  for (int li = 1; li < DEEP_LAYERS; ++li) {
+    const bool last = li == DEEP_LAYERS - 1;
+#pragma unroll
+    for (int i = 0; i < MAXT; ++i)
+#pragma unroll
+      for (int s = 0; s < NK; ++s) wc[i][s] = wn[i][s];
+    // the next layer's weights go out before this layer's products
+    const bf16x8* wnext = wl + (long long)NT * NK * 64;
+    if (li + 1 < DEEP_LAYERS) {
+      const int nt_next = li + 1 == DEEP_LAYERS - 1 ? TO : TW;
+#pragma unroll
+      for (int i = 0; i < MAXT; ++i)
+        if (i < nt_next)
+#pragma unroll
+          for (int s = 0; s < NK; ++s)
+            wn[i][s] = wnext[((wave + DEEP_WAVES * i) * NK + s) * 64 + lane];
+    }
+    bf16x8 a[NK];
+#pragma unroll
+    for (int s = 0; s < NK; ++s) a[s] = act[cur * NK * 64 + s * 64 + lane];
+    const int nt_here = last ? TO : TW;
+#pragma unroll
+    for (int i = 0; i < MAXT; ++i) {
+      if (i >= nt_here) break;
+      const int nt = wave + DEEP_WAVES * i;
+      const float* b = d.b[li] + 16 * nt + 4 * q;
+      f4 acc = {b[0], b[1], b[2], b[3]};
+#pragma unroll
+      for (int s = 0; s < NK; ++s) acc = mfma_bf16(wc[i][s], a[s], acc);
+      if (last) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sm[p * SM_ROW + 16 * nt + 4 * q + r] = acc[r];
+      } else {
+        __bf16* dst = reinterpret_cast<__bf16*>(&act[(cur ^ 1) * NK * 64 + (nt >> 1) * 64 +
+                                                     16 * q + p]) + 4 * (nt & 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[r] = (__bf16)relu(acc[r]);
+      }
+    }
+    wl = wnext;
+    cur ^= 1;
+    __syncthreads();
+  }
+}
+
 // The table rule for the 16 pixels of a tile.  sm: the wave's [16][SM_ROW]
 // scratch.  Afterwards lane (b, p) = (l / 16, l % 16) holds block b of pixel
 // p: its offset O_b and, in sm[p][64 b + k], the probabilities p_v.
@@ -160,6 +249,41 @@ __device__ __forceinline__ DeepBlock deep_softmax(float (&o)[DEEP_OUT / 16][4], 
   float sb = 0.0f;
 #pragma unroll 8
   for (int k = 0; k < 64; ++k) sb = sb + row[k];
+  const float s0 = __shfl(sb, p), s1 = __shfl(sb, p + 16), s2 = __shfl(sb, p + 32),
+              s3 = __shfl(sb, p + 48);
+  const float S = ((s0 + s1) + s2) + s3;
+  const float rr = 1.0f / S;
+  float tb = 0.0f;
+#pragma unroll 8
+  for (int k = 0; k < 64; ++k) {
+    const float pv = row[k] * rr;
+    row[k] = pv;
+    tb = tb + pv;
+  }
+  const float t0 = __shfl(tb, p), t1 = __shfl(tb, p + 16), t2 = __shfl(tb, p + 32);
+  const float o1 = t0, o2 = o1 + t1, o3 = o2 + t2;
+  DeepBlock blk;
+  blk.off = q == 0 ? 0.0f : (q == 1 ? o1 : (q == 2 ? o2 : o3));
+  return blk;
+}
+
+// As deep_softmax, with the logits already in sm[p][v] (one wave).
+__device__ __forceinline__ DeepBlock deep_softmax_lds(float* sm) {
+  const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+  const int p = lane & 15, q = lane >> 4;
+  float* row = sm + p * SM_ROW + 64 * q;
+  float m = row[0];
+#pragma unroll 8
+  for (int k = 1; k < 64; ++k) m = fmaxf(m, row[k]);
+  m = fmaxf(m, __shfl_xor(m, 16));
+  m = fmaxf(m, __shfl_xor(m, 32));
+  float sb = 0.0f;
+#pragma unroll 8
+  for (int k = 0; k < 64; ++k) {
+    const float e = expf(row[k] - m);
+    row[k] = e;
+    sb = sb + e;
+  }
   const float s0 = __shfl(sb, p), s1 = __shfl(sb, p + 16), s2 = __shfl(sb, p + 32),
               s3 = __shfl(sb, p + 48);
   const float S = ((s0 + s1) + s2) + s3;
@@ -319,11 +443,12 @@ __device__ int deep_check_header(const DeepDecArgs& a) {
 
 template <int H>
 __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArgs a) {
-  __shared__ float s_sm[DEEP_WAVES][16 * SM_ROW];
+  __shared__ float s_sm[16 * SM_ROW];
+  __shared__ bf16x8 s_act[2 * (H / 32) * 64];
   __shared__ int s_err;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = lane & 15, q = lane >> 4;
-  float* sm = s_sm[wave];
+  float* sm = s_sm;
   const int gw = blockIdx.x * DEEP_WAVES + wave;
   const int NW = gridDim.x * DEEP_WAVES;
   if (threadIdx.x == 0) s_err = deep_check_header(a);
@@ -365,25 +490,27 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
     const int y_lo = (int)(t - a.W + 1 > 0 ? (t - a.W + 1 + SKEW - 1) / SKEW : 0);
     const int y_hi = (int)(t / SKEW < a.H - 1 ? t / SKEW : a.H - 1);
     const int n_act = y_hi - y_lo + 1;
-    for (int tile = gw; tile * 16 < n_act; tile += NW) {
+    // one tile per workgroup, its layers split over the four waves
+    for (int tile = blockIdx.x; tile * 16 < n_act; tile += gridDim.x) {
       const int y = y_lo + 16 * tile + p;
       const bool valid = y <= y_hi;
       const int xx = valid ? (int)(t - (long long)SKEW * y) : 0;
       float f0, f1, f2;
       deep_features(a.K, a.img, a.H, a.W, valid ? y : 0, xx, valid, q, f0, f1, f2);
-      float o[DEEP_OUT / 16][4];
-      deep_run<H>(a.net, f0, f1, f2, o);
-      const DeepBlock blk = deep_softmax(o, sm);
-      const float* row = sm + p * SM_ROW + 64 * q;
-      float L = 0.0f;
-      uint16_t* tab = a.tables + (long long)(valid ? y : 0) * DEEP_OUT;
+      deep_run_wg<H>(a.net, f0, f1, f2, s_act, sm);
+      if (wave == 0) {
+        const DeepBlock blk = deep_softmax_lds(sm);
+        const float* row = sm + p * SM_ROW + 64 * q;
+        float L = 0.0f;
+        uint16_t* tab = a.tables + (long long)(valid ? y : 0) * DEEP_OUT;
 #pragma unroll 4
-      for (int k = 0; k < 64; ++k) {
-        const int v = 64 * q + k;
-        if (valid) tab[v] = (uint16_t)(v == 0 ? 0u : deep_F(v, blk.off + L));
-        L = L + row[k];
+        for (int k = 0; k < 64; ++k) {
+          const int v = 64 * q + k;
+          if (valid) tab[v] = (uint16_t)(v == 0 ? 0u : deep_F(v, blk.off + L));
+          L = L + row[k];
+        }
       }
-      wave_lds_handover();
+      __syncthreads();
     }
     alive = grid_sync(a.bar, a.abort_flag, k_bar, a.spin_limit);
     if (!alive) break;
