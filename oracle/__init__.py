@@ -33,6 +33,6 @@ from .container import (HEADER_SIZE, pack_header, parse_header, fingerprint,
 from .codec import (OracleCoder, encode_image, decode_image, cf_for_image,
                     params32_for_image, weights_fingerprint)
 from .nll import nll_bits, nll_and_grad_fd, adam_update, sample_features, PARAM_ORDER
-from . import softmax
+from . import softmax, volume
 
 __all__ = [n for n in dir() if not n.startswith("_")]

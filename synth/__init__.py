@@ -218,3 +218,47 @@ def random_symbols_from_tables(tables: np.ndarray, idx: np.ndarray, seed: int) -
         sel = flat == t
         sym[sel] = np.searchsorted(tables[t], u[sel], side="right") - 1
     return sym.reshape(idx.shape)
+
+
+def mri_volume(seed: int, depth: int = 35, size: int = 256) -> np.ndarray:
+    """MRI-like 8-bit volume whose slices are cuts through one 3-D object,
+    shape (depth, size, size), dtype uint8 (a 256x256x35 scan by default).
+
+    Recipe: 3-8 nested ellipsoids of random intensity 20-220 on a zero
+    background (semi-axes 70-115 px in-plane, 0.6-1.2 times the depth along
+    the slice axis, each inner one 0.45-0.85 of its parent, offset inside it),
+    a smooth multiplicative quadratic bias field over the volume, Rician noise
+    with sigma 4, rounded and clipped to 0..255.  Neighbouring slices are
+    strongly but not perfectly alike, as in a scan with a slice gap.
+    """
+    rng = np.random.default_rng(seed)
+    scale = size / 256.0
+    zz, yy, xx = np.meshgrid(np.arange(depth, dtype=np.float64) + 0.5,
+                             np.arange(size, dtype=np.float64),
+                             np.arange(size, dtype=np.float64), indexing="ij")
+    vol = np.zeros((depth, size, size), dtype=np.float64)
+    c = np.array([depth / 2.0 + rng.uniform(-0.1, 0.1) * depth,
+                  size / 2.0 + rng.uniform(-10.0, 10.0), size / 2.0 + rng.uniform(-10.0, 10.0)])
+    ax = np.array([rng.uniform(0.6, 1.2) * depth, rng.uniform(70.0, 115.0) * scale,
+                   rng.uniform(70.0, 115.0) * scale])
+    ang = rng.uniform(0.0, np.pi)
+    for i in range(int(rng.integers(3, 9))):
+        if i > 0:
+            na = ax * rng.uniform(0.45, 0.85, size=3)
+            c = c + rng.uniform(-1.0, 1.0, size=3) * 0.5 * (ax - na)
+            ax = na
+            ang = ang + rng.uniform(-0.5, 0.5)
+        dy, dx = yy - c[1], xx - c[2]
+        u = dx * np.cos(ang) + dy * np.sin(ang)
+        v = -dx * np.sin(ang) + dy * np.cos(ang)
+        inside = ((zz - c[0]) / ax[0]) ** 2 + (u / ax[2]) ** 2 + (v / ax[1]) ** 2 <= 1.0
+        vol[inside] = rng.uniform(20.0, 220.0)
+    coef = rng.normal(0.0, 0.5, size=6)
+    w = zz / depth * 2.0 - 1.0
+    uu = xx / (size - 1) * 2.0 - 1.0
+    vv = yy / (size - 1) * 2.0 - 1.0
+    bias = np.exp(0.3 * (coef[0] * uu + coef[1] * vv + coef[2] * uu * uu + coef[3] * vv * vv
+                         + coef[4] * uu * vv + coef[5] * w))
+    n1 = rng.normal(0.0, 4.0, size=vol.shape)
+    n2 = rng.normal(0.0, 4.0, size=vol.shape)
+    return np.clip(np.rint(np.sqrt((vol * bias + n1) ** 2 + n2 ** 2)), 0, 255).astype(np.uint8)
