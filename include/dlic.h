@@ -375,10 +375,14 @@ double dlic_wallclock_hz(void);
  * cooperative launch walks the W + 3H - 3 steps, the whole grid evaluating
  * the step's pixels, then every group decoding its rows' pixels of the step,
  * with a grid barrier after each phase.  It needs every group's wave
- * resident: G <= 256 (DLIC_ERR_UNSUPPORTED otherwise). */
+ * resident (DLIC_ERR_UNSUPPORTED otherwise): at least 256 groups fit.
+ *
+ * k_in is 12 for images; volumes (below) also take 21: the 12-pixel window
+ * and a 3 x 3 block of the slice below. */
 #define DLIC_DEEP_LAYERS 6
 typedef struct {
   int32_t hidden;                          /* H: 64 or 128 */
+  int32_t k_in;                            /* inputs of layer 1: 12, or 21 (volumes) */
   const uint16_t *d_w[DLIC_DEEP_LAYERS];   /* BF16 bit patterns, row-major [out][in] */
   const float *d_b[DLIC_DEEP_LAYERS];      /* FP32 biases */
   uint64_t fingerprint; /* FNV-1a 64 over W1, b1, ..., W6, b6 as stored (BF16 / FP32) */
@@ -411,6 +415,72 @@ dlic_status dlic_deep_decode(const dlic_deep_model *model, const dlic_coder *cod
 dlic_status dlic_deep_density(const dlic_deep_model *model, const uint8_t *d_img, int32_t h,
                               int32_t w, float *d_logits, uint32_t *d_cf, uint16_t *d_tables,
                               void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Grid of the deep decoders (dlic_deep_decode, dlic_volume_decode): the
+ * number of workgroups of the cooperative launch, clamped to what is resident
+ * and raised to fit every group; 0 restores the default (a step's tiles,
+ * 64..256).  Process-wide; dlic_deep_decode_grid gives the last launch's. */
+void dlic_set_deep_decode_grid(int32_t workgroups);
+int32_t dlic_deep_decode_grid(void);
+
+/* ---- volumes: the 3-D window and the 3-D wavefront (Section IV-C, 3D
+ * Dependencies and 3D Wavefront, Fig. 6) -------------------------------------
+ * A volume is z slices of h x w pixels, slice-major in device memory
+ * (d_vol[(s h + y) w + x]).  With a model of k_in = 21 a pixel's window is
+ * the 12 causal pixels of its own slice, then the 3 x 3 pixels of the slice
+ * below at rows y + ws - 3 .. y + ws - 1 and columns x - 1 .. x + 1, row by
+ * row, 0 outside the slice (and for the first slice); ws is the paper's
+ * window shift.  A model of k_in = 12 codes each slice on its own (ws = 0).
+ * The stream is the container of dlic_encode for the z h x w image of the
+ * stacked slices with coder->groups groups per slice (so every group lies in
+ * one slice): header H = z h, G = z coder->groups, window size k_in, and the
+ * header's flags hold z in bits 0..11 and ws in bits 12..15.
+ *
+ * The decoder walks the 3-D wavefront: pixel (s, y, x) is decoded in step
+ * x + 3 y + lag s, lag = max(0, 3 ws - 1) for k_in = 21 (else 0), the least
+ * lag that puts every lower-window pixel in an earlier step.  At ws = 0 all
+ * slices decode together; the first slice is complete after w + 3 h - 3
+ * steps, the volume after lag (z - 1) more.  Limits: 1 <= z <= 4095,
+ * 0 <= ws <= 15; coder valid for h (per slice) and z h (stacked), z groups at
+ * most 1024 and every group's wave resident. */
+#define DLIC_VOLUME_MAX_SLICES 4095
+#define DLIC_VOLUME_MAX_SHIFT 15
+
+/* Bytes of the largest stream of a volume (0 for an unsupported layout). */
+size_t dlic_volume_encode_bound(int32_t z, int32_t h, int32_t w, const dlic_coder *coder);
+
+/* Device workspace bytes: decode = 0 encode, 1 decode, -1 density hook. */
+size_t dlic_volume_workspace(int32_t z, int32_t h, int32_t w, const dlic_coder *coder,
+                             int32_t hidden, int32_t decode);
+
+/* Encode a volume (d_vol: z h w bytes); as dlic_deep_encode otherwise.
+ * DLIC_ERR_ARG for z, ws out of range or ws != 0 with k_in = 12. */
+dlic_status dlic_volume_encode(const dlic_deep_model *model, const dlic_coder *coder,
+                               const uint8_t *d_vol, int32_t z, int32_t h, int32_t w, int32_t ws,
+                               uint8_t *d_out, size_t out_cap, uint64_t *d_out_len, void *d_ws,
+                               size_t ws_bytes, hipStream_t stream);
+
+/* Decode a stream of dlic_volume_encode into d_vol (z h w bytes); z, h, ws
+ * and the coder as dlic_peek_volume gives them.  d_status as dlic_deep_decode
+ * (3 also when z, h, ws or the coder do not match the stream). */
+dlic_status dlic_volume_decode(const dlic_deep_model *model, const dlic_coder *coder,
+                               const uint8_t *d_bits, size_t n_bytes, uint8_t *d_vol, int32_t z,
+                               int32_t h, int32_t w, int32_t ws, int32_t *d_status, void *d_ws,
+                               size_t ws_bytes, hipStream_t stream);
+
+/* Test hook: the encoder's network and table rule on every pixel of a volume,
+ * outputs as dlic_deep_density in slice-major raster order. */
+dlic_status dlic_volume_density(const dlic_deep_model *model, const uint8_t *d_vol, int32_t z,
+                                int32_t h, int32_t w, int32_t ws, float *d_logits, uint32_t *d_cf,
+                                uint16_t *d_tables, void *d_ws, size_t ws_bytes,
+                                hipStream_t stream);
+
+/* Volume fields of a stream's header (host memory): slices, rows per slice,
+ * window shift, window size and the per-slice coder (any output may be NULL).
+ * DLIC_ERR_CORRUPT for a short or foreign header or one that is not a
+ * volume's (no slice count, or H or G not a multiple of it). */
+dlic_status dlic_peek_volume(const uint8_t *b, size_t n, int32_t *z, int32_t *h, int32_t *ws,
+                             int32_t *k_in, dlic_coder *coder);
 
 /* Measurement hook for the decode bound (Section II-B, Preprocessor and rANS:
  * each wavefront step waits for the previous one, so the decode takes at least

@@ -20,7 +20,10 @@ Readings where the paper is silent (the format's choices):
     in an earlier step;
   * stream: the Z slices stacked into one image of Z H rows, coded as a 2-D
     image with Z G groups (G per slice: every group lies in one slice); the
-    header's flags hold Z in bits 0..11 and WS in bits 12..15, k_in = 21.
+    header's flags hold Z in bits 0..11 and WS in bits 12..15, k_in = 21;
+  * a network of 12 inputs codes a volume slice by slice (the window of the
+    pixel's own slice only, WS = 0, no lag): the 3-D wavefront without the
+    3-D window.
 
 Parity: the window against a brute-force definition and causality (every
 lower-window pixel of every voxel is in an earlier step, and one step less of
@@ -80,8 +83,20 @@ def volume_features(vol, ws: int) -> np.ndarray:
     return out
 
 
-def n_steps_3d(Z: int, H: int, W: int, ws: int) -> int:
-    return W + SKEW * (H - 1) + lag(ws) * (Z - 1)
+def lag_of(k_in: int, ws: int) -> int:
+    """The lag of a network with k_in inputs: none without the slice below."""
+    return lag(ws) if k_in == K_IN_3D else 0
+
+
+def n_steps_3d(Z: int, H: int, W: int, ws: int, k_in: int = K_IN_3D) -> int:
+    return W + SKEW * (H - 1) + lag_of(k_in, ws) * (Z - 1)
+
+
+def _k_in(layers, ws: int) -> int:
+    k = int(np.asarray(layers[0][0]).shape[1])
+    if k not in (12, K_IN_3D) or (k == 12 and ws != 0):
+        raise ValueError("a volume takes 21 inputs, or 12 with WS = 0")
+    return k
 
 
 def volume_flags(Z: int, ws: int) -> int:
@@ -92,7 +107,7 @@ def cf_volume(vol, layers, ws: int):
     """(c, f) of every voxel by the softmax table rule, in stacked raster order."""
     from .softmax import deep_forward_bf16, table_softmax32
     vol = np.asarray(vol, dtype=np.uint8)
-    f = volume_features(vol, ws).reshape(-1, K_IN_3D)
+    f = volume_features(vol, ws).reshape(-1, K_IN_3D)[:, :_k_in(layers, ws)]
     F = table_softmax32(deep_forward_bf16(f, layers).astype(np.float32))
     v = vol.reshape(-1).astype(np.int64)
     rows = np.arange(v.size)
@@ -111,7 +126,8 @@ def encode_volume(vol, layers, groups: int, lanes: int, ws: int) -> bytes:
         idx = [y * W + x for (y, x, _) in grp]
         streams.append(rans_encode([(c[i], f[i]) for i in idx], [ln for (_, _, ln) in grp], lanes))
     Hn = np.asarray(layers[0][0]).shape[0]
-    hdr = pack_header(Z * H, W, Z * groups, lanes, dtype=1, h1=Hn, h2=Hn, n_mix=0, k_in=K_IN_3D,
+    hdr = pack_header(Z * H, W, Z * groups, lanes, dtype=1, h1=Hn, h2=Hn, n_mix=0,
+                      k_in=_k_in(layers, ws),
                       fp=stored_fingerprint(layers), flags=volume_flags(Z, ws))
     return assemble(hdr, streams)
 
@@ -121,9 +137,10 @@ def decode_volume(buf: bytes, layers) -> np.ndarray:
     from .rans import canonical_order, rans_decode
     from .softmax import deep_forward_bf16, stored_fingerprint, table_softmax32
     hdr = parse_header(buf)
-    if hdr["n_mix"] != 0 or hdr["k_in"] != K_IN_3D or hdr["fingerprint"] != stored_fingerprint(layers):
-        raise ValueError("stream was coded with another model")
     Z, ws = hdr["flags"] & 0xFFF, hdr["flags"] >> 12
+    k_in = _k_in(layers, ws)
+    if hdr["n_mix"] != 0 or hdr["k_in"] != k_in or hdr["fingerprint"] != stored_fingerprint(layers):
+        raise ValueError("stream was coded with another model")
     H, W = hdr["h"] // Z, hdr["w"]
     G, lanes = hdr["groups"] // Z, hdr["lanes"]
     vol = np.zeros((Z, H, W), dtype=np.uint8)
@@ -133,7 +150,7 @@ def decode_volume(buf: bytes, layers) -> np.ndarray:
         def find(i, slot, grp=grp):
             yt, x, _ = grp[i]
             z, y = divmod(yt, H)
-            o = deep_forward_bf16(voxel_features(vol, z, y, x, ws)[None, :], layers)
+            o = deep_forward_bf16(voxel_features(vol, z, y, x, ws)[None, :k_in], layers)
             F = table_softmax32(o.astype(np.float32))[0]
             v = int(np.searchsorted(F, slot, side="right")) - 1
             vol[z, y, x] = v

@@ -40,7 +40,9 @@ EXPORTS = (
     "dlic_encode_batch", "dlic_decode_batch", "dlic_batch_capture", "dlic_batch_replay",
     "dlic_wallclock_hz", "dlic_decode_noalloc", "dlic_batch_tune", "dlic_latency_probe",
     "dlic_set_decode_delays", "dlic_deep_workspace", "dlic_deep_encode", "dlic_deep_decode",
-    "dlic_deep_density",
+    "dlic_deep_density", "dlic_set_deep_decode_grid", "dlic_deep_decode_grid",
+    "dlic_volume_encode_bound", "dlic_volume_workspace", "dlic_volume_encode", "dlic_volume_decode",
+    "dlic_volume_density", "dlic_peek_volume",
     "dlic_net_forms",
 )
 
@@ -66,7 +68,7 @@ DEEP_LAYERS = 6
 
 
 class dlic_deep_model(ctypes.Structure):
-    _fields_ = [("hidden", c_int32), ("d_w", c_void_p * DEEP_LAYERS),
+    _fields_ = [("hidden", c_int32), ("k_in", c_int32), ("d_w", c_void_p * DEEP_LAYERS),
                 ("d_b", c_void_p * DEEP_LAYERS), ("fingerprint", c_uint64)]
 
 
@@ -135,6 +137,18 @@ def lib():
                                      c_int32, c_int32, P, P, S, P]),
         "dlic_deep_density": (c_int, [POINTER(dlic_deep_model), P, c_int32, c_int32, P, P, P, P,
                                       S, P]),
+        "dlic_set_deep_decode_grid": (None, [c_int32]),
+        "dlic_deep_decode_grid": (c_int32, []),
+        "dlic_volume_encode_bound": (S, [c_int32, c_int32, c_int32, POINTER(dlic_coder)]),
+        "dlic_volume_workspace": (S, [c_int32, c_int32, c_int32, P, c_int32, c_int32]),
+        "dlic_volume_encode": (c_int, [POINTER(dlic_deep_model), POINTER(dlic_coder), P, c_int32,
+                                       c_int32, c_int32, c_int32, P, S, P, P, S, P]),
+        "dlic_volume_decode": (c_int, [POINTER(dlic_deep_model), POINTER(dlic_coder), P, S, P,
+                                       c_int32, c_int32, c_int32, c_int32, P, P, S, P]),
+        "dlic_volume_density": (c_int, [POINTER(dlic_deep_model), P, c_int32, c_int32, c_int32,
+                                        c_int32, P, P, P, P, S, P]),
+        "dlic_peek_volume": (c_int, [P, S, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
+                                     POINTER(c_int32), POINTER(dlic_coder)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -432,14 +446,16 @@ def density(img, model: Model, tables=False, stream=None):
 
 class DeepModel:
     """The paper's six-layer network with the softmax head, resident on a device:
-    layers = [(W, b)] * 6 (FP32, W [out, in]: 12 -> H, H -> H x 4, H -> 256).  The
-    library's dlic_quantize_weights stores the matrices as BF16; biases stay FP32."""
+    layers = [(W, b)] * 6 (FP32, W [out, in]: k -> H, H -> H x 4, H -> 256 with k = 12,
+    or 21 for volumes with the slice below).  The library's dlic_quantize_weights stores
+    the matrices as BF16; biases stay FP32."""
 
     def __init__(self, layers, device="cuda"):
         import torch
         if len(layers) != DEEP_LAYERS:
             raise ValueError("six layers")
         self.hidden = int(np.asarray(layers[0][0]).shape[0])
+        self.k_in = int(np.asarray(layers[0][0]).shape[1])
         self.w, self.b = [], []
         h = FNV_OFFSET
         for W, b in layers:
@@ -450,7 +466,8 @@ class DeepModel:
             self.w.append(torch.from_numpy(wq.view(np.int16)).to(device))
             self.b.append(torch.from_numpy(bb).to(device))
         self.fingerprint = h
-        self.c = dlic_deep_model(self.hidden, (c_void_p * DEEP_LAYERS)(*[_ptr(t) for t in self.w]),
+        self.c = dlic_deep_model(self.hidden, self.k_in,
+                                 (c_void_p * DEEP_LAYERS)(*[_ptr(t) for t in self.w]),
                                  (c_void_p * DEEP_LAYERS)(*[_ptr(t) for t in self.b]), h)
 
 
@@ -507,6 +524,78 @@ def deep_density(img, model: DeepModel, logits=True, tables=False, stream=None):
                                    _ptr(lg) if lg is not None else None, _ptr(cf),
                                    _ptr(tab) if tab is not None else None, _ptr(ws), wsb,
                                    _stream(stream)), "dlic_deep_density")
+    return lg, cf, tab
+
+
+def dlic_set_deep_decode_grid(workgroups: int):
+    lib().dlic_set_deep_decode_grid(int(workgroups))
+
+
+def dlic_deep_decode_grid() -> int:
+    return int(lib().dlic_deep_decode_grid())
+
+
+def dlic_peek_volume(head: bytes) -> dict:
+    z, h, ws, k = (c_int32() for _ in range(4))
+    cd = dlic_coder()
+    buf = ctypes.create_string_buffer(bytes(head), len(head))
+    _check(lib().dlic_peek_volume(buf, len(head), ctypes.byref(z), ctypes.byref(h), ctypes.byref(ws),
+                                  ctypes.byref(k), ctypes.byref(cd)), "dlic_peek_volume")
+    return dict(z=z.value, h=h.value, ws=ws.value, k_in=k.value, coder=cd)
+
+
+def volume_encode(vol, model: DeepModel, coder: dlic_coder, ws: int = 0, stream=None):
+    """Encode a [z, h, w] uint8 device tensor (slices along the first axis)."""
+    import torch
+    z, h, w = vol.shape
+    cap = int(lib().dlic_volume_encode_bound(z, h, w, ctypes.byref(coder)))
+    if cap == 0:
+        raise DlicError(DLIC_ERR_UNSUPPORTED, "dlic_volume_encode_bound")
+    out = _empty(cap, torch.uint8, vol.device)
+    olen = _empty(1, torch.int64, vol.device)
+    wsb = int(lib().dlic_volume_workspace(z, h, w, ctypes.byref(coder), model.hidden, 0))
+    wsp = _empty(wsb, torch.uint8, vol.device)
+    _check(lib().dlic_volume_encode(ctypes.byref(model.c), ctypes.byref(coder),
+                                    _ptr(vol.contiguous()), z, h, w, ws, _ptr(out), cap, _ptr(olen),
+                                    _ptr(wsp), wsb, _stream(stream)), "dlic_volume_encode")
+    return out[:int(olen.item())]
+
+
+def volume_decode(bits, model: DeepModel, stream=None, check=True):
+    """Decode a stream of volume_encode; returns ([z, h, w] uint8 tensor, status)."""
+    import torch
+    hd = dlic_peek_header(bits[:HEADER_BYTES].cpu().numpy().tobytes())
+    hv = dlic_peek_volume(bits[:HEADER_BYTES].cpu().numpy().tobytes())
+    z, h, w, ws, coder = hv["z"], hv["h"], hd["w"], hv["ws"], hv["coder"]
+    vol = torch.empty((z, h, w), dtype=torch.uint8, device=bits.device)
+    st = torch.zeros(1, dtype=torch.int32, device=bits.device)
+    wsb = int(lib().dlic_volume_workspace(z, h, w, ctypes.byref(coder), model.hidden, 1))
+    if wsb == 0:
+        raise DlicError(DLIC_ERR_UNSUPPORTED, "dlic_volume_workspace")
+    wsp = _empty(wsb, torch.uint8, bits.device)
+    _check(lib().dlic_volume_decode(ctypes.byref(model.c), ctypes.byref(coder),
+                                    _ptr(bits.contiguous()), bits.numel(), _ptr(vol), z, h, w, ws,
+                                    _ptr(st), _ptr(wsp), wsb, _stream(stream)), "dlic_volume_decode")
+    status = int(st.item())
+    if check and status != DLIC_OK:
+        raise DlicError(status, "dlic_volume_decode (device status)")
+    return vol, status
+
+
+def volume_density(vol, model: DeepModel, ws: int = 0, logits=True, tables=False, stream=None):
+    """As deep_density for a [z, h, w] volume (slice-major raster order)."""
+    import torch
+    z, h, w = vol.shape
+    n = z * h * w
+    lg = torch.empty((n, 256), dtype=torch.float32, device=vol.device) if logits else None
+    cf = torch.empty(n, dtype=torch.int32, device=vol.device)
+    tab = torch.empty((n, 256), dtype=torch.int16, device=vol.device) if tables else None
+    wsb = int(lib().dlic_volume_workspace(z, h, w, None, model.hidden, -1))
+    wsp = _empty(wsb, torch.uint8, vol.device)
+    _check(lib().dlic_volume_density(ctypes.byref(model.c), _ptr(vol.contiguous()), z, h, w, ws,
+                                     _ptr(lg) if lg is not None else None, _ptr(cf),
+                                     _ptr(tab) if tab is not None else None, _ptr(wsp), wsb,
+                                     _stream(stream)), "dlic_volume_density")
     return lg, cf, tab
 
 

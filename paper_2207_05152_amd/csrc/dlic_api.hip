@@ -37,6 +37,8 @@ __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
 std::mutex g_mu;
 DeviceState g_dev[MAX_DEVICES];
 uint32_t g_spin_limit = 1u << 22;
+int g_deep_grid = 0;       // decode grid of the deep decoder; 0: by the step's tiles
+int g_deep_grid_used = 0;  // the grid of the last deep decode launch
 uint32_t g_delay_seed = 0, g_delay_max = 0;  // decoder delay injection (test hook)
 unsigned long long* g_prof = nullptr;
 
@@ -253,9 +255,11 @@ dlic_status run_rans_and_pack(int h, int w, const dlic_coder* coder, const uint3
 }
 
 // ---- the six-layer softmax-256 network -----------------------------------
-dlic_status deep_model_ok(const dlic_deep_model* m) {
+// volume: the model may take the slice below (k_in 21) or not (12); an image: 12
+dlic_status deep_model_ok(const dlic_deep_model* m, bool volume) {
   if (!m) return DLIC_ERR_ARG;
   if (m->hidden != 64 && m->hidden != 128) return DLIC_ERR_UNSUPPORTED;
+  if (m->k_in != K_IN && !(volume && m->k_in == K_IN_3D)) return DLIC_ERR_UNSUPPORTED;
   for (int i = 0; i < DLIC_DEEP_LAYERS; ++i)
     if (!m->d_w[i] || !m->d_b[i]) return DLIC_ERR_ARG;
   return DLIC_OK;
@@ -264,6 +268,7 @@ dlic_status deep_model_ok(const dlic_deep_model* m) {
 DeepNetArgs deep_net(const dlic_deep_model* m, void* wop) {
   DeepNetArgs n;
   n.H = m->hidden;
+  n.k_in = m->k_in;
   n.wop = wop;
   for (int i = 0; i < DLIC_DEEP_LAYERS; ++i) n.b[i] = m->d_b[i];
   return n;
@@ -271,14 +276,148 @@ DeepNetArgs deep_net(const dlic_deep_model* m, void* wop) {
 
 // Operand-order weights at the head of every deep workspace.
 dlic_status deep_stage(const dlic_deep_model* m, void* wop, hipStream_t s) {
-  launch_deep_pack(m->hidden, m->d_w, wop, s);
+  launch_deep_pack(m->hidden, m->k_in, m->d_w, wop, s);
   return launch_ok();
 }
 
-HeaderFields deep_header(const dlic_deep_model* m) {
+// Volume geometry: z slices, window shift ws; nullptr geometry for images.
+bool vol_geom(const dlic_deep_model* m, int z, int ws, VolGeom* vg) {
+  if (z < 1 || z > DLIC_VOLUME_MAX_SLICES || ws < 0 || ws > DLIC_VOLUME_MAX_SHIFT) return false;
+  if (m->k_in == K_IN && ws != 0) return false;  // no window in the slice below
+  vg->Z = z;
+  vg->ws = ws;
+  vg->lag = m->k_in == K_IN_3D ? (3 * ws - 1 > 0 ? 3 * ws - 1 : 0) : 0;
+  return true;
+}
+
+HeaderFields deep_header(const dlic_deep_model* m, const VolGeom* vg) {
   HeaderFields hf{DLIC_BF16, m->hidden, m->hidden, m->fingerprint};
   hf.n_mix = 0;
+  hf.k_in = m->k_in;
+  hf.flags = vg ? (vg->Z | (vg->ws << 12)) : 0;
   return hf;
+}
+
+// The stacked image's coder: G groups in each of z slices.
+dlic_coder stacked_coder(const dlic_coder* c, int z) {
+  dlic_coder t = *c;
+  t.groups = c->groups * z;
+  return t;
+}
+
+bool vol_coder_ok(int z, int h, const dlic_coder* c) {
+  if (!coder_ok(h, c)) return false;
+  const dlic_coder t = stacked_coder(c, z);
+  return coder_ok(z * h, &t);
+}
+
+size_t deep_ws_bytes(int z, int h, int w, const dlic_coder* coder, int hidden, int decode) {
+  const size_t wop = align256(deep_wop_bytes(hidden));
+  if (decode < 0) return wop;  // density hook
+  if (decode) return wop + align256((size_t)z * h * DEEP_OUT * 2) + 256;
+  return wop + enc_ws_layout(z * h, w, coder->groups * z, coder->lanes_per_group, nullptr, nullptr);
+}
+
+dlic_status deep_density_impl(const dlic_deep_model* model, const uint8_t* d_img, int h, int w,
+                              const VolGeom& vg, float* d_logits, uint32_t* d_cf,
+                              uint16_t* d_tables, void* d_ws, size_t ws_bytes,
+                              hipStream_t stream) {
+  if (ws_bytes < deep_ws_bytes(vg.Z, h, w, nullptr, model->hidden, -1)) return DLIC_ERR_CAPACITY;
+  const Consts* K = nullptr;
+  dlic_status rc = current_consts(&K);
+  if (rc != DLIC_OK) return rc;
+  if ((rc = deep_stage(model, d_ws, stream)) != DLIC_OK) return rc;
+  timing_begin("deep_density_kernel", stream);
+  if (!launch_deep_density(K, deep_net(model, d_ws), d_img, h, w, vg, d_cf, d_logits, d_tables,
+                           stream))
+    return DLIC_ERR_UNSUPPORTED;
+  timing_end(stream);
+  return launch_ok();
+}
+
+dlic_status deep_encode_impl(const dlic_deep_model* model, const dlic_coder* coder,
+                             const uint8_t* d_img, int h, int w, const VolGeom& vg,
+                             const HeaderFields& hf, uint8_t* d_out, size_t out_cap,
+                             uint64_t* d_out_len, void* d_ws, size_t ws_bytes,
+                             hipStream_t stream) {
+  const dlic_coder tc = stacked_coder(coder, vg.Z);
+  const int HT = vg.Z * h;
+  if (out_cap < dlic_encode_bound(HT, w, &tc)) return DLIC_ERR_CAPACITY;
+  if (ws_bytes < deep_ws_bytes(vg.Z, h, w, coder, model->hidden, 0)) return DLIC_ERR_CAPACITY;
+  const Consts* K = nullptr;
+  dlic_status rc = current_consts(&K);
+  if (rc != DLIC_OK) return rc;
+  const size_t wop = align256(deep_wop_bytes(model->hidden));
+  EncWs ws;
+  enc_ws_layout(HT, w, tc.groups, tc.lanes_per_group, (uint8_t*)d_ws + wop, &ws);
+  if ((rc = deep_stage(model, d_ws, stream)) != DLIC_OK) return rc;
+  timing_begin("deep_density_kernel", stream);
+  if (!launch_deep_density(K, deep_net(model, d_ws), d_img, h, w, vg, ws.cf, nullptr, nullptr,
+                           stream))
+    return DLIC_ERR_UNSUPPORTED;
+  timing_end(stream);
+  if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
+  return run_rans_and_pack(HT, w, &tc, ws.cf, ws, hf, d_out, d_out_len, stream);
+}
+
+// Upper bound on the tiles of one decode step: every slice's active rows.
+int deep_step_tiles(int z, int h, int w) {
+  const int rows = h < (w + SKEW - 1) / SKEW ? h : (w + SKEW - 1) / SKEW;
+  const long long t = (long long)z * ((rows + 15) / 16);
+  return t > (1 << 20) ? (1 << 20) : (int)t;
+}
+
+dlic_status deep_decode_impl(const dlic_deep_model* model, const dlic_coder* coder,
+                             const uint8_t* d_bits, size_t n_bytes, uint8_t* d_img, int h, int w,
+                             const VolGeom& vg, const HeaderFields& hf, int32_t* d_status,
+                             void* d_ws, size_t ws_bytes, hipStream_t stream) {
+  if (ws_bytes < deep_ws_bytes(vg.Z, h, w, coder, model->hidden, 1)) return DLIC_ERR_CAPACITY;
+  const Consts* K = nullptr;
+  dlic_status rc = current_consts(&K);
+  if (rc != DLIC_OK) return rc;
+  // one wave per group, all workgroups resident (cooperative launch); as many
+  // workgroups as a step has tiles, at least 64, at most 256 and the residency
+  const int GT = coder->groups * vg.Z;
+  const int resident = deep_decode_max_grid(model->hidden, model->k_in);
+  if (resident <= 0) return DLIC_ERR_HIP;
+  int grid = deep_step_tiles(vg.Z, h, w);
+  if (grid > 256) grid = 256;
+  if (grid < 64) grid = 64;
+  if (grid < (GT + DEEP_WAVES - 1) / DEEP_WAVES) grid = (GT + DEEP_WAVES - 1) / DEEP_WAVES;
+  if (g_deep_grid > 0) grid = g_deep_grid;
+  if (grid > resident) grid = resident;
+  if (GT > grid * DEEP_WAVES) return DLIC_ERR_UNSUPPORTED;
+  const size_t wop = align256(deep_wop_bytes(model->hidden));
+  uint8_t* base = (uint8_t*)d_ws;
+  DeepDecArgs a;
+  memset(&a, 0, sizeof(a));
+  a.net = deep_net(model, d_ws);
+  a.K = K;
+  a.bits = d_bits;
+  a.n_bytes = n_bytes;
+  a.img = d_img;
+  a.H = h;
+  a.W = w;
+  a.G = coder->groups;
+  a.L = coder->lanes_per_group;
+  a.vg = vg;
+  a.T = n_steps(h, w) + (long long)vg.lag * (vg.Z - 1);
+  a.tables = (uint16_t*)(base + wop);
+  uint32_t* ctl = (uint32_t*)(base + wop + align256((size_t)vg.Z * h * DEEP_OUT * 2));
+  a.bar = ctl;
+  a.abort_flag = (int*)(ctl + 16);
+  a.status = d_status;
+  a.spin_limit = g_spin_limit;
+  a.hf = hf;
+  if ((rc = deep_stage(model, d_ws, stream)) != DLIC_OK) return rc;
+  launch_fill_u32(ctl, 0u, 64, stream);
+  launch_fill_u32((uint32_t*)d_status, 0u, 1, stream);
+  if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
+  g_deep_grid_used = grid;
+  timing_begin("deep_decode_kernel", stream);
+  if (launch_deep_decode(a, grid, stream) != hipSuccess) return DLIC_ERR_HIP;
+  timing_end(stream);
+  return launch_ok();
 }
 
 }  // namespace
@@ -1024,11 +1163,8 @@ dlic_status dlic_latency_probe(double* h_out, int32_t n, void* d_ws, size_t ws_b
 size_t dlic_deep_workspace(int32_t h, int32_t w, const dlic_coder* coder, int32_t hidden,
                            int32_t decode) {
   if (h <= 0 || w <= 0 || (hidden != 64 && hidden != 128)) return 0;
-  const size_t wop = align256(deep_wop_bytes(hidden));
-  if (decode < 0) return wop;  // density hook
-  if (!coder_ok(h, coder)) return 0;
-  if (decode) return wop + align256((size_t)h * DEEP_OUT * 2) + 256;
-  return wop + enc_ws_layout(h, w, coder->groups, coder->lanes_per_group, nullptr, nullptr);
+  if (decode >= 0 && !coder_ok(h, coder)) return 0;
+  return deep_ws_bytes(1, h, w, coder, hidden, decode);
 }
 
 dlic_status dlic_deep_density(const dlic_deep_model* model, const uint8_t* d_img, int32_t h,
@@ -1037,16 +1173,10 @@ dlic_status dlic_deep_density(const dlic_deep_model* model, const uint8_t* d_img
   timing_reset();
   if (!d_img || !d_ws || h <= 0 || w <= 0 || (!d_logits && !d_cf && !d_tables))
     return DLIC_ERR_ARG;
-  dlic_status rc = deep_model_ok(model);
+  const dlic_status rc = deep_model_ok(model, false);
   if (rc != DLIC_OK) return rc;
-  if (ws_bytes < dlic_deep_workspace(h, w, nullptr, model->hidden, -1)) return DLIC_ERR_CAPACITY;
-  const Consts* K = nullptr;
-  if ((rc = current_consts(&K)) != DLIC_OK) return rc;
-  if ((rc = deep_stage(model, d_ws, stream)) != DLIC_OK) return rc;
-  timing_begin("deep_density_kernel", stream);
-  launch_deep_density(K, deep_net(model, d_ws), d_img, h, w, d_cf, d_logits, d_tables, stream);
-  timing_end(stream);
-  return launch_ok();
+  return deep_density_impl(model, d_img, h, w, VolGeom{}, d_logits, d_cf, d_tables, d_ws,
+                           ws_bytes, stream);
 }
 
 dlic_status dlic_deep_encode(const dlic_deep_model* model, const dlic_coder* coder,
@@ -1056,21 +1186,10 @@ dlic_status dlic_deep_encode(const dlic_deep_model* model, const dlic_coder* cod
   timing_reset();
   if (!d_img || !d_out || !d_out_len || !d_ws || h <= 0 || w <= 0) return DLIC_ERR_ARG;
   if (!coder_ok(h, coder)) return DLIC_ERR_UNSUPPORTED;
-  dlic_status rc = deep_model_ok(model);
+  const dlic_status rc = deep_model_ok(model, false);
   if (rc != DLIC_OK) return rc;
-  if (out_cap < dlic_encode_bound(h, w, coder)) return DLIC_ERR_CAPACITY;
-  if (ws_bytes < dlic_deep_workspace(h, w, coder, model->hidden, 0)) return DLIC_ERR_CAPACITY;
-  const Consts* K = nullptr;
-  if ((rc = current_consts(&K)) != DLIC_OK) return rc;
-  const size_t wop = align256(deep_wop_bytes(model->hidden));
-  EncWs ws;
-  enc_ws_layout(h, w, coder->groups, coder->lanes_per_group, (uint8_t*)d_ws + wop, &ws);
-  if ((rc = deep_stage(model, d_ws, stream)) != DLIC_OK) return rc;
-  timing_begin("deep_density_kernel", stream);
-  launch_deep_density(K, deep_net(model, d_ws), d_img, h, w, ws.cf, nullptr, nullptr, stream);
-  timing_end(stream);
-  if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
-  return run_rans_and_pack(h, w, coder, ws.cf, ws, deep_header(model), d_out, d_out_len, stream);
+  return deep_encode_impl(model, coder, d_img, h, w, VolGeom{}, deep_header(model, nullptr),
+                          d_out, out_cap, d_out_len, d_ws, ws_bytes, stream);
 }
 
 dlic_status dlic_deep_decode(const dlic_deep_model* model, const dlic_coder* coder,
@@ -1080,45 +1199,95 @@ dlic_status dlic_deep_decode(const dlic_deep_model* model, const dlic_coder* cod
   timing_reset();
   if (!d_bits || !d_img || !d_status || !d_ws || h <= 0 || w <= 0) return DLIC_ERR_ARG;
   if (!coder_ok(h, coder)) return DLIC_ERR_UNSUPPORTED;
-  dlic_status rc = deep_model_ok(model);
+  const dlic_status rc = deep_model_ok(model, false);
   if (rc != DLIC_OK) return rc;
-  if (ws_bytes < dlic_deep_workspace(h, w, coder, model->hidden, 1)) return DLIC_ERR_CAPACITY;
-  const Consts* K = nullptr;
-  if ((rc = current_consts(&K)) != DLIC_OK) return rc;
-  // one wave per group, all workgroups resident (cooperative launch)
-  int grid = deep_decode_max_grid(model->hidden);
-  if (grid > 64) grid = 64;
-  if (grid <= 0) return DLIC_ERR_HIP;
-  if (coder->groups > grid * DEEP_WAVES) return DLIC_ERR_UNSUPPORTED;
-  const size_t wop = align256(deep_wop_bytes(model->hidden));
-  uint8_t* base = (uint8_t*)d_ws;
-  DeepDecArgs a;
-  memset(&a, 0, sizeof(a));
-  a.net = deep_net(model, d_ws);
-  a.K = K;
-  a.bits = d_bits;
-  a.n_bytes = n_bytes;
-  a.img = d_img;
-  a.H = h;
-  a.W = w;
-  a.G = coder->groups;
-  a.L = coder->lanes_per_group;
-  a.T = n_steps(h, w);
-  a.tables = (uint16_t*)(base + wop);
-  uint32_t* ctl = (uint32_t*)(base + wop + align256((size_t)h * DEEP_OUT * 2));
-  a.bar = ctl;
-  a.abort_flag = (int*)(ctl + 16);
-  a.status = d_status;
-  a.spin_limit = g_spin_limit;
-  a.hf = deep_header(model);
-  if ((rc = deep_stage(model, d_ws, stream)) != DLIC_OK) return rc;
-  launch_fill_u32(ctl, 0u, 64, stream);
-  launch_fill_u32((uint32_t*)d_status, 0u, 1, stream);
-  if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
-  timing_begin("deep_decode_kernel", stream);
-  if (launch_deep_decode(a, grid, stream) != hipSuccess) return DLIC_ERR_HIP;
-  timing_end(stream);
-  return launch_ok();
+  return deep_decode_impl(model, coder, d_bits, n_bytes, d_img, h, w, VolGeom{},
+                          deep_header(model, nullptr), d_status, d_ws, ws_bytes, stream);
+}
+
+void dlic_set_deep_decode_grid(int32_t workgroups) { g_deep_grid = workgroups > 0 ? workgroups : 0; }
+
+int32_t dlic_deep_decode_grid(void) { return g_deep_grid_used; }
+
+size_t dlic_volume_encode_bound(int32_t z, int32_t h, int32_t w, const dlic_coder* coder) {
+  if (z < 1 || z > DLIC_VOLUME_MAX_SLICES || h <= 0 || w <= 0 || !vol_coder_ok(z, h, coder))
+    return 0;
+  const dlic_coder tc = stacked_coder(coder, z);
+  return dlic_encode_bound(z * h, w, &tc);
+}
+
+size_t dlic_volume_workspace(int32_t z, int32_t h, int32_t w, const dlic_coder* coder,
+                             int32_t hidden, int32_t decode) {
+  if (z < 1 || z > DLIC_VOLUME_MAX_SLICES || h <= 0 || w <= 0 || (hidden != 64 && hidden != 128))
+    return 0;
+  if (decode >= 0 && !vol_coder_ok(z, h, coder)) return 0;
+  return deep_ws_bytes(z, h, w, coder, hidden, decode);
+}
+
+dlic_status dlic_volume_density(const dlic_deep_model* model, const uint8_t* d_vol, int32_t z,
+                                int32_t h, int32_t w, int32_t ws, float* d_logits, uint32_t* d_cf,
+                                uint16_t* d_tables, void* d_ws, size_t ws_bytes,
+                                hipStream_t stream) {
+  timing_reset();
+  if (!d_vol || !d_ws || h <= 0 || w <= 0 || (!d_logits && !d_cf && !d_tables))
+    return DLIC_ERR_ARG;
+  const dlic_status rc = deep_model_ok(model, true);
+  if (rc != DLIC_OK) return rc;
+  VolGeom vg;
+  if (!vol_geom(model, z, ws, &vg)) return DLIC_ERR_ARG;
+  return deep_density_impl(model, d_vol, h, w, vg, d_logits, d_cf, d_tables, d_ws, ws_bytes,
+                           stream);
+}
+
+dlic_status dlic_volume_encode(const dlic_deep_model* model, const dlic_coder* coder,
+                               const uint8_t* d_vol, int32_t z, int32_t h, int32_t w, int32_t ws,
+                               uint8_t* d_out, size_t out_cap, uint64_t* d_out_len, void* d_ws,
+                               size_t ws_bytes, hipStream_t stream) {
+  timing_reset();
+  if (!d_vol || !d_out || !d_out_len || !d_ws || h <= 0 || w <= 0) return DLIC_ERR_ARG;
+  const dlic_status rc = deep_model_ok(model, true);
+  if (rc != DLIC_OK) return rc;
+  VolGeom vg;
+  if (!vol_geom(model, z, ws, &vg)) return DLIC_ERR_ARG;
+  if (!vol_coder_ok(z, h, coder)) return DLIC_ERR_UNSUPPORTED;
+  return deep_encode_impl(model, coder, d_vol, h, w, vg, deep_header(model, &vg), d_out, out_cap,
+                          d_out_len, d_ws, ws_bytes, stream);
+}
+
+dlic_status dlic_volume_decode(const dlic_deep_model* model, const dlic_coder* coder,
+                               const uint8_t* d_bits, size_t n_bytes, uint8_t* d_vol, int32_t z,
+                               int32_t h, int32_t w, int32_t ws, int32_t* d_status, void* d_ws,
+                               size_t ws_bytes, hipStream_t stream) {
+  timing_reset();
+  if (!d_bits || !d_vol || !d_status || !d_ws || h <= 0 || w <= 0) return DLIC_ERR_ARG;
+  const dlic_status rc = deep_model_ok(model, true);
+  if (rc != DLIC_OK) return rc;
+  VolGeom vg;
+  if (!vol_geom(model, z, ws, &vg)) return DLIC_ERR_ARG;
+  if (!vol_coder_ok(z, h, coder)) return DLIC_ERR_UNSUPPORTED;
+  return deep_decode_impl(model, coder, d_bits, n_bytes, d_vol, h, w, vg,
+                          deep_header(model, &vg), d_status, d_ws, ws_bytes, stream);
+}
+
+dlic_status dlic_peek_volume(const uint8_t* b, size_t n, int32_t* z, int32_t* h, int32_t* ws,
+                             int32_t* k_in, dlic_coder* coder) {
+  if (!b || n < (size_t)HEADER_BYTES) return DLIC_ERR_CORRUPT;
+  if (memcmp(b, "DLIC", 4) != 0) return DLIC_ERR_CORRUPT;
+  auto u16 = [&](int o) { return (uint32_t)b[o] | ((uint32_t)b[o + 1] << 8); };
+  auto u32 = [&](int o) { return u16(o) | (u16(o + 2) << 16); };
+  if (u16(4) != 1u) return DLIC_ERR_CORRUPT;
+  const int Z = (int)(u16(6) & 0xFFFu), S = (int)(u16(6) >> 12);
+  const int HT = (int)u32(8), GT = (int)u16(26);
+  if (Z < 1 || HT % Z != 0 || GT % Z != 0) return DLIC_ERR_CORRUPT;  // not a volume stream
+  if (z) *z = Z;
+  if (h) *h = HT / Z;
+  if (ws) *ws = S;
+  if (k_in) *k_in = b[16];
+  if (coder) {
+    coder->groups = GT / Z;
+    coder->lanes_per_group = b[25];
+  }
+  return DLIC_OK;
 }
 
 double dlic_wallclock_hz(void) {

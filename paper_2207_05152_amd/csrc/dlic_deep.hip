@@ -1,14 +1,17 @@
 // The paper's own density network and head (Section II-B, Neural Network
-// Architecture): six dense layers, 12 -> H -> H -> H -> H -> H -> 256 with
+// Architecture): six dense layers, k -> H -> H -> H -> H -> H -> 256 with
 // ReLU, and a softmax over the 256 grey levels; the PMF becomes the coder's
-// cumulative table by a prefix sum (Section II-B, rANS).
+// cumulative table by a prefix sum (Section II-B, rANS).  k = 12 for images;
+// for volumes (Section IV-C, 3D Dependencies and 3D Wavefront) k = 21: the
+// 12-pixel window of the pixel's own slice and a 3 x 3 block of the slice
+// below, rows y + WS - 3 .. y + WS - 1, columns x - 1 .. x + 1.
 //
 // Arithmetic (the format; encoder and decoder run these same functions):
 //  * BF16 weights and layer inputs, FP32 accumulation on
 //    v_mfma_f32_16x16x32_bf16 (16-pixel tiles, the layout of NetBF16: slot e
 //    of lane group q of k-step s is input neuron 32 s + 16 (e / 4) + 4 q + e % 4,
-//    layer 1 takes feature 4 e + q in slot e < 3); the bias seeds the
-//    accumulator;
+//    layer 1 takes feature 4 e + q in slot e while 4 e + q < k); the bias seeds
+//    the accumulator;
 //  * table rule in FP32: m = max logit, e_v = expf(o_v - m), S = ((S0 + S1) +
 //    S2) + S3 over four blocks of 64 levels each summed in level order,
 //    r = 1 / S, p_v = e_v r, block totals T_b in level order, offsets O_0 = 0,
@@ -22,7 +25,11 @@
 // split over the four waves) and writes their tables, a grid barrier, every
 // group's wave decodes its rows' pixels of the step from those tables, a grid
 // barrier.  Weights do not fit a CU's LDS (200 KB at H = 128), so every tile
-// reads them from the L2 in operand order.
+// reads them from the L2 in operand order.  A volume is coded as its slices
+// stacked into one image with G groups per slice; its decode walks the 3-D
+// wavefront: global step t holds pixel (z, y, x) with x + 3 y + lag z = t, so
+// every slice's pixels of a step are evaluated together (lag = 0: all slices
+// in lock-step).
 #include "dlic_device.hpp"
 #include "dlic_kernels.h"
 
@@ -42,8 +49,8 @@ __host__ __device__ constexpr long long deep_off(int i, int H) {
 size_t deep_wop_bytes(int H) { return (size_t)deep_off(DEEP_LAYERS, H) * 16; }
 
 // Input index of slot e of lane group q in k-step s of layer i (-1: zero slot).
-__device__ __forceinline__ int deep_slot_input(int i, int s, int q, int e) {
-  if (i == 0) return e < 3 ? 4 * e + q : -1;
+__device__ __forceinline__ int deep_slot_input(int i, int s, int q, int e, int k_in) {
+  if (i == 0) return 4 * e + q < k_in ? 4 * e + q : -1;
   return 32 * s + 16 * (e >> 2) + 4 * q + (e & 3);
 }
 
@@ -51,7 +58,8 @@ struct DeepPackArgs {
   const uint16_t* w[DEEP_LAYERS];
 };
 
-__global__ __launch_bounds__(256) void deep_pack_kernel(int H, DeepPackArgs p, uint16_t* wop) {
+__global__ __launch_bounds__(256) void deep_pack_kernel(int H, int k_in, DeepPackArgs p,
+                                                       uint16_t* wop) {
   const long long total = deep_off(DEEP_LAYERS, H);
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
@@ -62,34 +70,32 @@ __global__ __launch_bounds__(256) void deep_pack_kernel(int H, DeepPackArgs p, u
     const int NK = deep_in(i, H) / 32;
     const int nt = blk / NK, s = blk - nt * NK;
     const int row = 16 * nt + (lane & 15), q = lane >> 4;
-    const int fan_in = i == 0 ? K_IN : H;
+    const int fan_in = i == 0 ? k_in : H;
     for (int e = 0; e < 8; ++e) {
-      const int k = deep_slot_input(i, s, q, e);
+      const int k = deep_slot_input(i, s, q, e, k_in);
       wop[idx * 8 + e] = k >= 0 ? p.w[i][(long long)row * fan_in + k] : (uint16_t)0;
     }
   }
 }
 
-void launch_deep_pack(int H, const uint16_t* const* w, void* wop, hipStream_t s) {
+void launch_deep_pack(int H, int k_in, const uint16_t* const* w, void* wop, hipStream_t s) {
   DeepPackArgs p;
   for (int i = 0; i < DEEP_LAYERS; ++i) p.w[i] = w[i];
   const long long total = deep_off(DEEP_LAYERS, H);
   const int grid = (int)((total + 255) / 256);
-  hipLaunchKernelGGL(deep_pack_kernel, dim3(grid), dim3(256), 0, s, H, p, (uint16_t*)wop);
+  hipLaunchKernelGGL(deep_pack_kernel, dim3(grid), dim3(256), 0, s, H, k_in, p, (uint16_t*)wop);
 }
 
-// One 16-pixel tile through the six layers.  Lane l holds features 4e + l/16
-// (e = 0..2) of pixel l % 16 and gets logits 16 nt + 4 (l / 16) + r of that
-// pixel in o[nt][r].
+// One 16-pixel tile through the six layers.  Lane l holds the layer-1 operand
+// of pixel l % 16 (features 4 e + l / 16 in slot e) and gets logits
+// 16 nt + 4 (l / 16) + r of that pixel in o[nt][r].
 template <int H>
-__device__ __forceinline__ void deep_run(const DeepNetArgs& d, float f0, float f1, float f2,
+__device__ __forceinline__ void deep_run(const DeepNetArgs& d, const bf16x8 x,
                                          float (&o)[DEEP_OUT / 16][4]) {
   constexpr int NT = H / 16, NK = H / 32;
   const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
   const int q = lane >> 4;
   const bf16x8* w = reinterpret_cast<const bf16x8*>(d.wop);
-  const __bf16 z = (__bf16)0.0f;
-  const bf16x8 x = {(__bf16)f0, (__bf16)f1, (__bf16)f2, z, z, z, z, z};
   float h[NT][4];
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
@@ -142,8 +148,8 @@ __device__ __forceinline__ void deep_run(const DeepNetArgs& d, float f0, float f
 // the logits land in sm[p][v].  Each output tile's accumulation is the same
 // chain of the same MFMAs as in deep_run, so the results are identical.
 template <int H>
-__device__ __forceinline__ void deep_run_wg(const DeepNetArgs& d, float f0, float f1, float f2,
-                                            bf16x8* act, float* sm) {
+__device__ __forceinline__ void deep_run_wg(const DeepNetArgs& d, const bf16x8 x, bf16x8* act,
+                                            float* sm) {
   constexpr int NT = H / 16, NK = H / 32;
   constexpr int TW = NT / DEEP_WAVES;            // hidden tiles per wave (1 or 2)
   constexpr int TO = DEEP_OUT / 16 / DEEP_WAVES;  // output tiles per wave (4)
@@ -151,8 +157,6 @@ __device__ __forceinline__ void deep_run_wg(const DeepNetArgs& d, float f0, floa
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, p = lane & 15;
   const bf16x8* w = reinterpret_cast<const bf16x8*>(d.wop);
-  const __bf16 z = (__bf16)0.0f;
-  const bf16x8 x = {(__bf16)f0, (__bf16)f1, (__bf16)f2, z, z, z, z, z};
   bf16x8 wc[MAXT][NK], wn[MAXT][NK];
   // layer 0 weights, then layer 1's in flight
 #pragma unroll
@@ -308,43 +312,56 @@ __device__ __forceinline__ uint32_t deep_F(int v, float C) {
   return (uint32_t)v + qv;
 }
 
-// Features 4e + q (e = 0..2) of pixel (y, x): scaled window values, 0 outside.
-__device__ __forceinline__ void deep_features(const Consts* __restrict__ K, const uint8_t* img,
-                                              int H, int W, int y, int x, bool valid, int q,
-                                              float& f0, float& f1, float& f2) {
-  float f[3];
+// Layer-1 operand of lane group q for pixel (z, y, x) (y, the row in slice z
+// of the stacked image): slot e holds window value 4 e + q scaled to [-1, 1],
+// 0 outside the slice (or below the first slice) and past the window.  Values
+// 0..11 are the pixel's own slice, 12..20 the slice below, row by row.
+template <int KIN>
+__device__ __forceinline__ bf16x8 deep_features(const Consts* __restrict__ K, const uint8_t* img,
+                                                int H, int W, int ws, int z, int y, int x,
+                                                bool valid, int q) {
+  const __bf16 zero = (__bf16)0.0f;
+  bf16x8 o = {zero, zero, zero, zero, zero, zero, zero, zero};
+  const uint8_t* sl = img + (long long)z * H * W;
 #pragma unroll
-  for (int e = 0; e < 3; ++e) {
+  for (int e = 0; e < (KIN + 3) / 4; ++e) {
     const int k = 4 * e + q;
-    const int yy = y + nb_dy(k), xx = x + nb_dx(k);
-    const bool in = valid && yy >= 0 && xx >= 0 && xx < W;
-    f[e] = in ? K->scale[img[(long long)yy * W + xx]] : 0.0f;
+    float f = 0.0f;
+    if (k < K_IN) {
+      const int yy = y + nb_dy(k), xx = x + nb_dx(k);
+      if (valid && yy >= 0 && xx >= 0 && xx < W) f = K->scale[sl[(long long)yy * W + xx]];
+    } else if (k < KIN) {
+      const int j = k - K_IN;
+      const int yy = y + ws - 3 + j / 3, xx = x + j % 3 - 1;
+      if (valid && z > 0 && yy >= 0 && yy < H && xx >= 0 && xx < W)
+        f = K->scale[sl[(long long)(yy - H) * W + xx]];
+    }
+    o[e] = (__bf16)f;
   }
-  f0 = f[0];
-  f1 = f[1];
-  f2 = f[2];
+  return o;
 }
 
 // Encoder side: every pixel's interval (and optionally logits / tables).
-template <int H>
+template <int H, int KIN>
 __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_density_kernel(
     const Consts* __restrict__ K, DeepNetArgs net, const uint8_t* __restrict__ img, int Hh, int W,
-    uint32_t* __restrict__ cf, float* __restrict__ logits, uint16_t* __restrict__ tables) {
+    VolGeom vg, uint32_t* __restrict__ cf, float* __restrict__ logits,
+    uint16_t* __restrict__ tables) {
   __shared__ float s_sm[DEEP_WAVES][16 * SM_ROW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = lane & 15, q = lane >> 4;
   float* sm = s_sm[wave];
-  const long long n = (long long)Hh * W;
+  const long long n = (long long)vg.Z * Hh * W;
   const long long n_tiles = (n + 15) / 16;
   for (long long tile = (long long)blockIdx.x * DEEP_WAVES + wave; tile < n_tiles;
        tile += (long long)gridDim.x * DEEP_WAVES) {
     const long long px = tile * 16 + p;
     const bool valid = px < n;
-    const int y = valid ? (int)(px / W) : 0, x = valid ? (int)(px - (long long)y * W) : 0;
-    float f0, f1, f2;
-    deep_features(K, img, Hh, W, y, x, valid, q, f0, f1, f2);
+    const int Y = valid ? (int)(px / W) : 0, x = valid ? (int)(px - (long long)Y * W) : 0;
+    const int z = Y / Hh, y = Y - z * Hh;
+    const bf16x8 xin = deep_features<KIN>(K, img, Hh, W, vg.ws, z, y, x, valid, q);
     float o[DEEP_OUT / 16][4];
-    deep_run<H>(net, f0, f1, f2, o);
+    deep_run<H>(net, xin, o);
     if (logits && valid) {
 #pragma unroll
       for (int nt = 0; nt < DEEP_OUT / 16; ++nt)
@@ -371,18 +388,30 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_density_kernel(
   }
 }
 
+template <int H, int KIN>
+static void density_at(unsigned grid, hipStream_t s, const Consts* K, const DeepNetArgs& net,
+                       const uint8_t* img, int Hh, int W, const VolGeom& vg, uint32_t* cf,
+                       float* logits, uint16_t* tables) {
+  hipLaunchKernelGGL((deep_density_kernel<H, KIN>), dim3(grid), dim3(DEEP_WAVES * 64), 0, s, K,
+                     net, img, Hh, W, vg, cf, logits, tables);
+}
+
 bool launch_deep_density(const Consts* K, const DeepNetArgs& net, const uint8_t* img, int H,
-                         int W, uint32_t* cf, float* logits, uint16_t* tables, hipStream_t s) {
-  const long long tiles = ((long long)H * W + 15) / 16;
+                         int W, const VolGeom& vg, uint32_t* cf, float* logits, uint16_t* tables,
+                         hipStream_t s) {
+  const long long tiles = ((long long)vg.Z * H * W + 15) / 16;
   long long grid = (tiles + DEEP_WAVES - 1) / DEEP_WAVES;
   if (grid > 2048) grid = 2048;
   if (grid < 1) grid = 1;
-  if (net.H == 64)
-    hipLaunchKernelGGL(deep_density_kernel<64>, dim3((unsigned)grid), dim3(DEEP_WAVES * 64), 0, s,
-                       K, net, img, H, W, cf, logits, tables);
-  else if (net.H == 128)
-    hipLaunchKernelGGL(deep_density_kernel<128>, dim3((unsigned)grid), dim3(DEEP_WAVES * 64), 0,
-                       s, K, net, img, H, W, cf, logits, tables);
+  const unsigned g = (unsigned)grid;
+  if (net.k_in == K_IN && net.H == 64)
+    density_at<64, K_IN>(g, s, K, net, img, H, W, vg, cf, logits, tables);
+  else if (net.k_in == K_IN && net.H == 128)
+    density_at<128, K_IN>(g, s, K, net, img, H, W, vg, cf, logits, tables);
+  else if (net.k_in == K_IN_3D && net.H == 64)
+    density_at<64, K_IN_3D>(g, s, K, net, img, H, W, vg, cf, logits, tables);
+  else if (net.k_in == K_IN_3D && net.H == 128)
+    density_at<128, K_IN_3D>(g, s, K, net, img, H, W, vg, cf, logits, tables);
   else
     return false;
   return true;
@@ -423,25 +452,29 @@ __device__ __forceinline__ bool grid_sync(unsigned* bar, int* abort_flag, unsign
   }
   __syncthreads();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return s_ok != 0;
+  // uniform by construction, so loops that end on it keep their barriers whole
+  return __builtin_amdgcn_readfirstlane(s_ok) != 0;
 }
 
+// 3: the stream does not fit the geometry (or is damaged); 4: another model.
 __device__ int deep_check_header(const DeepDecArgs& a) {
-  if (a.n_bytes < (unsigned long long)(HEADER_BYTES + 4LL * a.G)) return 3;
+  const int GT = a.vg.Z * a.G;
+  if (a.n_bytes < (unsigned long long)(HEADER_BYTES + 4LL * GT)) return 3;
   const uint8_t* b = a.bits;
   if (b[0] != 'D' || b[1] != 'L' || b[2] != 'I' || b[3] != 'C') return 3;
-  if (rd16(b + 4) != 1u) return 3;
-  if (rd32(b + 8) != (uint32_t)a.H || rd32(b + 12) != (uint32_t)a.W) return 3;
-  if (b[16] != K_IN || b[19] != SKEW || b[24] != PROB_BITS) return 3;
-  if (b[25] != (uint8_t)a.L || rd16(b + 26) != (uint32_t)a.G) return 3;
+  if (rd16(b + 4) != 1u || rd16(b + 6) != (uint32_t)a.hf.flags) return 3;
+  if (rd32(b + 8) != (uint32_t)(a.vg.Z * a.H) || rd32(b + 12) != (uint32_t)a.W) return 3;
+  if (b[19] != SKEW || b[24] != PROB_BITS) return 3;
+  if (b[25] != (uint8_t)a.L || rd16(b + 26) != (uint32_t)GT) return 3;
   const uint64_t fp = (uint64_t)rd32(b + 28) | ((uint64_t)rd32(b + 32) << 32);
-  if (b[17] != 0 || b[18] != (uint8_t)a.hf.dtype || rd16(b + 20) != (uint32_t)a.hf.h1 ||
-      rd16(b + 22) != (uint32_t)a.hf.h2 || fp != a.hf.fingerprint)
+  if (b[16] != (uint8_t)a.hf.k_in || b[17] != 0 || b[18] != (uint8_t)a.hf.dtype ||
+      rd16(b + 20) != (uint32_t)a.hf.h1 || rd16(b + 22) != (uint32_t)a.hf.h2 ||
+      fp != a.hf.fingerprint)
     return 4;
   return 0;
 }
 
-template <int H>
+template <int H, int KIN>
 __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArgs a) {
   __shared__ float s_sm[16 * SM_ROW];
   __shared__ bf16x8 s_act[2 * (H / 32) * 64];
@@ -449,24 +482,26 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = lane & 15, q = lane >> 4;
   float* sm = s_sm;
-  const int gw = blockIdx.x * DEEP_WAVES + wave;
-  const int NW = gridDim.x * DEEP_WAVES;
   if (threadIdx.x == 0) s_err = deep_check_header(a);
   __syncthreads();
-  const int err = s_err;
+  const int err = __builtin_amdgcn_readfirstlane(s_err);
+  const int Z = a.vg.Z, lag = a.vg.lag;
+  const int HT = Z * a.H, GT = Z * a.G;
+  const long long T2 = (long long)a.W + SKEW * (a.H - 1);  // steps of one slice
   // the group this wave decodes, if any: its lanes' states live in registers
-  const int g = gw;
-  const bool coder = err == 0 && g < a.G;
-  int r0 = 0, R = 0, J = 0;
+  const int g = blockIdx.x * DEEP_WAVES + wave;
+  const bool coder = err == 0 && g < GT;
+  int r0 = 0, R = 0, J = 0, zg = 0;
   uint32_t n_words = 0, Pw = 0, x = RANS_L;
   const uint16_t* gw16 = nullptr;
   bool bad = false;
   if (coder) {
-    r0 = (int)(((long long)g * a.H) / a.G);
-    R = (int)(((long long)(g + 1) * a.H) / a.G) - r0;
+    r0 = group_row(g, HT, GT);
+    R = group_row(g + 1, HT, GT) - r0;
     J = (R + a.L - 1) / a.L;
+    zg = r0 / a.H;  // every group lies in one slice
     unsigned long long before = 0, total = 0;
-    for (int i = lane; i < a.G; i += 64) {
+    for (int i = lane; i < GT; i += 64) {
       const uint32_t c = rd32(a.bits + HEADER_BYTES + 4 * i);
       total += c;
       if (i < g) before += c;
@@ -476,9 +511,9 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
       before += __shfl_xor(before, sh);
     }
     n_words = rd32(a.bits + HEADER_BYTES + 4 * g);
-    bad = (unsigned long long)(HEADER_BYTES + 4LL * a.G) + 2ull * total != a.n_bytes ||
+    bad = (unsigned long long)(HEADER_BYTES + 4LL * GT) + 2ull * total != a.n_bytes ||
           n_words < 2u * (uint32_t)a.L;
-    gw16 = reinterpret_cast<const uint16_t*>(a.bits + HEADER_BYTES + 4LL * a.G + 2ull * before);
+    gw16 = reinterpret_cast<const uint16_t*>(a.bits + HEADER_BYTES + 4LL * GT + 2ull * before);
     if (!bad && lane < a.L) x = (uint32_t)gw16[2 * lane] | ((uint32_t)gw16[2 * lane + 1] << 16);
     Pw = 2u * (uint32_t)a.L;
   }
@@ -486,48 +521,61 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
   unsigned k_bar = 0;
   bool alive = err == 0;
   for (long long t = 0; t < a.T && alive; ++t) {
-    // ---- the step's pixels through the network, one 16-row tile per wave
-    const int y_lo = (int)(t - a.W + 1 > 0 ? (t - a.W + 1 + SKEW - 1) / SKEW : 0);
-    const int y_hi = (int)(t / SKEW < a.H - 1 ? t / SKEW : a.H - 1);
-    const int n_act = y_hi - y_lo + 1;
-    // one tile per workgroup, its layers split over the four waves
-    for (int tile = blockIdx.x; tile * 16 < n_act; tile += gridDim.x) {
-      const int y = y_lo + 16 * tile + p;
-      const bool valid = y <= y_hi;
-      const int xx = valid ? (int)(t - (long long)SKEW * y) : 0;
-      float f0, f1, f2;
-      deep_features(a.K, a.img, a.H, a.W, valid ? y : 0, xx, valid, q, f0, f1, f2);
-      deep_run_wg<H>(a.net, f0, f1, f2, s_act, sm);
-      if (wave == 0) {
-        const DeepBlock blk = deep_softmax_lds(sm);
-        const float* row = sm + p * SM_ROW + 64 * q;
-        float L = 0.0f;
-        uint16_t* tab = a.tables + (long long)(valid ? y : 0) * DEEP_OUT;
+    // ---- the step's pixels through the network: tile k of the step is the
+    // k-th 16-row block of the active rows, slice by slice; one tile per
+    // workgroup, its layers split over the four waves
+    int z_lo = 0, z_hi = Z - 1;
+    if (lag > 0) {
+      z_hi = (int)(t / lag < Z - 1 ? t / lag : Z - 1);
+      z_lo = (int)(t - T2 + 1 > 0 ? (t - T2 + lag) / lag : 0);
+    }
+    int k = blockIdx.x, base = 0;
+    for (int z = z_lo; z <= z_hi; ++z) {
+      const long long tz = t - (long long)lag * z;  // the slice's own step, 0 <= tz < T2
+      const int y_lo = (int)(tz - a.W + 1 > 0 ? (tz - a.W + SKEW) / SKEW : 0);
+      const int y_hi = (int)(tz / SKEW < a.H - 1 ? tz / SKEW : a.H - 1);
+      const int n_act = y_hi - y_lo + 1;
+      const int nt = n_act > 0 ? (n_act + 15) / 16 : 0;
+      for (; k < base + nt; k += gridDim.x) {
+        const int y = y_lo + 16 * (k - base) + p;
+        const bool valid = y <= y_hi;
+        const int xx = valid ? (int)(tz - (long long)SKEW * y) : 0;
+        const bf16x8 xin =
+            deep_features<KIN>(a.K, a.img, a.H, a.W, a.vg.ws, z, valid ? y : 0, xx, valid, q);
+        deep_run_wg<H>(a.net, xin, s_act, sm);
+        if (wave == 0) {
+          const DeepBlock blk = deep_softmax_lds(sm);
+          const float* row = sm + p * SM_ROW + 64 * q;
+          float L = 0.0f;
+          uint16_t* tab = a.tables + (long long)(z * a.H + (valid ? y : 0)) * DEEP_OUT;
 #pragma unroll 4
-        for (int k = 0; k < 64; ++k) {
-          const int v = 64 * q + k;
-          if (valid) tab[v] = (uint16_t)(v == 0 ? 0u : deep_F(v, blk.off + L));
-          L = L + row[k];
+          for (int kk = 0; kk < 64; ++kk) {
+            const int v = 64 * q + kk;
+            if (valid) tab[v] = (uint16_t)(v == 0 ? 0u : deep_F(v, blk.off + L));
+            L = L + row[kk];
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
+      base += nt;
     }
     alive = grid_sync(a.bar, a.abort_flag, k_bar, a.spin_limit);
     if (!alive) break;
     // ---- each group decodes its rows' pixels of the step
-    if (coder && !bad) {
+    const long long tg = t - (long long)lag * zg;  // the step within the group's slice
+    if (coder && !bad && tg >= 0 && tg < T2) {
       for (int j = 0; j < J; ++j) {
         const int rr = j * a.L + lane;
-        const int y = r0 + rr;
-        const long long xc = t - (long long)SKEW * y;
+        const int Y = r0 + rr;
+        const long long xc = tg - (long long)SKEW * (Y - zg * a.H);
         const bool act = lane < a.L && rr < R && xc >= 0 && xc < a.W;
         if (__ballot(act) == 0ull) continue;
         const uint32_t slot = x & 0xFFFFu;
-        const uint16_t* tab = a.tables + (long long)(act ? y : 0) * DEEP_OUT;
+        const uint16_t* tab = a.tables + (long long)(act ? Y : 0) * DEEP_OUT;
         // bucket of 16 levels from the boundaries F(16 k), then the level in it
         int nb = 0;
 #pragma unroll
-        for (int k = 1; k < 16; ++k) nb += ((uint32_t)tab[16 * k] <= slot) ? 1 : 0;
+        for (int kk = 1; kk < 16; ++kk) nb += ((uint32_t)tab[16 * kk] <= slot) ? 1 : 0;
         uint32_t Fl[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) Fl[i] = tab[16 * nb + i];
@@ -556,7 +604,7 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
         }
         if (act) x = ren ? ((xd << 16) | wv) : xd;
         Pw += (uint32_t)__popcll(m);
-        if (act) a.img[(long long)y * a.W + xc] = (uint8_t)v;
+        if (act) a.img[(long long)Y * a.W + xc] = (uint8_t)v;
       }
     }
     alive = grid_sync(a.bar, a.abort_flag, k_bar, a.spin_limit);
@@ -577,30 +625,40 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
   }
 }
 
-int deep_decode_max_grid(int H) {
-  int dev = 0, cus = 0, per_cu = 0;
+template <int H, int KIN>
+static int decode_residency() {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, deep_decode_kernel<H, KIN>,
+                                                   DEEP_WAVES * 64, 0) != hipSuccess)
+    return 0;
+  return per_cu;
+}
+
+int deep_decode_max_grid(int H, int k_in) {
+  int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  const hipError_t e =
-      H == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, deep_decode_kernel<64>,
-                                                             DEEP_WAVES * 64, 0)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, deep_decode_kernel<128>,
-                                                             DEEP_WAVES * 64, 0);
-  if (e != hipSuccess) return 0;
+  int per_cu = 0;
+  if (k_in == K_IN)
+    per_cu = H == 64 ? decode_residency<64, K_IN>() : decode_residency<128, K_IN>();
+  else
+    per_cu = H == 64 ? decode_residency<64, K_IN_3D>() : decode_residency<128, K_IN_3D>();
   return cus * per_cu;
 }
 
 hipError_t launch_deep_decode(const DeepDecArgs& a, int grid, hipStream_t s) {
   DeepDecArgs args = a;
   void* kargs[] = {&args};
-  if (a.net.H == 64)
-    return hipLaunchCooperativeKernel((const void*)deep_decode_kernel<64>, dim3(grid),
-                                      dim3(DEEP_WAVES * 64), kargs, 0, s);
-  if (a.net.H == 128)
-    return hipLaunchCooperativeKernel((const void*)deep_decode_kernel<128>, dim3(grid),
-                                      dim3(DEEP_WAVES * 64), kargs, 0, s);
-  return hipErrorInvalidValue;
+  const void* fn = nullptr;
+  if (a.net.k_in == K_IN)
+    fn = a.net.H == 64 ? (const void*)deep_decode_kernel<64, K_IN>
+                       : (const void*)deep_decode_kernel<128, K_IN>;
+  else if (a.net.k_in == K_IN_3D)
+    fn = a.net.H == 64 ? (const void*)deep_decode_kernel<64, K_IN_3D>
+                       : (const void*)deep_decode_kernel<128, K_IN_3D>;
+  if (!fn || (a.net.H != 64 && a.net.H != 128)) return hipErrorInvalidValue;
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(DEEP_WAVES * 64), kargs, 0, s);
 }
 
 }  // namespace dlic

@@ -402,10 +402,10 @@ __device__ __forceinline__ void pack_group_part(const uint16_t* __restrict__ wor
     if (threadIdx.x == 0) {
       out[0] = 'D'; out[1] = 'L'; out[2] = 'I'; out[3] = 'C';
       put_u16(out + 4, 1u);
-      put_u16(out + 6, 0u);
+      put_u16(out + 6, (uint32_t)hf.flags);
       put_u32(out + 8, (uint32_t)H);
       put_u32(out + 12, (uint32_t)W);
-      out[16] = (uint8_t)K_IN;
+      out[16] = (uint8_t)hf.k_in;
       out[17] = (uint8_t)hf.n_mix;
       out[18] = (uint8_t)hf.dtype;
       out[19] = (uint8_t)SKEW;

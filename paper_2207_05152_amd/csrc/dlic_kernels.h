@@ -12,6 +12,8 @@ struct HeaderFields {
   int dtype, h1, h2;
   uint64_t fingerprint;
   int n_mix = N_MIX;  // 0: the six-layer softmax-256 network
+  int k_in = K_IN;    // window size: 12, or 21 with the slice below (volumes)
+  int flags = 0;      // volumes: slices in bits 0..11, window shift in bits 12..15
 };
 
 // Decoder limits: rows per group, and the per-group stream ring in LDS.
@@ -124,29 +126,40 @@ int probe_links(int probe);
 // ---- six-layer softmax-256 network (the paper's own head) -----------------
 constexpr int DEEP_LAYERS = 6;
 constexpr int DEEP_OUT = 256;
+constexpr int K_IN_3D = 21;   // the 12-pixel window plus 3 x 3 pixels of the slice below
 struct DeepNetArgs {
   int H;                        // hidden width (64 or 128)
+  int k_in;                     // K_IN, or K_IN_3D for volumes
   const void* wop;              // weights in MFMA operand order (deep_pack_weights)
   const float* b[DEEP_LAYERS];  // FP32 biases
 };
-// Bytes of the operand-order weights of a 12 -> H x 5 -> 256 net.
+// Geometry of what the deep kernels code: Z slices of H x W stacked into one
+// image of Z H rows (an image: Z = 1).  Slice z trails z - 1 by lag wavefront
+// steps; the window reaches rows y + ws - 3 .. y + ws - 1 of the slice below.
+struct VolGeom {
+  int Z = 1, ws = 0, lag = 0;
+};
+// Bytes of the operand-order weights of a k_in -> H x 5 -> 256 net (k_in <= 32).
 size_t deep_wop_bytes(int H);
 // Rearrange row-major BF16 weights (w[i]: [out][in]) into operand order at wop.
-void launch_deep_pack(int H, const uint16_t* const* w, void* wop, hipStream_t s);
+void launch_deep_pack(int H, int k_in, const uint16_t* const* w, void* wop, hipStream_t s);
 // Encoder density: packed interval c | (f - 1) << 16 of every pixel (raster
-// order) by the softmax table rule; optionally the FP32 logits [n][256] and the
-// tables F(0..255) [n][256] (u16).  False for an unsupported width.
+// order of the stacked image) by the softmax table rule; optionally the FP32
+// logits [n][256] and the tables F(0..255) [n][256] (u16).  H: rows per slice.
+// False for an unsupported width or window.
 bool launch_deep_density(const Consts* K, const DeepNetArgs& net, const uint8_t* img, int H,
-                         int W, uint32_t* cf, float* logits, uint16_t* tables, hipStream_t s);
+                         int W, const VolGeom& vg, uint32_t* cf, float* logits,
+                         uint16_t* tables, hipStream_t s);
 struct DeepDecArgs {
   DeepNetArgs net;
   const Consts* K;
   const uint8_t* bits;
   unsigned long long n_bytes;
   uint8_t* img;
-  int H, W, G, L;
-  long long T;
-  uint16_t* tables;   // [H][256]: F(0..255) of each row's pixel of the current step
+  int H, W, G, L;     // H: rows per slice; G: groups per slice
+  VolGeom vg;
+  long long T;        // W + 3 (H - 1) + lag (Z - 1)
+  uint16_t* tables;   // [Z H][256]: F(0..255) of each row's pixel of the current step
   unsigned* bar;      // grid barrier counter, cleared before launch
   int* abort_flag;    // cleared before launch
   int* status;
@@ -155,7 +168,7 @@ struct DeepDecArgs {
 };
 // Cooperative launch of the per-step decoder; returns the hipError of the launch.
 hipError_t launch_deep_decode(const DeepDecArgs& a, int grid, hipStream_t s);
-int deep_decode_max_grid(int H);
+int deep_decode_max_grid(int H, int k_in);
 constexpr int DEEP_WAVES = 4;  // waves per workgroup of the deep kernels
 
 // Training: waves per workgroup of the FP32 / FP64 loss-and-gradient kernel.

@@ -65,6 +65,28 @@ def test_bounds_and_workspace():
     assert dl.dlic_encode_bound(257, 10, dl.dlic_coder(1, 32)) == 0     # > 256 rows per group
 
 
+def test_volume_bound_workspace_and_peek():
+    # the stacked image's bound: z h rows, z G groups
+    c = dl.dlic_coder(8, 8)
+    L = dl.lib()
+    assert L.dlic_volume_encode_bound(35, 256, 256, ctypes.byref(c)) == \
+        36 + 4 * 8 * 35 + 2 * (35 * 256 * 256 + 2 * 8 * 8 * 35)
+    assert L.dlic_volume_encode_bound(0, 256, 256, ctypes.byref(c)) == 0
+    assert L.dlic_volume_encode_bound(4096, 256, 256, ctypes.byref(c)) == 0
+    assert L.dlic_volume_encode_bound(200, 256, 256, ctypes.byref(c)) == 0   # 1600 groups
+    assert L.dlic_volume_workspace(35, 256, 256, ctypes.byref(c), 128, 1) >= 35 * 256 * 512
+    assert L.dlic_volume_workspace(35, 256, 256, ctypes.byref(c), 96, 1) == 0
+    hdr = oracle.pack_header(35 * 256, 256, 35 * 8, 8, dtype=1, h1=128, h2=128, n_mix=0, k_in=21,
+                             flags=oracle.volume.volume_flags(35, 2))
+    p = dl.dlic_peek_volume(hdr)
+    assert (p["z"], p["h"], p["ws"], p["k_in"], p["coder"].groups, p["coder"].lanes_per_group) == \
+        (35, 256, 2, 21, 8, 8)
+    with pytest.raises(dl.DlicError):   # an image's header holds no slice count
+        dl.dlic_peek_volume(oracle.pack_header(256, 256, 8, 8))
+    with pytest.raises(dl.DlicError):   # rows not a multiple of the slices
+        dl.dlic_peek_volume(oracle.pack_header(257, 256, 35, 8, flags=35))
+
+
 def test_peek_header_reads_oracle_header():
     hdr = oracle.pack_header(1536, 2048, 8, 32, dtype=0, h1=64, h2=64, fp=0xFEEDFACE01234567)
     raw = hdr + bytes(4 * 8)

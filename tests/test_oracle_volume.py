@@ -132,3 +132,20 @@ def test_length_near_ideal_and_model_check():
     other = _layers(H=16, seed=22)
     with pytest.raises(ValueError):
         vo.decode_volume(buf, other)
+
+
+def test_twelve_input_network_codes_slices_alone():
+    # 12 inputs: each slice's body is its 2-D body; no lag, WS must be 0
+    l2 = _layers(H=16, seed=31, k_in=12)
+    vol = synth.mri_volume(8, depth=2, size=12)
+    buf = vo.encode_volume(vol, l2, 1, 3, 0)
+    hdr = oracle.parse_header(buf)
+    assert hdr["k_in"] == 12 and hdr["flags"] == 2
+    b0, b1 = (sm.encode_image_softmax(vol[z], l2, 1, 3) for z in range(2))
+    s0, s1 = oracle.split_streams(b0, 1)[0], oracle.split_streams(b1, 1)[0]
+    assert buf[oracle.HEADER_SIZE:] == (np.asarray([len(s0), len(s1)], "<u4").tobytes()
+                                        + np.asarray(list(s0) + list(s1), "<u2").tobytes())
+    assert np.array_equal(vo.decode_volume(buf, l2), vol)
+    assert vo.lag_of(12, 0) == 0 and vo.n_steps_3d(5, 12, 12, 0, k_in=12) == 12 + 33
+    with pytest.raises(ValueError):
+        vo.encode_volume(vol, l2, 1, 3, 1)
