@@ -414,6 +414,64 @@ def deep_sweep(dl, torch, img, H, W, hidden=128, layout=(48, 32), reps=2):
             "decode_us_per_step": dcd * 1e3 / (W + 3 * H - 3)}
 
 
+def volume_sweep(dl, torch, hidden=128, Z=35, size=256, layout=(8, 8), shifts=(0, 1, 2), reps=2):
+    """Volumes (3-D window and 3-D wavefront) on a 256x256x35 phantom scan, the six-layer
+    network with 21 inputs: encode and decode kernel times per window shift, MPix/s, bpp,
+    the step at which the first slice is complete; and the same scan with a 12-input
+    network, once with all slices in one 3-D wavefront and once slice by slice through the
+    image decoder (outside the timed region of the headline step)."""
+    import synth
+    vol = torch.from_numpy(synth.mri_volume(2024, depth=Z, size=size)).cuda()
+    n_px = vol.numel()
+    coder = dl.dlic_coder(*layout)
+    T2 = size + 3 * (size - 1)
+
+    def run(m, ws):
+        dl.dlic_set_timing(True)
+        kt = {}
+        for r in range(reps + 1):
+            bits = dl.volume_encode(vol, m, coder, ws)
+            ke = dict(dl.dlic_kernel_times())
+            dec, st = dl.volume_decode(bits, m, check=False)
+            kd = dict(dl.dlic_kernel_times())
+            if r:
+                for k, v in list(ke.items()) + list(kd.items()):
+                    kt.setdefault(k, []).append(v)
+        torch.cuda.synchronize()
+        dl.dlic_set_timing(False)
+        assert st == 0 and torch.equal(dec, vol), "volume round trip"
+        avg = {k: float(np.mean(v)) for k, v in kt.items()}
+        enc = avg["deep_density_kernel"] + avg["rans_encode_kernel"] + avg["pack_kernel"]
+        dcd = avg["deep_decode_kernel"]
+        lag = max(0, 3 * ws - 1) if m.k_in == 21 else 0
+        T = T2 + lag * (Z - 1)
+        return {"kernel_ms": avg, "encode_mpix_s": n_px / enc / 1e3,
+                "decode_mpix_s": n_px / dcd / 1e3, "decode_ms": dcd,
+                "bpp_total": 8.0 * bits.numel() / n_px, "lag": lag, "steps": T,
+                "first_slice_steps": T2, "decode_grid": dl.dlic_deep_decode_grid(),
+                "decode_us_per_step": dcd * 1e3 / T}
+
+    m3 = dl.DeepModel(synth.xavier_deep(hidden, 3, k_in=21), "cuda:0")
+    out = {"workload": f"{size}x{size}x{Z} phantom scan (seed 2024), six dense layers "
+                       f"21-{hidden}x5-256 with a softmax over 256 levels, BF16 weights (Glorot "
+                       f"seed 3), {layout[0]} groups x {layout[1]} lanes per slice",
+           "params": int(sum(W_.size + b.size for W_, b in synth.xavier_deep(hidden, 3, k_in=21))),
+           "window_shift": {}}
+    for ws in shifts:
+        out["window_shift"][str(ws)] = run(m3, ws)
+    m2 = dl.DeepModel(synth.xavier_deep(hidden, 3, k_in=12), "cuda:0")
+    out["slices_in_one_wavefront_12_inputs"] = run(m2, 0)
+    # the same slices one image at a time through the image decoder
+    bits = [dl.deep_encode(vol[z], m2, coder) for z in range(Z)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for z in range(Z):
+        dec, st = dl.deep_decode(bits[z], m2, check=False)
+    torch.cuda.synchronize()
+    out["slice_by_slice_12_inputs_decode_ms"] = (time.perf_counter() - t0) * 1e3
+    return out
+
+
 def _phantom_job(seed):
     import synth
     return synth.mri_phantom(seed, 256)
@@ -652,6 +710,7 @@ def main():
         res["batch"] = batch_sweep(dl, torch)
         res["training"] = training_sweep(dl, torch)
         res["softmax_net"] = deep_sweep(dl, torch, img, H, W)
+        res["volume"] = volume_sweep(dl, torch)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(img_np, weights, args.groups, args.lanes)
     print(json.dumps(res))

@@ -383,8 +383,8 @@ dlic_status deep_decode_impl(const dlic_deep_model* model, const dlic_coder* cod
   int grid = deep_step_tiles(vg.Z, h, w);
   if (grid > 256) grid = 256;
   if (grid < 64) grid = 64;
-  if (grid < (GT + DEEP_WAVES - 1) / DEEP_WAVES) grid = (GT + DEEP_WAVES - 1) / DEEP_WAVES;
   if (g_deep_grid > 0) grid = g_deep_grid;
+  if (grid < (GT + DEEP_WAVES - 1) / DEEP_WAVES) grid = (GT + DEEP_WAVES - 1) / DEEP_WAVES;
   if (grid > resident) grid = resident;
   if (GT > grid * DEEP_WAVES) return DLIC_ERR_UNSUPPORTED;
   const size_t wop = align256(deep_wop_bytes(model->hidden));

@@ -427,8 +427,11 @@ __device__ __forceinline__ uint32_t rd16(const uint8_t* p) {
 }
 
 // Grid barrier over a cooperative launch: a counter that only grows (barrier
-// k completes when it reaches k * gridDim.x).  The wait is bounded; giving up
-// sets the abort flag, which ends every workgroup's walk.
+// k completes when it reaches k * gridDim.x).  One thread per workgroup
+// arrives with a release add and polls with plain (relaxed) loads, then takes
+// one acquire fence: an acquire per poll would invalidate the cache the
+// network's weights are read through on every spin.  The wait is bounded;
+// giving up sets the abort flag, which ends every workgroup's walk.
 __device__ __forceinline__ bool grid_sync(unsigned* bar, int* abort_flag, unsigned& k,
                                           uint32_t limit) {
   __shared__ int s_ok;
@@ -439,7 +442,7 @@ __device__ __forceinline__ bool grid_sync(unsigned* bar, int* abort_flag, unsign
     __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t spins = 0;
     int ok = 1;
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
           ++spins > limit) {
         __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -448,10 +451,10 @@ __device__ __forceinline__ bool grid_sync(unsigned* bar, int* abort_flag, unsign
       }
       __builtin_amdgcn_s_sleep(1);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_ok = ok;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   // uniform by construction, so loops that end on it keep their barriers whole
   return __builtin_amdgcn_readfirstlane(s_ok) != 0;
 }
