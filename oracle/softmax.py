@@ -1,5 +1,5 @@
 """The paper's own density network: six dense layers and a softmax over the 256
-grey levels (oracle; test infrastructure).
+grey levels, or the 4096 levels of 12-bit images (oracle; test infrastructure).
 
 Paper passages followed:
   * Section II-B (Neural Network Architecture): a dense network of six dense
@@ -10,6 +10,8 @@ Paper passages followed:
     coder, so that encoder and decoder round identically.
   * Section II-B (rANS): the coder consumes the PDF as a cumulative integer
     table.
+  * Section IV-C (Higher Bit Depth): 12-bit MRI samples take 4096 output
+    neurons (the mixture head did not converge there).
 
 Readings where the paper is silent (the format's choices):
   * the six layers are 12 -> H -> H -> H -> H -> H -> 256 with ReLU after the
@@ -27,7 +29,14 @@ Readings where the paper is silent (the format's choices):
     F(v) = v + min(M', floor(C_v M')) for v = 1..255, F(0) = 0, F(256) = M.
     C is non-decreasing (every addend is >= 0 and FP32 addition is monotone,
     and O_{b+1} = O_b + T_b >= O_b + L of any level of block b), so every
-    frequency F(v + 1) - F(v) is at least 1 and they sum to M.
+    frequency F(v + 1) - F(v) is at least 1 and they sum to M;
+  * N = 2^d levels for d-bit samples (d = 8 or 12): the output layer has N
+    neurons, inputs are scaled by (2v - (N - 1)) / (N - 1), and the rule runs
+    over N / 64 blocks of 64 levels (S and the offsets summed left to right)
+    with M' = M - N; 12-bit streams set the high nibble of the header's dtype
+    byte to d - 8 = 4.  The 16-bit table then reserves N / M = 1/16 of the
+    mass for the floor of one count per level: at most -log2(15/16) = 0.093
+    bits per pixel above the network's own rate.
 
 Parity: the network against PyTorch FP64 linear layers (library routine) and
 the zero-weight identity; the softmax against closed forms (equal logits give
@@ -88,47 +97,63 @@ def ideal_bits_softmax(logits, v) -> float:
     return float(-lp.sum() / np.log(2.0))
 
 
+def levels_of(depth: int) -> int:
+    return 1 << depth
+
+
+def depth_of_levels(n: int) -> int:
+    if n not in (256, 4096):
+        raise ValueError("256 or 4096 output levels")
+    return 8 if n == 256 else 12
+
+
 def table_softmax_exact(logits) -> np.ndarray:
-    """F(v) = v + min(M', floor(C_v M')) with C from the FP64 PMF: (n, 257) int64."""
+    """F(v) = v + min(M', floor(C_v M')) with C from the FP64 PMF, M' = M - N:
+    (n, N + 1) int64."""
     p = softmax_pmf(logits)
+    N = p.shape[-1]
+    mp = M_TOTAL - N
     C = np.concatenate([np.zeros((p.shape[0], 1)), np.cumsum(p, axis=-1)], axis=-1)
-    v = np.arange(N_LEVELS + 1)
-    F = v + np.minimum(M_PRIME, np.floor(C * M_PRIME)).astype(np.int64)
+    v = np.arange(N + 1)
+    F = v + np.minimum(mp, np.floor(C * mp)).astype(np.int64)
     F[:, 0] = 0
-    F[:, N_LEVELS] = M_TOTAL
+    F[:, N] = M_TOTAL
     return F
 
 
 def table_softmax32(logits32) -> np.ndarray:
-    """The format's FP32 table rule (module header) on FP32 logits: (n, 257) int64.
+    """The format's FP32 table rule (module header) on FP32 logits over N = 256 or
+    4096 levels: (n, N + 1) int64.
 
     Every operation is one FP32 operation in the stated order; the exponential
     is the correctly rounded FP32 value of the exact one (through FP64)."""
     o = np.asarray(logits32, dtype=np.float32)
-    n = o.shape[0]
+    n, N = o.shape
+    depth_of_levels(N)
+    mp = M_TOTAL - N
     m = o.max(axis=-1, keepdims=True)
     d = (o - m).astype(np.float32)                       # one FP32 subtraction
     e = np.exp(d.astype(np.float64)).astype(np.float32)
     S = np.zeros(n, dtype=np.float32)
-    for b in range(N_LEVELS // BLOCK):
+    for b in range(N // BLOCK):
         sb = np.zeros(n, dtype=np.float32)
         for v in range(BLOCK * b, BLOCK * (b + 1)):
             sb = (sb + e[:, v]).astype(np.float32)
         S = sb if b == 0 else (S + sb).astype(np.float32)
     r = (np.float32(1.0) / S).astype(np.float32)
     p = (e * r[:, None]).astype(np.float32)
-    C = np.zeros((n, N_LEVELS + 1), dtype=np.float32)
+    C = np.zeros((n, N + 1), dtype=np.float32)
     off = np.zeros(n, dtype=np.float32)
-    for b in range(N_LEVELS // BLOCK):
+    for b in range(N // BLOCK):
         run = np.zeros(n, dtype=np.float32)
         for v in range(BLOCK * b, BLOCK * (b + 1)):
             C[:, v] = (off + run).astype(np.float32)
             run = (run + p[:, v]).astype(np.float32)
         off = (off + run).astype(np.float32)
-    q = np.floor((C * np.float32(M_PRIME)).astype(np.float32)).astype(np.int64)
-    F = np.arange(N_LEVELS + 1) + np.minimum(M_PRIME, q)
+    q = np.floor((C * np.float32(mp)).astype(np.float32)).astype(np.int64)
+    F = np.arange(N + 1) + np.minimum(mp, q)
     F[:, 0] = 0
-    F[:, N_LEVELS] = M_TOTAL
+    F[:, N] = M_TOTAL
     return F
 
 
@@ -146,13 +171,25 @@ def stored_fingerprint(layers) -> int:
     return fingerprint(arrays)
 
 
+def header_dtype(depth: int) -> int:
+    """The dtype byte of a softmax-network stream: BF16 (1), the depth above 8 in
+    the high nibble."""
+    return 1 | ((depth - 8) << 4)
+
+
+def net_depth(layers) -> int:
+    return depth_of_levels(int(np.asarray(layers[-1][0]).shape[0]))
+
+
 def cf_softmax_image(img, layers, logits32=None):
     """(c, f) of every pixel's value by the FP32 rule, raster order.  logits32: FP32
-    logits to apply the rule to (default: the FP32 rounding of the oracle's)."""
+    logits to apply the rule to (default: the FP32 rounding of the oracle's).  The
+    bit depth is the network's: 2^d outputs."""
     from .window import causal_features
-    img = np.asarray(img, dtype=np.uint8)
+    d = net_depth(layers)
+    img = np.asarray(img, dtype=np.uint8 if d == 8 else np.uint16)
     if logits32 is None:
-        logits32 = deep_forward_bf16(causal_features(img).reshape(-1, 12), layers).astype(np.float32)
+        logits32 = deep_forward_bf16(causal_features(img, d).reshape(-1, 12), layers).astype(np.float32)
     F = table_softmax32(logits32)
     v = img.reshape(-1).astype(np.int64)
     rows = np.arange(v.size)
@@ -162,7 +199,8 @@ def cf_softmax_image(img, layers, logits32=None):
 def encode_image_softmax(img, layers, groups, lanes) -> bytes:
     from .container import assemble, pack_header
     from .rans import canonical_order, rans_encode
-    img = np.asarray(img, dtype=np.uint8)
+    d = net_depth(layers)
+    img = np.asarray(img, dtype=np.uint8 if d == 8 else np.uint16)
     h, w = img.shape
     c, f = cf_softmax_image(img, layers)
     streams = []
@@ -170,7 +208,7 @@ def encode_image_softmax(img, layers, groups, lanes) -> bytes:
         idx = [y * w + x for (y, x, _) in grp]
         streams.append(rans_encode([(c[i], f[i]) for i in idx], [ln for (_, _, ln) in grp], lanes))
     H = np.asarray(layers[0][0]).shape[0]
-    hdr = pack_header(h, w, groups, lanes, dtype=1, h1=H, h2=H, n_mix=0,
+    hdr = pack_header(h, w, groups, lanes, dtype=header_dtype(d), h1=H, h2=H, n_mix=0,
                       fp=stored_fingerprint(layers))
     return assemble(hdr, streams)
 
@@ -180,14 +218,16 @@ def decode_image_softmax(buf: bytes, layers) -> np.ndarray:
     from .rans import canonical_order, rans_decode
     from .window import pixel_features
     hdr = parse_header(buf)
-    if hdr["n_mix"] != 0 or hdr["fingerprint"] != stored_fingerprint(layers):
+    d = net_depth(layers)
+    if (hdr["n_mix"] != 0 or hdr["dtype"] != header_dtype(d)
+            or hdr["fingerprint"] != stored_fingerprint(layers)):
         raise ValueError("stream was coded with another model")
     h, w, groups, lanes = hdr["h"], hdr["w"], hdr["groups"], hdr["lanes"]
-    img = np.zeros((h, w), dtype=np.uint8)
+    img = np.zeros((h, w), dtype=np.uint8 if d == 8 else np.uint16)
     for grp, words in zip(canonical_order(h, w, groups, lanes), split_streams(buf, groups)):
         def find(i, slot, grp=grp):
             y, x, _ = grp[i]
-            o = deep_forward_bf16(pixel_features(img, y, x)[None, :], layers).astype(np.float32)
+            o = deep_forward_bf16(pixel_features(img, y, x, d)[None, :], layers).astype(np.float32)
             F = table_softmax32(o)[0]
             v = int(np.searchsorted(F, slot, side="right")) - 1
             img[y, x] = v

@@ -49,7 +49,7 @@ def lag(ws: int) -> int:
     return max(0, max(dx + SKEW * dy for dy, dx in lower_offsets(ws)) + 1)
 
 
-def voxel_features(vol, z: int, y: int, x: int, ws: int) -> np.ndarray:
+def voxel_features(vol, z: int, y: int, x: int, ws: int, depth: int = 8) -> np.ndarray:
     """The 21 scaled window values of voxel (z, y, x), FP64."""
     vol = np.asarray(vol)
     Z, H, W = vol.shape
@@ -57,20 +57,20 @@ def voxel_features(vol, z: int, y: int, x: int, ws: int) -> np.ndarray:
     for k, (dy, dx) in enumerate(NEIGHBOURS):
         yy, xx = y + dy, x + dx
         if 0 <= yy < H and 0 <= xx < W:
-            out[k] = scale(int(vol[z, yy, xx]))
+            out[k] = scale(int(vol[z, yy, xx]), depth)
     if z > 0:
         for k, (dy, dx) in enumerate(lower_offsets(ws)):
             yy, xx = y + dy, x + dx
             if 0 <= yy < H and 0 <= xx < W:
-                out[12 + k] = scale(int(vol[z - 1, yy, xx]))
+                out[12 + k] = scale(int(vol[z - 1, yy, xx]), depth)
     return out
 
 
-def volume_features(vol, ws: int) -> np.ndarray:
+def volume_features(vol, ws: int, depth: int = 8) -> np.ndarray:
     """Features of every voxel, (Z, H, W, 21), vectorised."""
     vol = np.asarray(vol)
     Z, H, W = vol.shape
-    s = np.array([scale(v) for v in range(256)], dtype=np.float64)[vol.astype(np.int64)]
+    s = scale(vol.astype(np.int64), depth)
     out = np.zeros((Z, H, W, K_IN_3D), dtype=np.float64)
     offs = [(0, dy, dx) for dy, dx in NEIGHBOURS] + [(-1, dy, dx) for dy, dx in lower_offsets(ws)]
     for k, (dz, dy, dx) in enumerate(offs):
@@ -105,9 +105,10 @@ def volume_flags(Z: int, ws: int) -> int:
 
 def cf_volume(vol, layers, ws: int):
     """(c, f) of every voxel by the softmax table rule, in stacked raster order."""
-    from .softmax import deep_forward_bf16, table_softmax32
-    vol = np.asarray(vol, dtype=np.uint8)
-    f = volume_features(vol, ws).reshape(-1, K_IN_3D)[:, :_k_in(layers, ws)]
+    from .softmax import deep_forward_bf16, net_depth, table_softmax32
+    d = net_depth(layers)
+    vol = np.asarray(vol, dtype=np.uint8 if d == 8 else np.uint16)
+    f = volume_features(vol, ws, d).reshape(-1, K_IN_3D)[:, :_k_in(layers, ws)]
     F = table_softmax32(deep_forward_bf16(f, layers).astype(np.float32))
     v = vol.reshape(-1).astype(np.int64)
     rows = np.arange(v.size)
@@ -117,8 +118,9 @@ def cf_volume(vol, layers, ws: int):
 def encode_volume(vol, layers, groups: int, lanes: int, ws: int) -> bytes:
     from .container import assemble, pack_header
     from .rans import canonical_order, rans_encode
-    from .softmax import stored_fingerprint
-    vol = np.asarray(vol, dtype=np.uint8)
+    from .softmax import header_dtype, net_depth, stored_fingerprint
+    d = net_depth(layers)
+    vol = np.asarray(vol, dtype=np.uint8 if d == 8 else np.uint16)
     Z, H, W = vol.shape
     c, f = cf_volume(vol, layers, ws)
     streams = []
@@ -126,7 +128,7 @@ def encode_volume(vol, layers, groups: int, lanes: int, ws: int) -> bytes:
         idx = [y * W + x for (y, x, _) in grp]
         streams.append(rans_encode([(c[i], f[i]) for i in idx], [ln for (_, _, ln) in grp], lanes))
     Hn = np.asarray(layers[0][0]).shape[0]
-    hdr = pack_header(Z * H, W, Z * groups, lanes, dtype=1, h1=Hn, h2=Hn, n_mix=0,
+    hdr = pack_header(Z * H, W, Z * groups, lanes, dtype=header_dtype(d), h1=Hn, h2=Hn, n_mix=0,
                       k_in=_k_in(layers, ws),
                       fp=stored_fingerprint(layers), flags=volume_flags(Z, ws))
     return assemble(hdr, streams)
@@ -135,22 +137,25 @@ def encode_volume(vol, layers, groups: int, lanes: int, ws: int) -> bytes:
 def decode_volume(buf: bytes, layers) -> np.ndarray:
     from .container import parse_header, split_streams
     from .rans import canonical_order, rans_decode
-    from .softmax import deep_forward_bf16, stored_fingerprint, table_softmax32
+    from .softmax import (deep_forward_bf16, header_dtype, net_depth, stored_fingerprint,
+                          table_softmax32)
     hdr = parse_header(buf)
     Z, ws = hdr["flags"] & 0xFFF, hdr["flags"] >> 12
     k_in = _k_in(layers, ws)
-    if hdr["n_mix"] != 0 or hdr["k_in"] != k_in or hdr["fingerprint"] != stored_fingerprint(layers):
+    d = net_depth(layers)
+    if (hdr["n_mix"] != 0 or hdr["k_in"] != k_in or hdr["dtype"] != header_dtype(d)
+            or hdr["fingerprint"] != stored_fingerprint(layers)):
         raise ValueError("stream was coded with another model")
     H, W = hdr["h"] // Z, hdr["w"]
     G, lanes = hdr["groups"] // Z, hdr["lanes"]
-    vol = np.zeros((Z, H, W), dtype=np.uint8)
+    vol = np.zeros((Z, H, W), dtype=np.uint8 if d == 8 else np.uint16)
     streams = split_streams(buf, Z * G)
     # a slice's windows reach only the slice below: slices in order, groups in order
     for grp, words in zip(canonical_order(Z * H, W, Z * G, lanes), streams):
         def find(i, slot, grp=grp):
             yt, x, _ = grp[i]
             z, y = divmod(yt, H)
-            o = deep_forward_bf16(voxel_features(vol, z, y, x, ws)[None, :k_in], layers)
+            o = deep_forward_bf16(voxel_features(vol, z, y, x, ws, d)[None, :k_in], layers)
             F = table_softmax32(o.astype(np.float32))[0]
             v = int(np.searchsorted(F, slot, side="right")) - 1
             vol[z, y, x] = v

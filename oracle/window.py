@@ -32,31 +32,33 @@ SKEW = 3
 DUMMY = 0.0
 
 
-def scale(v):
-    """Map 8-bit grey levels to [-1, 1]: s(v) = (2v - 255)/255, in FP64."""
-    return (2.0 * np.asarray(v, dtype=np.float64) - 255.0) / 255.0
+def scale(v, depth: int = 8):
+    """Map grey levels to [-1, 1]: s(v) = (2v - m)/m with m = 2^depth - 1 (255 for
+    8-bit images, 4095 for 12-bit ones), in FP64."""
+    m = float((1 << depth) - 1)
+    return (2.0 * np.asarray(v, dtype=np.float64) - m) / m
 
 
-def pixel_features(img: np.ndarray, y: int, x: int) -> np.ndarray:
+def pixel_features(img: np.ndarray, y: int, x: int, depth: int = 8) -> np.ndarray:
     """Window of one pixel, read one neighbour at a time (FP64, length 12)."""
     h, w = img.shape
     out = np.empty(K_IN, dtype=np.float64)
     for k, (dy, dx) in enumerate(NEIGHBOURS):
         yy, xx = y + dy, x + dx
         if 0 <= yy < h and 0 <= xx < w:
-            out[k] = scale(img[yy, xx])
+            out[k] = scale(img[yy, xx], depth)
         else:
             out[k] = DUMMY
     return out
 
 
-def causal_features(img: np.ndarray) -> np.ndarray:
+def causal_features(img: np.ndarray, depth: int = 8) -> np.ndarray:
     """Windows of every pixel as one matrix, one row per pixel: (h*w, 12) FP64.
 
     Row order is raster order (row y, then column x).
     """
     h, w = img.shape
-    s = scale(img)
+    s = scale(img, depth)
     feats = np.full((h, w, K_IN), DUMMY, dtype=np.float64)
     for k, (dy, dx) in enumerate(NEIGHBOURS):
         y0, y1 = max(0, -dy), min(h, h - dy)

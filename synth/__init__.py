@@ -220,9 +220,10 @@ def random_symbols_from_tables(tables: np.ndarray, idx: np.ndarray, seed: int) -
     return sym.reshape(idx.shape)
 
 
-def mri_volume(seed: int, depth: int = 35, size: int = 256) -> np.ndarray:
-    """MRI-like 8-bit volume whose slices are cuts through one 3-D object,
-    shape (depth, size, size), dtype uint8 (a 256x256x35 scan by default).
+def mri_volume(seed: int, depth: int = 35, size: int = 256, bits: int = 8) -> np.ndarray:
+    """MRI-like volume whose slices are cuts through one 3-D object, shape
+    (depth, size, size): uint8 for 8-bit samples (a 256x256x35 scan by default),
+    uint16 for 12-bit ones (intensities and noise scaled by 4095/255).
 
     Recipe: 3-8 nested ellipsoids of random intensity 20-220 on a zero
     background (semi-axes 70-115 px in-plane, 0.6-1.2 times the depth along
@@ -261,4 +262,6 @@ def mri_volume(seed: int, depth: int = 35, size: int = 256) -> np.ndarray:
                          + coef[4] * uu * vv + coef[5] * w))
     n1 = rng.normal(0.0, 4.0, size=vol.shape)
     n2 = rng.normal(0.0, 4.0, size=vol.shape)
-    return np.clip(np.rint(np.sqrt((vol * bias + n1) ** 2 + n2 ** 2)), 0, 255).astype(np.uint8)
+    top = (1 << bits) - 1
+    mag = np.sqrt((vol * bias + n1) ** 2 + n2 ** 2) * (top / 255.0)
+    return np.clip(np.rint(mag), 0, top).astype(np.uint8 if bits == 8 else np.uint16)

@@ -42,3 +42,7 @@ def test_frozen_digests():
     assert _sha(cat(synth.xavier_mlp((12, 32, 32, 15), 7))) == "e099f6af56746afa"
     assert _sha(cat(synth.xavier_mlp((12, 64, 64, 15), 3))) == "95746706a4c78c26"
     assert _sha(synth.mri_phantom(2000)) == "e9ce845f50d81e98"
+    assert _sha(synth.mri_volume(2024)) == "0f17a7e3c311f383"
+    v12 = synth.mri_volume(5, 3, 32, bits=12)
+    assert v12.dtype == np.uint16 and v12.max() < 4096
+    assert _sha(v12) == "df3185f795d56173"
