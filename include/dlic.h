@@ -112,6 +112,11 @@ uint64_t dlic_fnv1a64(uint64_t h, const void *h_bytes, size_t n);
  * levels scale[256].  Any pointer may be NULL. */
 void dlic_host_constants(float *h_S, float *h_D, float *h_beta, float *h_scale);
 
+/* The network's input scale of each level as the kernels use it,
+ * RN32((2v - m) / m) with m = 2^depth - 1: 256 floats for depth 8, 4096 for
+ * depth 12 (DLIC_ERR_ARG for another depth). */
+dlic_status dlic_host_scale(int32_t depth, float *h_out);
+
 /* Weight storage of the reduced-precision networks (the network of Section
  * II-B run with BF16 or FP8 operands and FP32 accumulation).  Converts one
  * FP32 matrix of n finite elements, host to host:
@@ -378,7 +383,15 @@ double dlic_wallclock_hz(void);
  * resident (DLIC_ERR_UNSUPPORTED otherwise): at least 256 groups fit.
  *
  * k_in is 12 for images; volumes (below) also take 21: the 12-pixel window
- * and a 3 x 3 block of the slice below. */
+ * and a 3 x 3 block of the slice below.
+ *
+ * 12-bit samples (Section IV-C, Higher Bit Depth: 4096 output neurons):
+ * depth = 12, an output layer of 4096 neurons, samples as u16 below 4096
+ * (d_img / d_vol point to u16 then, u8 for depth 8).  Inputs are scaled by
+ * (2v - 4095) / 4095; the table rule is the one above over 64 blocks of 64
+ * levels with 65536 - 4096 in place of 65280; the header's dtype byte holds
+ * the depth above 8 in its high nibble (0x41).  The encoder writes a stream
+ * length of 0 if a sample exceeds 4095. */
 #define DLIC_DEEP_LAYERS 6
 typedef struct {
   int32_t hidden;                          /* H: 64 or 128 */
@@ -386,33 +399,36 @@ typedef struct {
   const uint16_t *d_w[DLIC_DEEP_LAYERS];   /* BF16 bit patterns, row-major [out][in] */
   const float *d_b[DLIC_DEEP_LAYERS];      /* FP32 biases */
   uint64_t fingerprint; /* FNV-1a 64 over W1, b1, ..., W6, b6 as stored (BF16 / FP32) */
+  int32_t depth;        /* bits per sample: 8 (256 outputs) or 12 (4096 outputs) */
 } dlic_deep_model;
 
-/* Device workspace bytes: decode = 0 for dlic_deep_encode, 1 for
- * dlic_deep_decode, -1 for dlic_deep_density (coder may be NULL then).  0 for
- * an unsupported size, width or layout. */
-size_t dlic_deep_workspace(int32_t h, int32_t w, const dlic_coder *coder, int32_t hidden,
-                           int32_t decode);
+/* Device workspace bytes for the model (host struct): decode = 0 for
+ * dlic_deep_encode, 1 for dlic_deep_decode, -1 for dlic_deep_density (coder
+ * may be NULL then).  0 for an unsupported model, size or layout.  At depth 12
+ * encoding takes about 260 MB (the logits of 16384 pixels at a time) and
+ * decoding 24 KB per row. */
+size_t dlic_deep_workspace(const dlic_deep_model *model, int32_t h, int32_t w,
+                           const dlic_coder *coder, int32_t decode);
 
 /* Encode one image with the softmax network: as dlic_encode (same bound,
  * output and length conventions). */
 dlic_status dlic_deep_encode(const dlic_deep_model *model, const dlic_coder *coder,
-                             const uint8_t *d_img, int32_t h, int32_t w, uint8_t *d_out,
+                             const void *d_img, int32_t h, int32_t w, uint8_t *d_out,
                              size_t out_cap, uint64_t *d_out_len, void *d_ws, size_t ws_bytes,
                              hipStream_t stream);
 
 /* Decode a stream of dlic_deep_encode: as dlic_decode (d_status 0, 3 corrupt,
  * 4 other model, 7 a bounded wait gave up). */
 dlic_status dlic_deep_decode(const dlic_deep_model *model, const dlic_coder *coder,
-                             const uint8_t *d_bits, size_t n_bytes, uint8_t *d_img, int32_t h,
+                             const uint8_t *d_bits, size_t n_bytes, void *d_img, int32_t h,
                              int32_t w, int32_t *d_status, void *d_ws, size_t ws_bytes,
                              hipStream_t stream);
 
 /* Test hook: the encoder's network and table rule on every pixel of an image
- * (raster order): FP32 logits [n][256], packed intervals c | (f - 1) << 16
- * [n] of each pixel's own value, tables F(0..255) [n][256] (u16); each output
- * optional (NULL), at least one. */
-dlic_status dlic_deep_density(const dlic_deep_model *model, const uint8_t *d_img, int32_t h,
+ * (raster order): FP32 logits [n][levels], packed intervals c | (f - 1) << 16
+ * [n] of each pixel's own value, tables F(0..levels-1) [n][levels] (u16);
+ * each output optional (NULL), at least one. */
+dlic_status dlic_deep_density(const dlic_deep_model *model, const void *d_img, int32_t h,
                               int32_t w, float *d_logits, uint32_t *d_cf, uint16_t *d_tables,
                               void *d_ws, size_t ws_bytes, hipStream_t stream);
 
@@ -449,28 +465,29 @@ int32_t dlic_deep_decode_grid(void);
 /* Bytes of the largest stream of a volume (0 for an unsupported layout). */
 size_t dlic_volume_encode_bound(int32_t z, int32_t h, int32_t w, const dlic_coder *coder);
 
-/* Device workspace bytes: decode = 0 encode, 1 decode, -1 density hook. */
-size_t dlic_volume_workspace(int32_t z, int32_t h, int32_t w, const dlic_coder *coder,
-                             int32_t hidden, int32_t decode);
+/* Device workspace bytes for the model: decode = 0 encode, 1 decode, -1
+ * density hook. */
+size_t dlic_volume_workspace(const dlic_deep_model *model, int32_t z, int32_t h, int32_t w,
+                             const dlic_coder *coder, int32_t decode);
 
-/* Encode a volume (d_vol: z h w bytes); as dlic_deep_encode otherwise.
+/* Encode a volume (d_vol: z h w samples); as dlic_deep_encode otherwise.
  * DLIC_ERR_ARG for z, ws out of range or ws != 0 with k_in = 12. */
 dlic_status dlic_volume_encode(const dlic_deep_model *model, const dlic_coder *coder,
-                               const uint8_t *d_vol, int32_t z, int32_t h, int32_t w, int32_t ws,
+                               const void *d_vol, int32_t z, int32_t h, int32_t w, int32_t ws,
                                uint8_t *d_out, size_t out_cap, uint64_t *d_out_len, void *d_ws,
                                size_t ws_bytes, hipStream_t stream);
 
-/* Decode a stream of dlic_volume_encode into d_vol (z h w bytes); z, h, ws
+/* Decode a stream of dlic_volume_encode into d_vol (z h w samples); z, h, ws
  * and the coder as dlic_peek_volume gives them.  d_status as dlic_deep_decode
  * (3 also when z, h, ws or the coder do not match the stream). */
 dlic_status dlic_volume_decode(const dlic_deep_model *model, const dlic_coder *coder,
-                               const uint8_t *d_bits, size_t n_bytes, uint8_t *d_vol, int32_t z,
+                               const uint8_t *d_bits, size_t n_bytes, void *d_vol, int32_t z,
                                int32_t h, int32_t w, int32_t ws, int32_t *d_status, void *d_ws,
                                size_t ws_bytes, hipStream_t stream);
 
 /* Test hook: the encoder's network and table rule on every pixel of a volume,
  * outputs as dlic_deep_density in slice-major raster order. */
-dlic_status dlic_volume_density(const dlic_deep_model *model, const uint8_t *d_vol, int32_t z,
+dlic_status dlic_volume_density(const dlic_deep_model *model, const void *d_vol, int32_t z,
                                 int32_t h, int32_t w, int32_t ws, float *d_logits, uint32_t *d_cf,
                                 uint16_t *d_tables, void *d_ws, size_t ws_bytes,
                                 hipStream_t stream);

@@ -42,7 +42,7 @@ EXPORTS = (
     "dlic_set_decode_delays", "dlic_deep_workspace", "dlic_deep_encode", "dlic_deep_decode",
     "dlic_deep_density", "dlic_set_deep_decode_grid", "dlic_deep_decode_grid",
     "dlic_volume_encode_bound", "dlic_volume_workspace", "dlic_volume_encode", "dlic_volume_decode",
-    "dlic_volume_density", "dlic_peek_volume",
+    "dlic_volume_density", "dlic_peek_volume", "dlic_host_scale",
     "dlic_net_forms",
 )
 
@@ -69,7 +69,7 @@ DEEP_LAYERS = 6
 
 class dlic_deep_model(ctypes.Structure):
     _fields_ = [("hidden", c_int32), ("k_in", c_int32), ("d_w", c_void_p * DEEP_LAYERS),
-                ("d_b", c_void_p * DEEP_LAYERS), ("fingerprint", c_uint64)]
+                ("d_b", c_void_p * DEEP_LAYERS), ("fingerprint", c_uint64), ("depth", c_int32)]
 
 
 _lib = None
@@ -130,7 +130,7 @@ def lib():
         "dlic_batch_replay": (c_int, [P, c_int32, P]),
         "dlic_wallclock_hz": (ctypes.c_double, []),
         "dlic_latency_probe": (c_int, [P, c_int32, P, S, P]),
-        "dlic_deep_workspace": (S, [c_int32, c_int32, P, c_int32, c_int32]),
+        "dlic_deep_workspace": (S, [POINTER(dlic_deep_model), c_int32, c_int32, P, c_int32]),
         "dlic_deep_encode": (c_int, [POINTER(dlic_deep_model), POINTER(dlic_coder), P, c_int32,
                                      c_int32, P, S, P, P, S, P]),
         "dlic_deep_decode": (c_int, [POINTER(dlic_deep_model), POINTER(dlic_coder), P, S, P,
@@ -140,7 +140,9 @@ def lib():
         "dlic_set_deep_decode_grid": (None, [c_int32]),
         "dlic_deep_decode_grid": (c_int32, []),
         "dlic_volume_encode_bound": (S, [c_int32, c_int32, c_int32, POINTER(dlic_coder)]),
-        "dlic_volume_workspace": (S, [c_int32, c_int32, c_int32, P, c_int32, c_int32]),
+        "dlic_volume_workspace": (S, [POINTER(dlic_deep_model), c_int32, c_int32, c_int32, P,
+                                      c_int32]),
+        "dlic_host_scale": (c_int, [c_int32, P]),
         "dlic_volume_encode": (c_int, [POINTER(dlic_deep_model), POINTER(dlic_coder), P, c_int32,
                                        c_int32, c_int32, c_int32, P, S, P, P, S, P]),
         "dlic_volume_decode": (c_int, [POINTER(dlic_deep_model), POINTER(dlic_coder), P, S, P,
@@ -446,9 +448,10 @@ def density(img, model: Model, tables=False, stream=None):
 
 class DeepModel:
     """The paper's six-layer network with the softmax head, resident on a device:
-    layers = [(W, b)] * 6 (FP32, W [out, in]: k -> H, H -> H x 4, H -> 256 with k = 12,
-    or 21 for volumes with the slice below).  The library's dlic_quantize_weights stores
-    the matrices as BF16; biases stay FP32."""
+    layers = [(W, b)] * 6 (FP32, W [out, in]: k -> H, H -> H x 4, H -> N with k = 12,
+    or 21 for volumes with the slice below, and N = 256 levels for 8-bit samples or
+    4096 for 12-bit ones).  The library's dlic_quantize_weights stores the matrices as
+    BF16; biases stay FP32."""
 
     def __init__(self, layers, device="cuda"):
         import torch
@@ -456,6 +459,10 @@ class DeepModel:
             raise ValueError("six layers")
         self.hidden = int(np.asarray(layers[0][0]).shape[0])
         self.k_in = int(np.asarray(layers[0][0]).shape[1])
+        n_out = int(np.asarray(layers[-1][0]).shape[0])
+        if n_out not in (256, 4096):
+            raise ValueError("256 or 4096 output levels")
+        self.depth = 8 if n_out == 256 else 12
         self.w, self.b = [], []
         h = FNV_OFFSET
         for W, b in layers:
@@ -468,37 +475,68 @@ class DeepModel:
         self.fingerprint = h
         self.c = dlic_deep_model(self.hidden, self.k_in,
                                  (c_void_p * DEEP_LAYERS)(*[_ptr(t) for t in self.w]),
-                                 (c_void_p * DEEP_LAYERS)(*[_ptr(t) for t in self.b]), h)
+                                 (c_void_p * DEEP_LAYERS)(*[_ptr(t) for t in self.b]), h,
+                                 self.depth)
 
 
-def dlic_deep_workspace(h, w, coder, hidden, decode) -> int:
-    return int(lib().dlic_deep_workspace(h, w, ctypes.byref(coder) if coder is not None else None,
-                                         hidden, decode))
+def dlic_deep_workspace(model: "DeepModel", h, w, coder, decode) -> int:
+    return int(lib().dlic_deep_workspace(ctypes.byref(model.c), h, w,
+                                         ctypes.byref(coder) if coder is not None else None, decode))
+
+
+def dlic_volume_workspace(model: "DeepModel", z, h, w, coder, decode) -> int:
+    return int(lib().dlic_volume_workspace(ctypes.byref(model.c), z, h, w,
+                                           ctypes.byref(coder) if coder is not None else None,
+                                           decode))
+
+
+def dlic_host_scale(depth: int) -> np.ndarray:
+    out = np.zeros(1 << depth, np.float32)
+    _check(lib().dlic_host_scale(int(depth), out.ctypes.data), "dlic_host_scale")
+    return out
+
+
+def _sample_dtype(depth):
+    """Device storage of samples: uint8, or int16 holding 12-bit values (< 4096)."""
+    import torch
+    return torch.uint8 if depth == 8 else torch.int16
+
+
+def _check_samples(t, model):
+    import torch
+    if t.dtype != _sample_dtype(model.depth):
+        want = "uint8" if model.depth == 8 else "int16 (12-bit values)"
+        raise ValueError(f"samples of a {model.depth}-bit model are {want} tensors")
 
 
 def deep_encode(img, model: DeepModel, coder: dlic_coder, stream=None):
-    """Encode a [h, w] uint8 device tensor with the softmax network."""
+    """Encode a [h, w] device tensor with the softmax network: uint8 samples, or
+    int16 tensors of 12-bit values for a 4096-level network."""
     import torch
+    _check_samples(img, model)
     h, w = img.shape
     cap = dlic_encode_bound(h, w, coder)
     out = _empty(cap, torch.uint8, img.device)
     olen = _empty(1, torch.int64, img.device)
-    wsb = dlic_deep_workspace(h, w, coder, model.hidden, 0)
+    wsb = dlic_deep_workspace(model, h, w, coder, 0)
     ws = _empty(wsb, torch.uint8, img.device)
     _check(lib().dlic_deep_encode(ctypes.byref(model.c), ctypes.byref(coder),
                                   _ptr(img.contiguous()), h, w, _ptr(out), cap, _ptr(olen),
                                   _ptr(ws), wsb, _stream(stream)), "dlic_deep_encode")
-    return out[:int(olen.item())]
+    n = int(olen.item())
+    if n == 0:
+        raise DlicError(DLIC_ERR_ARG, "dlic_deep_encode: a sample exceeds the bit depth")
+    return out[:n]
 
 
 def deep_decode(bits, model: DeepModel, stream=None, check=True):
-    """Decode a stream of deep_encode; returns ([h, w] uint8 tensor, status)."""
+    """Decode a stream of deep_encode; returns ([h, w] tensor, status)."""
     import torch
     hd = dlic_peek_header(bits[:HEADER_BYTES].cpu().numpy().tobytes())
     h, w, coder = hd["h"], hd["w"], hd["coder"]
-    img = torch.empty((h, w), dtype=torch.uint8, device=bits.device)
+    img = torch.empty((h, w), dtype=_sample_dtype(model.depth), device=bits.device)
     st = torch.zeros(1, dtype=torch.int32, device=bits.device)
-    wsb = dlic_deep_workspace(h, w, coder, model.hidden, 1)
+    wsb = dlic_deep_workspace(model, h, w, coder, 1)
     ws = _empty(wsb, torch.uint8, bits.device)
     _check(lib().dlic_deep_decode(ctypes.byref(model.c), ctypes.byref(coder),
                                   _ptr(bits.contiguous()), bits.numel(), _ptr(img), h, w,
@@ -510,15 +548,16 @@ def deep_decode(bits, model: DeepModel, stream=None, check=True):
 
 
 def deep_density(img, model: DeepModel, logits=True, tables=False, stream=None):
-    """Logits [n, 256] FP32, packed intervals [n] and optionally tables F(0..255)
-    [n, 256] (u16 in int16 storage) of every pixel of an image."""
+    """Logits [n, N] FP32, packed intervals [n] and optionally tables F(0..N-1)
+    [n, N] (u16 in int16 storage) of every pixel of an image (N = 256 or 4096)."""
     import torch
+    _check_samples(img, model)
     h, w = img.shape
-    n = h * w
-    lg = torch.empty((n, 256), dtype=torch.float32, device=img.device) if logits else None
+    n, N = h * w, 1 << model.depth
+    lg = torch.empty((n, N), dtype=torch.float32, device=img.device) if logits else None
     cf = torch.empty(n, dtype=torch.int32, device=img.device)
-    tab = torch.empty((n, 256), dtype=torch.int16, device=img.device) if tables else None
-    wsb = dlic_deep_workspace(h, w, None, model.hidden, -1)
+    tab = torch.empty((n, N), dtype=torch.int16, device=img.device) if tables else None
+    wsb = dlic_deep_workspace(model, h, w, None, -1)
     ws = _empty(wsb, torch.uint8, img.device)
     _check(lib().dlic_deep_density(ctypes.byref(model.c), _ptr(img.contiguous()), h, w,
                                    _ptr(lg) if lg is not None else None, _ptr(cf),
@@ -545,31 +584,36 @@ def dlic_peek_volume(head: bytes) -> dict:
 
 
 def volume_encode(vol, model: DeepModel, coder: dlic_coder, ws: int = 0, stream=None):
-    """Encode a [z, h, w] uint8 device tensor (slices along the first axis)."""
+    """Encode a [z, h, w] device tensor (slices along the first axis; samples as for
+    deep_encode)."""
     import torch
+    _check_samples(vol, model)
     z, h, w = vol.shape
     cap = int(lib().dlic_volume_encode_bound(z, h, w, ctypes.byref(coder)))
     if cap == 0:
         raise DlicError(DLIC_ERR_UNSUPPORTED, "dlic_volume_encode_bound")
     out = _empty(cap, torch.uint8, vol.device)
     olen = _empty(1, torch.int64, vol.device)
-    wsb = int(lib().dlic_volume_workspace(z, h, w, ctypes.byref(coder), model.hidden, 0))
+    wsb = dlic_volume_workspace(model, z, h, w, coder, 0)
     wsp = _empty(wsb, torch.uint8, vol.device)
     _check(lib().dlic_volume_encode(ctypes.byref(model.c), ctypes.byref(coder),
                                     _ptr(vol.contiguous()), z, h, w, ws, _ptr(out), cap, _ptr(olen),
                                     _ptr(wsp), wsb, _stream(stream)), "dlic_volume_encode")
-    return out[:int(olen.item())]
+    n = int(olen.item())
+    if n == 0:
+        raise DlicError(DLIC_ERR_ARG, "dlic_volume_encode: a sample exceeds the bit depth")
+    return out[:n]
 
 
 def volume_decode(bits, model: DeepModel, stream=None, check=True):
-    """Decode a stream of volume_encode; returns ([z, h, w] uint8 tensor, status)."""
+    """Decode a stream of volume_encode; returns ([z, h, w] tensor, status)."""
     import torch
     hd = dlic_peek_header(bits[:HEADER_BYTES].cpu().numpy().tobytes())
     hv = dlic_peek_volume(bits[:HEADER_BYTES].cpu().numpy().tobytes())
     z, h, w, ws, coder = hv["z"], hv["h"], hd["w"], hv["ws"], hv["coder"]
-    vol = torch.empty((z, h, w), dtype=torch.uint8, device=bits.device)
+    vol = torch.empty((z, h, w), dtype=_sample_dtype(model.depth), device=bits.device)
     st = torch.zeros(1, dtype=torch.int32, device=bits.device)
-    wsb = int(lib().dlic_volume_workspace(z, h, w, ctypes.byref(coder), model.hidden, 1))
+    wsb = dlic_volume_workspace(model, z, h, w, coder, 1)
     if wsb == 0:
         raise DlicError(DLIC_ERR_UNSUPPORTED, "dlic_volume_workspace")
     wsp = _empty(wsb, torch.uint8, bits.device)
@@ -585,12 +629,13 @@ def volume_decode(bits, model: DeepModel, stream=None, check=True):
 def volume_density(vol, model: DeepModel, ws: int = 0, logits=True, tables=False, stream=None):
     """As deep_density for a [z, h, w] volume (slice-major raster order)."""
     import torch
+    _check_samples(vol, model)
     z, h, w = vol.shape
-    n = z * h * w
-    lg = torch.empty((n, 256), dtype=torch.float32, device=vol.device) if logits else None
+    n, N = z * h * w, 1 << model.depth
+    lg = torch.empty((n, N), dtype=torch.float32, device=vol.device) if logits else None
     cf = torch.empty(n, dtype=torch.int32, device=vol.device)
-    tab = torch.empty((n, 256), dtype=torch.int16, device=vol.device) if tables else None
-    wsb = int(lib().dlic_volume_workspace(z, h, w, None, model.hidden, -1))
+    tab = torch.empty((n, N), dtype=torch.int16, device=vol.device) if tables else None
+    wsb = dlic_volume_workspace(model, z, h, w, None, -1)
     wsp = _empty(wsb, torch.uint8, vol.device)
     _check(lib().dlic_volume_density(ctypes.byref(model.c), _ptr(vol.contiguous()), z, h, w, ws,
                                      _ptr(lg) if lg is not None else None, _ptr(cf),

@@ -22,7 +22,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libdlic.so")
 
 SOURCES = ["dlic_api.hip", "dlic_encode.hip", "dlic_decode.hip", "dlic_train.hip", "dlic_probe.hip",
-           "dlic_deep.hip"]
+           "dlic_deep.hip", "dlic_deep12.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

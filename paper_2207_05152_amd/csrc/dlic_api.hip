@@ -67,6 +67,7 @@ void build_consts(Consts* c) {
   c->beta[0] = -INFINITY;
   c->beta[256] = INFINITY;
   for (int v = 0; v < 256; ++v) c->scale[v] = ((float)(2 * v) - 255.0f) / 255.0f;
+  for (int v = 0; v < 4096; ++v) c->scale12[v] = ((float)(2 * v) - 4095.0f) / 4095.0f;
 }
 
 dlic_status ensure_device(int device, const Consts** out) {
@@ -259,6 +260,7 @@ dlic_status run_rans_and_pack(int h, int w, const dlic_coder* coder, const uint3
 dlic_status deep_model_ok(const dlic_deep_model* m, bool volume) {
   if (!m) return DLIC_ERR_ARG;
   if (m->hidden != 64 && m->hidden != 128) return DLIC_ERR_UNSUPPORTED;
+  if (m->depth != 8 && m->depth != 12) return DLIC_ERR_UNSUPPORTED;
   if (m->k_in != K_IN && !(volume && m->k_in == K_IN_3D)) return DLIC_ERR_UNSUPPORTED;
   for (int i = 0; i < DLIC_DEEP_LAYERS; ++i)
     if (!m->d_w[i] || !m->d_b[i]) return DLIC_ERR_ARG;
@@ -269,6 +271,7 @@ DeepNetArgs deep_net(const dlic_deep_model* m, void* wop) {
   DeepNetArgs n;
   n.H = m->hidden;
   n.k_in = m->k_in;
+  n.nout = m->depth == 12 ? DEEP_OUT12 : DEEP_OUT;
   n.wop = wop;
   for (int i = 0; i < DLIC_DEEP_LAYERS; ++i) n.b[i] = m->d_b[i];
   return n;
@@ -276,7 +279,7 @@ DeepNetArgs deep_net(const dlic_deep_model* m, void* wop) {
 
 // Operand-order weights at the head of every deep workspace.
 dlic_status deep_stage(const dlic_deep_model* m, void* wop, hipStream_t s) {
-  launch_deep_pack(m->hidden, m->k_in, m->d_w, wop, s);
+  launch_deep_pack(m->hidden, m->k_in, m->depth == 12 ? DEEP_OUT12 : DEEP_OUT, m->d_w, wop, s);
   return launch_ok();
 }
 
@@ -291,7 +294,8 @@ bool vol_geom(const dlic_deep_model* m, int z, int ws, VolGeom* vg) {
 }
 
 HeaderFields deep_header(const dlic_deep_model* m, const VolGeom* vg) {
-  HeaderFields hf{DLIC_BF16, m->hidden, m->hidden, m->fingerprint};
+  // the dtype byte's high nibble holds the bit depth above 8
+  HeaderFields hf{DLIC_BF16 | ((m->depth - 8) << 4), m->hidden, m->hidden, m->fingerprint};
   hf.n_mix = 0;
   hf.k_in = m->k_in;
   hf.flags = vg ? (vg->Z | (vg->ws << 12)) : 0;
@@ -311,55 +315,6 @@ bool vol_coder_ok(int z, int h, const dlic_coder* c) {
   return coder_ok(z * h, &t);
 }
 
-size_t deep_ws_bytes(int z, int h, int w, const dlic_coder* coder, int hidden, int decode) {
-  const size_t wop = align256(deep_wop_bytes(hidden));
-  if (decode < 0) return wop;  // density hook
-  if (decode) return wop + align256((size_t)z * h * DEEP_OUT * 2) + 256;
-  return wop + enc_ws_layout(z * h, w, coder->groups * z, coder->lanes_per_group, nullptr, nullptr);
-}
-
-dlic_status deep_density_impl(const dlic_deep_model* model, const uint8_t* d_img, int h, int w,
-                              const VolGeom& vg, float* d_logits, uint32_t* d_cf,
-                              uint16_t* d_tables, void* d_ws, size_t ws_bytes,
-                              hipStream_t stream) {
-  if (ws_bytes < deep_ws_bytes(vg.Z, h, w, nullptr, model->hidden, -1)) return DLIC_ERR_CAPACITY;
-  const Consts* K = nullptr;
-  dlic_status rc = current_consts(&K);
-  if (rc != DLIC_OK) return rc;
-  if ((rc = deep_stage(model, d_ws, stream)) != DLIC_OK) return rc;
-  timing_begin("deep_density_kernel", stream);
-  if (!launch_deep_density(K, deep_net(model, d_ws), d_img, h, w, vg, d_cf, d_logits, d_tables,
-                           stream))
-    return DLIC_ERR_UNSUPPORTED;
-  timing_end(stream);
-  return launch_ok();
-}
-
-dlic_status deep_encode_impl(const dlic_deep_model* model, const dlic_coder* coder,
-                             const uint8_t* d_img, int h, int w, const VolGeom& vg,
-                             const HeaderFields& hf, uint8_t* d_out, size_t out_cap,
-                             uint64_t* d_out_len, void* d_ws, size_t ws_bytes,
-                             hipStream_t stream) {
-  const dlic_coder tc = stacked_coder(coder, vg.Z);
-  const int HT = vg.Z * h;
-  if (out_cap < dlic_encode_bound(HT, w, &tc)) return DLIC_ERR_CAPACITY;
-  if (ws_bytes < deep_ws_bytes(vg.Z, h, w, coder, model->hidden, 0)) return DLIC_ERR_CAPACITY;
-  const Consts* K = nullptr;
-  dlic_status rc = current_consts(&K);
-  if (rc != DLIC_OK) return rc;
-  const size_t wop = align256(deep_wop_bytes(model->hidden));
-  EncWs ws;
-  enc_ws_layout(HT, w, tc.groups, tc.lanes_per_group, (uint8_t*)d_ws + wop, &ws);
-  if ((rc = deep_stage(model, d_ws, stream)) != DLIC_OK) return rc;
-  timing_begin("deep_density_kernel", stream);
-  if (!launch_deep_density(K, deep_net(model, d_ws), d_img, h, w, vg, ws.cf, nullptr, nullptr,
-                           stream))
-    return DLIC_ERR_UNSUPPORTED;
-  timing_end(stream);
-  if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
-  return run_rans_and_pack(HT, w, &tc, ws.cf, ws, hf, d_out, d_out_len, stream);
-}
-
 // Upper bound on the tiles of one decode step: every slice's active rows.
 int deep_step_tiles(int z, int h, int w) {
   const int rows = h < (w + SKEW - 1) / SKEW ? h : (w + SKEW - 1) / SKEW;
@@ -367,18 +322,161 @@ int deep_step_tiles(int z, int h, int w) {
   return t > (1 << 20) ? (1 << 20) : (int)t;
 }
 
+// Pixels per pass of the 12-bit encoder's three stages (logits: 256 MB).
+constexpr long long DEEP12_CHUNK = 16384;
+
+// Workspace of the deep entry points, in order: operand-order weights, then
+//  density / encode: 12-bit: h5 of a chunk, logits of a chunk, an error flag;
+//                    encode: the rANS encoder's scratch;
+//  decode: tables [Z H][levels] u16; 12-bit: logits [Z H][4096], h5 and rows
+//          of a step's tiles; 256 bytes of barrier state.
+struct DeepWs {
+  size_t wop = 0, h5 = 0, logits = 0, bad = 0, enc = 0, tables = 0, rows = 0, ctl = 0, total = 0;
+};
+
+DeepWs deep_ws(int z, int h, int w, const dlic_coder* coder, int hidden, int depth, int decode) {
+  DeepWs o;
+  const int nout = depth == 12 ? DEEP_OUT12 : DEEP_OUT;
+  size_t at = align256(deep_wop_bytes(hidden, nout));
+  if (decode <= 0) {
+    if (depth == 12) {
+      const long long n = (long long)z * h * w;
+      const long long ch = n < DEEP12_CHUNK ? n : DEEP12_CHUNK;
+      o.h5 = at;
+      at += align256((size_t)((ch + 15) / 16) * deep12_tile_bytes(hidden));
+      o.logits = at;
+      at += align256((size_t)ch * DEEP_OUT12 * 4);
+      o.bad = at;
+      at += 256;
+    }
+    if (decode == 0) {
+      o.enc = at;
+      at += enc_ws_layout(z * h, w, coder->groups * z, coder->lanes_per_group, nullptr, nullptr);
+    }
+  } else {
+    o.tables = at;
+    at += align256((size_t)z * h * nout * 2);
+    if (depth == 12) {
+      const size_t tiles = (size_t)deep_step_tiles(z, h, w);
+      o.logits = at;
+      at += align256((size_t)z * h * DEEP_OUT12 * 4);
+      o.h5 = at;
+      at += align256(tiles * deep12_tile_bytes(hidden));
+      o.rows = at;
+      at += align256(tiles * sizeof(int2));
+    }
+    o.ctl = at;
+    at += 256;
+  }
+  o.total = at;
+  return o;
+}
+
+size_t deep_ws_bytes(int z, int h, int w, const dlic_coder* coder, int hidden, int depth,
+                     int decode) {
+  return deep_ws(z, h, w, coder, hidden, depth, decode).total;
+}
+
+// The 12-bit encoder's stages over every pixel, chunk by chunk: packed
+// intervals into cf and, for the density hook, logits and tables.
+dlic_status deep12_stages(const Consts* K, const DeepNetArgs& net, const uint16_t* img, int h,
+                          int w, const VolGeom& vg, const DeepWs& L, uint8_t* base,
+                          uint32_t* d_cf, float* d_logits, uint16_t* d_tables,
+                          hipStream_t stream) {
+  const long long n = (long long)vg.Z * h * w;
+  int* bad = (int*)(base + L.bad);
+  launch_fill_u32((uint32_t*)bad, 0u, 1, stream);
+  for (long long px0 = 0; px0 < n; px0 += DEEP12_CHUNK) {
+    const long long nn = n - px0 < DEEP12_CHUNK ? n - px0 : DEEP12_CHUNK;
+    float* lg = d_logits ? d_logits + px0 * DEEP_OUT12 : (float*)(base + L.logits);
+    timing_begin("deep12_hidden_kernel", stream);
+    if (!launch_deep12_hidden(K, net, img, h, w, vg, px0, nn, base + L.h5, bad, stream))
+      return DLIC_ERR_UNSUPPORTED;
+    timing_end(stream);
+    timing_begin("deep12_logits_kernel", stream);
+    if (!launch_deep12_logits(net, base + L.h5, nn, lg, stream)) return DLIC_ERR_UNSUPPORTED;
+    timing_end(stream);
+    timing_begin("deep12_softmax_kernel", stream);
+    launch_deep12_softmax(lg, img, px0, nn, d_cf, d_tables ? d_tables + px0 * DEEP_OUT12 : nullptr,
+                          stream);
+    timing_end(stream);
+  }
+  return launch_ok();
+}
+
+dlic_status deep_density_impl(const dlic_deep_model* model, const void* d_img, int h, int w,
+                              const VolGeom& vg, float* d_logits, uint32_t* d_cf,
+                              uint16_t* d_tables, void* d_ws, size_t ws_bytes,
+                              hipStream_t stream) {
+  const DeepWs L = deep_ws(vg.Z, h, w, nullptr, model->hidden, model->depth, -1);
+  if (ws_bytes < L.total) return DLIC_ERR_CAPACITY;
+  const Consts* K = nullptr;
+  dlic_status rc = current_consts(&K);
+  if (rc != DLIC_OK) return rc;
+  if ((rc = deep_stage(model, d_ws, stream)) != DLIC_OK) return rc;
+  if (model->depth == 12)
+    return deep12_stages(K, deep_net(model, d_ws), (const uint16_t*)d_img, h, w, vg, L,
+                         (uint8_t*)d_ws, d_cf, d_logits, d_tables, stream);
+  timing_begin("deep_density_kernel", stream);
+  if (!launch_deep_density(K, deep_net(model, d_ws), (const uint8_t*)d_img, h, w, vg, d_cf,
+                           d_logits, d_tables, stream))
+    return DLIC_ERR_UNSUPPORTED;
+  timing_end(stream);
+  return launch_ok();
+}
+
+dlic_status deep_encode_impl(const dlic_deep_model* model, const dlic_coder* coder,
+                             const void* d_img, int h, int w, const VolGeom& vg,
+                             const HeaderFields& hf, uint8_t* d_out, size_t out_cap,
+                             uint64_t* d_out_len, void* d_ws, size_t ws_bytes,
+                             hipStream_t stream) {
+  const dlic_coder tc = stacked_coder(coder, vg.Z);
+  const int HT = vg.Z * h;
+  if (out_cap < dlic_encode_bound(HT, w, &tc)) return DLIC_ERR_CAPACITY;
+  const DeepWs L = deep_ws(vg.Z, h, w, coder, model->hidden, model->depth, 0);
+  if (ws_bytes < L.total) return DLIC_ERR_CAPACITY;
+  const Consts* K = nullptr;
+  dlic_status rc = current_consts(&K);
+  if (rc != DLIC_OK) return rc;
+  uint8_t* base = (uint8_t*)d_ws;
+  EncWs ws;
+  enc_ws_layout(HT, w, tc.groups, tc.lanes_per_group, base + L.enc, &ws);
+  if ((rc = deep_stage(model, d_ws, stream)) != DLIC_OK) return rc;
+  if (model->depth == 12) {
+    if ((rc = deep12_stages(K, deep_net(model, d_ws), (const uint16_t*)d_img, h, w, vg, L, base,
+                            ws.cf, nullptr, nullptr, stream)) != DLIC_OK)
+      return rc;
+  } else {
+    timing_begin("deep_density_kernel", stream);
+    if (!launch_deep_density(K, deep_net(model, d_ws), (const uint8_t*)d_img, h, w, vg, ws.cf,
+                             nullptr, nullptr, stream))
+      return DLIC_ERR_UNSUPPORTED;
+    timing_end(stream);
+  }
+  if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
+  rc = run_rans_and_pack(HT, w, &tc, ws.cf, ws, hf, d_out, d_out_len, stream);
+  if (rc == DLIC_OK && model->depth == 12) {
+    launch_deep12_reject((const int*)(base + L.bad), d_out_len, stream);
+    rc = launch_ok();
+  }
+  return rc;
+}
+
 dlic_status deep_decode_impl(const dlic_deep_model* model, const dlic_coder* coder,
-                             const uint8_t* d_bits, size_t n_bytes, uint8_t* d_img, int h, int w,
+                             const uint8_t* d_bits, size_t n_bytes, void* d_img, int h, int w,
                              const VolGeom& vg, const HeaderFields& hf, int32_t* d_status,
                              void* d_ws, size_t ws_bytes, hipStream_t stream) {
-  if (ws_bytes < deep_ws_bytes(vg.Z, h, w, coder, model->hidden, 1)) return DLIC_ERR_CAPACITY;
+  const DeepWs L = deep_ws(vg.Z, h, w, coder, model->hidden, model->depth, 1);
+  if (ws_bytes < L.total) return DLIC_ERR_CAPACITY;
   const Consts* K = nullptr;
   dlic_status rc = current_consts(&K);
   if (rc != DLIC_OK) return rc;
   // one wave per group, all workgroups resident (cooperative launch); as many
   // workgroups as a step has tiles, at least 64, at most 256 and the residency
   const int GT = coder->groups * vg.Z;
-  const int resident = deep_decode_max_grid(model->hidden, model->k_in);
+  const bool d12 = model->depth == 12;
+  const int resident = d12 ? deep12_decode_max_grid(model->hidden, model->k_in)
+                           : deep_decode_max_grid(model->hidden, model->k_in);
   if (resident <= 0) return DLIC_ERR_HIP;
   int grid = deep_step_tiles(vg.Z, h, w);
   if (grid > 256) grid = 256;
@@ -387,7 +485,6 @@ dlic_status deep_decode_impl(const dlic_deep_model* model, const dlic_coder* cod
   if (grid < (GT + DEEP_WAVES - 1) / DEEP_WAVES) grid = (GT + DEEP_WAVES - 1) / DEEP_WAVES;
   if (grid > resident) grid = resident;
   if (GT > grid * DEEP_WAVES) return DLIC_ERR_UNSUPPORTED;
-  const size_t wop = align256(deep_wop_bytes(model->hidden));
   uint8_t* base = (uint8_t*)d_ws;
   DeepDecArgs a;
   memset(&a, 0, sizeof(a));
@@ -402,8 +499,13 @@ dlic_status deep_decode_impl(const dlic_deep_model* model, const dlic_coder* cod
   a.L = coder->lanes_per_group;
   a.vg = vg;
   a.T = n_steps(h, w) + (long long)vg.lag * (vg.Z - 1);
-  a.tables = (uint16_t*)(base + wop);
-  uint32_t* ctl = (uint32_t*)(base + wop + align256((size_t)vg.Z * h * DEEP_OUT * 2));
+  a.tables = (uint16_t*)(base + L.tables);
+  if (d12) {
+    a.logits = (float*)(base + L.logits);
+    a.h5 = base + L.h5;
+    a.tile_rows = (int2*)(base + L.rows);
+  }
+  uint32_t* ctl = (uint32_t*)(base + L.ctl);
   a.bar = ctl;
   a.abort_flag = (int*)(ctl + 16);
   a.status = d_status;
@@ -414,8 +516,10 @@ dlic_status deep_decode_impl(const dlic_deep_model* model, const dlic_coder* cod
   launch_fill_u32((uint32_t*)d_status, 0u, 1, stream);
   if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
   g_deep_grid_used = grid;
-  timing_begin("deep_decode_kernel", stream);
-  if (launch_deep_decode(a, grid, stream) != hipSuccess) return DLIC_ERR_HIP;
+  timing_begin(d12 ? "deep12_decode_kernel" : "deep_decode_kernel", stream);
+  if ((d12 ? launch_deep12_decode(a, grid, stream) : launch_deep_decode(a, grid, stream)) !=
+      hipSuccess)
+    return DLIC_ERR_HIP;
   timing_end(stream);
   return launch_ok();
 }
@@ -558,6 +662,18 @@ void dlic_host_constants(float* h_S, float* h_D, float* h_beta, float* h_scale) 
   if (h_beta) memcpy(h_beta, c->beta, sizeof(c->beta));
   if (h_scale) memcpy(h_scale, c->scale, sizeof(c->scale));
   delete c;
+}
+
+dlic_status dlic_host_scale(int32_t depth, float* h_out) {
+  if (!h_out || (depth != 8 && depth != 12)) return DLIC_ERR_ARG;
+  Consts* c = new Consts;
+  build_consts(c);
+  if (depth == 8)
+    memcpy(h_out, c->scale, sizeof(c->scale));
+  else
+    memcpy(h_out, c->scale12, sizeof(c->scale12));
+  delete c;
+  return DLIC_OK;
 }
 
 dlic_status dlic_quantize_weights(int32_t dtype, const float* h_w, size_t n, void* h_out,
@@ -1160,14 +1276,14 @@ dlic_status dlic_latency_probe(double* h_out, int32_t n, void* d_ws, size_t ws_b
   return all_ok ? DLIC_OK : DLIC_ERR_TIMEOUT;
 }
 
-size_t dlic_deep_workspace(int32_t h, int32_t w, const dlic_coder* coder, int32_t hidden,
-                           int32_t decode) {
-  if (h <= 0 || w <= 0 || (hidden != 64 && hidden != 128)) return 0;
+size_t dlic_deep_workspace(const dlic_deep_model* model, int32_t h, int32_t w,
+                           const dlic_coder* coder, int32_t decode) {
+  if (!model || h <= 0 || w <= 0 || deep_model_ok(model, true) != DLIC_OK) return 0;
   if (decode >= 0 && !coder_ok(h, coder)) return 0;
-  return deep_ws_bytes(1, h, w, coder, hidden, decode);
+  return deep_ws_bytes(1, h, w, coder, model->hidden, model->depth, decode);
 }
 
-dlic_status dlic_deep_density(const dlic_deep_model* model, const uint8_t* d_img, int32_t h,
+dlic_status dlic_deep_density(const dlic_deep_model* model, const void* d_img, int32_t h,
                               int32_t w, float* d_logits, uint32_t* d_cf, uint16_t* d_tables,
                               void* d_ws, size_t ws_bytes, hipStream_t stream) {
   timing_reset();
@@ -1180,7 +1296,7 @@ dlic_status dlic_deep_density(const dlic_deep_model* model, const uint8_t* d_img
 }
 
 dlic_status dlic_deep_encode(const dlic_deep_model* model, const dlic_coder* coder,
-                             const uint8_t* d_img, int32_t h, int32_t w, uint8_t* d_out,
+                             const void* d_img, int32_t h, int32_t w, uint8_t* d_out,
                              size_t out_cap, uint64_t* d_out_len, void* d_ws, size_t ws_bytes,
                              hipStream_t stream) {
   timing_reset();
@@ -1193,7 +1309,7 @@ dlic_status dlic_deep_encode(const dlic_deep_model* model, const dlic_coder* cod
 }
 
 dlic_status dlic_deep_decode(const dlic_deep_model* model, const dlic_coder* coder,
-                             const uint8_t* d_bits, size_t n_bytes, uint8_t* d_img, int32_t h,
+                             const uint8_t* d_bits, size_t n_bytes, void* d_img, int32_t h,
                              int32_t w, int32_t* d_status, void* d_ws, size_t ws_bytes,
                              hipStream_t stream) {
   timing_reset();
@@ -1216,15 +1332,16 @@ size_t dlic_volume_encode_bound(int32_t z, int32_t h, int32_t w, const dlic_code
   return dlic_encode_bound(z * h, w, &tc);
 }
 
-size_t dlic_volume_workspace(int32_t z, int32_t h, int32_t w, const dlic_coder* coder,
-                             int32_t hidden, int32_t decode) {
-  if (z < 1 || z > DLIC_VOLUME_MAX_SLICES || h <= 0 || w <= 0 || (hidden != 64 && hidden != 128))
+size_t dlic_volume_workspace(const dlic_deep_model* model, int32_t z, int32_t h, int32_t w,
+                             const dlic_coder* coder, int32_t decode) {
+  if (!model || z < 1 || z > DLIC_VOLUME_MAX_SLICES || h <= 0 || w <= 0 ||
+      deep_model_ok(model, true) != DLIC_OK)
     return 0;
   if (decode >= 0 && !vol_coder_ok(z, h, coder)) return 0;
-  return deep_ws_bytes(z, h, w, coder, hidden, decode);
+  return deep_ws_bytes(z, h, w, coder, model->hidden, model->depth, decode);
 }
 
-dlic_status dlic_volume_density(const dlic_deep_model* model, const uint8_t* d_vol, int32_t z,
+dlic_status dlic_volume_density(const dlic_deep_model* model, const void* d_vol, int32_t z,
                                 int32_t h, int32_t w, int32_t ws, float* d_logits, uint32_t* d_cf,
                                 uint16_t* d_tables, void* d_ws, size_t ws_bytes,
                                 hipStream_t stream) {
@@ -1240,7 +1357,7 @@ dlic_status dlic_volume_density(const dlic_deep_model* model, const uint8_t* d_v
 }
 
 dlic_status dlic_volume_encode(const dlic_deep_model* model, const dlic_coder* coder,
-                               const uint8_t* d_vol, int32_t z, int32_t h, int32_t w, int32_t ws,
+                               const void* d_vol, int32_t z, int32_t h, int32_t w, int32_t ws,
                                uint8_t* d_out, size_t out_cap, uint64_t* d_out_len, void* d_ws,
                                size_t ws_bytes, hipStream_t stream) {
   timing_reset();
@@ -1255,7 +1372,7 @@ dlic_status dlic_volume_encode(const dlic_deep_model* model, const dlic_coder* c
 }
 
 dlic_status dlic_volume_decode(const dlic_deep_model* model, const dlic_coder* coder,
-                               const uint8_t* d_bits, size_t n_bytes, uint8_t* d_vol, int32_t z,
+                               const uint8_t* d_bits, size_t n_bytes, void* d_vol, int32_t z,
                                int32_t h, int32_t w, int32_t ws, int32_t* d_status, void* d_ws,
                                size_t ws_bytes, hipStream_t stream) {
   timing_reset();

@@ -30,42 +30,26 @@
 // wavefront: global step t holds pixel (z, y, x) with x + 3 y + lag z = t, so
 // every slice's pixels of a step are evaluated together (lag = 0: all slices
 // in lock-step).
-#include "dlic_device.hpp"
-#include "dlic_kernels.h"
+#include "dlic_deep.hpp"
 
 namespace dlic {
 
 constexpr int SM_ROW = DEEP_OUT + 4;  // floats per pixel row of the softmax scratch
 
-__host__ __device__ constexpr int deep_in(int i, int H) { return i == 0 ? 32 : H; }
-__host__ __device__ constexpr int deep_out(int i, int H) { return i == DEEP_LAYERS - 1 ? DEEP_OUT : H; }
-// bf16x8 operands (64 per (tile, k-step)) before layer i
-__host__ __device__ constexpr long long deep_off(int i, int H) {
-  long long o = 0;
-  for (int l = 0; l < i; ++l) o += (long long)(deep_out(l, H) / 16) * (deep_in(l, H) / 32) * 64;
-  return o;
-}
-
-size_t deep_wop_bytes(int H) { return (size_t)deep_off(DEEP_LAYERS, H) * 16; }
-
-// Input index of slot e of lane group q in k-step s of layer i (-1: zero slot).
-__device__ __forceinline__ int deep_slot_input(int i, int s, int q, int e, int k_in) {
-  if (i == 0) return 4 * e + q < k_in ? 4 * e + q : -1;
-  return 32 * s + 16 * (e >> 2) + 4 * q + (e & 3);
-}
+size_t deep_wop_bytes(int H, int nout) { return (size_t)deep_off(DEEP_LAYERS, H, nout) * 16; }
 
 struct DeepPackArgs {
   const uint16_t* w[DEEP_LAYERS];
 };
 
-__global__ __launch_bounds__(256) void deep_pack_kernel(int H, int k_in, DeepPackArgs p,
-                                                       uint16_t* wop) {
-  const long long total = deep_off(DEEP_LAYERS, H);
+__global__ __launch_bounds__(256) void deep_pack_kernel(int H, int k_in, int nout,
+                                                       DeepPackArgs p, uint16_t* wop) {
+  const long long total = deep_off(DEEP_LAYERS, H, nout);
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
     int i = 0;
-    while (idx >= deep_off(i + 1, H)) ++i;
-    const long long r = idx - deep_off(i, H);
+    while (idx >= deep_off(i + 1, H, nout)) ++i;
+    const long long r = idx - deep_off(i, H, nout);
     const int lane = (int)(r & 63), blk = (int)(r >> 6);
     const int NK = deep_in(i, H) / 32;
     const int nt = blk / NK, s = blk - nt * NK;
@@ -78,12 +62,14 @@ __global__ __launch_bounds__(256) void deep_pack_kernel(int H, int k_in, DeepPac
   }
 }
 
-void launch_deep_pack(int H, int k_in, const uint16_t* const* w, void* wop, hipStream_t s) {
+void launch_deep_pack(int H, int k_in, int nout, const uint16_t* const* w, void* wop,
+                      hipStream_t s) {
   DeepPackArgs p;
   for (int i = 0; i < DEEP_LAYERS; ++i) p.w[i] = w[i];
-  const long long total = deep_off(DEEP_LAYERS, H);
+  const long long total = deep_off(DEEP_LAYERS, H, nout);
   const int grid = (int)((total + 255) / 256);
-  hipLaunchKernelGGL(deep_pack_kernel, dim3(grid), dim3(256), 0, s, H, k_in, p, (uint16_t*)wop);
+  hipLaunchKernelGGL(deep_pack_kernel, dim3(grid), dim3(256), 0, s, H, k_in, nout, p,
+                     (uint16_t*)wop);
 }
 
 // One 16-pixel tile through the six layers.  Lane l holds the layer-1 operand
@@ -92,43 +78,12 @@ void launch_deep_pack(int H, int k_in, const uint16_t* const* w, void* wop, hipS
 template <int H>
 __device__ __forceinline__ void deep_run(const DeepNetArgs& d, const bf16x8 x,
                                          float (&o)[DEEP_OUT / 16][4]) {
-  constexpr int NT = H / 16, NK = H / 32;
+  constexpr int NK = H / 32;
   const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
   const int q = lane >> 4;
-  const bf16x8* w = reinterpret_cast<const bf16x8*>(d.wop);
-  float h[NT][4];
-#pragma unroll
-  for (int nt = 0; nt < NT; ++nt) {
-    const float* b = d.b[0] + 16 * nt + 4 * q;
-    f4 acc = {b[0], b[1], b[2], b[3]};
-    acc = mfma_bf16(w[nt * 64 + lane], x, acc);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) h[nt][r] = relu(acc[r]);
-  }
-  w += NT * 64;
-#pragma unroll 1
-  for (int li = 1; li < DEEP_LAYERS - 1; ++li) {
-    bf16x8 a[NK];
-#pragma unroll
-    for (int s = 0; s < NK; ++s)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) a[s][e] = (__bf16)h[2 * s + (e >> 2)][e & 3];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const float* b = d.b[li] + 16 * nt + 4 * q;
-      f4 acc = {b[0], b[1], b[2], b[3]};
-#pragma unroll
-      for (int s = 0; s < NK; ++s) acc = mfma_bf16(w[(nt * NK + s) * 64 + lane], a[s], acc);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) h[nt][r] = relu(acc[r]);
-    }
-    w += NT * NK * 64;
-  }
   bf16x8 a[NK];
-#pragma unroll
-  for (int s = 0; s < NK; ++s)
-#pragma unroll
-    for (int e = 0; e < 8; ++e) a[s][e] = (__bf16)h[2 * s + (e >> 2)][e & 3];
+  deep_hidden<H>(d, x, a);
+  const bf16x8* w = reinterpret_cast<const bf16x8*>(d.wop) + deep_off(DEEP_LAYERS - 1, H, DEEP_OUT);
 #pragma unroll
   for (int nt = 0; nt < DEEP_OUT / 16; ++nt) {
     const float* b = d.b[DEEP_LAYERS - 1] + 16 * nt + 4 * q;
@@ -306,41 +261,6 @@ __device__ __forceinline__ DeepBlock deep_softmax_lds(float* sm) {
   return blk;
 }
 
-__device__ __forceinline__ uint32_t deep_F(int v, float C) {
-  const float t = floorf(C * (float)M_PRIME);
-  const uint32_t qv = t >= (float)M_PRIME ? M_PRIME : (uint32_t)t;
-  return (uint32_t)v + qv;
-}
-
-// Layer-1 operand of lane group q for pixel (z, y, x) (y, the row in slice z
-// of the stacked image): slot e holds window value 4 e + q scaled to [-1, 1],
-// 0 outside the slice (or below the first slice) and past the window.  Values
-// 0..11 are the pixel's own slice, 12..20 the slice below, row by row.
-template <int KIN>
-__device__ __forceinline__ bf16x8 deep_features(const Consts* __restrict__ K, const uint8_t* img,
-                                                int H, int W, int ws, int z, int y, int x,
-                                                bool valid, int q) {
-  const __bf16 zero = (__bf16)0.0f;
-  bf16x8 o = {zero, zero, zero, zero, zero, zero, zero, zero};
-  const uint8_t* sl = img + (long long)z * H * W;
-#pragma unroll
-  for (int e = 0; e < (KIN + 3) / 4; ++e) {
-    const int k = 4 * e + q;
-    float f = 0.0f;
-    if (k < K_IN) {
-      const int yy = y + nb_dy(k), xx = x + nb_dx(k);
-      if (valid && yy >= 0 && xx >= 0 && xx < W) f = K->scale[sl[(long long)yy * W + xx]];
-    } else if (k < KIN) {
-      const int j = k - K_IN;
-      const int yy = y + ws - 3 + j / 3, xx = x + j % 3 - 1;
-      if (valid && z > 0 && yy >= 0 && yy < H && xx >= 0 && xx < W)
-        f = K->scale[sl[(long long)(yy - H) * W + xx]];
-    }
-    o[e] = (__bf16)f;
-  }
-  return o;
-}
-
 // Encoder side: every pixel's interval (and optionally logits / tables).
 template <int H, int KIN>
 __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_density_kernel(
@@ -359,7 +279,7 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_density_kernel(
     const bool valid = px < n;
     const int Y = valid ? (int)(px / W) : 0, x = valid ? (int)(px - (long long)Y * W) : 0;
     const int z = Y / Hh, y = Y - z * Hh;
-    const bf16x8 xin = deep_features<KIN>(K, img, Hh, W, vg.ws, z, y, x, valid, q);
+    const bf16x8 xin = deep_features<KIN, uint8_t>(K->scale, img, Hh, W, vg.ws, z, y, x, valid, q);
     float o[DEEP_OUT / 16][4];
     deep_run<H>(net, xin, o);
     if (logits && valid) {
@@ -377,11 +297,11 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_density_kernel(
 #pragma unroll 4
     for (int k = 0; k < 64; ++k) {
       const int v = 64 * q + k;
-      const uint32_t Fv = v == 0 ? 0u : deep_F(v, blk.off + L);
+      const uint32_t Fv = v == 0 ? 0u : deep_F(v, blk.off + L, M_PRIME);
       if (tables && valid) tables[px * DEEP_OUT + v] = (uint16_t)Fv;
       if (v == xv) c = Fv;
       L = L + row[k];
-      if (v == xv) fnext = v == DEEP_OUT - 1 ? M_TOTAL : deep_F(v + 1, blk.off + L);
+      if (v == xv) fnext = v == DEEP_OUT - 1 ? M_TOTAL : deep_F(v + 1, blk.off + L, M_PRIME);
     }
     if (valid && mine && cf) cf[px] = c | ((fnext - c - 1u) << 16);
     wave_lds_handover();
@@ -418,64 +338,6 @@ bool launch_deep_density(const Consts* K, const DeepNetArgs& net, const uint8_t*
 }
 
 // ---- decoder ----------------------------------------------------------------
-
-__device__ __forceinline__ uint32_t rd32(const uint8_t* p) {
-  return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
-}
-__device__ __forceinline__ uint32_t rd16(const uint8_t* p) {
-  return (uint32_t)p[0] | ((uint32_t)p[1] << 8);
-}
-
-// Grid barrier over a cooperative launch: a counter that only grows (barrier
-// k completes when it reaches k * gridDim.x).  One thread per workgroup
-// arrives with a release add and polls with plain (relaxed) loads, then takes
-// one acquire fence: an acquire per poll would invalidate the cache the
-// network's weights are read through on every spin.  The wait is bounded;
-// giving up sets the abort flag, which ends every workgroup's walk.
-__device__ __forceinline__ bool grid_sync(unsigned* bar, int* abort_flag, unsigned& k,
-                                          uint32_t limit) {
-  __shared__ int s_ok;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    ++k;
-    const unsigned target = k * gridDim.x;
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t spins = 0;
-    int ok = 1;
-    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-          ++spins > limit) {
-        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    s_ok = ok;
-  }
-  __syncthreads();
-  // uniform by construction, so loops that end on it keep their barriers whole
-  return __builtin_amdgcn_readfirstlane(s_ok) != 0;
-}
-
-// 3: the stream does not fit the geometry (or is damaged); 4: another model.
-__device__ int deep_check_header(const DeepDecArgs& a) {
-  const int GT = a.vg.Z * a.G;
-  if (a.n_bytes < (unsigned long long)(HEADER_BYTES + 4LL * GT)) return 3;
-  const uint8_t* b = a.bits;
-  if (b[0] != 'D' || b[1] != 'L' || b[2] != 'I' || b[3] != 'C') return 3;
-  if (rd16(b + 4) != 1u || rd16(b + 6) != (uint32_t)a.hf.flags) return 3;
-  if (rd32(b + 8) != (uint32_t)(a.vg.Z * a.H) || rd32(b + 12) != (uint32_t)a.W) return 3;
-  if (b[19] != SKEW || b[24] != PROB_BITS) return 3;
-  if (b[25] != (uint8_t)a.L || rd16(b + 26) != (uint32_t)GT) return 3;
-  const uint64_t fp = (uint64_t)rd32(b + 28) | ((uint64_t)rd32(b + 32) << 32);
-  if (b[16] != (uint8_t)a.hf.k_in || b[17] != 0 || b[18] != (uint8_t)a.hf.dtype ||
-      rd16(b + 20) != (uint32_t)a.hf.h1 || rd16(b + 22) != (uint32_t)a.hf.h2 ||
-      fp != a.hf.fingerprint)
-    return 4;
-  return 0;
-}
 
 template <int H, int KIN>
 __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArgs a) {
@@ -544,7 +406,8 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
         const bool valid = y <= y_hi;
         const int xx = valid ? (int)(tz - (long long)SKEW * y) : 0;
         const bf16x8 xin =
-            deep_features<KIN>(a.K, a.img, a.H, a.W, a.vg.ws, z, valid ? y : 0, xx, valid, q);
+            deep_features<KIN, uint8_t>(a.K->scale, (const uint8_t*)a.img, a.H, a.W, a.vg.ws, z,
+                                        valid ? y : 0, xx, valid, q);
         deep_run_wg<H>(a.net, xin, s_act, sm);
         if (wave == 0) {
           const DeepBlock blk = deep_softmax_lds(sm);
@@ -554,7 +417,7 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
 #pragma unroll 4
           for (int kk = 0; kk < 64; ++kk) {
             const int v = 64 * q + kk;
-            if (valid) tab[v] = (uint16_t)(v == 0 ? 0u : deep_F(v, blk.off + L));
+            if (valid) tab[v] = (uint16_t)(v == 0 ? 0u : deep_F(v, blk.off + L, M_PRIME));
             L = L + row[kk];
           }
         }
@@ -607,7 +470,7 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
         }
         if (act) x = ren ? ((xd << 16) | wv) : xd;
         Pw += (uint32_t)__popcll(m);
-        if (act) a.img[(long long)Y * a.W + xc] = (uint8_t)v;
+        if (act) reinterpret_cast<uint8_t*>(a.img)[(long long)Y * a.W + xc] = (uint8_t)v;
       }
     }
     alive = grid_sync(a.bar, a.abort_flag, k_bar, a.spin_limit);

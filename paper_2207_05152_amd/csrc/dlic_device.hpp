@@ -36,6 +36,7 @@ struct Consts {
   float2 sd[LUT_N];   // (S_j, D_j): knot value and exact slope to the next knot
   float beta[257];    // FP32 bin edges, beta[0] = -inf, beta[256] = +inf
   float scale[256];   // RN32((2v - 255) / 255)
+  float scale12[4096];  // RN32((2v - 4095) / 4095), 12-bit samples
 };
 
 // Network weights as the kernels see them: row-major [out][in] matrices in

@@ -127,9 +127,11 @@ int probe_links(int probe);
 constexpr int DEEP_LAYERS = 6;
 constexpr int DEEP_OUT = 256;
 constexpr int K_IN_3D = 21;   // the 12-pixel window plus 3 x 3 pixels of the slice below
+constexpr int DEEP_OUT12 = 4096;  // output levels of 12-bit samples
 struct DeepNetArgs {
   int H;                        // hidden width (64 or 128)
   int k_in;                     // K_IN, or K_IN_3D for volumes
+  int nout;                     // DEEP_OUT, or DEEP_OUT12 for 12-bit samples
   const void* wop;              // weights in MFMA operand order (deep_pack_weights)
   const float* b[DEEP_LAYERS];  // FP32 biases
 };
@@ -139,10 +141,11 @@ struct DeepNetArgs {
 struct VolGeom {
   int Z = 1, ws = 0, lag = 0;
 };
-// Bytes of the operand-order weights of a k_in -> H x 5 -> 256 net (k_in <= 32).
-size_t deep_wop_bytes(int H);
+// Bytes of the operand-order weights of a k_in -> H x 5 -> nout net (k_in <= 32).
+size_t deep_wop_bytes(int H, int nout);
 // Rearrange row-major BF16 weights (w[i]: [out][in]) into operand order at wop.
-void launch_deep_pack(int H, int k_in, const uint16_t* const* w, void* wop, hipStream_t s);
+void launch_deep_pack(int H, int k_in, int nout, const uint16_t* const* w, void* wop,
+                      hipStream_t s);
 // Encoder density: packed interval c | (f - 1) << 16 of every pixel (raster
 // order of the stacked image) by the softmax table rule; optionally the FP32
 // logits [n][256] and the tables F(0..255) [n][256] (u16).  H: rows per slice.
@@ -155,11 +158,16 @@ struct DeepDecArgs {
   const Consts* K;
   const uint8_t* bits;
   unsigned long long n_bytes;
-  uint8_t* img;
+  void* img;          // u8 samples, or u16 for 12-bit ones
   int H, W, G, L;     // H: rows per slice; G: groups per slice
   VolGeom vg;
   long long T;        // W + 3 (H - 1) + lag (Z - 1)
-  uint16_t* tables;   // [Z H][256]: F(0..255) of each row's pixel of the current step
+  uint16_t* tables;   // [Z H][levels]: F(0..levels-1) of each row's pixel of the current step
+  // 12-bit decoder: the step's tiles (last hidden layer as operands, first row
+  // and row count) and each row's logits [Z H][4096]
+  void* h5;
+  int2* tile_rows;
+  float* logits;
   unsigned* bar;      // grid barrier counter, cleared before launch
   int* abort_flag;    // cleared before launch
   int* status;
@@ -169,6 +177,27 @@ struct DeepDecArgs {
 // Cooperative launch of the per-step decoder; returns the hipError of the launch.
 hipError_t launch_deep_decode(const DeepDecArgs& a, int grid, hipStream_t s);
 int deep_decode_max_grid(int H, int k_in);
+
+// ---- 12-bit samples: 4096 output levels ----------------------------------
+// Encoder stages over pixels [px0, px0 + n) of the stacked image (u16
+// samples): hidden layers of every 16-pixel tile into h5 (operand order,
+// NK * 64 bf16x8 per tile); the output layer as a GEMM into logits [n][4096]
+// FP32; the table rule per pixel into packed intervals cf[px] (and optionally
+// tables [n][4096] u16).  bad: set to 1 where a sample exceeds 4095.
+bool launch_deep12_hidden(const Consts* K, const DeepNetArgs& net, const uint16_t* img, int H,
+                          int W, const VolGeom& vg, long long px0, long long n, void* h5,
+                          int* bad, hipStream_t s);
+bool launch_deep12_logits(const DeepNetArgs& net, const void* h5, long long n_px,
+                          float* logits, hipStream_t s);
+void launch_deep12_softmax(const float* logits, const uint16_t* img, long long px0, long long n,
+                           uint32_t* cf, uint16_t* tables, hipStream_t s);
+// Zero *out_len when bad is set (the stream of an invalid image is empty).
+void launch_deep12_reject(const int* bad, uint64_t* out_len, hipStream_t s);
+// Cooperative per-step decoder of 12-bit streams (four grid barriers a step).
+hipError_t launch_deep12_decode(const DeepDecArgs& a, int grid, hipStream_t s);
+int deep12_decode_max_grid(int H, int k_in);
+// h5 bytes of one 16-pixel tile
+inline size_t deep12_tile_bytes(int H) { return (size_t)H * 16 * 2; }
 constexpr int DEEP_WAVES = 4;  // waves per workgroup of the deep kernels
 
 // Training: waves per workgroup of the FP32 / FP64 loss-and-gradient kernel.

@@ -74,8 +74,16 @@ def test_volume_bound_workspace_and_peek():
     assert L.dlic_volume_encode_bound(0, 256, 256, ctypes.byref(c)) == 0
     assert L.dlic_volume_encode_bound(4096, 256, 256, ctypes.byref(c)) == 0
     assert L.dlic_volume_encode_bound(200, 256, 256, ctypes.byref(c)) == 0   # 1600 groups
-    assert L.dlic_volume_workspace(35, 256, 256, ctypes.byref(c), 128, 1) >= 35 * 256 * 512
-    assert L.dlic_volume_workspace(35, 256, 256, ctypes.byref(c), 96, 1) == 0
+    ptrs = (ctypes.c_void_p * 6)(*([16] * 6))       # never dereferenced by these host calls
+    m = dl.dlic_deep_model(128, 21, ptrs, ptrs, 0, 8)
+    assert L.dlic_volume_workspace(ctypes.byref(m), 35, 256, 256, ctypes.byref(c), 1) >= 35 * 256 * 512
+    m12 = dl.dlic_deep_model(128, 21, ptrs, ptrs, 0, 12)
+    # 12-bit decoding keeps each row's table and logits: 24 KB per row
+    assert L.dlic_volume_workspace(ctypes.byref(m12), 35, 256, 256, ctypes.byref(c), 1) >= \
+        35 * 256 * (8192 + 16384)
+    for bad in (dl.dlic_deep_model(96, 21, ptrs, ptrs, 0, 8), dl.dlic_deep_model(128, 21, ptrs, ptrs, 0, 10),
+                dl.dlic_deep_model(128, 13, ptrs, ptrs, 0, 8)):
+        assert L.dlic_volume_workspace(ctypes.byref(bad), 35, 256, 256, ctypes.byref(c), 1) == 0
     hdr = oracle.pack_header(35 * 256, 256, 35 * 8, 8, dtype=1, h1=128, h2=128, n_mix=0, k_in=21,
                              flags=oracle.volume.volume_flags(35, 2))
     p = dl.dlic_peek_volume(hdr)
@@ -85,6 +93,15 @@ def test_volume_bound_workspace_and_peek():
         dl.dlic_peek_volume(oracle.pack_header(256, 256, 8, 8))
     with pytest.raises(dl.DlicError):   # rows not a multiple of the slices
         dl.dlic_peek_volume(oracle.pack_header(257, 256, 35, 8, flags=35))
+
+
+@pytest.mark.parametrize("depth", [8, 12])
+def test_host_scale_matches_oracle_bit_for_bit(depth):
+    got = dl.dlic_host_scale(depth)
+    want = oracle.scale(np.arange(1 << depth), depth).astype(np.float32)
+    assert got.shape == want.shape and np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    with pytest.raises(dl.DlicError):
+        dl.dlic_host_scale(10)
 
 
 def test_peek_header_reads_oracle_header():

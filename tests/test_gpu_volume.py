@@ -196,7 +196,7 @@ def test_errors(dev, net):
     out = torch.empty((3, 14, 18), dtype=torch.uint8, device=dev)
     stt = torch.zeros(1, dtype=torch.int32, device=dev)
     for z, h, ws in [(3, 14, 2), (6, 7, 1)]:
-        wsb = dl.lib().dlic_volume_workspace(z, h, 18, dl.ctypes.byref(coder), H, 1)
+        wsb = dl.dlic_volume_workspace(m, z, h, 18, coder, 1)
         wsp = torch.empty(wsb, dtype=torch.uint8, device=dev)
         say("volume geometry", z, h, ws)
         rc = dl.lib().dlic_volume_decode(dl.ctypes.byref(m.c), dl.ctypes.byref(coder), bits.data_ptr(),
