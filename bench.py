@@ -373,9 +373,9 @@ def batch_sweep(dl, torch, reps=3, tune_budget_s=60.0):
     return res
 
 
-def deep_flops_per_px(hidden):
-    """FLOP per pixel of the six-layer 12 -> H x 5 -> 256 network (2 per MAC)."""
-    return 2 * (12 * hidden + 4 * hidden * hidden + hidden * 256)
+def deep_flops_per_px(hidden, k_in=12, n_out=256):
+    """FLOP per pixel of the six-layer k_in -> H x 5 -> n_out network (2 per MAC)."""
+    return 2 * (k_in * hidden + 4 * hidden * hidden + hidden * n_out)
 
 
 def deep_sweep(dl, torch, img, H, W, hidden=128, layout=(48, 32), reps=2):
@@ -417,16 +417,18 @@ def deep_sweep(dl, torch, img, H, W, hidden=128, layout=(48, 32), reps=2):
 def volume_sweep(dl, torch, hidden=128, Z=35, size=256, layout=(8, 8), shifts=(0, 1, 2), reps=2):
     """Volumes (3-D window and 3-D wavefront) on a 256x256x35 phantom scan, the six-layer
     network with 21 inputs: encode and decode kernel times per window shift, MPix/s, bpp,
-    the step at which the first slice is complete; and the same scan with a 12-input
+    the step at which the first slice is complete; the same scan with a 12-input
     network, once with all slices in one 3-D wavefront and once slice by slice through the
-    image decoder (outside the timed region of the headline step)."""
+    image decoder; and the 12-bit scan with 4096 output levels (outside the timed region of
+    the headline step)."""
     import synth
     vol = torch.from_numpy(synth.mri_volume(2024, depth=Z, size=size)).cuda()
+    vol12 = torch.from_numpy(synth.mri_volume(2024, depth=Z, size=size, bits=12).astype(np.int16)).cuda()
     n_px = vol.numel()
     coder = dl.dlic_coder(*layout)
     T2 = size + 3 * (size - 1)
 
-    def run(m, ws):
+    def run(m, ws, vol=vol):
         dl.dlic_set_timing(True)
         kt = {}
         for r in range(reps + 1):
@@ -441,15 +443,20 @@ def volume_sweep(dl, torch, hidden=128, Z=35, size=256, layout=(8, 8), shifts=(0
         dl.dlic_set_timing(False)
         assert st == 0 and torch.equal(dec, vol), "volume round trip"
         avg = {k: float(np.mean(v)) for k, v in kt.items()}
-        enc = avg["deep_density_kernel"] + avg["rans_encode_kernel"] + avg["pack_kernel"]
-        dcd = avg["deep_decode_kernel"]
+        d12 = m.depth == 12
+        dens = avg["deep12_density" if d12 else "deep_density_kernel"]
+        enc = dens + avg["rans_encode_kernel"] + avg["pack_kernel"]
+        dcd = avg["deep12_decode_kernel" if d12 else "deep_decode_kernel"]
         lag = max(0, 3 * ws - 1) if m.k_in == 21 else 0
         T = T2 + lag * (Z - 1)
+        flop = n_px * deep_flops_per_px(hidden, m.k_in, 1 << m.depth)
         return {"kernel_ms": avg, "encode_mpix_s": n_px / enc / 1e3,
                 "decode_mpix_s": n_px / dcd / 1e3, "decode_ms": dcd,
                 "bpp_total": 8.0 * bits.numel() / n_px, "lag": lag, "steps": T,
                 "first_slice_steps": T2, "decode_grid": dl.dlic_deep_decode_grid(),
-                "decode_us_per_step": dcd * 1e3 / T}
+                "decode_us_per_step": dcd * 1e3 / T,
+                "density_tflops": flop / (dens * 1e-3) / 1e12,
+                "density_frac_bf16_mfma": flop / (dens * 1e-3) / MI355X_BF16_MFMA}
 
     m3 = dl.DeepModel(synth.xavier_deep(hidden, 3, k_in=21), "cuda:0")
     out = {"workload": f"{size}x{size}x{Z} phantom scan (seed 2024), six dense layers "
@@ -469,6 +476,10 @@ def volume_sweep(dl, torch, hidden=128, Z=35, size=256, layout=(8, 8), shifts=(0
         dec, st = dl.deep_decode(bits[z], m2, check=False)
     torch.cuda.synchronize()
     out["slice_by_slice_12_inputs_decode_ms"] = (time.perf_counter() - t0) * 1e3
+    m12 = dl.DeepModel(synth.xavier_deep(hidden, 3, k_in=21, n_out=4096), "cuda:0")
+    out["bits12_window_shift_1"] = run(m12, 1, vol12)
+    out["bits12_params"] = int(sum(W_.size + b.size for W_, b in
+                                   synth.xavier_deep(hidden, 3, k_in=21, n_out=4096)))
     return out
 
 

@@ -386,21 +386,19 @@ dlic_status deep12_stages(const Consts* K, const DeepNetArgs& net, const uint16_
   const long long n = (long long)vg.Z * h * w;
   int* bad = (int*)(base + L.bad);
   launch_fill_u32((uint32_t*)bad, 0u, 1, stream);
+  // one timed span over every chunk's three kernels (the per-kernel split is in
+  // a kernel trace)
+  timing_begin("deep12_density", stream);
   for (long long px0 = 0; px0 < n; px0 += DEEP12_CHUNK) {
     const long long nn = n - px0 < DEEP12_CHUNK ? n - px0 : DEEP12_CHUNK;
     float* lg = d_logits ? d_logits + px0 * DEEP_OUT12 : (float*)(base + L.logits);
-    timing_begin("deep12_hidden_kernel", stream);
     if (!launch_deep12_hidden(K, net, img, h, w, vg, px0, nn, base + L.h5, bad, stream))
       return DLIC_ERR_UNSUPPORTED;
-    timing_end(stream);
-    timing_begin("deep12_logits_kernel", stream);
     if (!launch_deep12_logits(net, base + L.h5, nn, lg, stream)) return DLIC_ERR_UNSUPPORTED;
-    timing_end(stream);
-    timing_begin("deep12_softmax_kernel", stream);
     launch_deep12_softmax(lg, img, px0, nn, d_cf, d_tables ? d_tables + px0 * DEEP_OUT12 : nullptr,
                           stream);
-    timing_end(stream);
   }
+  timing_end(stream);
   return launch_ok();
 }
 
