@@ -96,87 +96,110 @@ __device__ __forceinline__ void deep_run(const DeepNetArgs& d, const bf16x8 x,
 }
 
 // The same network evaluated by the four waves of a workgroup on one tile:
-// wave w computes the neuron tiles nt = w, w + 4, ... of every layer, so it
-// needs a quarter of the weights, all of one layer loaded at once and the next
-// layer's loads issued before this layer's products.  Layer outputs go through
-// LDS as the next layer's BF16 operands (act: two buffers of NK * 64 bf16x8);
-// the logits land in sm[p][v].  Each output tile's accumulation is the same
-// chain of the same MFMAs as in deep_run, so the results are identical.
+// wave w computes the neuron tiles nt = w, w + 4, ... of every layer.  The
+// decoder runs it once per wavefront step with a grid barrier in between,
+// whose acquire invalidates the cache, so the wave keeps its quarter of the
+// weights in registers for the whole launch (WgNet, loaded once) and the
+// biases sit in LDS.  Layer outputs go through LDS as the next layer's BF16
+// operands (act: two buffers of NK * 64 bf16x8); the logits land in sm[p][v].
+// Each output tile's accumulation is the same chain of the same MFMAs as in
+// deep_run, so the results are identical.
 template <int H>
-__device__ __forceinline__ void deep_run_wg(const DeepNetArgs& d, const bf16x8 x, bf16x8* act,
-                                            float* sm) {
-  constexpr int NT = H / 16, NK = H / 32;
-  constexpr int TW = NT / DEEP_WAVES;            // hidden tiles per wave (1 or 2)
-  constexpr int TO = DEEP_OUT / 16 / DEEP_WAVES;  // output tiles per wave (4)
-  constexpr int MAXT = TO > TW ? TO : TW;
+struct WgNet {
+  static constexpr int NT = H / 16, NK = H / 32;
+  static constexpr int TW = NT / DEEP_WAVES;            // hidden tiles per wave (1 or 2)
+  static constexpr int TO = DEEP_OUT / 16 / DEEP_WAVES;  // output tiles per wave (4)
+  static constexpr int NB = (DEEP_LAYERS - 1) * H + DEEP_OUT;  // biases
+  bf16x8 w0[TW];
+  bf16x8 wh[DEEP_LAYERS - 2][TW][NK];
+  bf16x8 wo[TO][NK];
+
+  __device__ __forceinline__ void load(const DeepNetArgs& d, int wave, int lane) {
+    const bf16x8* w = reinterpret_cast<const bf16x8*>(d.wop);
+#pragma unroll
+    for (int i = 0; i < TW; ++i) w0[i] = w[(wave + DEEP_WAVES * i) * 64 + lane];
+#pragma unroll
+    for (int l = 0; l < DEEP_LAYERS - 2; ++l) {
+      const bf16x8* wl = w + deep_off(l + 1, H, DEEP_OUT);
+#pragma unroll
+      for (int i = 0; i < TW; ++i)
+#pragma unroll
+        for (int s = 0; s < NK; ++s) wh[l][i][s] = wl[((wave + DEEP_WAVES * i) * NK + s) * 64 + lane];
+    }
+    const bf16x8* wl = w + deep_off(DEEP_LAYERS - 1, H, DEEP_OUT);
+#pragma unroll
+    for (int i = 0; i < TO; ++i)
+#pragma unroll
+      for (int s = 0; s < NK; ++s) wo[i][s] = wl[((wave + DEEP_WAVES * i) * NK + s) * 64 + lane];
+  }
+  // biases of layer l start at bias_off(l) in the LDS copy
+  static __device__ __forceinline__ int bias_off(int l) { return l * H; }
+};
+
+template <int H>
+__device__ __forceinline__ void deep_stage_biases(const DeepNetArgs& d, float* s_bias) {
+  for (int i = threadIdx.x; i < WgNet<H>::NB; i += blockDim.x) {
+    const int l = i / H < DEEP_LAYERS - 1 ? i / H : DEEP_LAYERS - 1;
+    s_bias[i] = d.b[l][i - l * H];
+  }
+}
+
+template <int H>
+__device__ __forceinline__ void deep_run_wg(const WgNet<H>& n, const float* s_bias,
+                                            const bf16x8 x, bf16x8* act, float* sm) {
+  constexpr int NK = WgNet<H>::NK, TW = WgNet<H>::TW, TO = WgNet<H>::TO;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, p = lane & 15;
-  const bf16x8* w = reinterpret_cast<const bf16x8*>(d.wop);
-  bf16x8 wc[MAXT][NK], wn[MAXT][NK];
-  // layer 0 weights, then layer 1's in flight
-#pragma unroll
-  for (int i = 0; i < TW; ++i) wc[i][0] = w[(wave + DEEP_WAVES * i) * 64 + lane];
-  const bf16x8* wl = w + NT * 64;  // layer 1
-#pragma unroll
-  for (int i = 0; i < TW; ++i)
-#pragma unroll
-    for (int s = 0; s < NK; ++s) wn[i][s] = wl[((wave + DEEP_WAVES * i) * NK + s) * 64 + lane];
   // layer 0
 #pragma unroll
   for (int i = 0; i < TW; ++i) {
     const int nt = wave + DEEP_WAVES * i;
-    const float* b = d.b[0] + 16 * nt + 4 * q;
+    const float* b = s_bias + WgNet<H>::bias_off(0) + 16 * nt + 4 * q;
     f4 acc = {b[0], b[1], b[2], b[3]};
-    acc = mfma_bf16(wc[i][0], x, acc);
+    acc = mfma_bf16(n.w0[i], x, acc);
     // neuron 16 nt + 4 q + r goes to slot e = 4 (nt % 2) + r of lane group q, k-step nt / 2
     __bf16* dst = reinterpret_cast<__bf16*>(&act[(nt >> 1) * 64 + 16 * q + p]) + 4 * (nt & 1);
 #pragma unroll
     for (int r = 0; r < 4; ++r) dst[r] = (__bf16)relu(acc[r]);
   }
   __syncthreads();
-  int cur = 0;
-#pragma unroll 1
-  for (int li = 1; li < DEEP_LAYERS; ++li) {
-    const bool last = li == DEEP_LAYERS - 1;
+  // hidden layers 1 .. 4
 #pragma unroll
-    for (int i = 0; i < MAXT; ++i)
-#pragma unroll
-      for (int s = 0; s < NK; ++s) wc[i][s] = wn[i][s];
-    // the next layer's weights go out before this layer's products
-    const bf16x8* wnext = wl + (long long)NT * NK * 64;
-    if (li + 1 < DEEP_LAYERS) {
-      const int nt_next = li + 1 == DEEP_LAYERS - 1 ? TO : TW;
-#pragma unroll
-      for (int i = 0; i < MAXT; ++i)
-        if (i < nt_next)
-#pragma unroll
-          for (int s = 0; s < NK; ++s)
-            wn[i][s] = wnext[((wave + DEEP_WAVES * i) * NK + s) * 64 + lane];
-    }
+  for (int l = 0; l < DEEP_LAYERS - 2; ++l) {
+    const int cur = l & 1;
     bf16x8 a[NK];
 #pragma unroll
     for (int s = 0; s < NK; ++s) a[s] = act[cur * NK * 64 + s * 64 + lane];
-    const int nt_here = last ? TO : TW;
 #pragma unroll
-    for (int i = 0; i < MAXT; ++i) {
-      if (i >= nt_here) break;
+    for (int i = 0; i < TW; ++i) {
       const int nt = wave + DEEP_WAVES * i;
-      const float* b = d.b[li] + 16 * nt + 4 * q;
+      const float* b = s_bias + WgNet<H>::bias_off(l + 1) + 16 * nt + 4 * q;
       f4 acc = {b[0], b[1], b[2], b[3]};
 #pragma unroll
-      for (int s = 0; s < NK; ++s) acc = mfma_bf16(wc[i][s], a[s], acc);
-      if (last) {
+      for (int s = 0; s < NK; ++s) acc = mfma_bf16(n.wh[l][i][s], a[s], acc);
+      __bf16* dst = reinterpret_cast<__bf16*>(&act[(cur ^ 1) * NK * 64 + (nt >> 1) * 64 +
+                                                   16 * q + p]) + 4 * (nt & 1);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sm[p * SM_ROW + 16 * nt + 4 * q + r] = acc[r];
-      } else {
-        __bf16* dst = reinterpret_cast<__bf16*>(&act[(cur ^ 1) * NK * 64 + (nt >> 1) * 64 +
-                                                     16 * q + p]) + 4 * (nt & 1);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) dst[r] = (__bf16)relu(acc[r]);
-      }
+      for (int r = 0; r < 4; ++r) dst[r] = (__bf16)relu(acc[r]);
     }
-    wl = wnext;
-    cur ^= 1;
+    __syncthreads();
+  }
+  // output layer (its input is buffer (DEEP_LAYERS - 2) & 1)
+  {
+    constexpr int cur = (DEEP_LAYERS - 2) & 1;
+    bf16x8 a[NK];
+#pragma unroll
+    for (int s = 0; s < NK; ++s) a[s] = act[cur * NK * 64 + s * 64 + lane];
+#pragma unroll
+    for (int i = 0; i < TO; ++i) {
+      const int nt = wave + DEEP_WAVES * i;
+      const float* b = s_bias + WgNet<H>::bias_off(DEEP_LAYERS - 1) + 16 * nt + 4 * q;
+      f4 acc = {b[0], b[1], b[2], b[3]};
+#pragma unroll
+      for (int s = 0; s < NK; ++s) acc = mfma_bf16(n.wo[i][s], a[s], acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sm[p * SM_ROW + 16 * nt + 4 * q + r] = acc[r];
+    }
     __syncthreads();
   }
 }
@@ -226,39 +249,65 @@ __device__ __forceinline__ DeepBlock deep_softmax(float (&o)[DEEP_OUT / 16][4], 
   return blk;
 }
 
-// As deep_softmax, with the logits already in sm[p][v] (one wave).
-__device__ __forceinline__ DeepBlock deep_softmax_lds(float* sm) {
+// The decoder's table rule for the 16 pixels of a tile (one wave), logits in
+// sm[p][v]: lane (b, p) = (l / 16, l % 16) takes block b of pixel p into
+// registers and writes F(64 b .. 64 b + 63) of that pixel to tab (256 u16 per
+// pixel; pixel p's row at tab_p).  The same operations in the same order as
+// deep_softmax and the encoder's table loop, so the tables are the encoder's.
+__device__ __forceinline__ void deep_tables_reg(const float* sm, uint16_t* tab_p, bool valid) {
   const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
   const int p = lane & 15, q = lane >> 4;
-  float* row = sm + p * SM_ROW + 64 * q;
-  float m = row[0];
-#pragma unroll 8
-  for (int k = 1; k < 64; ++k) m = fmaxf(m, row[k]);
+  const f4* src = reinterpret_cast<const f4*>(sm + p * SM_ROW + 64 * q);
+  float v[64];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const f4 t = src[j];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[4 * j + r] = t[r];
+  }
+  float m = v[0];
+#pragma unroll
+  for (int k = 1; k < 64; ++k) m = fmaxf(m, v[k]);
   m = fmaxf(m, __shfl_xor(m, 16));
   m = fmaxf(m, __shfl_xor(m, 32));
   float sb = 0.0f;
-#pragma unroll 8
+#pragma unroll
   for (int k = 0; k < 64; ++k) {
-    const float e = expf(row[k] - m);
-    row[k] = e;
-    sb = sb + e;
+    v[k] = expf(v[k] - m);
+    sb = sb + v[k];
   }
   const float s0 = __shfl(sb, p), s1 = __shfl(sb, p + 16), s2 = __shfl(sb, p + 32),
               s3 = __shfl(sb, p + 48);
   const float S = ((s0 + s1) + s2) + s3;
   const float rr = 1.0f / S;
   float tb = 0.0f;
-#pragma unroll 8
+#pragma unroll
   for (int k = 0; k < 64; ++k) {
-    const float pv = row[k] * rr;
-    row[k] = pv;
-    tb = tb + pv;
+    v[k] = v[k] * rr;
+    tb = tb + v[k];
   }
   const float t0 = __shfl(tb, p), t1 = __shfl(tb, p + 16), t2 = __shfl(tb, p + 32);
   const float o1 = t0, o2 = o1 + t1, o3 = o2 + t2;
-  DeepBlock blk;
-  blk.off = q == 0 ? 0.0f : (q == 1 ? o1 : (q == 2 ? o2 : o3));
-  return blk;
+  const float off = q == 0 ? 0.0f : (q == 1 ? o1 : (q == 2 ? o2 : o3));
+  float L = 0.0f;
+  uint4* dst = reinterpret_cast<uint4*>(tab_p + 64 * q);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    uint32_t w[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      uint32_t pair = 0;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int k = 8 * j + 2 * h + e, lv = 64 * q + k;
+        const uint32_t Fv = lv == 0 ? 0u : deep_F(lv, off + L, M_PRIME);
+        pair |= Fv << (16 * e);
+        L = L + v[k];
+      }
+      w[h] = pair;
+    }
+    if (valid) dst[j] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
 }
 
 // Encoder side: every pixel's interval (and optionally logits / tables).
@@ -343,11 +392,17 @@ template <int H, int KIN>
 __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArgs a) {
   __shared__ float s_sm[16 * SM_ROW];
   __shared__ bf16x8 s_act[2 * (H / 32) * 64];
+  __shared__ float s_bias[WgNet<H>::NB];
+  __shared__ float s_scale[256];
   __shared__ int s_err;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = lane & 15, q = lane >> 4;
   float* sm = s_sm;
   if (threadIdx.x == 0) s_err = deep_check_header(a);
+  deep_stage_biases<H>(a.net, s_bias);
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) s_scale[i] = a.K->scale[i];
+  WgNet<H> wnet;
+  wnet.load(a.net, wave, lane);
   __syncthreads();
   const int err = __builtin_amdgcn_readfirstlane(s_err);
   const int Z = a.vg.Z, lag = a.vg.lag;
@@ -406,21 +461,11 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
         const bool valid = y <= y_hi;
         const int xx = valid ? (int)(tz - (long long)SKEW * y) : 0;
         const bf16x8 xin =
-            deep_features<KIN, uint8_t>(a.K->scale, (const uint8_t*)a.img, a.H, a.W, a.vg.ws, z,
+            deep_features<KIN, uint8_t>(s_scale, (const uint8_t*)a.img, a.H, a.W, a.vg.ws, z,
                                         valid ? y : 0, xx, valid, q);
-        deep_run_wg<H>(a.net, xin, s_act, sm);
-        if (wave == 0) {
-          const DeepBlock blk = deep_softmax_lds(sm);
-          const float* row = sm + p * SM_ROW + 64 * q;
-          float L = 0.0f;
-          uint16_t* tab = a.tables + (long long)(z * a.H + (valid ? y : 0)) * DEEP_OUT;
-#pragma unroll 4
-          for (int kk = 0; kk < 64; ++kk) {
-            const int v = 64 * q + kk;
-            if (valid) tab[v] = (uint16_t)(v == 0 ? 0u : deep_F(v, blk.off + L, M_PRIME));
-            L = L + row[kk];
-          }
-        }
+        deep_run_wg<H>(wnet, s_bias, xin, s_act, sm);
+        if (wave == 0)
+          deep_tables_reg(sm, a.tables + (long long)(z * a.H + (valid ? y : 0)) * DEEP_OUT, valid);
         __syncthreads();
       }
       base += nt;
