@@ -65,63 +65,42 @@ __device__ __forceinline__ T sigmoid(T x) {
   return e / (T(1) + e);
 }
 
-// Loss (bits) of one sample and d loss / d o (scaled by `scale`) into d[15].
+// One mixture component of one sample: the log mass lp_k of bin v (before the
+// mixture weight) and the factors of its mean and log-scale derivatives,
+// u_mu = inv_s (dA + dB) and u_ls = A dA + B dB (0 where the clamp binds).
+// hi, lo: the bin's upper and lower edges (0 where unused).
 template <typename T>
-__device__ T sample_loss_grad(const T* o, int v, T scale, T* d) {
-  const T LN2 = T(0.69314718055994530942);
-  T m = o[0];
-#pragma unroll
-  for (int k = 1; k < N_MIX; ++k) m = o[k] > m ? o[k] : m;
-  T se = T(0);
-#pragma unroll
-  for (int k = 0; k < N_MIX; ++k) se += Mma<T>::exp_(o[k] - m);
-  const T lse = m + Mma<T>::log_(se);
-  const T hi = (v < 255) ? (T(2 * v + 1) / T(255) - T(1)) : T(0);
-  const T lo = (v > 0) ? (T(2 * v - 1) / T(255) - T(1)) : T(0);
-  T lp[N_MIX], dA[N_MIX], dB[N_MIX], Av[N_MIX], Bv[N_MIX], is[N_MIX];
-#pragma unroll
-  for (int k = 0; k < N_MIX; ++k) {
-    const T mu = o[N_MIX + k];
-    const T ls = o[2 * N_MIX + k] > T(LOG_SCALE_MIN) ? o[2 * N_MIX + k] : T(LOG_SCALE_MIN);
-    is[k] = Mma<T>::exp_(-ls);
-    const T A = (hi - mu) * is[k], B = (lo - mu) * is[k];
-    Av[k] = A;
-    Bv[k] = B;
-    T lpk;
-    if (v == 0) {
-      lpk = -softplus(-A);
-      dA[k] = sigmoid(-A);
-      dB[k] = T(0);
-    } else if (v == 255) {
-      lpk = -softplus(B);
-      dA[k] = T(0);
-      dB[k] = -sigmoid(B);
-    } else {
-      const T em = Mma<T>::expm1_(A - B);        // > 0
-      lpk = -softplus(-A) - softplus(B) + Mma<T>::log_(-Mma<T>::expm1_(B - A));
-      const T E = T(1) / em;
-      dA[k] = sigmoid(-A) + E;
-      dB[k] = -sigmoid(B) - E;
-    }
-    lp[k] = (o[k] - lse) + lpk;
+struct CompTerms {
+  T lpk, u_mu, u_ls;
+};
+
+template <typename T>
+__device__ __forceinline__ CompTerms<T> component_terms(const T* o, int k, int v, T hi, T lo) {
+  CompTerms<T> c;
+  const T mu = o[N_MIX + k];
+  const bool free_ls = o[2 * N_MIX + k] > T(LOG_SCALE_MIN);
+  const T ls = free_ls ? o[2 * N_MIX + k] : T(LOG_SCALE_MIN);
+  const T is = Mma<T>::exp_(-ls);
+  const T A = (hi - mu) * is, B = (lo - mu) * is;
+  T dA, dB;
+  if (v == 0) {
+    c.lpk = -softplus(-A);
+    dA = sigmoid(-A);
+    dB = T(0);
+  } else if (v == 255) {
+    c.lpk = -softplus(B);
+    dA = T(0);
+    dB = -sigmoid(B);
+  } else {
+    const T em = Mma<T>::expm1_(A - B);  // > 0
+    c.lpk = -softplus(-A) - softplus(B) + Mma<T>::log_(-Mma<T>::expm1_(B - A));
+    const T E = T(1) / em;
+    dA = sigmoid(-A) + E;
+    dB = -sigmoid(B) - E;
   }
-  T mx = lp[0];
-#pragma unroll
-  for (int k = 1; k < N_MIX; ++k) mx = lp[k] > mx ? lp[k] : mx;
-  T s = T(0);
-#pragma unroll
-  for (int k = 0; k < N_MIX; ++k) s += Mma<T>::exp_(lp[k] - mx);
-  const T LP = mx + Mma<T>::log_(s);
-#pragma unroll
-  for (int k = 0; k < N_MIX; ++k) {
-    const T r = Mma<T>::exp_(lp[k] - LP);
-    const T pi = Mma<T>::exp_(o[k] - lse);
-    d[k] = (pi - r) * scale;
-    d[N_MIX + k] = r * is[k] * (dA[k] + dB[k]) * scale;
-    d[2 * N_MIX + k] =
-        (o[2 * N_MIX + k] > T(LOG_SCALE_MIN)) ? r * (Av[k] * dA[k] + Bv[k] * dB[k]) * scale : T(0);
-  }
-  return -LP / LN2;
+  c.u_mu = is * (dA + dB);
+  c.u_ls = free_ls ? A * dA + B * dB : T(0);
+  return c;
 }
 
 template <typename T>
@@ -285,24 +264,60 @@ __global__ __launch_bounds__(WAVES * 64) void nll_fwd_bwd_kernel(TrainArgs<T> a)
 #pragma unroll
       for (int r = 0; r < 4; ++r) so[i16 * 16 + Mma<T>::row(q, r)] = acc[r];
     }
-    // ---- loss and d loss / d o, one lane per sample
-    if (lane < 16) {
-      T o[N_OUT], d[N_OUT];
+    // ---- loss and d loss / d o: lane group q of sample i16 takes mixture
+    // component q (and group 0 component 4 as well); the five log masses meet
+    // through shuffles, and every lane then has the sample's loss
+    {
+      T o[N_OUT];
 #pragma unroll
-      for (int k = 0; k < N_OUT; ++k) o[k] = so[lane * 16 + k];
-      if (valid) {
-        const int v = sl[(long long)py * a.sw + px];
-        lsum += sample_loss_grad(o, v, a.scale, d);
-      } else {
+      for (int k = 0; k < N_OUT; ++k) o[k] = so[i16 * 16 + k];
+      const T LN2 = T(0.69314718055994530942);
+      const int v = valid ? (int)sl[(long long)py * a.sw + px] : 0;
+      T m = o[0];
 #pragma unroll
-        for (int k = 0; k < N_OUT; ++k) d[k] = T(0);
+      for (int k = 1; k < N_MIX; ++k) m = o[k] > m ? o[k] : m;
+      T se = T(0);
+#pragma unroll
+      for (int k = 0; k < N_MIX; ++k) se += Mma<T>::exp_(o[k] - m);
+      const T lse = m + Mma<T>::log_(se);
+      const T hi = (v < 255) ? (T(2 * v + 1) / T(255) - T(1)) : T(0);
+      const T lo = (v > 0) ? (T(2 * v - 1) / T(255) - T(1)) : T(0);
+      const CompTerms<T> ca = component_terms(o, q, v, hi, lo);
+      const CompTerms<T> cb = component_terms(o, N_MIX - 1, v, hi, lo);  // used by group 0
+      const T lpa = (o[q] - lse) + ca.lpk;
+      const T lpb = (o[N_MIX - 1] - lse) + cb.lpk;
+      T lp[N_MIX];
+#pragma unroll
+      for (int k = 0; k < N_MIX - 1; ++k) lp[k] = __shfl(lpa, i16 + 16 * k);
+      lp[N_MIX - 1] = __shfl(lpb, i16);
+      T mx = lp[0];
+#pragma unroll
+      for (int k = 1; k < N_MIX; ++k) mx = lp[k] > mx ? lp[k] : mx;
+      T ssum = T(0);
+#pragma unroll
+      for (int k = 0; k < N_MIX; ++k) ssum += Mma<T>::exp_(lp[k] - mx);
+      const T LP = mx + Mma<T>::log_(ssum);
+      const T sc = valid ? a.scale : T(0);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        if (c == 1 && q != 0) break;
+        const int k = c == 0 ? q : N_MIX - 1;
+        const CompTerms<T>& t = c == 0 ? ca : cb;
+        const T r = Mma<T>::exp_(lp[k] - LP);
+        const T pi = Mma<T>::exp_(o[k] - lse);
+        so[i16 * 16 + k] = (pi - r) * sc;
+        so[i16 * 16 + N_MIX + k] = r * t.u_mu * sc;
+        so[i16 * 16 + 2 * N_MIX + k] = r * t.u_ls * sc;
       }
-#pragma unroll
-      for (int k = 0; k < N_OUT; ++k) {
-        so[lane * 16 + k] = d[k];
-        gb3[k] += d[k];
+      if (q == 0) {
+        so[i16 * 16 + 15] = T(0);
+        if (valid) lsum += -LP / LN2;
       }
-      so[lane * 16 + 15] = T(0);
+      wave_lds_handover();
+      if (q == 0) {
+#pragma unroll
+        for (int k = 0; k < N_OUT; ++k) gb3[k] += so[i16 * 16 + k];
+      }
     }
     if (!a.want_grad) continue;
     wave_lds_handover();
