@@ -76,17 +76,18 @@ __device__ __forceinline__ bf16x8 deep_features(const float* __restrict__ sc, co
 // the output layer's operand a[s] (slot e: neuron 32 s + 16 (e / 4) +
 // 4 (l / 16) + e % 4 of that pixel, as BF16).  Bias-seeded FP32 accumulation,
 // one chain of MFMAs per neuron tile in k order, ReLU, then BF16.
-template <int H>
-__device__ __forceinline__ void deep_hidden(const DeepNetArgs& d, const bf16x8 x,
-                                            bf16x8 (&a)[H / 32]) {
+// w: the operand-order weights from layer 1 on; bias(l): layer l's biases
+// (global memory, or copies in LDS).
+template <int H, class Bias>
+__device__ __forceinline__ void deep_hidden_at(const bf16x8* w, Bias bias, const bf16x8 x,
+                                               bf16x8 (&a)[H / 32]) {
   constexpr int NT = H / 16, NK = H / 32;
   const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
   const int q = lane >> 4;
-  const bf16x8* w = reinterpret_cast<const bf16x8*>(d.wop);
   float h[NT][4];
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
-    const float* b = d.b[0] + 16 * nt + 4 * q;
+    const float* b = bias(0) + 16 * nt + 4 * q;
     f4 acc = {b[0], b[1], b[2], b[3]};
     acc = mfma_bf16(w[nt * 64 + lane], x, acc);
 #pragma unroll
@@ -101,7 +102,7 @@ __device__ __forceinline__ void deep_hidden(const DeepNetArgs& d, const bf16x8 x
       for (int e = 0; e < 8; ++e) a[s][e] = (__bf16)h[2 * s + (e >> 2)][e & 3];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const float* b = d.b[li] + 16 * nt + 4 * q;
+      const float* b = bias(li) + 16 * nt + 4 * q;
       f4 acc = {b[0], b[1], b[2], b[3]};
 #pragma unroll
       for (int s = 0; s < NK; ++s) acc = mfma_bf16(w[(nt * NK + s) * 64 + lane], a[s], acc);
@@ -114,6 +115,12 @@ __device__ __forceinline__ void deep_hidden(const DeepNetArgs& d, const bf16x8 x
   for (int s = 0; s < NK; ++s)
 #pragma unroll
     for (int e = 0; e < 8; ++e) a[s][e] = (__bf16)h[2 * s + (e >> 2)][e & 3];
+}
+
+template <int H>
+__device__ __forceinline__ void deep_hidden(const DeepNetArgs& d, const bf16x8 x,
+                                            bf16x8 (&a)[H / 32]) {
+  deep_hidden_at<H>(reinterpret_cast<const bf16x8*>(d.wop), [&](int l) { return d.b[l]; }, x, a);
 }
 
 __device__ __forceinline__ uint32_t rd32(const uint8_t* p) {

@@ -132,22 +132,24 @@ __device__ __forceinline__ float lane_value(float v, int j) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), j));
 }
 
-// One pixel's 4096 logits (one wave; lane b holds block b, levels 64 b ..
-// 64 b + 63): afterwards pv[k] = p_v of level 64 b + k and off = O_b.
-__device__ __forceinline__ void deep12_rule(const float* __restrict__ lg, float (&pv)[64],
-                                            float& off) {
-  const int b = threadIdx.x & 63;
-  const f4* src = reinterpret_cast<const f4*>(lg + 64 * b);
-  float m = -INFINITY;
+// Lane b's block of one pixel's logits: levels 64 b .. 64 b + 63.
+__device__ __forceinline__ void deep12_load_block(const float* __restrict__ lg, float (&pv)[64]) {
+  const f4* src = reinterpret_cast<const f4*>(lg + 64 * (threadIdx.x & 63));
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const f4 v = src[j];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      pv[4 * j + r] = v[r];
-      m = fmaxf(m, v[r]);
-    }
+    for (int r = 0; r < 4; ++r) pv[4 * j + r] = v[r];
   }
+}
+
+// The rule on one pixel's logits, lane b holding block b in pv (one wave):
+// afterwards pv[k] = p_v of level 64 b + k and off = O_b.
+__device__ __forceinline__ void deep12_rule_regs(float (&pv)[64], float& off) {
+  const int b = threadIdx.x & 63;
+  float m = pv[0];
+#pragma unroll
+  for (int k = 1; k < 64; ++k) m = fmaxf(m, pv[k]);
 #pragma unroll
   for (int sh = 32; sh >= 1; sh >>= 1) m = fmaxf(m, __shfl_xor(m, sh));
   float sb = 0.0f;
@@ -171,6 +173,12 @@ __device__ __forceinline__ void deep12_rule(const float* __restrict__ lg, float 
     if (j < b) o = o + t;
   }
   off = o;
+}
+
+__device__ __forceinline__ void deep12_rule(const float* __restrict__ lg, float (&pv)[64],
+                                            float& off) {
+  deep12_load_block(lg, pv);
+  deep12_rule_regs(pv, off);
 }
 
 // Table of one pixel: F(0..4095) as u16 (F(0) = 0), 8 levels per 16-byte store.
@@ -233,13 +241,31 @@ __global__ void deep12_reject_kernel(const int* bad, uint64_t* out_len) {
 }
 
 // ---- decoder ------------------------------------------------------------------
+// The hidden layers' weights and biases and the input scale of the decoder,
+// copied to LDS once: a grid barrier's acquire invalidates the cache every step.
+template <int H>
+struct Hidden12Lds {
+  static constexpr long long N_OPS = deep_off(DEEP_LAYERS - 1, H, N12);  // bf16x8
+  static constexpr int N_BIAS = (DEEP_LAYERS - 1) * H;
+};
+
 template <int H, int KIN>
 __global__ __launch_bounds__(DEEP_WAVES * 64) void deep12_decode_kernel(DeepDecArgs a) {
   constexpr int NK = H / 32;
+  __shared__ bf16x8 s_w[Hidden12Lds<H>::N_OPS];
+  __shared__ float s_b[Hidden12Lds<H>::N_BIAS];
+  __shared__ float s_scale[N12];
   __shared__ int s_err;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = lane & 15, q = lane >> 4;
   if (threadIdx.x == 0) s_err = deep_check_header(a);
+  {
+    const bf16x8* w = reinterpret_cast<const bf16x8*>(a.net.wop);
+    for (int i = threadIdx.x; i < Hidden12Lds<H>::N_OPS; i += blockDim.x) s_w[i] = w[i];
+    for (int i = threadIdx.x; i < Hidden12Lds<H>::N_BIAS; i += blockDim.x)
+      s_b[i] = a.net.b[i / H][i % H];
+    for (int i = threadIdx.x; i < N12; i += blockDim.x) s_scale[i] = a.K->scale12[i];
+  }
   __syncthreads();
   const int err = __builtin_amdgcn_readfirstlane(s_err);
   const int Z = a.vg.Z, lag = a.vg.lag;
@@ -301,10 +327,10 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep12_decode_kernel(DeepDecA
         const int y = y0 + p;
         const bool valid = y <= y_hi;
         const int xx = valid ? (int)(tz - (long long)SKEW * y) : 0;
-        const bf16x8 xin = deep_features<KIN, uint16_t>(a.K->scale12, img, a.H, a.W, a.vg.ws, z,
+        const bf16x8 xin = deep_features<KIN, uint16_t>(s_scale, img, a.H, a.W, a.vg.ws, z,
                                                         valid ? y : 0, xx, valid, q);
         bf16x8 av[NK];
-        deep_hidden<H>(a.net, xin, av);
+        deep_hidden_at<H>(s_w, [&](int l) { return s_b + l * H; }, xin, av);
 #pragma unroll
         for (int s = 0; s < NK; ++s) h5[((long long)k * NK + s) * 64 + lane] = av[s];
         if (lane == 0) a.tile_rows[k] = make_int2(z * a.H + y0, y_hi - y0 + 1 < 16 ? y_hi - y0 + 1 : 16);
