@@ -331,7 +331,8 @@ constexpr long long DEEP12_CHUNK = 16384;
 //  decode: tables [Z H][levels] u16; 12-bit: logits [Z H][4096], h5 and rows
 //          of a step's tiles; 256 bytes of barrier state.
 struct DeepWs {
-  size_t wop = 0, h5 = 0, logits = 0, bad = 0, enc = 0, tables = 0, rows = 0, ctl = 0, total = 0;
+  size_t wop = 0, h5 = 0, logits = 0, bad = 0, enc = 0, tables = 0, steps = 0, rows = 0, ctl = 0,
+         total = 0;
 };
 
 DeepWs deep_ws(int z, int h, int w, const dlic_coder* coder, int hidden, int depth, int decode) {
@@ -356,6 +357,8 @@ DeepWs deep_ws(int z, int h, int w, const dlic_coder* coder, int hidden, int dep
   } else {
     o.tables = at;
     at += align256((size_t)z * h * nout * 2);
+    o.steps = at;  // per row: newest pixel step, newest table step
+    at += align256((size_t)z * h * 2 * sizeof(int));
     if (depth == 12) {
       const size_t tiles = (size_t)deep_step_tiles(z, h, w);
       o.logits = at;
@@ -504,6 +507,8 @@ dlic_status deep_decode_impl(const dlic_deep_model* model, const dlic_coder* cod
     a.tile_rows = (int2*)(base + L.rows);
   }
   uint32_t* ctl = (uint32_t*)(base + L.ctl);
+  a.pix_step = (int*)(base + L.steps);
+  a.tab_step = a.pix_step + (size_t)vg.Z * h;
   a.bar = ctl;
   a.abort_flag = (int*)(ctl + 16);
   a.status = d_status;
@@ -511,6 +516,7 @@ dlic_status deep_decode_impl(const dlic_deep_model* model, const dlic_coder* cod
   a.hf = hf;
   if ((rc = deep_stage(model, d_ws, stream)) != DLIC_OK) return rc;
   launch_fill_u32(ctl, 0u, 64, stream);
+  launch_fill_u32((uint32_t*)a.pix_step, 0xFFFFFFFFu, 2LL * vg.Z * h, stream);
   launch_fill_u32((uint32_t*)d_status, 0u, 1, stream);
   if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
   g_deep_grid_used = grid;

@@ -20,11 +20,16 @@
 //
 // Decoding follows the paper's GPU scheme (Section II-B, Preprocessor: all
 // pixels of one wavefront step enter the network as one matrix): one
-// cooperative launch walks the steps; in each, the whole grid evaluates the
-// network for the step's pixels (one 16-pixel tile per workgroup, its layers
-// split over the four waves) and writes their tables, a grid barrier, every
-// group's wave decodes its rows' pixels of the step from those tables, a grid
-// barrier.  Weights do not fit a CU's LDS (200 KB at H = 128), so every tile
+// cooperative launch walks the steps; in each, the grid evaluates the network
+// for the step's pixels (one 16-pixel tile per workgroup, its layers split
+// over the four waves) and writes their tables, then every group's wave
+// decodes its rows' pixels of the step from those tables.  Instead of grid
+// barriers between the phases, each row carries two progress counters: the
+// step of its newest table and of its newest decoded pixel.  A tile waits for
+// the pixels its windows read (rows above, its own rows' left neighbours, the
+// slice below), a group for its rows' tables; every wait is for an event of an
+// earlier step or phase, which every workgroup reaches in the same order, so
+// with all workgroups resident the pipeline cannot deadlock.  Weights do not fit a CU's LDS (200 KB at H = 128), so every tile
 // reads them from the L2 in operand order.  A volume is coded as its slices
 // stacked into one image with G groups per slice; its decode walks the 3-D
 // wavefront: global step t holds pixel (z, y, x) with x + 3 y + lag z = t, so
@@ -438,9 +443,17 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
     Pw = 2u * (uint32_t)a.L;
   }
   bool over = false;
-  unsigned k_bar = 0;
   bool alive = err == 0;
+  __shared__ int s_alive;
   for (long long t = 0; t < a.T && alive; ++t) {
+    // every wave of the workgroup goes on or stops together: a wait that gave
+    // up has set the abort flag
+    __syncthreads();
+    if (threadIdx.x == 0)
+      s_alive = __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    __syncthreads();
+    alive = __builtin_amdgcn_readfirstlane(s_alive) != 0;
+    if (!alive) break;
     // ---- the step's pixels through the network: tile k of the step is the
     // k-th 16-row block of the active rows, slice by slice; one tile per
     // workgroup, its layers split over the four waves
@@ -450,32 +463,109 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
       z_lo = (int)(t - T2 + 1 > 0 ? (t - T2 + lag) / lag : 0);
     }
     int k = blockIdx.x, base = 0;
-    for (int z = z_lo; z <= z_hi; ++z) {
+    for (int z = z_lo; z <= z_hi && alive; ++z) {
       const long long tz = t - (long long)lag * z;  // the slice's own step, 0 <= tz < T2
       const int y_lo = (int)(tz - a.W + 1 > 0 ? (tz - a.W + SKEW) / SKEW : 0);
       const int y_hi = (int)(tz / SKEW < a.H - 1 ? tz / SKEW : a.H - 1);
       const int n_act = y_hi - y_lo + 1;
       const int nt = n_act > 0 ? (n_act + 15) / 16 : 0;
-      for (; k < base + nt; k += gridDim.x) {
-        const int y = y_lo + 16 * (k - base) + p;
+      for (; k < base + nt && alive; k += gridDim.x) {
+        const int y0 = y_lo + 16 * (k - base);
+        // wait for the decoded pixels the tile's windows read: all pixels of
+        // steps before this one in rows y0 - 2 .. y0 + 15 and, with the 3-D
+        // window, in the slice below's rows the window reaches
+        if (wave == 0) {
+          int fy = -1;
+          long long need = 0;
+          if (lane < 18) {
+            const int r = y0 - 2 + lane;
+            const long long first = (long long)SKEW * r + (long long)lag * z;
+            if (r >= 0 && r <= y_hi && first <= t - 1) {
+              fy = z * a.H + r;
+              const long long last = first + a.W - 1;
+              need = t - 1 < last ? t - 1 : last;
+            }
+          } else if (KIN == K_IN_3D && lane >= 32 && lane < 50 && z > 0) {
+            const int r = y0 + a.vg.ws - 3 + (lane - 32);
+            const long long first = (long long)SKEW * r + (long long)lag * (z - 1);
+            if (r >= 0 && r < a.H && first <= t - 1) {
+              fy = (z - 1) * a.H + r;
+              const long long last = first + a.W - 1;
+              need = t - 1 < last ? t - 1 : last;
+            }
+          }
+          uint32_t spins = 0;
+          int ok = 1;
+          for (;;) {
+            const bool ready = fy < 0 || (long long)__hip_atomic_load(
+                                             &a.pix_step[fy], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT) >= need;
+            if (__ballot(!ready) == 0ull) break;
+            if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                ++spins > a.spin_limit) {
+              __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              ok = 0;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          if (lane == 0) s_alive = ok;
+        }
+        __syncthreads();
+        alive = __builtin_amdgcn_readfirstlane(s_alive) != 0;
+        if (!alive) break;
+        const int y = y0 + p;
         const bool valid = y <= y_hi;
         const int xx = valid ? (int)(tz - (long long)SKEW * y) : 0;
         const bf16x8 xin =
             deep_features<KIN, uint8_t>(s_scale, (const uint8_t*)a.img, a.H, a.W, a.vg.ws, z,
                                         valid ? y : 0, xx, valid, q);
         deep_run_wg<H>(wnet, s_bias, xin, s_act, sm);
-        if (wave == 0)
+        if (wave == 0) {
           deep_tables_reg(sm, a.tables + (long long)(z * a.H + (valid ? y : 0)) * DEEP_OUT, valid);
+          // the tables out, then the rows' table counters
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          if (q == 0 && valid)
+            __hip_atomic_store(&a.tab_step[z * a.H + y], (int)t, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
         __syncthreads();
       }
       base += nt;
     }
-    alive = grid_sync(a.bar, a.abort_flag, k_bar, a.spin_limit);
     if (!alive) break;
-    // ---- each group decodes its rows' pixels of the step
+    // ---- each group decodes its rows' pixels of the step, once their tables
+    // are there, and then publishes them (a damaged stream is not decoded but
+    // still published, so that nothing waits on it)
     const long long tg = t - (long long)lag * zg;  // the step within the group's slice
-    if (coder && !bad && tg >= 0 && tg < T2) {
-      for (int j = 0; j < J; ++j) {
+    if (coder && tg >= 0 && tg < T2) {
+      bool waited = true;
+      if (!bad) {
+        uint32_t spins = 0;
+        for (;;) {
+          bool ready = true;
+          for (int j = 0; j < J; ++j) {
+            const int rr = j * a.L + lane;
+            const int Y = r0 + rr;
+            const long long xc = tg - (long long)SKEW * (Y - zg * a.H);
+            const bool act = lane < a.L && rr < R && xc >= 0 && xc < a.W;
+            if (act && __hip_atomic_load(&a.tab_step[Y], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT) < (int)t)
+              ready = false;
+          }
+          if (__ballot(!ready) == 0ull) break;
+          if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+              ++spins > a.spin_limit) {
+            __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            waited = false;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      for (int j = 0; j < J && waited && !bad; ++j) {
         const int rr = j * a.L + lane;
         const int Y = r0 + rr;
         const long long xc = tg - (long long)SKEW * (Y - zg * a.H);
@@ -517,14 +607,23 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
         Pw += (uint32_t)__popcll(m);
         if (act) reinterpret_cast<uint8_t*>(a.img)[(long long)Y * a.W + xc] = (uint8_t)v;
       }
+      // the pixels out, then the rows' pixel counters
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      for (int j = 0; j < J; ++j) {
+        const int rr = j * a.L + lane;
+        const int Y = r0 + rr;
+        const long long xc = tg - (long long)SKEW * (Y - zg * a.H);
+        if (lane < a.L && rr < R && xc >= 0 && xc < a.W)
+          __hip_atomic_store(&a.pix_step[Y], (int)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
-    alive = grid_sync(a.bar, a.abort_flag, k_bar, a.spin_limit);
   }
   if (err != 0) {
     if (threadIdx.x == 0 && blockIdx.x == 0) atomicMax(a.status, err);
     return;
   }
-  if (!alive) {
+  if (!alive ||
+      __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
     if (threadIdx.x == 0) atomicMax(a.status, 7);
     return;
   }

@@ -168,7 +168,9 @@ struct DeepDecArgs {
   void* h5;
   int2* tile_rows;
   float* logits;
-  unsigned* bar;      // grid barrier counter, cleared before launch
+  unsigned* bar;      // grid barrier counter, cleared before launch (12-bit decoder)
+  int* pix_step;      // [Z H]: step of each row's newest decoded pixel, -1 before launch
+  int* tab_step;      // [Z H]: step of each row's newest table, -1 before launch
   int* abort_flag;    // cleared before launch
   int* status;
   uint32_t spin_limit;
