@@ -508,6 +508,8 @@ dlic_status deep_decode_impl(const dlic_deep_model* model, const dlic_coder* cod
   }
   uint32_t* ctl = (uint32_t*)(base + L.ctl);
   a.pix_step = (int*)(base + L.steps);
+  a.delay_seed = g_delay_seed;
+  a.delay_max = g_delay_max;
   a.tab_step = a.pix_step + (size_t)vg.Z * h;
   a.bar = ctl;
   a.abort_flag = (int*)(ctl + 16);

@@ -475,6 +475,7 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
         // steps before this one in rows y0 - 2 .. y0 + 15 and, with the 3-D
         // window, in the slice below's rows the window reaches
         if (wave == 0) {
+          deep_delay(a.delay_seed, a.delay_max, 1u, blockIdx.x, (uint32_t)t);
           int fy = -1;
           long long need = 0;
           if (lane < 18) {
@@ -524,6 +525,7 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
         deep_run_wg<H>(wnet, s_bias, xin, s_act, sm);
         if (wave == 0) {
           deep_tables_reg(sm, a.tables + (long long)(z * a.H + (valid ? y : 0)) * DEEP_OUT, valid);
+          deep_delay(a.delay_seed, a.delay_max, 2u, blockIdx.x, (uint32_t)t);
           // the tables out, then the rows' table counters
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
           if (q == 0 && valid)
@@ -541,6 +543,7 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
     const long long tg = t - (long long)lag * zg;  // the step within the group's slice
     if (coder && tg >= 0 && tg < T2) {
       bool waited = true;
+      deep_delay(a.delay_seed, a.delay_max, 3u, (uint32_t)g, (uint32_t)t);
       if (!bad) {
         uint32_t spins = 0;
         for (;;) {
@@ -607,6 +610,7 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
         Pw += (uint32_t)__popcll(m);
         if (act) reinterpret_cast<uint8_t*>(a.img)[(long long)Y * a.W + xc] = (uint8_t)v;
       }
+      deep_delay(a.delay_seed, a.delay_max, 4u, (uint32_t)g, (uint32_t)t);
       // the pixels out, then the rows' pixel counters
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       for (int j = 0; j < J; ++j) {

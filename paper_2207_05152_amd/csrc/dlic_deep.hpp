@@ -123,6 +123,22 @@ __device__ __forceinline__ void deep_hidden(const DeepNetArgs& d, const bf16x8 x
   deep_hidden_at<H>(reinterpret_cast<const bf16x8*>(d.wop), [&](int l) { return d.b[l]; }, x, a);
 }
 
+// Test hook: a seeded pause of up to max_cycles shader cycles (in 64-cycle
+// sleeps) at one point of one wave, so that the decoder's hand-offs between
+// workgroups meet in other orders.  No-op when max_cycles is 0.
+__device__ __forceinline__ void deep_delay(uint32_t seed, uint32_t max_cycles, uint32_t site,
+                                           uint32_t who, uint32_t step) {
+  if (max_cycles == 0) return;
+  uint32_t h = seed ^ (site * 0x9E3779B1u) ^ (who * 0x85EBCA77u) ^ (step * 0xC2B2AE3Du);
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  h *= 0x297A2D39u;
+  h ^= h >> 15;
+  const uint32_t n = (h % max_cycles) >> 6;
+  for (uint32_t i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(1);
+}
+
 __device__ __forceinline__ uint32_t rd32(const uint8_t* p) {
   return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
 }

@@ -171,6 +171,7 @@ struct DeepDecArgs {
   unsigned* bar;      // grid barrier counter, cleared before launch (12-bit decoder)
   int* pix_step;      // [Z H]: step of each row's newest decoded pixel, -1 before launch
   int* tab_step;      // [Z H]: step of each row's newest table, -1 before launch
+  uint32_t delay_seed, delay_max;  // injected wave delays (test hook), 0: none
   int* abort_flag;    // cleared before launch
   int* status;
   uint32_t spin_limit;

@@ -55,3 +55,25 @@ def test_batch_under_injected_delays(dev, delays):
     for i, img in enumerate(imgs):
         assert np.array_equal(b.image(i).cpu().numpy(), img), i
     b.close()
+
+
+@pytest.mark.parametrize("seed,max_cycles", [(1, 3000), (2, 20000)])
+def test_softmax_and_volume_decoders_under_injected_delays(dev, delays, seed, max_cycles):
+    # the six-layer decoder hands tables and pixels between workgroups through per-row
+    # step counters; pauses at the tile's wait, before its tables are published, at the
+    # coder's wait and before its pixels are published reorder those hand-offs
+    layers = synth.xavier_deep(64, 5)
+    m = dl.DeepModel(layers, dev)
+    img = synth.synth_image(48, 70, 3 + seed)
+    bits = dl.deep_encode(to_dev(img, dev), m, dl.dlic_coder(3, 4))
+    m3 = dl.DeepModel(synth.xavier_deep(64, 6, k_in=21), dev)
+    vol = synth.mri_volume(30 + seed, 4, 24)[:, :, :20]
+    vbits = dl.volume_encode(to_dev(vol, dev), m3, dl.dlic_coder(2, 4), 1)
+    torch.cuda.synchronize()
+    delays(seed, max_cycles)
+    say("deep delays", seed, max_cycles)
+    dec, st = dl.deep_decode(bits, m, check=False)
+    vdec, vst = dl.volume_decode(vbits, m3, check=False)
+    torch.cuda.synchronize()
+    assert st == 0 and np.array_equal(dec.cpu().numpy(), img)
+    assert vst == 0 and np.array_equal(vdec.cpu().numpy(), vol)
