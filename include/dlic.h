@@ -377,9 +377,10 @@ double dlic_wallclock_hz(void);
  *
  * Decoding follows the paper's GPU scheme (Section II-B, Preprocessor: the
  * pixels of one wavefront step enter the network together as a matrix): one
- * cooperative launch walks the W + 3H - 3 steps, the whole grid evaluating
- * the step's pixels, then every group decoding its rows' pixels of the step,
- * with a grid barrier after each phase.  It needs every group's wave
+ * cooperative launch walks the W + 3H - 3 steps, the grid evaluating the
+ * step's pixels, then every group decoding its rows' pixels of the step
+ * (8-bit samples: the phases hand over through per-row step counters; 12-bit
+ * samples: a grid barrier after each phase).  It needs every group's wave
  * resident (DLIC_ERR_UNSUPPORTED otherwise): at least 256 groups fit.
  *
  * k_in is 12 for images; volumes (below) also take 21: the 12-pixel window
