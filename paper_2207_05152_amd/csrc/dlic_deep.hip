@@ -254,65 +254,99 @@ __device__ __forceinline__ DeepBlock deep_softmax(float (&o)[DEEP_OUT / 16][4], 
   return blk;
 }
 
-// The decoder's table rule for the 16 pixels of a tile (one wave), logits in
-// sm[p][v]: lane (b, p) = (l / 16, l % 16) takes block b of pixel p into
-// registers and writes F(64 b .. 64 b + 63) of that pixel to tab (256 u16 per
-// pixel; pixel p's row at tab_p).  The same operations in the same order as
-// deep_softmax and the encoder's table loop, so the tables are the encoder's.
-__device__ __forceinline__ void deep_tables_reg(const float* sm, uint16_t* tab_p, bool valid) {
-  const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-  const int p = lane & 15, q = lane >> 4;
-  const f4* src = reinterpret_cast<const f4*>(sm + p * SM_ROW + 64 * q);
-  float v[64];
+// The decoder's tables for the 16 pixels of a tile, by the four waves of a
+// workgroup (logits in sm[p][v]; afterwards F(v) of pixel p in
+// tab_lds[p][v]), with the operations and order of deep_softmax and the
+// encoder's table loop, so the tables are the encoder's: the exponentials and
+// the F evaluations, which no sum orders, are spread over all 256 threads;
+// wave 0 keeps the order-fixed sums (lane (b, p): block b of pixel p) and
+// leaves each level's C_v in sm.  part: 256 floats of scratch.
+__device__ __forceinline__ void deep_tables_wg(float* sm, float* part, uint16_t* tab_lds) {
+  const int tid = threadIdx.x;
+  const int p = tid & 15, s16 = tid >> 4;  // pixel, 16-level slice
+  {
+    const f4* src = reinterpret_cast<const f4*>(sm + p * SM_ROW + 16 * s16);
+    float m = -INFINITY;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const f4 t = src[j];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) v[4 * j + r] = t[r];
-  }
-  float m = v[0];
-#pragma unroll
-  for (int k = 1; k < 64; ++k) m = fmaxf(m, v[k]);
-  m = fmaxf(m, __shfl_xor(m, 16));
-  m = fmaxf(m, __shfl_xor(m, 32));
-  float sb = 0.0f;
-#pragma unroll
-  for (int k = 0; k < 64; ++k) {
-    v[k] = expf(v[k] - m);
-    sb = sb + v[k];
-  }
-  const float s0 = __shfl(sb, p), s1 = __shfl(sb, p + 16), s2 = __shfl(sb, p + 32),
-              s3 = __shfl(sb, p + 48);
-  const float S = ((s0 + s1) + s2) + s3;
-  const float rr = 1.0f / S;
-  float tb = 0.0f;
-#pragma unroll
-  for (int k = 0; k < 64; ++k) {
-    v[k] = v[k] * rr;
-    tb = tb + v[k];
-  }
-  const float t0 = __shfl(tb, p), t1 = __shfl(tb, p + 16), t2 = __shfl(tb, p + 32);
-  const float o1 = t0, o2 = o1 + t1, o3 = o2 + t2;
-  const float off = q == 0 ? 0.0f : (q == 1 ? o1 : (q == 2 ? o2 : o3));
-  float L = 0.0f;
-  uint4* dst = reinterpret_cast<uint4*>(tab_p + 64 * q);
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    uint32_t w[4];
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      uint32_t pair = 0;
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int k = 8 * j + 2 * h + e, lv = 64 * q + k;
-        const uint32_t Fv = lv == 0 ? 0u : deep_F(lv, off + L, M_PRIME);
-        pair |= Fv << (16 * e);
-        L = L + v[k];
-      }
-      w[h] = pair;
+    for (int j = 0; j < 4; ++j) {
+      const f4 v = src[j];
+      m = fmaxf(fmaxf(m, v[0]), fmaxf(fmaxf(v[1], v[2]), v[3]));
     }
-    if (valid) dst[j] = make_uint4(w[0], w[1], w[2], w[3]);
+    part[s16 * 16 + p] = m;
   }
+  __syncthreads();
+  {
+    float m = part[p];
+#pragma unroll
+    for (int j = 1; j < 16; ++j) m = fmaxf(m, part[j * 16 + p]);
+    f4* row = reinterpret_cast<f4*>(sm + p * SM_ROW + 16 * s16);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      f4 v = row[j];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = expf(v[r] - m);
+      row[j] = v;
+    }
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int q = tid >> 4;  // block
+    f4* row = reinterpret_cast<f4*>(sm + p * SM_ROW + 64 * q);
+    float v[64];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const f4 t = row[j];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[4 * j + r] = t[r];
+    }
+    float sb = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 64; ++k) sb = sb + v[k];
+    const float s0 = __shfl(sb, p), s1 = __shfl(sb, p + 16), s2 = __shfl(sb, p + 32),
+                s3 = __shfl(sb, p + 48);
+    const float S = ((s0 + s1) + s2) + s3;
+    const float rr = 1.0f / S;
+    float tb = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 64; ++k) {
+      v[k] = v[k] * rr;
+      tb = tb + v[k];
+    }
+    const float t0 = __shfl(tb, p), t1 = __shfl(tb, p + 16), t2 = __shfl(tb, p + 32);
+    const float o1 = t0, o2 = o1 + t1, o3 = o2 + t2;
+    const float off = q == 0 ? 0.0f : (q == 1 ? o1 : (q == 2 ? o2 : o3));
+    float L = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      f4 c;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        c[r] = off + L;
+        L = L + v[4 * j + r];
+      }
+      row[j] = c;
+    }
+  }
+  __syncthreads();
+  {
+    const f4* src = reinterpret_cast<const f4*>(sm + p * SM_ROW + 16 * s16);
+    uint32_t w[8];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const f4 c = src[j];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int l0 = 16 * s16 + 4 * j + 2 * h;
+        const uint32_t F0 = l0 == 0 ? 0u : deep_F(l0, c[2 * h], M_PRIME);
+        const uint32_t F1 = deep_F(l0 + 1, c[2 * h + 1], M_PRIME);
+        w[2 * j + h] = F0 | (F1 << 16);
+      }
+    }
+    uint4* dst = reinterpret_cast<uint4*>(tab_lds + p * DEEP_OUT + 16 * s16);
+    dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+  }
+  __syncthreads();
 }
 
 // Encoder side: every pixel's interval (and optionally logits / tables).
@@ -399,6 +433,8 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
   __shared__ bf16x8 s_act[2 * (H / 32) * 64];
   __shared__ float s_bias[WgNet<H>::NB];
   __shared__ float s_scale[256];
+  __shared__ float s_part[256];
+  __shared__ __attribute__((aligned(16))) uint16_t s_tab[16 * DEEP_OUT];
   __shared__ int s_err;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = lane & 15, q = lane >> 4;
@@ -523,8 +559,17 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
             deep_features<KIN, uint8_t>(s_scale, (const uint8_t*)a.img, a.H, a.W, a.vg.ws, z,
                                         valid ? y : 0, xx, valid, q);
         deep_run_wg<H>(wnet, s_bias, xin, s_act, sm);
+        deep_tables_wg(sm, s_part, s_tab);
         if (wave == 0) {
-          deep_tables_reg(sm, a.tables + (long long)(z * a.H + (valid ? y : 0)) * DEEP_OUT, valid);
+          // the tile's tables to device memory: lane (q, p) copies block q of
+          // pixel p's 256 levels
+          if (valid) {
+            const uint4* src = reinterpret_cast<const uint4*>(s_tab + p * DEEP_OUT + 64 * q);
+            uint4* dst = reinterpret_cast<uint4*>(a.tables + (long long)(z * a.H + y) * DEEP_OUT +
+                                                  64 * q);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) dst[j] = src[j];
+          }
           deep_delay(a.delay_seed, a.delay_max, 2u, blockIdx.x, (uint32_t)t);
           // the tables out, then the rows' table counters
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
