@@ -53,16 +53,13 @@ struct Mma<double> {
   __device__ static __forceinline__ double expm1_(double x) { return expm1(x); }
 };
 
+// softplus(x) = max(x, 0) + log1p(exp(-|x|)) and sigmoid(x) = 1 / (1 + exp(-x))
+// (e / (1 + e) for x < 0), sharing the one exponential exp(-|x|).
 template <typename T>
-__device__ __forceinline__ T softplus(T x) {
-  const T ax = x > T(0) ? x : -x;
-  return (x > T(0) ? x : T(0)) + Mma<T>::log1p_(Mma<T>::exp_(-ax));
-}
-template <typename T>
-__device__ __forceinline__ T sigmoid(T x) {
-  if (x >= T(0)) return T(1) / (T(1) + Mma<T>::exp_(-x));
-  const T e = Mma<T>::exp_(x);
-  return e / (T(1) + e);
+__device__ __forceinline__ void softplus_sigmoid(T x, T& sp, T& sg) {
+  const T e = Mma<T>::exp_(x > T(0) ? -x : x);
+  sp = (x > T(0) ? x : T(0)) + Mma<T>::log1p_(e);
+  sg = x >= T(0) ? T(1) / (T(1) + e) : e / (T(1) + e);
 }
 
 // One mixture component of one sample: the log mass lp_k of bin v (before the
@@ -84,19 +81,26 @@ __device__ __forceinline__ CompTerms<T> component_terms(const T* o, int k, int v
   const T A = (hi - mu) * is, B = (lo - mu) * is;
   T dA, dB;
   if (v == 0) {
-    c.lpk = -softplus(-A);
-    dA = sigmoid(-A);
+    T sp, sg;
+    softplus_sigmoid(-A, sp, sg);
+    c.lpk = -sp;
+    dA = sg;
     dB = T(0);
   } else if (v == 255) {
-    c.lpk = -softplus(B);
+    T sp, sg;
+    softplus_sigmoid(B, sp, sg);
+    c.lpk = -sp;
     dA = T(0);
-    dB = -sigmoid(B);
+    dB = -sg;
   } else {
+    T spa, sga, spb, sgb;
+    softplus_sigmoid(-A, spa, sga);
+    softplus_sigmoid(B, spb, sgb);
     const T em = Mma<T>::expm1_(A - B);  // > 0
-    c.lpk = -softplus(-A) - softplus(B) + Mma<T>::log_(-Mma<T>::expm1_(B - A));
+    c.lpk = -spa - spb + Mma<T>::log_(-Mma<T>::expm1_(B - A));
     const T E = T(1) / em;
-    dA = sigmoid(-A) + E;
-    dB = -sigmoid(B) - E;
+    dA = sga + E;
+    dB = -sgb - E;
   }
   c.u_mu = is * (dA + dB);
   c.u_ls = free_ls ? A * dA + B * dB : T(0);
