@@ -444,6 +444,15 @@ def volume_sweep(dl, torch, hidden=128, Z=35, size=256, layout=(8, 8), shifts=(0
         assert st == 0 and torch.equal(dec, vol), "volume round trip"
         avg = {k: float(np.mean(v)) for k, v in kt.items()}
         d12 = m.depth == 12
+        stamps = {}
+        if not d12:
+            # device real-time stamps of the last decode: start, each slice done
+            s_ = dl.dlic_deep_slice_stamps(Z + 1).astype(np.int64)
+            hz = dl.dlic_wallclock_hz()
+            first = (s_[1] - s_[0]) / hz * 1e3
+            complete = (s_[1:].max() - s_[0]) / hz * 1e3
+            stamps = {"first_slice_ms": first, "complete_ms": complete,
+                      "first_over_complete": first / complete}
         dens = avg["deep12_density" if d12 else "deep_density_kernel"]
         enc = dens + avg["rans_encode_kernel"] + avg["pack_kernel"]
         dcd = avg["deep12_decode_kernel" if d12 else "deep_decode_kernel"]
@@ -454,7 +463,7 @@ def volume_sweep(dl, torch, hidden=128, Z=35, size=256, layout=(8, 8), shifts=(0
                 "decode_mpix_s": n_px / dcd / 1e3, "decode_ms": dcd,
                 "bpp_total": 8.0 * bits.numel() / n_px, "lag": lag, "steps": T,
                 "first_slice_steps": T2, "decode_grid": dl.dlic_deep_decode_grid(),
-                "decode_us_per_step": dcd * 1e3 / T,
+                "decode_us_per_step": dcd * 1e3 / T, **stamps,
                 "density_tflops": flop / (dens * 1e-3) / 1e12,
                 "density_frac_bf16_mfma": flop / (dens * 1e-3) / MI355X_BF16_MFMA}
 

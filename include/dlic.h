@@ -440,6 +440,15 @@ dlic_status dlic_deep_density(const dlic_deep_model *model, const void *d_img, i
 void dlic_set_deep_decode_grid(int32_t workgroups);
 int32_t dlic_deep_decode_grid(void);
 
+/* Measurement hook for the paper's first-slice and complete-scan times
+ * (Section IV-D, Table III): device real-time stamps (dlic_wallclock_hz ticks)
+ * of the last 8-bit dlic_deep_decode / dlic_volume_decode on the current
+ * device, h_out[0] its start and h_out[1 + s] the moment slice s's last pixel
+ * was published (an image is slice 0).  Waits for the device; n is 1 + the
+ * number of slices wanted (at most 4096).  Concurrent decodes overwrite each
+ * other's stamps. */
+dlic_status dlic_deep_slice_stamps(uint64_t *h_out, int32_t n);
+
 /* ---- volumes: the 3-D window and the 3-D wavefront (Section IV-C, 3D
  * Dependencies and 3D Wavefront, Fig. 6) -------------------------------------
  * A volume is z slices of h x w pixels, slice-major in device memory

@@ -42,7 +42,7 @@ EXPORTS = (
     "dlic_set_decode_delays", "dlic_deep_workspace", "dlic_deep_encode", "dlic_deep_decode",
     "dlic_deep_density", "dlic_set_deep_decode_grid", "dlic_deep_decode_grid",
     "dlic_volume_encode_bound", "dlic_volume_workspace", "dlic_volume_encode", "dlic_volume_decode",
-    "dlic_volume_density", "dlic_peek_volume", "dlic_host_scale",
+    "dlic_volume_density", "dlic_peek_volume", "dlic_host_scale", "dlic_deep_slice_stamps",
     "dlic_net_forms",
 )
 
@@ -143,6 +143,7 @@ def lib():
         "dlic_volume_workspace": (S, [POINTER(dlic_deep_model), c_int32, c_int32, c_int32, P,
                                       c_int32]),
         "dlic_host_scale": (c_int, [c_int32, P]),
+        "dlic_deep_slice_stamps": (c_int, [P, c_int32]),
         "dlic_volume_encode": (c_int, [POINTER(dlic_deep_model), POINTER(dlic_coder), P, c_int32,
                                        c_int32, c_int32, c_int32, P, S, P, P, S, P]),
         "dlic_volume_decode": (c_int, [POINTER(dlic_deep_model), POINTER(dlic_coder), P, S, P,
@@ -488,6 +489,13 @@ def dlic_volume_workspace(model: "DeepModel", z, h, w, coder, decode) -> int:
     return int(lib().dlic_volume_workspace(ctypes.byref(model.c), z, h, w,
                                            ctypes.byref(coder) if coder is not None else None,
                                            decode))
+
+
+def dlic_deep_slice_stamps(n: int) -> np.ndarray:
+    """Real-time stamps of the last 8-bit deep decode: [start, slice 0 done, ...]."""
+    out = np.zeros(n, np.uint64)
+    _check(lib().dlic_deep_slice_stamps(out.ctypes.data, int(n)), "dlic_deep_slice_stamps")
+    return out
 
 
 def dlic_host_scale(depth: int) -> np.ndarray:

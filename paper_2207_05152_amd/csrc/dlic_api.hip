@@ -1329,6 +1329,11 @@ dlic_status dlic_deep_decode(const dlic_deep_model* model, const dlic_coder* cod
 
 void dlic_set_deep_decode_grid(int32_t workgroups) { g_deep_grid = workgroups > 0 ? workgroups : 0; }
 
+dlic_status dlic_deep_slice_stamps(uint64_t* h_out, int32_t n) {
+  if (!h_out) return DLIC_ERR_ARG;
+  return deep_slice_stamps((unsigned long long*)h_out, n) == 0 ? DLIC_OK : DLIC_ERR_ARG;
+}
+
 int32_t dlic_deep_decode_grid(void) { return g_deep_grid_used; }
 
 size_t dlic_volume_encode_bound(int32_t z, int32_t h, int32_t w, const dlic_coder* coder) {

@@ -427,6 +427,10 @@ bool launch_deep_density(const Consts* K, const DeepNetArgs& net, const uint8_t*
 
 // ---- decoder ----------------------------------------------------------------
 
+// Device real-time stamps of the last decode (a measurement hook): [0] the
+// launch's start, [1 + z] the moment slice z's last pixel was published.
+__device__ unsigned long long g_slice_stamps[1 + DEEP_MAX_SLICES];
+
 template <int H, int KIN>
 __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArgs a) {
   __shared__ float s_sm[16 * SM_ROW];
@@ -440,6 +444,7 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
   const int p = lane & 15, q = lane >> 4;
   float* sm = s_sm;
   if (threadIdx.x == 0) s_err = deep_check_header(a);
+  if (threadIdx.x == 0 && blockIdx.x == 0) g_slice_stamps[0] = __builtin_amdgcn_s_memrealtime();
   deep_stage_biases<H>(a.net, s_bias);
   for (int i = threadIdx.x; i < 256; i += blockDim.x) s_scale[i] = a.K->scale[i];
   WgNet<H> wnet;
@@ -662,8 +667,12 @@ __global__ __launch_bounds__(DEEP_WAVES * 64) void deep_decode_kernel(DeepDecArg
         const int rr = j * a.L + lane;
         const int Y = r0 + rr;
         const long long xc = tg - (long long)SKEW * (Y - zg * a.H);
-        if (lane < a.L && rr < R && xc >= 0 && xc < a.W)
+        if (lane < a.L && rr < R && xc >= 0 && xc < a.W) {
           __hip_atomic_store(&a.pix_step[Y], (int)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          // the slice's last pixel
+          if (Y - zg * a.H == a.H - 1 && xc == a.W - 1)
+            g_slice_stamps[1 + zg] = __builtin_amdgcn_s_memrealtime();
+        }
       }
     }
   }
@@ -691,6 +700,13 @@ static int decode_residency() {
                                                    DEEP_WAVES * 64, 0) != hipSuccess)
     return 0;
   return per_cu;
+}
+
+int deep_slice_stamps(unsigned long long* h_out, int n) {
+  if (n < 1 || n > 1 + DEEP_MAX_SLICES) return -1;
+  if (hipDeviceSynchronize() != hipSuccess) return -1;
+  return hipMemcpyFromSymbol(h_out, HIP_SYMBOL(g_slice_stamps), sizeof(unsigned long long) * n, 0,
+                             hipMemcpyDeviceToHost) == hipSuccess ? 0 : -1;
 }
 
 int deep_decode_max_grid(int H, int k_in) {

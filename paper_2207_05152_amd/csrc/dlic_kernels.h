@@ -180,6 +180,10 @@ struct DeepDecArgs {
 // Cooperative launch of the per-step decoder; returns the hipError of the launch.
 hipError_t launch_deep_decode(const DeepDecArgs& a, int grid, hipStream_t s);
 int deep_decode_max_grid(int H, int k_in);
+constexpr int DEEP_MAX_SLICES = 4095;
+// Host copy of the last 8-bit deep decode's real-time stamps (start, then each
+// slice's completion); -1 on a bad count or a HIP error.
+int deep_slice_stamps(unsigned long long* h_out, int n);
 
 // ---- 12-bit samples: 4096 output levels ----------------------------------
 // Encoder stages over pixels [px0, px0 + n) of the stacked image (u16

@@ -245,3 +245,20 @@ def test_scan_full_size(dev):
     ref = sm.deep_forward_bf16(feats, layers)
     err = np.abs(got - ref) / np.maximum(1.0, np.abs(ref))
     assert err.max() <= 2.0 ** -6 and (err.max(axis=1) <= 2.0 ** -8).mean() >= 0.99
+
+
+def test_slice_stamps_follow_the_wavefront(dev, net):
+    # with WS = 2 slice z + 1 trails slice z by five steps and its last pixel's window
+    # reads slice z's last pixel, so the slices complete in order after the start
+    H, layers, m = net
+    Z = 5
+    vol = _vol(Z, 20, 24, 8)
+    bits = dl.volume_encode(to_dev(vol, dev), m, dl.dlic_coder(2, 4), 2)
+    say("volume stamps", H)
+    dec, st = dl.volume_decode(bits, m, check=False)
+    torch.cuda.synchronize()
+    assert st == 0 and np.array_equal(dec.cpu().numpy(), vol)
+    s = dl.dlic_deep_slice_stamps(Z + 1).astype(np.int64)
+    assert np.all(s[1:] > s[0]) and np.all(np.diff(s[1:]) >= 0), s
+    with pytest.raises(dl.DlicError):
+        dl.dlic_deep_slice_stamps(5000)
