@@ -27,9 +27,10 @@ from .mixture import (bin_edges, sigmoid, mixture_cdf, log_pmf, pmf_table,
 from .freq import (PROB_BITS, M_TOTAL, M_PRIME, table_exact, sigma_lut32,
                    sigma_hat32, table_coords32, beta32, scale32, table_levels32,
                    table_full32)
-from .rans import (RANS_L, group_rows, canonical_order, rans_encode, rans_decode)
+from .rans import (RANS_L, group_rows, group_strips, canonical_order, rans_encode,
+                   rans_decode, RansDecoder)
 from .container import (HEADER_SIZE, pack_header, parse_header, fingerprint,
-                         assemble, split_streams)
+                         assemble, split_streams, image_flags, image_strips)
 from .codec import (OracleCoder, encode_image, decode_image, cf_for_image,
                     params32_for_image, weights_fingerprint)
 from .nll import nll_bits, nll_and_grad_fd, adam_update, sample_features, PARAM_ORDER

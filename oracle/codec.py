@@ -13,9 +13,9 @@ The oracle encodes in two plain passes: every pixel's (c, f) from the whole
 image (the network applied to the matrix of all windows), then each group's
 rANS walk.  Decoding goes pixel by pixel in canonical order, evaluating the
 network on windows of the partially decoded image, which is the paper's
-decoder without its parallelism.  Groups are decoded one after another: a
-group's windows reach only into rows of earlier groups and into its own
-earlier canonical positions.
+decoder without its parallelism.  Strips are decoded in ascending order, each
+continuing its group's coder state: a strip's windows reach only into rows of
+earlier strips and into its own earlier canonical positions.
 
 Parity: pinned by oracle round trips (decode(encode(x)) == x) and by the
 coded length against the ideal code length.
@@ -26,10 +26,11 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .container import pack_header, parse_header, assemble, split_streams, fingerprint
+from .container import (pack_header, parse_header, assemble, split_streams, fingerprint,
+                        image_flags, image_strips)
 from .freq import table_levels32, table_full32
 from .network import mlp_forward, mixture_head
-from .rans import canonical_order, rans_encode, rans_decode
+from .rans import RansDecoder, canonical_order, group_rows, group_strips, rans_encode
 from .window import causal_features, pixel_features
 
 
@@ -37,6 +38,7 @@ from .window import causal_features, pixel_features
 class OracleCoder:
     groups: int = 1
     lanes: int = 32
+    strips: int = 1  # row strips per group
 
 
 def weights_fingerprint(weights) -> int:
@@ -67,13 +69,13 @@ def encode_image(img, weights, coder: OracleCoder) -> bytes:
     h, w = img.shape
     c, f = cf_for_image(img, weights)
     streams = []
-    for grp in canonical_order(h, w, coder.groups, coder.lanes):
+    for grp in canonical_order(h, w, coder.groups, coder.lanes, strips=coder.strips):
         idx = [y * w + x for (y, x, _) in grp]
         streams.append(rans_encode([(c[i], f[i]) for i in idx],
                                    [lane for (_, _, lane) in grp], coder.lanes))
     hdr = pack_header(h, w, coder.groups, coder.lanes, dtype=0,
                       h1=weights["W1"].shape[0], h2=weights["W2"].shape[0],
-                      fp=weights_fingerprint(weights))
+                      fp=weights_fingerprint(weights), flags=image_flags(coder.strips))
     return assemble(hdr, streams)
 
 
@@ -82,19 +84,30 @@ def decode_image(buf: bytes, weights) -> np.ndarray:
     if hdr["fingerprint"] != weights_fingerprint(weights):
         raise ValueError("stream was coded with another model")
     h, w, groups, lanes = hdr["h"], hdr["w"], hdr["groups"], hdr["lanes"]
+    strips = image_strips(hdr["flags"])
     streams = split_streams(buf, groups)
     img = np.zeros((h, w), dtype=np.uint8)
-    for grp, words in zip(canonical_order(h, w, groups, lanes), streams):
-        def find(i, slot, grp=grp):
-            y, x, _ = grp[i]
-            o = _mlp(weights, pixel_features(img, y, x)[None, :])
-            pi, mu, inv_s = mixture_head(o)
-            F = table_full32(pi.astype(np.float32), mu.astype(np.float32),
-                             inv_s.astype(np.float32))[0]
-            v = int(np.searchsorted(F, slot, side="right")) - 1
-            img[y, x] = v
-            return v, int(F[v]), int(F[v + 1] - F[v])
-        _, ok = rans_decode(words, lanes, [lane for (_, _, lane) in grp], find)
-        if not ok:
-            raise ValueError("corrupt stream")
+    order = canonical_order(h, w, groups, lanes, strips=strips)
+    decs = [RansDecoder(words, lanes) for words in streams]
+    if any(len(words) < 2 * lanes for words in streams):
+        raise ValueError("corrupt stream")
+    rows = group_rows(h, groups * strips)
+    done = [0] * groups  # canonical positions decoded per group
+    for s in range(strips):
+        for g in range(groups):
+            b = group_strips(groups, strips, g)[s]
+            n = (rows[b + 1] - rows[b]) * w
+            for y, x, lane in order[g][done[g]:done[g] + n]:
+                def find(slot, y=y, x=x):
+                    o = _mlp(weights, pixel_features(img, y, x)[None, :])
+                    pi, mu, inv_s = mixture_head(o)
+                    F = table_full32(pi.astype(np.float32), mu.astype(np.float32),
+                                     inv_s.astype(np.float32))[0]
+                    v = int(np.searchsorted(F, slot, side="right")) - 1
+                    img[y, x] = v
+                    return v, int(F[v]), int(F[v + 1] - F[v])
+                decs[g].decode(lane, find)
+            done[g] += n
+    if not all(d.finished() for d in decs):
+        raise ValueError("corrupt stream")
     return img

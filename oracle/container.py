@@ -15,6 +15,9 @@ The paper defines no container.  Our reading, little-endian:
   G streams       each as little-endian 16-bit words, in group order.
 The model fingerprint is 64-bit FNV-1a over the little-endian bytes of
 W1, b1, W2, b2, W3, b3 in that order, as stored.
+flags: a volume stores its slice count Z (1..4095) in bits 0..11 and its
+window shift in bits 12..15; an image has bits 0..11 zero and stores S - 1,
+S the row strips per group (1..16), in bits 12..15.
 
 Parity: pinned by round trips of header fields and by the published FNV-1a
 test vectors.
@@ -59,6 +62,20 @@ def parse_header(buf: bytes) -> dict:
     keys = ("magic", "version", "flags", "h", "w", "k_in", "n_mix", "dtype", "skew",
             "h1", "h2", "prob_bits", "lanes", "groups", "fingerprint")
     return dict(zip(keys, f))
+
+
+def image_flags(strips: int) -> int:
+    """The flags field of an image coded with `strips` row strips per group."""
+    if not 1 <= strips <= 16:
+        raise ValueError("1..16 strips per group")
+    return (strips - 1) << 12
+
+
+def image_strips(flags: int) -> int:
+    """Row strips per group of an image stream; raises for a volume's flags."""
+    if flags & 0xFFF:
+        raise ValueError("a volume stream, not an image")
+    return (flags >> 12) + 1
 
 
 def assemble(header: bytes, streams) -> bytes:

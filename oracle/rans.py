@@ -18,11 +18,17 @@ renormalisation words:
                          if x < 2^16: x = (x << 16) | next word
 
 Layout readings (the paper fixes none of this), all explicit in the arguments:
-  * G groups; group g owns rows [floor(gH/G), floor((g+1)H/G)) and one
-    stream shared by its L lanes (interleaved rANS).
-  * Row y of group g belongs to lane (y - r_g) mod L, block j = (y - r_g) div L.
-  * Canonical order in a group: ascending (t = x + 3y, j, lane).  Encoding
-    walks it backwards; every lane starts at 2^16; after the last symbol
+  * G groups, each coding S row strips (S = 1 by default).  The image is cut
+    into S*G strips, strip b owning rows [floor(bH/(SG)), floor((b+1)H/(SG)));
+    group g codes strips g, G + g, ..., (S-1)G + g, spread over the image, so
+    that when a strip is shorter than the wavefront's band of active rows a
+    group has rows in fewer steps at once.  One stream per group, shared by
+    its L lanes (interleaved rANS).
+  * Row y of a strip starting at row r belongs to lane (y - r) mod L, block
+    j = (y - r) div L.
+  * Canonical order in a group: its strips in ascending order, each strip in
+    ascending (t = x + 3y, j, lane); a lane's state carries from one strip to
+    the next.  Encoding walks it backwards; every lane starts at 2^16; after the last symbol
     the lanes' states are appended (for lanes L-1..0: high half, then low
     half) and the whole push sequence is reversed, so a stream read forward
     starts with the L states as (low, high) 16-bit pairs for lanes 0..L-1,
@@ -42,29 +48,43 @@ PROB_BITS = 16
 
 
 def group_rows(h: int, groups: int) -> list:
-    """Row boundaries r_0..r_G of the G row strips."""
+    """Row boundaries r_0..r_G of G row strips of near-equal height."""
     return [(g * h) // groups for g in range(groups + 1)]
 
 
-def canonical_order(h: int, w: int, groups: int, lanes: int, skew: int = SKEW, only=None) -> list:
+def group_strips(groups: int, strips: int, g: int) -> list:
+    """Indices of the strips group g codes, in its coding order."""
+    return [s * groups + g for s in range(strips)]
+
+
+def _strip_order(y0: int, y1: int, w: int, lanes: int, skew: int) -> list:
+    items = []
+    for y in range(y0, y1):
+        r = y - y0
+        lane, blk = r % lanes, r // lanes
+        for x in range(w):
+            items.append((x + skew * y, blk, lane, y, x))
+    items.sort()
+    return [(it[3], it[4], it[2]) for it in items]
+
+
+def canonical_order(h: int, w: int, groups: int, lanes: int, skew: int = SKEW, only=None,
+                    strips: int = 1) -> list:
     """For each group, the list of (y, x, lane) in canonical order.
 
     only: optional set of group indices to build (others are left empty).
+    strips: row strips per group (S above).
     """
-    rows = group_rows(h, groups)
+    rows = group_rows(h, groups * strips)
     out = []
     for g in range(groups):
-        items = []
         if only is not None and g not in only:
             out.append([])
             continue
-        for y in range(rows[g], rows[g + 1]):
-            r = y - rows[g]
-            lane, blk = r % lanes, r // lanes
-            for x in range(w):
-                items.append((x + skew * y, blk, lane, y, x))
-        items.sort()
-        out.append([(it[3], it[4], it[2]) for it in items])
+        seq = []
+        for b in group_strips(groups, strips, g):
+            seq += _strip_order(rows[b], rows[b + 1], w, lanes, skew)
+        out.append(seq)
     return out
 
 
@@ -93,6 +113,43 @@ def rans_encode(cf, lanes_seq, n_lanes: int) -> list:
     return pushes[::-1]
 
 
+class RansDecoder:
+    """One group's stream, decoded one symbol at a time in canonical order.
+
+    Decoding can pause between symbols, so that a caller may interleave the
+    groups in any order the symbols' dependencies allow (strips of one group
+    depend on strips of other groups).
+    """
+
+    def __init__(self, words, n_lanes: int):
+        self.words = words
+        self.n = len(words)
+        self.ok = self.n >= 2 * n_lanes
+        self.x = ([words[2 * l] | (words[2 * l + 1] << 16) for l in range(n_lanes)]
+                  if self.ok else [RANS_L] * n_lanes)
+        self.pos = 2 * n_lanes
+
+    def decode(self, lane: int, find):
+        """find(slot) -> (symbol, c, f); returns the symbol."""
+        s = self.x[lane]
+        slot = s & 0xFFFF
+        sym, c, f = find(slot)
+        s = f * (s >> 16) + slot - c
+        if s < RANS_L:
+            if self.pos < self.n:
+                s = (s << 16) | self.words[self.pos]
+            else:
+                self.ok = False
+                s = s << 16
+            self.pos += 1
+        self.x[lane] = s
+        return sym
+
+    def finished(self) -> bool:
+        """Every lane back at 2^16, every word consumed, no read past the end."""
+        return self.ok and self.pos == self.n and all(v == RANS_L for v in self.x)
+
+
 def rans_decode(words, n_lanes: int, lanes_seq, find):
     """Decode one group's symbols in canonical order.
 
@@ -101,26 +158,8 @@ def rans_decode(words, n_lanes: int, lanes_seq, find):
     decoded.  Returns (symbols, ok) where ok means every lane ended at 2^16,
     every word was consumed and no read ran past the end.
     """
-    n = len(words)
-    if n < 2 * n_lanes:
+    if len(words) < 2 * n_lanes:
         return [], False
-    x = [words[2 * l] | (words[2 * l + 1] << 16) for l in range(n_lanes)]
-    pos = 2 * n_lanes
-    ok = True
-    out = []
-    for i, lane in enumerate(lanes_seq):
-        s = x[lane]
-        slot = s & 0xFFFF
-        sym, c, f = find(i, slot)
-        s = f * (s >> 16) + slot - c
-        if s < RANS_L:
-            if pos < n:
-                s = (s << 16) | words[pos]
-            else:
-                ok = False
-                s = s << 16
-            pos += 1
-        x[lane] = s
-        out.append(sym)
-    ok = ok and pos == n and all(v == RANS_L for v in x)
-    return out, ok
+    dec = RansDecoder(words, n_lanes)
+    out = [dec.decode(lane, lambda slot, i=i: find(i, slot)) for i, lane in enumerate(lanes_seq)]
+    return out, dec.finished()
