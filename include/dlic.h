@@ -85,14 +85,25 @@ typedef struct dlic_model {
 } dlic_model;
 
 /* Coder instances (Section II-B, rANS: several coder instances and
- * bitstreams).  G groups of row strips, each one stream shared by
- * lanes_per_group interleaved 32-bit rANS states.  Group g owns rows
- * [g*H/G, (g+1)*H/G); row y of group g is lane (y - r_g) % L.
- * Constraints: 1 <= L <= 64; G <= 1024; G == 1 or H >= 2*G; at most 256
- * rows per group (the decoder keeps a group's pixel ring in LDS). */
+ * bitstreams).  G groups, each one stream shared by lanes_per_group
+ * interleaved 32-bit rANS states.  With S = strips (0 or 1: S = 1) the image
+ * is cut into S*G row strips, strip b owning rows [b*H/(SG), (b+1)*H/(SG)),
+ * and group g codes strips g, G + g, ..., (S-1)G + g one after another, its
+ * lanes' states carrying from strip to strip; row y of a strip starting at
+ * row r is lane (y - r) % L.  Spread strips let a group's decode work in
+ * fewer wavefront steps at once when a strip is shorter than the band of
+ * rows the wavefront keeps active (about W/3 rows).  An image stream stores
+ * S - 1 in bits 12..15 of its header flags.
+ * Constraints: 1 <= L <= 64; G <= 1024; S <= DLIC_MAX_STRIPS; S*G == 1 or
+ * H >= 2*S*G; at most 256 rows per strip (the decoder keeps a strip's pixel
+ * ring in LDS).  S > 1: the mixture-network image codec only (dlic_encode,
+ * dlic_decode, dlic_rans_encode_cf, dlic_rans_decode_tables), with all G
+ * decoder workgroups resident at once (DLIC_ERR_UNSUPPORTED otherwise). */
+#define DLIC_MAX_STRIPS 16
 typedef struct dlic_coder {
   int32_t groups;
   int32_t lanes_per_group;
+  int32_t strips;
 } dlic_coder;
 
 /* ---- host-only helpers (no device needed) ----------------------------- */
@@ -151,7 +162,8 @@ size_t dlic_encode_workspace(int32_t h, int32_t w, const dlic_coder *coder);
 size_t dlic_decode_workspace(int32_t h, int32_t w, const dlic_coder *coder);
 
 /* Parse the 36-byte stream header from host bytes.  Any out pointer may be
- * NULL.  Returns DLIC_ERR_CORRUPT for a bad magic, version or length. */
+ * NULL.  coder receives groups, lanes and strips (1 for a volume stream).
+ * Returns DLIC_ERR_CORRUPT for a bad magic, version or length. */
 dlic_status dlic_peek_header(const uint8_t *h_bits, size_t n, int32_t *h, int32_t *w,
                              dlic_coder *coder, uint64_t *fingerprint,
                              int32_t *h1, int32_t *h2, int32_t *dtype);

@@ -61,7 +61,8 @@ class dlic_model(ctypes.Structure):
 
 
 class dlic_coder(ctypes.Structure):
-    _fields_ = [("groups", c_int32), ("lanes_per_group", c_int32)]
+    """groups, lanes_per_group, strips (row strips per group; 0 or 1: one)."""
+    _fields_ = [("groups", c_int32), ("lanes_per_group", c_int32), ("strips", c_int32)]
 
 
 DEEP_LAYERS = 6
@@ -329,16 +330,21 @@ def dlic_kernel_times(max_n: int = 16):
 
 # ---- conveniences (torch-allocated buffers) -------------------------------------
 
-def default_coder(h: int, lanes: int = 4, rows_per_group: int = 24) -> dlic_coder:
-    """G = ceil(h / rows_per_group) row strips of `lanes` interleaved lanes.
+def default_coder(h: int, lanes: int = 4, rows_per_group: int = 24, strips: int = 1) -> dlic_coder:
+    """G = ceil(h / rows_per_group) groups of `lanes` interleaved lanes, each
+    coding `strips` row strips spread over the image.
 
-    The default, strips of 24 rows with 4 lanes each (64 x 4 = 256 lanes on a
-    1536-row image), decodes fastest: a decoder workgroup per strip and 16 of
-    its coder lanes per pixel in the symbol search."""
+    Groups of 24 rows with 4 lanes each (64 x 4 = 256 lanes on a 1536-row
+    image) decode with a workgroup per group and 16 of its coder lanes per
+    pixel in the symbol search.  With 2 strips per group, when a strip is
+    shorter than the wavefront's band of active rows (about w/3), a group has
+    rows in half as many steps at once."""
     g = max(1, math.ceil(h / rows_per_group))
     if g > 1 and h < 2 * g:
         g = max(1, h // 2)
-    return dlic_coder(g, lanes)
+    while strips > 1 and h < 2 * g * strips:
+        strips -= 1
+    return dlic_coder(g, lanes, strips)
 
 
 DTYPES = {"fp32": DLIC_FP32, "bf16": DLIC_BF16, "fp8": DLIC_FP8_E4M3, "fp8a8": DLIC_FP8_W8A8}

@@ -156,16 +156,27 @@ int max_group_rows(int h, int G) {
   return m;
 }
 
-// Layouts this library writes and reads: 1..64 lanes, at most 1024 groups,
-// every group at least 2 rows (G == 1 aside) and at most 256 rows.
+// Row strips per group: 0 and 1 both mean one contiguous strip; -1 for an
+// out-of-range value.
+int coder_strips(const dlic_coder* c) {
+  if (c->strips < 0 || c->strips > DLIC_MAX_STRIPS) return -1;
+  return c->strips > 1 ? c->strips : 1;
+}
+
+// Layouts this library writes and reads: 1..64 lanes, at most 1024 groups of
+// 1..16 row strips each, every strip at least 2 rows (one strip in all aside)
+// and at most 256 rows.
 bool coder_ok(int h, const dlic_coder* c) {
   if (!c) return false;
-  const int G = c->groups, L = c->lanes_per_group;
-  if (L < 1 || L > 64 || G < 1 || G > 1024) return false;
-  if (G > 1 && h < 2 * G) return false;
-  if (max_group_rows(h, G) > DEC_RMAX) return false;
+  const int G = c->groups, L = c->lanes_per_group, S = coder_strips(c);
+  if (L < 1 || L > 64 || G < 1 || G > 1024 || S < 1) return false;
+  if (G * S > 1 && h < 2 * G * S) return false;
+  if (max_group_rows(h, G * S) > DEC_RMAX) return false;
   return true;
 }
+
+// The deep network's codecs, the volumes and the batches code one strip per group.
+bool flat_coder_ok(int h, const dlic_coder* c) { return coder_ok(h, c) && coder_strips(c) == 1; }
 
 dlic_status model_ok(const dlic_model* m) {
   if (!m) return DLIC_ERR_ARG;
@@ -243,13 +254,13 @@ int pack_chunks(long long n, int G) {
 dlic_status run_rans_and_pack(int h, int w, const dlic_coder* coder, const uint32_t* cf,
                               const EncWs& ws, const HeaderFields& hf, uint8_t* d_out,
                               uint64_t* d_out_len, hipStream_t s) {
-  const int G = coder->groups, L = coder->lanes_per_group;
+  const int G = coder->groups, L = coder->lanes_per_group, S = coder_strips(coder);
   timing_begin("rans_encode_kernel", s);
-  launch_rans_encode(cf, h, w, G, L, ws.words, ws.counts, s);
+  launch_rans_encode(cf, h, w, G, L, S, ws.words, ws.counts, s);
   timing_end(s);
   if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
   timing_begin("pack_kernel", s);
-  launch_pack(ws.words, ws.counts, h, w, G, L, hf, d_out, d_out_len,
+  launch_pack(ws.words, ws.counts, h, w, G, L, S, hf, d_out, d_out_len,
               pack_chunks((long long)h * w, G), s);
   timing_end(s);
   return launch_ok();
@@ -310,7 +321,7 @@ dlic_coder stacked_coder(const dlic_coder* c, int z) {
 }
 
 bool vol_coder_ok(int z, int h, const dlic_coder* c) {
-  if (!coder_ok(h, c)) return false;
+  if (!flat_coder_ok(h, c)) return false;
   const dlic_coder t = stacked_coder(c, z);
   return coder_ok(z * h, &t);
 }
@@ -761,8 +772,9 @@ size_t dlic_encode_workspace(int32_t h, int32_t w, const dlic_coder* coder) {
 
 size_t dlic_decode_workspace(int32_t h, int32_t w, const dlic_coder* coder) {
   if (h <= 0 || w <= 0 || !coder_ok(h, coder)) return 0;
-  // records [G][T], then the group ticket
-  return align256(4 * ((size_t)coder->groups * (size_t)n_steps(h, w) + 1));
+  // records [S*G][T] (one row per strip), then the group ticket
+  const size_t strips = (size_t)coder->groups * (size_t)coder_strips(coder);
+  return align256(4 * (strips * (size_t)n_steps(h, w) + 1));
 }
 
 dlic_status dlic_peek_header(const uint8_t* b, size_t n, int32_t* h, int32_t* w,
@@ -782,6 +794,9 @@ dlic_status dlic_peek_header(const uint8_t* b, size_t n, int32_t* h, int32_t* w,
   if (coder) {
     coder->groups = G;
     coder->lanes_per_group = L;
+    // an image's flags hold its strips per group - 1 in bits 12..15
+    const uint32_t flags = u16(6);
+    coder->strips = (flags & 0xFFFu) == 0 ? (int32_t)(flags >> 12) + 1 : 1;
   }
   if (fingerprint) *fingerprint = (uint64_t)u32(28) | ((uint64_t)u32(32) << 32);
   return DLIC_OK;
@@ -810,6 +825,7 @@ dlic_status dlic_encode(const dlic_model* model, const dlic_coder* coder, const 
   timing_end(stream);
   if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
   HeaderFields hf{model->dtype, model->h1, model->h2, model->fingerprint};
+  hf.flags = (coder_strips(coder) - 1) << 12;
   return run_rans_and_pack(h, w, coder, ws.cf, ws, hf, d_out, d_out_len, stream);
 }
 
@@ -844,6 +860,7 @@ dlic_status dlic_rans_encode_cf(const dlic_coder* coder, int32_t h, int32_t w,
   EncWs ws;
   enc_ws_layout(h, w, coder->groups, coder->lanes_per_group, d_ws, &ws);
   HeaderFields hf{0, 0, 0, 0ull};
+  hf.flags = (coder_strips(coder) - 1) << 12;
   return run_rans_and_pack(h, w, coder, d_cf, ws, hf, d_out, d_out_len, stream);
 }
 
@@ -856,7 +873,6 @@ static dlic_status decode_common(const dlic_model* model, bool tables_mode,
   timing_reset();
   if (!d_bits || !d_img || !d_status || !d_ws || h <= 0 || w <= 0) return DLIC_ERR_ARG;
   if (!coder_ok(h, coder)) return DLIC_ERR_UNSUPPORTED;
-  if (max_group_rows(h, coder->groups) > DEC_RMAX) return DLIC_ERR_UNSUPPORTED;
   // sub-round counters are 32-bit: (W + 3R) * ceil(R / L) < 2^31
   if (((long long)w + 3LL * DEC_RMAX) * DEC_RMAX >= (1LL << 31)) return DLIC_ERR_UNSUPPORTED;
   if (ws_bytes < dlic_decode_workspace(h, w, coder)) return DLIC_ERR_CAPACITY;
@@ -872,9 +888,10 @@ static dlic_status decode_common(const dlic_model* model, bool tables_mode,
   a.W = w;
   a.G = coder->groups;
   a.L = coder->lanes_per_group;
+  a.S = coder_strips(coder);
   a.rec = (uint32_t*)d_ws;
   a.T = n_steps(h, w);
-  a.ticket = (unsigned*)(a.rec + (long long)a.G * a.T);
+  a.ticket = (unsigned*)(a.rec + (long long)a.G * a.S * a.T);
   a.status = d_status;
   a.spin_limit = g_spin_limit;
   a.delay_seed = g_delay_seed;
@@ -897,7 +914,7 @@ static dlic_status decode_common(const dlic_model* model, bool tables_mode,
     wtype = weight_type(model);
   }
   timing_begin("fill_u32_kernel", stream);
-  launch_fill_u32(a.rec, 0u, (long long)a.G * a.T + 1, stream);
+  launch_fill_u32(a.rec, 0u, (long long)a.G * a.S * a.T + 1, stream);
   launch_fill_u32((uint32_t*)d_status, 0u, 1, stream);
   timing_end(stream);
   if (launch_ok() != DLIC_OK) return DLIC_ERR_HIP;
@@ -1077,8 +1094,9 @@ dlic_status dlic_batch_create(const dlic_model* model, int32_t n_img, const int3
     } else {
       c.groups = h > 192 ? (h + 191) / 192 : 1;
       c.lanes_per_group = 32;
+      c.strips = 1;
     }
-    if (h <= 0 || w <= 0 || !coder_ok(h, &c) ||
+    if (h <= 0 || w <= 0 || !flat_coder_ok(h, &c) ||
         ((long long)w + 3LL * DEC_RMAX) * DEC_RMAX >= (1LL << 31)) {
       delete b;
       return h <= 0 || w <= 0 ? DLIC_ERR_ARG : DLIC_ERR_UNSUPPORTED;
@@ -1285,7 +1303,7 @@ dlic_status dlic_latency_probe(double* h_out, int32_t n, void* d_ws, size_t ws_b
 size_t dlic_deep_workspace(const dlic_deep_model* model, int32_t h, int32_t w,
                            const dlic_coder* coder, int32_t decode) {
   if (!model || h <= 0 || w <= 0 || deep_model_ok(model, true) != DLIC_OK) return 0;
-  if (decode >= 0 && !coder_ok(h, coder)) return 0;
+  if (decode >= 0 && !flat_coder_ok(h, coder)) return 0;
   return deep_ws_bytes(1, h, w, coder, model->hidden, model->depth, decode);
 }
 
@@ -1307,7 +1325,7 @@ dlic_status dlic_deep_encode(const dlic_deep_model* model, const dlic_coder* cod
                              hipStream_t stream) {
   timing_reset();
   if (!d_img || !d_out || !d_out_len || !d_ws || h <= 0 || w <= 0) return DLIC_ERR_ARG;
-  if (!coder_ok(h, coder)) return DLIC_ERR_UNSUPPORTED;
+  if (!flat_coder_ok(h, coder)) return DLIC_ERR_UNSUPPORTED;
   const dlic_status rc = deep_model_ok(model, false);
   if (rc != DLIC_OK) return rc;
   return deep_encode_impl(model, coder, d_img, h, w, VolGeom{}, deep_header(model, nullptr),
@@ -1320,7 +1338,7 @@ dlic_status dlic_deep_decode(const dlic_deep_model* model, const dlic_coder* cod
                              hipStream_t stream) {
   timing_reset();
   if (!d_bits || !d_img || !d_status || !d_ws || h <= 0 || w <= 0) return DLIC_ERR_ARG;
-  if (!coder_ok(h, coder)) return DLIC_ERR_UNSUPPORTED;
+  if (!flat_coder_ok(h, coder)) return DLIC_ERR_UNSUPPORTED;
   const dlic_status rc = deep_model_ok(model, false);
   if (rc != DLIC_OK) return rc;
   return deep_decode_impl(model, coder, d_bits, n_bytes, d_img, h, w, VolGeom{},

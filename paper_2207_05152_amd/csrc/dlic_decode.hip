@@ -81,6 +81,8 @@ __device__ int check_header(const DecArgs& a) {
   if (rd_u32(b + 8) != (uint32_t)a.H || rd_u32(b + 12) != (uint32_t)a.W) return 3;
   if (b[16] != K_IN || b[17] != N_MIX || b[19] != SKEW || b[24] != PROB_BITS) return 3;
   if (b[25] != (uint8_t)a.L || rd_u16(b + 26) != (uint32_t)a.G) return 3;
+  // an image's flags: strips per group - 1 in bits 12..15, nothing else
+  if (rd_u16(b + 6) != ((uint32_t)(a.S - 1) << 12)) return 3;
   if (a.check_model) {
     const uint64_t fp = (uint64_t)rd_u32(b + 28) | ((uint64_t)rd_u32(b + 32) << 32);
     if (b[18] != (uint8_t)a.hf.dtype || rd_u16(b + 20) != (uint32_t)a.hf.h1 ||
@@ -185,6 +187,27 @@ __device__ __forceinline__ float bin_edge(int v) { return div255(2 * v - 256); }
 
 // Decode of group g of one stream by the whole workgroup.  LPP is
 // coder_lpp(L): how many coder lanes share each pixel's symbol search.
+// The coder wave's end of a strip.  After the group's last strip every lane
+// must be back at its initial state and every word consumed; after an earlier
+// one the states and the word position go to LDS for the next strip, and a
+// failure stops the group.
+__device__ __forceinline__ void coder_strip_end(const DecArgs& a, int g, bool last_strip, int lane,
+                                                bool in_use, uint32_t x, uint32_t Pw,
+                                                uint32_t n_words, bool bad, bool stuck,
+                                                bool timeout, uint32_t* s_x, uint32_t* s_pw,
+                                                int* s_stop) {
+  (void)g;
+  const bool lane_bad = last_strip && in_use && x != RANS_L;
+  const bool any_bad = __ballot(lane_bad || bad) != 0ull;
+  if (!last_strip) s_x[lane] = x;
+  if (lane == 0) {
+    if (any_bad || stuck || (last_strip && Pw != n_words)) atomicMax(a.status, 3);
+    if (timeout) atomicMax(a.status, 7);
+    if (!last_strip) *s_pw = Pw;
+    if (any_bad || stuck || timeout) *s_stop = 1;
+  }
+}
+
 template <class Net, bool TABLES, int LPP, bool DELAY = false>
 __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const DevModel& m,
                                              const DecArgs& a, const int g) {
@@ -203,7 +226,8 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
   __shared__ int s_decoded;
   __shared__ uint32_t s_pw, s_end;  // words consumed by the coder / loaded into the ring
   __shared__ unsigned long long s_total, s_before;
-  __shared__ int s_err, s_flag;
+  __shared__ int s_err, s_flag, s_stop;
+  __shared__ uint32_t s_x[64];          // lane states carried from strip to strip
   __shared__ __attribute__((aligned(16))) char s_w2[Net::LDS_BYTES > 0 ? Net::LDS_BYTES : 16];
   __shared__ __attribute__((aligned(16)))
   float s_xs[Net::SCRATCH_FLOATS > 0 ? dec_workers<Net>() * Net::SCRATCH_FLOATS : 4];
@@ -217,13 +241,11 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     for (int i = tid; i < 257; i += NTH) s_beta[i] = K->beta[i];
     Net::stage(m, s_w2, tid, NTH);
   }
-  if (tid < NSLOT * 4) s_done[tid / 4][tid % 4] = -1;
   if (tid == 0) {
     s_err = check_header(a);
     s_total = 0;
     s_before = 0;
-    s_decoded = 0;
-    s_flag = 0;
+    s_stop = 0;
     s_pw = 0;
     s_end = 0;
   }
@@ -245,22 +267,40 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     return;
   }
 
-  const int r0 = group_row(g, H, G), r1 = group_row(g + 1, H, G);
+  const uint32_t n_words = rd_u32(a.bits + HEADER_BYTES + 4 * g);
+  const uint16_t* gw = reinterpret_cast<const uint16_t*>(
+      a.bits + HEADER_BYTES + 4LL * G + 2ull * s_before);
+  const bool bad = n_words < 2u * (uint32_t)L;
+  const uint32_t E0 = bad ? 0u : min(n_words, (uint32_t)DEC_RING);
+  for (uint32_t i = tid; i < E0; i += NTH) s_words[i] = gw[i];
+  if (tid == 0) s_end = E0;
+
+  // The group's strips one after another (strip b = sG + g of the S*G strips,
+  // its upstream neighbour strip b - 1, which for g = 0 is the last group's
+  // previous strip); the coder's lane states, its word position and the word
+  // ring carry over.  Every wave passes the barriers at the strip's start and
+  // end, whatever its role.
+  const int GS = G * a.S;
+  for (int sp = 0; sp < a.S; ++sp) {
+  const int b = sp * G + g;
+  const bool first_strip = sp == 0, last_strip = sp == a.S - 1;
+  const int r0 = group_row(b, H, GS), r1 = group_row(b + 1, H, GS);
   const int R = r1 - r0;
   const int J = (R + L - 1) / L;
   const int NT = (L + 15) / 16;
   const int t_first = SKEW * r0, t_last = SKEW * (r1 - 1) + W - 1;
   const int P = (t_last - t_first + 1) * J;  // sub-rounds (host keeps this below 2^31)
-  const int up_last = (g > 0) ? SKEW * (r0 - 1) + W - 1 : -1;
-  const uint32_t n_words = rd_u32(a.bits + HEADER_BYTES + 4 * g);
-  const uint16_t* gw = reinterpret_cast<const uint16_t*>(
-      a.bits + HEADER_BYTES + 4LL * G + 2ull * s_before);
-  const bool bad = n_words < 2u * (uint32_t)L;
-  const uint32_t* up_rec = a.rec + (long long)(g - 1) * a.T;
-  uint32_t* my_rec = a.rec + (long long)g * a.T;
+  const int up_last = (b > 0) ? SKEW * (r0 - 1) + W - 1 : -1;
+  const uint32_t* up_rec = a.rec + (long long)(b - 1) * a.T;
+  uint32_t* my_rec = a.rec + (long long)b * a.T;
 
-  // upstream records of the steps before this group's first one
-  if (tid == 0 && g > 0) {
+  if (tid < NSLOT * 4) s_done[tid / 4][tid % 4] = -1;
+  if (tid == 0) {
+    s_decoded = 0;
+    s_flag = 0;
+  }
+  // upstream records of the steps before this strip's first one
+  if (tid == 0 && b > 0) {
     bool ok = true;
     for (int s = t_first - 2 * SKEW; s <= t_first - 2 && ok; ++s) {
       uint32_t v;
@@ -269,10 +309,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     }
     if (!ok) s_flag = 7;
   }
-  const uint32_t E0 = bad ? 0u : min(n_words, (uint32_t)DEC_RING);
-  for (uint32_t i = tid; i < E0; i += NTH) s_words[i] = gw[i];
   if (tid == 0) {
-    s_end = E0;
     s_pub = t_first - 1;
     s_rcv = t_first - 2;
   }
@@ -301,11 +338,16 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     // the work is branch-free.
     const int cl = lane >> 4, h = lane & 15;
     uint32_t x = RANS_L;
-    if (cl < L && !bad) x = (uint32_t)gw[2 * cl] | ((uint32_t)gw[2 * cl + 1] << 16);
-    uint32_t Pw = 2u * (uint32_t)L;
+    if (!first_strip)
+      x = s_x[lane];
+    else if (cl < L && !bad)
+      x = (uint32_t)gw[2 * cl] | ((uint32_t)gw[2 * cl + 1] << 16);
+    uint32_t Pw = first_strip ? 2u * (uint32_t)L : s_pw;
     bool over = false, stuck = false;
     const bool timeout = s_flag != 0;
-    uint32_t E = E0;
+    uint32_t E = first_strip
+                     ? E0
+                     : __hip_atomic_load(&s_end, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
     int t = t_first, j = -1, pub = t_first - 1;
     const unsigned long long k0 = a.prof ? clk_now() : 0ull;
     const unsigned long long rt0 = a.prof ? __builtin_amdgcn_s_memrealtime() : 0ull;
@@ -315,9 +357,11 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     unsigned long long n_late = 0, t_late = 0;
     const uint64_t below = (1ull << (16 * cl)) - 1ull;
     // stream words wbase .. wbase + 63, one per lane (the ring holds at least
-    // min(n_words, 4096) words at the start)
+    // min(n_words, 4096) words at the start; a later strip loads its window
+    // in its first sub-round, once the ring is known to hold it)
     uint32_t wbase = Pw;
-    uint32_t wwin = s_words[(wbase + (uint32_t)lane) & RING_MASK];
+    uint32_t wwin = first_strip ? s_words[(wbase + (uint32_t)lane) & RING_MASK] : 0u;
+    bool win_ok = first_strip;
     // the batch of sub-round pre_q, issued during the sub-round before it
     int pre_q = -1, nd = 0;
     f4 n0 = {0.0f, 0.0f, 0.0f, 0.0f}, n1 = n0, n2 = n0, n3 = n0;
@@ -340,10 +384,11 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         }
       }
       if (j == 0 && !stuck) stuck = !wait_publisher(&s_pub, t, pub);
-      if (Pw + 4u > wbase + 64u) {
+      if (Pw + 4u > wbase + 64u || !win_ok) {
         // the ring holds min(n_words, Pw + 64) words by now
         wbase = Pw;
         wwin = s_words[(wbase + (uint32_t)lane) & RING_MASK];
+        win_ok = true;
       }
       const int rr = j * L + cl;
       const int y = r0 + rr;
@@ -500,22 +545,19 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         c_ld = c_sr = 0;
       }
     }
-    const bool lane_bad = (cl < L) && (x != RANS_L);
-    const bool any_bad = __ballot(lane_bad || over || bad) != 0ull;
-    if (lane == 0) {
-      if (any_bad || Pw != n_words || stuck) atomicMax(a.status, 3);
-      if (timeout) atomicMax(a.status, 7);
-      if (a.prof) {
-        a.prof[g * PROF_SLOTS + 0] = t_wait;
-        a.prof[g * PROF_SLOTS + 1] = t_busy;
-        a.prof[g * PROF_SLOTS + 8] = t_load;
-        a.prof[g * PROF_SLOTS + 9] = t_search;
-        a.prof[g * PROF_SLOTS + 10] = (unsigned long long)P;
-        a.prof[g * PROF_SLOTS + 12] = t_late;
-        a.prof[g * PROF_SLOTS + 13] = clk_now() - k0;
-        a.prof[g * PROF_SLOTS + 14] = __builtin_amdgcn_s_memrealtime() - rt0;
-        a.prof[g * PROF_SLOTS + 15] = n_late;
-      }
+    coder_strip_end(a, g, last_strip, lane, cl < L, x, Pw, n_words, over || bad, stuck, timeout,
+                    s_x, &s_pw, &s_stop);
+    if (lane == 0 && a.prof) {
+      // counters add up over the strips (the caller clears them)
+      a.prof[g * PROF_SLOTS + 0] += t_wait;
+      a.prof[g * PROF_SLOTS + 1] += t_busy;
+      a.prof[g * PROF_SLOTS + 8] += t_load;
+      a.prof[g * PROF_SLOTS + 9] += t_search;
+      a.prof[g * PROF_SLOTS + 10] += (unsigned long long)P;
+      a.prof[g * PROF_SLOTS + 12] += t_late;
+      a.prof[g * PROF_SLOTS + 13] += clk_now() - k0;
+      a.prof[g * PROF_SLOTS + 14] += __builtin_amdgcn_s_memrealtime() - rt0;
+      a.prof[g * PROF_SLOTS + 15] += n_late;
     }
   } else if (!TABLES && wave == 4) {
     // --------------------------------------------------------------- courier
@@ -534,7 +576,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     // overwritten before they are published.
     int pub_t = t_first;      // next own step to publish
     int rcv = t_first - 1;    // next upstream record to receive
-    const int rcv_last = g > 0 ? up_last : rcv - 1;
+    const int rcv_last = b > 0 ? up_last : rcv - 1;
     bool stuck = false, timeout = s_flag != 0;
     uint32_t idle = 0, rspins = 0;
     while ((pub_t <= t_last || (rcv <= rcv_last && !timeout)) && !stuck) {
@@ -542,7 +584,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       bool progress = false;
       const int done_q = lds_acquire(&s_decoded);
       while (pub_t <= t_last && done_q >= (pub_t - t_first + 1) * J) {
-        if (lane == 0 && g + 1 < G) {
+        if (lane == 0 && b + 1 < GS) {
           const int d1 = pub_t - SKEW * (r1 - 1), d2 = pub_t - SKEW * (r1 - 2);
           uint32_t rv = 0x80000000u;
           if (d1 >= 0 && d1 < W) rv |= (uint32_t)s_ring[(R - 1 + 2) * 16 + (d1 & 15)];
@@ -593,8 +635,10 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     }
     if (lane == 0) {
       // density waves stop waiting for records that will not come
-      if (timeout || stuck)
+      if (timeout || stuck) {
         __hip_atomic_store(&s_rcv, 0x7FFFFFFF, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        s_stop = 1;
+      }
       if (stuck) atomicMax(a.status, 3);
       if (timeout) atomicMax(a.status, 7);
     }
@@ -602,10 +646,16 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     // ------------------------------------------------------------------ coder
     const int cl = lane;  // the pixel (coder lane) this lane serves
     uint32_t x = RANS_L;
-    if (cl < L && !bad) x = (uint32_t)gw[2 * cl] | ((uint32_t)gw[2 * cl + 1] << 16);
-    uint32_t Pw = 2u * (uint32_t)L;  // words consumed
+    if (!first_strip)
+      x = s_x[lane];
+    else if (cl < L && !bad)
+      x = (uint32_t)gw[2 * cl] | ((uint32_t)gw[2 * cl + 1] << 16);
+    uint32_t Pw = first_strip ? 2u * (uint32_t)L : s_pw;  // words consumed
     bool over = false, stuck = false, timeout = s_flag != 0;
-    uint32_t E = E0;                   // words known to be in the ring
+    // words known to be in the ring
+    uint32_t E = first_strip
+                     ? E0
+                     : __hip_atomic_load(&s_end, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
     int t = t_first, j = -1, pub = t_first - 1;
     const unsigned long long k0 = a.prof ? clk_now() : 0ull;
     const unsigned long long rt0 = a.prof ? __builtin_amdgcn_s_memrealtime() : 0ull;
@@ -809,7 +859,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       }
       // after the last block of step t, hand rows r1-2 and r1-1 to the next
       // group (with density waves the publisher wave does this)
-      if (TABLES && j == J - 1 && lane == 0 && g + 1 < G) {
+      if (TABLES && j == J - 1 && lane == 0 && b + 1 < GS) {
         const int d1 = t - SKEW * (r1 - 1), d2 = t - SKEW * (r1 - 2);
         uint32_t rv = 0x80000000u;
         if (d1 >= 0 && d1 < W) rv |= (uint32_t)s_ring[(R - 1 + 2) * 16 + (d1 & 15)];
@@ -817,26 +867,25 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         __hip_atomic_store(my_rec + t, rv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
-    const bool lane_bad = (cl < L) && (x != RANS_L);
-    const bool any_bad = __ballot(lane_bad || over || bad) != 0ull;
-    if (lane == 0) {
-      if (any_bad || Pw != n_words || stuck) atomicMax(a.status, 3);
-      if (timeout) atomicMax(a.status, 7);
-      if (a.prof) {
-        a.prof[g * PROF_SLOTS + 0] = t_wait;
-        a.prof[g * PROF_SLOTS + 1] = t_busy;
-        a.prof[g * PROF_SLOTS + 8] = t_load;
-        a.prof[g * PROF_SLOTS + 9] = t_search;
-        a.prof[g * PROF_SLOTS + 10] = (unsigned long long)P;
-        a.prof[g * PROF_SLOTS + 12] = t_wait0;
-        a.prof[g * PROF_SLOTS + 13] = clk_now() - k0;
-        a.prof[g * PROF_SLOTS + 14] = __builtin_amdgcn_s_memrealtime() - rt0;
-      }
+    // the table coder keeps its own ring: its end carries to the next strip
+    if (TABLES && lane == 0 && !last_strip) s_end = E;
+    coder_strip_end(a, g, last_strip, lane, cl < L, x, Pw, n_words, over || bad, stuck, timeout,
+                    s_x, &s_pw, &s_stop);
+    if (lane == 0 && a.prof) {
+      a.prof[g * PROF_SLOTS + 0] += t_wait;
+      a.prof[g * PROF_SLOTS + 1] += t_busy;
+      a.prof[g * PROF_SLOTS + 8] += t_load;
+      a.prof[g * PROF_SLOTS + 9] += t_search;
+      a.prof[g * PROF_SLOTS + 10] += (unsigned long long)P;
+      a.prof[g * PROF_SLOTS + 12] += t_wait0;
+      a.prof[g * PROF_SLOTS + 13] += clk_now() - k0;
+      a.prof[g * PROF_SLOTS + 14] += __builtin_amdgcn_s_memrealtime() - rt0;
     }
   } else if (!TABLES) {
     // -------------------------------------------------------- density waves
     // waves 4, 8, ... share the coder's SIMD and compute no densities
-    if ((wave & 3) == 0) return;
+    do {
+    if ((wave & 3) == 0) break;
     constexpr int nwork = dec_workers<Net>();
     const int w = wave - 1 - (wave >> 2);
     Net net;
@@ -898,7 +947,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       if (__ballot(valid) != 0ull) {
         // the tile holding row r0 needs the group above's step t-1 in the
         // ring; the courier has usually put it there already
-        if (rr == 0 && valid && lane == 0 && g > 0 && t - 1 <= up_last && !stuck) {
+        if (rr == 0 && valid && lane == 0 && b > 0 && t - 1 <= up_last && !stuck) {
           uint32_t spins = 0;
           while (lds_acquire(&s_rcv) < t - 1) {
             if (++spins > LDS_SPIN_LIMIT) {
@@ -1047,6 +1096,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       }
     }
     if (lane == 0) {
+      if (stuck || timeout) s_stop = 1;
       if (stuck) atomicMax(a.status, 3);
       if (timeout) atomicMax(a.status, 7);
       if (a.prof) {
@@ -1058,7 +1108,12 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         atomicAdd(&a.prof[g * PROF_SLOTS + 7], n_tiles);
       }
     }
+    } while (false);
   }
+  // the strip is done on every wave; a failed strip ends the group
+  __syncthreads();
+  if (__builtin_amdgcn_readfirstlane(s_stop) != 0) break;
+  }  // strips
 }
 
 // One image: each workgroup takes its group by ticket, so group g - 1 was
@@ -1104,6 +1159,7 @@ __global__ __launch_bounds__(dec_waves<Net>() * 64) void batch_decode_kernel(
     a.W = im.W;
     a.G = im.G;
     a.L = im.L;
+    a.S = 1;
     a.rec = b.rec + im.rec_off;
     a.ticket = nullptr;
     a.T = im.T;
@@ -1235,8 +1291,13 @@ bool launch_batch_decode(int wtype, int width, const Consts* K, const DevModel& 
 }
 
 template <class Net, bool TABLES, int LPP>
-static void launch_wavefront(const Consts* K, const DevModel& m, const DecArgs& a, hipStream_t s) {
+static bool launch_wavefront(const Consts* K, const DevModel& m, const DecArgs& a, hipStream_t s) {
   const dim3 grid(a.G), block(dec_waves<Net>() * 64);
+  // With several strips per group, group 0's second strip waits for the last
+  // group's first: every group's workgroup must be resident at once.
+  if (a.S > 1 && persistent_grid(wavefront_decode_kernel<Net, TABLES, LPP, false>,
+                                 (int)block.x, a.G) < a.G)
+    return false;
   // the delay-injecting form (a test hook) is a separate kernel, so that the
   // production kernel carries no trace of it
   if (a.delay_max > 0)
@@ -1245,29 +1306,27 @@ static void launch_wavefront(const Consts* K, const DevModel& m, const DecArgs& 
   else
     hipLaunchKernelGGL((wavefront_decode_kernel<Net, TABLES, LPP, false>), grid, block, 0, s, K,
                        m, a);
+  return true;
 }
 
 // The table-driven coder (no density waves) runs one lane per pixel.
 template <class Net, bool TB>
-static void launch_decode_t(const Consts* K, const DevModel& m, const DecArgs& a, hipStream_t s) {
+static bool launch_decode_t(const Consts* K, const DevModel& m, const DecArgs& a, hipStream_t s) {
   if constexpr (TB) {
-    launch_wavefront<Net, true, 1>(K, m, a, s);
+    return launch_wavefront<Net, true, 1>(K, m, a, s);
   } else {
     const int lpp = coder_lpp(a.L);
-    if (lpp == 16)
-      launch_wavefront<Net, false, 16>(K, m, a, s);
-    else if (lpp == 2)
-      launch_wavefront<Net, false, 2>(K, m, a, s);
-    else
-      launch_wavefront<Net, false, 1>(K, m, a, s);
+    if (lpp == 16) return launch_wavefront<Net, false, 16>(K, m, a, s);
+    if (lpp == 2) return launch_wavefront<Net, false, 2>(K, m, a, s);
+    return launch_wavefront<Net, false, 1>(K, m, a, s);
   }
 }
 
 // Nets for tiles of at most 4 pixels run only with the 16-lane coder (L <= 4).
 template <class Net>
-static void launch_decode_lpp16(const Consts* K, const DevModel& m, const DecArgs& a,
+static bool launch_decode_lpp16(const Consts* K, const DevModel& m, const DecArgs& a,
                                 hipStream_t s) {
-  launch_wavefront<Net, false, 16>(K, m, a, s);
+  return launch_wavefront<Net, false, 16>(K, m, a, s);
 }
 
 // Layer-2 weights of the BF16 nets go to LDS at H = 128: six density waves
@@ -1281,24 +1340,19 @@ static bool launch_decode_h(int wtype, const Consts* K, const DevModel& m, const
       // sub-round, latency-bound): the 4-pixel 4x4 MFMA form at H = 64 and
       // 128; wider layouts need the 9 density waves of the 12-wave form at
       // H = 64
-      if (H >= 64 && a.L <= 4)
-        launch_decode_lpp16<NetF32x4<(H >= 64 ? H : 64)>>(K, m, a, s);
-      else
-        launch_decode_t<NetF32<H, (H >= 64)>, false>(K, m, a, s);
-      return true;
-    case WT_BF16: launch_decode_t<NetBF16<H, WT_BF16, (H > 64)>, false>(K, m, a, s); return true;
-    case WT_FP8: launch_decode_t<NetBF16<H, WT_FP8, (H > 64)>, false>(K, m, a, s); return true;
-    case WT_FP8A8: launch_decode_t<NetFP8A<H, (H > 64)>, false>(K, m, a, s); return true;
+      if (H >= 64 && a.L <= 4) return launch_decode_lpp16<NetF32x4<(H >= 64 ? H : 64)>>(K, m, a, s);
+      return launch_decode_t<NetF32<H, (H >= 64)>, false>(K, m, a, s);
+    case WT_BF16: return launch_decode_t<NetBF16<H, WT_BF16, (H > 64)>, false>(K, m, a, s);
+    case WT_FP8: return launch_decode_t<NetBF16<H, WT_FP8, (H > 64)>, false>(K, m, a, s);
+    case WT_FP8A8: return launch_decode_t<NetFP8A<H, (H > 64)>, false>(K, m, a, s);
     default: return false;
   }
 }
 
+// False for an unsupported model or layout (nothing launched then).
 bool launch_decode(int wtype, int width, bool tables_mode, const Consts* K, const DevModel& m,
                    const DecArgs& a, hipStream_t s) {
-  if (tables_mode) {
-    launch_decode_t<NetF32<32>, true>(K, m, a, s);
-    return true;
-  }
+  if (tables_mode) return launch_decode_t<NetF32<32>, true>(K, m, a, s);
   switch (width) {
     case 32: return launch_decode_h<32>(wtype, K, m, a, s);
     case 64: return launch_decode_h<64>(wtype, K, m, a, s);

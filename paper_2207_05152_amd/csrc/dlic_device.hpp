@@ -946,4 +946,19 @@ __device__ __forceinline__ int group_row(int g, int H, int G) {
   return (int)(((long long)g * H) / G);
 }
 
+// With S strips per group the image is cut into S*G strips and group g codes
+// strips g, G + g, ..., (S - 1) G + g in that order.  rows: the rows of those
+// strips; before: the rows of the strips of groups 0 .. g-1 (a group's word
+// scratch follows theirs).  S = 1 gives the contiguous strip of group_row.
+__device__ __forceinline__ void group_span(int g, int H, int G, int S, int& before, int& rows) {
+  const int GS = G * S;
+  before = 0;
+  rows = 0;
+  for (int s = 0; s < S; ++s) {
+    const int b = s * G + g;
+    before += group_row(b, H, GS) - group_row(s * G, H, GS);
+    rows += group_row(b + 1, H, GS) - group_row(b, H, GS);
+  }
+}
+
 }  // namespace dlic

@@ -273,27 +273,59 @@ constexpr int ENC_PER_STAGER = (ENC_SLOTS + ENC_STAGERS - 1) / ENC_STAGERS;
 // + L), inactive slots (rows past the group, steps before its first) marked,
 // so the coder's reads are one running index.  Words go below the top of the
 // group's scratch slice (cap_g = R*W + 2L words, the worst case), so a stream
-// is contiguous at [cap_g - count, cap_g).
+// is contiguous at [cap_g - count, cap_g).  With S strips per group the walk
+// takes the group's strips from the last to the first, each from its last
+// step back, the lanes' states carrying from strip to strip.
+struct EncStrip {
+  int r0, R, J, t_first, t_last, n_chunks;
+};
+
+__device__ __forceinline__ EncStrip enc_strip(int b, int H, int W, int GS, int L) {
+  EncStrip st;
+  st.r0 = group_row(b, H, GS);
+  st.R = group_row(b + 1, H, GS) - st.r0;
+  st.J = (st.R + L - 1) / L;
+  st.t_first = SKEW * st.r0;
+  st.t_last = SKEW * (st.r0 + st.R - 1) + W - 1;
+  st.n_chunks = st.R > 0 ? (st.t_last - st.t_first + ENC_CHUNK) / ENC_CHUNK : 0;
+  return st;
+}
+
 __device__ __forceinline__ void rans_encode_group(uint32_t (*s_cf)[ENC_SLOTS],
                                                   const uint32_t* __restrict__ cf, int H, int W,
-                                                  int G, int L, int g,
+                                                  int G, int L, int S, int g,
                                                   uint16_t* __restrict__ words,
                                                   uint32_t* __restrict__ counts) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r0 = group_row(g, H, G), r1 = group_row(g + 1, H, G);
-  const int R = r1 - r0;
-  const int J = (R + L - 1) / L;
-  const long long cap = (long long)R * W + 2LL * L;
-  uint16_t* out = words + (long long)r0 * W + 2LL * L * g;
-  const int t_first = SKEW * r0, t_last = SKEW * (r1 - 1) + W - 1;
-  const int n_chunks = R > 0 ? (t_last - t_first + ENC_CHUNK) / ENC_CHUNK : 0;
+  const int GS = G * S;
+  int before, rows;
+  group_span(g, H, G, S, before, rows);
+  const long long cap = (long long)rows * W + 2LL * L;
+  uint16_t* out = words + (long long)before * W + 2LL * L * g;
+  int n_chunks = 0;
+  for (int s = 0; s < S; ++s) n_chunks += enc_strip(s * G + g, H, W, GS, L).n_chunks;
+  // chunk k of the walk: its strip and its index c within the strip
+  auto locate = [&](int k, int& c) {
+    EncStrip st{};
+    for (int s = S - 1; s >= 0; --s) {
+      st = enc_strip(s * G + g, H, W, GS, L);
+      if (k < st.n_chunks) break;
+      k -= st.n_chunks;
+    }
+    c = k;
+    return st;
+  };
 
-  // chunk c holds steps [t_last - 32c - 31, t_last - 32c]; the interval of
-  // step t_lo + k, row j * L + l of the group goes to slot i * L + l with
-  // i = (31 - k) * J + (J - 1 - j), its sub-round in the reverse walk
-  const int JL = J * L;  // <= R + L - 1 <= ENC_ROWS - 1
-  auto stage = [&](int c, uint32_t* buf, int first, int stride) {
-    const int t_lo = t_last - ENC_CHUNK * c - (ENC_CHUNK - 1);
+  // chunk c of a strip holds steps [t_last - 32c - 31, t_last - 32c]; the
+  // interval of step t_lo + k, row j * L + l of the strip goes to slot
+  // i * L + l with i = (31 - k) * J + (J - 1 - j), its sub-round in the
+  // reverse walk
+  auto stage = [&](int kc, uint32_t* buf, int first, int stride) {
+    int c;
+    const EncStrip st = locate(kc, c);
+    const int r0 = st.r0, R = st.R, J = st.J, t_first = st.t_first;
+    const int JL = J * L;  // <= R + L - 1 <= ENC_ROWS - 1
+    const int t_lo = st.t_last - ENC_CHUNK * c - (ENC_CHUNK - 1);
     uint32_t v[ENC_PER_STAGER];
 #pragma unroll
     for (int i = 0; i < ENC_PER_STAGER; ++i) {
@@ -324,6 +356,8 @@ __device__ __forceinline__ void rans_encode_group(uint32_t (*s_cf)[ENC_SLOTS],
       if (c + 1 < n_chunks) stage(c + 1, s_cf[(c + 1) & 1], tid - 64, ENC_STAGERS);
     } else {
       const uint32_t* buf = s_cf[c & 1];
+      int cs;
+      const int J = locate(c, cs).J;
       const int n_sub = ENC_CHUNK * J;  // a multiple of ENC_BATCH
       for (int s0 = 0; s0 < n_sub; s0 += ENC_BATCH) {
         uint32_t v[ENC_BATCH];
@@ -354,11 +388,11 @@ __device__ __forceinline__ void rans_encode_group(uint32_t (*s_cf)[ENC_SLOTS],
 }
 
 __global__ __launch_bounds__(256) void rans_encode_kernel(const uint32_t* __restrict__ cf, int H,
-                                                          int W, int G, int L,
+                                                          int W, int G, int L, int S,
                                                           uint16_t* __restrict__ words,
                                                           uint32_t* __restrict__ counts) {
   __shared__ uint32_t s_cf[2][ENC_SLOTS];
-  rans_encode_group(s_cf, cf, H, W, G, L, blockIdx.x, words, counts);
+  rans_encode_group(s_cf, cf, H, W, G, L, S, blockIdx.x, words, counts);
 }
 
 // Batched form: workgroup i codes work item i (image, group).
@@ -366,7 +400,7 @@ __global__ __launch_bounds__(256) void batch_rans_encode_kernel(BatchArgs b) {
   __shared__ uint32_t s_cf[2][ENC_SLOTS];
   const BatchItem it = b.items[blockIdx.x];
   const BatchImage im = b.images[it.image];
-  rans_encode_group(s_cf, b.cf + im.px_off, im.H, im.W, im.G, im.L, it.group,
+  rans_encode_group(s_cf, b.cf + im.px_off, im.H, im.W, im.G, im.L, 1, it.group,
                     b.words + im.words_off, b.counts + im.counts_off);
 }
 
@@ -382,7 +416,7 @@ __device__ __forceinline__ void put_u32(uint8_t* p, uint32_t v) {
 // writes the header, the counts and the total length.
 __device__ __forceinline__ void pack_group_part(const uint16_t* __restrict__ words,
                                                 const uint32_t* __restrict__ counts, int H,
-                                                int W, int G, int L, const HeaderFields& hf,
+                                                int W, int G, int L, int S, const HeaderFields& hf,
                                                 uint8_t* __restrict__ out,
                                                 uint64_t* __restrict__ out_len, int g, int part,
                                                 int parts) {
@@ -420,10 +454,11 @@ __device__ __forceinline__ void pack_group_part(const uint16_t* __restrict__ wor
     }
     for (int i = threadIdx.x; i < G; i += blockDim.x) put_u32(out + HEADER_BYTES + 4 * i, counts[i]);
   }
-  const int r0 = group_row(g, H, G), r1 = group_row(g + 1, H, G);
-  const long long cap = (long long)(r1 - r0) * W + 2LL * L;
+  int before, rows;
+  group_span(g, H, G, S, before, rows);
+  const long long cap = (long long)rows * W + 2LL * L;
   const uint32_t cnt = counts[g];
-  const uint16_t* src = words + (long long)r0 * W + 2LL * L * g + (cap - cnt);
+  const uint16_t* src = words + (long long)before * W + 2LL * L * g + (cap - cnt);
   uint8_t* dst = out + hdr + 2LL * (long long)s_before;
   for (long long i = (long long)part * blockDim.x + threadIdx.x; i < cnt;
        i += (long long)parts * blockDim.x)
@@ -433,10 +468,11 @@ __device__ __forceinline__ void pack_group_part(const uint16_t* __restrict__ wor
 // grid (chunks, G): block (c, g) copies part c of group g's stream.
 __global__ __launch_bounds__(256) void pack_kernel(const uint16_t* __restrict__ words,
                                                    const uint32_t* __restrict__ counts, int H,
-                                                   int W, int G, int L, HeaderFields hf,
+                                                   int W, int G, int L, int S, HeaderFields hf,
                                                    uint8_t* __restrict__ out,
                                                    uint64_t* __restrict__ out_len) {
-  pack_group_part(words, counts, H, W, G, L, hf, out, out_len, blockIdx.y, blockIdx.x, gridDim.x);
+  pack_group_part(words, counts, H, W, G, L, S, hf, out, out_len, blockIdx.y, blockIdx.x,
+                  gridDim.x);
 }
 
 // Batched form, grid (parts, items).  The last block of an image to finish
@@ -444,7 +480,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const uint16_t* __restrict__ 
 __global__ __launch_bounds__(256) void batch_pack_kernel(BatchArgs b) {
   const BatchItem it = b.items[blockIdx.y];
   const BatchImage im = b.images[it.image];
-  pack_group_part(b.words + im.words_off, b.counts + im.counts_off, im.H, im.W, im.G, im.L, b.hf,
+  pack_group_part(b.words + im.words_off, b.counts + im.counts_off, im.H, im.W, im.G, im.L, 1, b.hf,
                   b.out + im.out_off, b.len + it.image, it.group, blockIdx.x, gridDim.x);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -533,16 +569,17 @@ void launch_batch_pack(const BatchArgs& b, int parts, hipStream_t s) {
   hipLaunchKernelGGL(batch_pack_kernel, dim3(parts, b.n_items), dim3(256), 0, s, b);
 }
 
-void launch_rans_encode(const uint32_t* cf, int H, int W, int G, int L, uint16_t* words,
+void launch_rans_encode(const uint32_t* cf, int H, int W, int G, int L, int S, uint16_t* words,
                         uint32_t* counts, hipStream_t s) {
-  hipLaunchKernelGGL(rans_encode_kernel, dim3(G), dim3(256), 0, s, cf, H, W, G, L, words, counts);
+  hipLaunchKernelGGL(rans_encode_kernel, dim3(G), dim3(256), 0, s, cf, H, W, G, L, S, words,
+                     counts);
 }
 
-void launch_pack(const uint16_t* words, const uint32_t* counts, int H, int W, int G, int L,
+void launch_pack(const uint16_t* words, const uint32_t* counts, int H, int W, int G, int L, int S,
                  const HeaderFields& hf, uint8_t* out, uint64_t* out_len, int chunks,
                  hipStream_t s) {
-  hipLaunchKernelGGL(pack_kernel, dim3(chunks, G), dim3(256), 0, s, words, counts, H, W, G, L, hf,
-                     out, out_len);
+  hipLaunchKernelGGL(pack_kernel, dim3(chunks, G), dim3(256), 0, s, words, counts, H, W, G, L, S,
+                     hf, out, out_len);
 }
 
 }  // namespace dlic

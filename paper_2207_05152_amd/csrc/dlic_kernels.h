@@ -13,7 +13,8 @@ struct HeaderFields {
   uint64_t fingerprint;
   int n_mix = N_MIX;  // 0: the six-layer softmax-256 network
   int k_in = K_IN;    // window size: 12, or 21 with the slice below (volumes)
-  int flags = 0;      // volumes: slices in bits 0..11, window shift in bits 12..15
+  int flags = 0;      // volumes: slices in bits 0..11, window shift in bits 12..15;
+                      // images: strips per group - 1 in bits 12..15
 };
 
 // Decoder limits: rows per group, and the per-group stream ring in LDS.
@@ -25,7 +26,8 @@ struct DecArgs {
   unsigned long long n_bytes;
   uint8_t* img;
   int H, W, G, L;
-  uint32_t* rec;          // [G][T] progress records, cleared before launch
+  int S;                  // row strips per group (1: one contiguous strip)
+  uint32_t* rec;          // [S*G][T] progress records (one row per strip), cleared before launch
   unsigned* ticket;       // one-image decode: next group to take, cleared before launch
   long long T;            // wavefront steps W + 3H - 3
   int* status;
@@ -90,9 +92,10 @@ bool launch_activation_range(int width, const Consts* K, const DevModel& m, cons
 // (a multiple of 16) feature rows; out16 / out4: [n][15].  False for another width.
 bool launch_net_forms(int width, const DevModel& m, const float* feats, long long n, int lanes,
                       float* out16, float* out4, hipStream_t s);
-void launch_rans_encode(const uint32_t* cf, int H, int W, int G, int L, uint16_t* words,
+// S: row strips per group (1: one contiguous strip)
+void launch_rans_encode(const uint32_t* cf, int H, int W, int G, int L, int S, uint16_t* words,
                         uint32_t* counts, hipStream_t s);
-void launch_pack(const uint16_t* words, const uint32_t* counts, int H, int W, int G, int L,
+void launch_pack(const uint16_t* words, const uint32_t* counts, int H, int W, int G, int L, int S,
                  const HeaderFields& hf, uint8_t* out, uint64_t* out_len, int chunks,
                  hipStream_t s);
 bool launch_decode(int wtype, int width, bool tables_mode, const Consts* K, const DevModel& m,

@@ -212,3 +212,25 @@ def test_w8a8_multipliers_match_oracle():
         got = dl.dlic_w8a8_multipliers(vals[i:i + 3])
         want = [lowp.w8a8_multiplier(float(v)) for v in vals[i:i + 3]]
         np.testing.assert_array_equal(got, np.array(want, np.float32))
+
+
+def test_strip_layouts_host_checks():
+    """Strips per group: limits, workspace of one record row per strip, header peek."""
+    one = dl.dlic_coder(4, 4)
+    two = dl.dlic_coder(4, 4, 2)
+    assert dl.dlic_encode_bound(64, 10, two) == dl.dlic_encode_bound(64, 10, one) > 0
+    assert dl.dlic_decode_workspace(64, 10, two) >= 2 * dl.dlic_decode_workspace(64, 10, one) - 256
+    assert dl.dlic_encode_bound(15, 10, dl.dlic_coder(4, 4, 2)) == 0     # strips of < 2 rows
+    assert dl.dlic_encode_bound(64, 10, dl.dlic_coder(1, 4, 17)) == 0    # > 16 strips
+    assert dl.dlic_encode_bound(64, 10, dl.dlic_coder(1, 4, -1)) == 0
+    assert dl.dlic_encode_bound(600, 10, dl.dlic_coder(1, 4, 2)) == 0    # 300-row strips
+    assert dl.dlic_encode_bound(600, 10, dl.dlic_coder(1, 4, 3)) > 0     # 200-row strips
+    # the deep network's codecs code one strip per group (the workspace call reads
+    # only the model's sizes and that its pointers are set)
+    class _M:
+        c = dl.dlic_deep_model(hidden=64, k_in=12, depth=8)
+    for i in range(dl.DEEP_LAYERS):
+        _M.c.d_w[i] = 256 * (i + 1)
+        _M.c.d_b[i] = 256 * (i + 9)
+    assert dl.dlic_deep_workspace(_M, 64, 10, one, 0) > 0
+    assert dl.dlic_deep_workspace(_M, 64, 10, two, 0) == 0
