@@ -6,8 +6,8 @@ fetch the stream length, decode it (wavefront kernel).  The input image is
 resident in HBM before the timed region.  Prints one JSON line.
 
 Workload (default): a 2048x1536 synthetic greyscale image (seed 1), network
-12-64-64-15 FP32 (Glorot, seed 3), 64 row groups x 4 interleaved rANS lanes
-(256 lanes).
+12-64-64-15 FP32 (Glorot, seed 3), 64 groups x 4 interleaved rANS lanes (256
+lanes), each group coding 2 row strips of 12 rows spread over the image.
 """
 from __future__ import annotations
 
@@ -56,17 +56,21 @@ def mlp_flops_per_px(h1, h2):
     return 2 * (12 * h1 + h1 * h2 + h2 * 15)
 
 
-def schedule_bound_px(h, w, G):
-    """Sum over wavefront steps of the largest per-group active pixel count."""
-    rows = [(g * h) // G for g in range(G + 1)]
+def schedule_bound_px(h, w, G, S=1):
+    """Sum over wavefront steps of the largest per-group active pixel count (a group's
+    S strips counted together)."""
+    rows = [(b * h) // (G * S) for b in range(G * S + 1)]
     T = w + 3 * h - 3
     t = np.arange(T)
     worst = np.zeros(T, dtype=np.int64)
     for g in range(G):
-        r0, r1 = rows[g], rows[g + 1]
-        ylo = np.maximum(r0, np.floor_divide(t - w, 3) + 1)
-        yhi = np.minimum(r1 - 1, np.floor_divide(t, 3))
-        worst = np.maximum(worst, np.maximum(0, yhi - ylo + 1))
+        act = np.zeros(T, dtype=np.int64)
+        for b in range(g, G * S, G):
+            r0, r1 = rows[b], rows[b + 1]
+            ylo = np.maximum(r0, np.floor_divide(t - w, 3) + 1)
+            yhi = np.minimum(r1 - 1, np.floor_divide(t, 3))
+            act += np.maximum(0, yhi - ylo + 1)
+        worst = np.maximum(worst, act)
     return int(worst.sum())
 
 
@@ -111,18 +115,18 @@ def step_chain_cycles(probe, hidden):
     return sum(parts.values()), sum(coder.values()), {**parts, **{"coder_" + k: v for k, v in coder.items()}}
 
 
-def decode_latency_bound_ms(probe, H, W, G, L, hidden):
+def decode_latency_bound_ms(probe, H, W, G, L, hidden, S=1):
     """Lower bound on the decode time from dependent latencies: every one of the
     T = W + 3H - 3 wavefront steps waits for the step before it (left and up-right
-    neighbours), a lane decodes its J = ceil(rows per group / L) rows of a step one
-    after another (its state carries from row to row), and each of the G - 1
-    group boundaries on the critical path passes a pixel between workgroups
+    neighbours), a lane decodes its J = ceil(rows per strip / L) rows of a step one
+    after another (its state carries from row to row), and each of the G*S - 1
+    strip boundaries on the critical path passes a pixel between workgroups
     through device memory instead of LDS."""
     dens, coder, parts = step_chain_cycles(probe, hidden)
     T = W + 3 * H - 3
-    J = -(-(-(-H // G)) // L)
+    J = -(-(-(-H // (G * S))) // L)
     per_step = max(J * coder, dens + coder)
-    cross = (G - 1) * max(0.0, probe["global_flag_handoff"] - probe["lds_store_load"])
+    cross = (G * S - 1) * max(0.0, probe["global_flag_handoff"] - probe["lds_store_load"])
     cycles = T * per_step + cross
     return cycles / (probe["shader_clock_mhz"] * 1e3), {
         "steps": T, "rows_per_lane_per_step": J, "density_chain_cycles": dens,
@@ -148,7 +152,7 @@ def host_info():
             "blas": blas}
 
 
-def cpu_baseline(img, weights, groups, lanes, target_s=15.0):
+def cpu_baseline(img, weights, groups, lanes, strips=1, target_s=15.0):
     """Time the oracle's encode and decode on a crop of the image: the encoder's
     network as BLAS matrix products on every core this process may use, its rANS
     walk in one Python thread, the per-pixel decoder in one thread (BLAS too)."""
@@ -170,7 +174,8 @@ def cpu_baseline(img, weights, groups, lanes, target_s=15.0):
         cw = min(img.shape[1], 512)
         ch = max(2, min(img.shape[0], n_px // cw))
         crop = np.ascontiguousarray(img[:ch, :cw])
-        coder = oracle.OracleCoder(max(1, min(groups, ch // 2)), lanes)
+        g = max(1, min(groups, ch // 2))
+        coder = oracle.OracleCoder(g, lanes, max(1, min(strips, ch // (2 * g))))
         t0 = time.perf_counter()
         bits = oracle.encode_image(crop, weights, coder)
         t1 = time.perf_counter()
@@ -185,7 +190,8 @@ def cpu_baseline(img, weights, groups, lanes, target_s=15.0):
             "kind": "oracle",
             "encode_mpix_s": crop.size / te / 1e6, "decode_mpix_s": crop.size / td / 1e6,
             "sample": f"oracle encode then decode of the top-left {ch}x{cw} crop of the same "
-                      f"image ({coder.groups}x{lanes} lanes): network products through BLAS on "
+                      f"image ({coder.groups}x{lanes} lanes, {coder.strips} strips per group): "
+                      f"network products through BLAS on "
                       f"{used} threads in encode, rANS and the per-pixel decode in one thread; encode "
                       f"{te:.1f} s, decode {td:.1f} s"}
 
@@ -271,18 +277,19 @@ def precision_sweep(dl, torch, img, H, W, coder, hidden=128, reps=3):
 
 
 def layout_sweep(dl, torch, img, H, W, model, probe, hidden,
-                 layouts=((8, 32), (16, 16), (32, 8), (128, 2), (256, 1), (128, 4), (192, 4),
-                          (384, 4), (48, 32)), reps=3):
+                 layouts=((64, 4, 1), (64, 4, 3), (64, 4, 4), (128, 2, 1), (128, 2, 2),
+                          (8, 32, 1), (16, 16, 1), (32, 8, 1), (256, 1, 1), (128, 4, 1),
+                          (128, 4, 2), (192, 4, 1), (384, 4, 1), (48, 32, 1)), reps=3):
     """The headline image and net coded with other coder layouts (G groups x L
-    lanes).  The first five have the headline's 256 lanes; the decoder gives a
-    pixel 16 coder lanes when L <= 4.  More lanes cut the sequential sub-rounds
-    per wavefront step, ceil(rows per group / L), at the price of 4 flushed
-    bytes per lane; 384 x 4 and 48 x 32 give every row its own lane (one
-    sub-round per step)."""
+    lanes x S row strips per group).  Those up to 256 x 1 have the headline's 256
+    lanes; the decoder gives a pixel 16 coder lanes when L <= 4.  Strips spread
+    over the image, and more lanes, cut the sequential sub-rounds per wavefront
+    step, ceil(rows per strip / L); more lanes cost 4 flushed bytes per lane;
+    384 x 4 and 48 x 32 give every row its own lane (one sub-round per step)."""
     out = []
     dl.dlic_set_timing(True)
-    for G, L in layouts:
-        coder = dl.dlic_coder(G, L)
+    for G, L, S in layouts:
+        coder = dl.dlic_coder(G, L, S)
         bits = dl.encode(img, model, coder)
         dec = torch.empty((H, W), dtype=torch.uint8, device="cuda")
         st = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -293,10 +300,10 @@ def layout_sweep(dl, torch, img, H, W, model, probe, hidden,
             if r:
                 ms.append(dict(dl.dlic_kernel_times())["wavefront_decode_kernel"])
         torch.cuda.synchronize()
-        assert int(st.item()) == 0 and torch.equal(dec, img), f"layout {G}x{L} round trip"
-        rows = -(-H // G)
-        bound_ms, _ = decode_latency_bound_ms(probe, H, W, G, L, hidden)
-        out.append({"groups": G, "lanes": L, "sub_rounds_per_step": -(-rows // L),
+        assert int(st.item()) == 0 and torch.equal(dec, img), f"layout {G}x{L}x{S} round trip"
+        rows = -(-H // (G * S))
+        bound_ms, _ = decode_latency_bound_ms(probe, H, W, G, L, hidden, S)
+        out.append({"groups": G, "lanes": L, "strips": S, "sub_rounds_per_step": -(-rows // L),
                     "decode_ms": float(np.mean(ms)), "decode_mpix_s": H * W / np.mean(ms) / 1e3,
                     "latency_bound_ms": bound_ms, "frac_latency": bound_ms / float(np.mean(ms)),
                     "bpp_total": 8.0 * bits.numel() / (H * W)})
@@ -549,6 +556,7 @@ def main():
     ap.add_argument("--hidden", type=int, default=64)
     ap.add_argument("--groups", type=int, default=64)
     ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--strips", type=int, default=2, help="row strips per group")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed steps, run one plain elementwise copy of MIB MiB "
@@ -575,7 +583,7 @@ def main():
     img_np = synth.synth_image(H, W, 1)
     weights = synth.xavier_mlp((12, Hd, Hd, 15), 3)
     model = dl.Model(weights, "cuda:0")
-    coder = dl.dlic_coder(args.groups, args.lanes)
+    coder = dl.dlic_coder(args.groups, args.lanes, args.strips)
     img = torch.from_numpy(img_np).cuda()
     n_px = H * W
 
@@ -657,14 +665,15 @@ def main():
     dom = max(avg, key=avg.get)
     dom_flops = flops if dom in ("wavefront_decode_kernel", "density_kernel") else 0
     achieved = dom_flops / (avg[dom] * 1e-3) if dom_flops else 0.0
-    crit_px = schedule_bound_px(H, W, args.groups)
+    crit_px = schedule_bound_px(H, W, args.groups, args.strips)
     sched_ms = crit_px * mlp_flops_per_px(Hd, Hd) / (MI355X_FP32_MFMA / MI355X_CUS) * 1e3
     steps_T = W + 3 * (H - 1)
-    J = -(-(-(-H // args.groups)) // args.lanes)
+    J = -(-(-(-H // (args.groups * args.strips))) // args.lanes)
     crit_sub = steps_T * J
 
     probe = dl.dlic_latency_probe()
-    lat_ms, lat_detail = decode_latency_bound_ms(probe, H, W, args.groups, args.lanes, Hd)
+    lat_ms, lat_detail = decode_latency_bound_ms(probe, H, W, args.groups, args.lanes, Hd,
+                                                 args.strips)
     dec_kernel_ms = avg.get("wavefront_decode_kernel")
 
     res = {
@@ -682,9 +691,10 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{W}x{H} synthetic greyscale image (seed 1), MLP 12-{Hd}-{Hd}-15 FP32 "
-                        f"(Glorot seed 3), {args.groups} row groups x {args.lanes} rANS lanes; "
-                        f"one step = encode + decode",
+                        f"(Glorot seed 3), {args.groups} groups x {args.lanes} rANS lanes, "
+                        f"{args.strips} row strips per group; one step = encode + decode",
             "image": [H, W], "hidden": Hd, "groups": args.groups, "lanes_per_group": args.lanes,
+            "strips_per_group": args.strips,
         },
         "encode_mpix_s": n_px / (enc_ms * 1e-3) / 1e6 if enc_ms else None,
         "decode_mpix_s": n_px / (dec_ms * 1e-3) / 1e6 if dec_ms else None,
@@ -732,7 +742,7 @@ def main():
         res["softmax_net"] = deep_sweep(dl, torch, img, H, W)
         res["volume"] = volume_sweep(dl, torch)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(img_np, weights, args.groups, args.lanes)
+        res["cpu_baseline"] = cpu_baseline(img_np, weights, args.groups, args.lanes, args.strips)
     print(json.dumps(res))
 
 

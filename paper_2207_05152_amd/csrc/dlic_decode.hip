@@ -208,7 +208,9 @@ __device__ __forceinline__ void coder_strip_end(const DecArgs& a, int g, bool la
   }
 }
 
-template <class Net, bool TABLES, int LPP, bool DELAY = false>
+// STRIPS: the group may code several row strips (a.S); without it the strip
+// loop runs once and compiles away.
+template <class Net, bool TABLES, int LPP, bool DELAY = false, bool STRIPS = false>
 __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const DevModel& m,
                                              const DecArgs& a, const int g) {
   __shared__ float2 s_sd[LUT_N];
@@ -280,10 +282,11 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
   // previous strip); the coder's lane states, its word position and the word
   // ring carry over.  Every wave passes the barriers at the strip's start and
   // end, whatever its role.
-  const int GS = G * a.S;
-  for (int sp = 0; sp < a.S; ++sp) {
+  const int n_strips = STRIPS ? a.S : 1;
+  const int GS = G * n_strips;
+  for (int sp = 0; sp < n_strips; ++sp) {
   const int b = sp * G + g;
-  const bool first_strip = sp == 0, last_strip = sp == a.S - 1;
+  const bool first_strip = sp == 0, last_strip = sp == n_strips - 1;
   const int r0 = group_row(b, H, GS), r1 = group_row(b + 1, H, GS);
   const int R = r1 - r0;
   const int J = (R + L - 1) / L;
@@ -1119,7 +1122,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
 // One image: each workgroup takes its group by ticket, so group g - 1 was
 // taken by a workgroup that is running or done before group g waits on it,
 // whatever order the dispatcher starts workgroups in.
-template <class Net, bool TABLES, int LPP, bool DELAY = false>
+template <class Net, bool TABLES, int LPP, bool DELAY = false, bool STRIPS = false>
 __global__ __launch_bounds__(dec_waves<Net>() * 64) void wavefront_decode_kernel(
     const Consts* __restrict__ K, DevModel m, DecArgs a) {
   __shared__ int s_group;
@@ -1127,7 +1130,7 @@ __global__ __launch_bounds__(dec_waves<Net>() * 64) void wavefront_decode_kernel
   __syncthreads();
   const int g = __builtin_amdgcn_readfirstlane(s_group);
   if (g >= a.G) return;
-  decode_group<Net, TABLES, LPP, DELAY>(K, m, a, g);
+  decode_group<Net, TABLES, LPP, DELAY, STRIPS>(K, m, a, g);
 }
 
 // Batched decode, persistent: a grid of resident workgroups, each taking the
@@ -1293,11 +1296,20 @@ bool launch_batch_decode(int wtype, int width, const Consts* K, const DevModel& 
 template <class Net, bool TABLES, int LPP>
 static bool launch_wavefront(const Consts* K, const DevModel& m, const DecArgs& a, hipStream_t s) {
   const dim3 grid(a.G), block(dec_waves<Net>() * 64);
-  // With several strips per group, group 0's second strip waits for the last
-  // group's first: every group's workgroup must be resident at once.
-  if (a.S > 1 && persistent_grid(wavefront_decode_kernel<Net, TABLES, LPP, false>,
-                                 (int)block.x, a.G) < a.G)
-    return false;
+  if (a.S > 1) {
+    // With several strips per group, group 0's second strip waits for the last
+    // group's first: every group's workgroup must be resident at once.
+    if (persistent_grid(wavefront_decode_kernel<Net, TABLES, LPP, false, true>, (int)block.x,
+                        a.G) < a.G)
+      return false;
+    if (a.delay_max > 0)
+      hipLaunchKernelGGL((wavefront_decode_kernel<Net, TABLES, LPP, true, true>), grid, block, 0,
+                         s, K, m, a);
+    else
+      hipLaunchKernelGGL((wavefront_decode_kernel<Net, TABLES, LPP, false, true>), grid, block, 0,
+                         s, K, m, a);
+    return true;
+  }
   // the delay-injecting form (a test hook) is a separate kernel, so that the
   // production kernel carries no trace of it
   if (a.delay_max > 0)

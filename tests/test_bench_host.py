@@ -69,3 +69,30 @@ def test_latency_bound_takes_the_longer_chain():
     ms1, d1 = bench.decode_latency_bound_ms(PROBE, 1536, 2048, 384, 4, 64)
     assert d1["rows_per_lane_per_step"] == 1
     assert d1["per_step_cycles"] == pytest.approx(dens + coder)
+
+
+def test_latency_bound_with_strips():
+    dens, coder, _ = bench.step_chain_cycles(PROBE, 64)
+    T = 2048 + 3 * 1536 - 3
+    # 64 groups of 4 lanes, 2 strips each: 12 rows per strip, 3 rows per lane and step,
+    # and 127 strip boundaries between workgroups
+    ms, d = bench.decode_latency_bound_ms(PROBE, 1536, 2048, 64, 4, 64, 2)
+    assert d["rows_per_lane_per_step"] == 3
+    assert d["per_step_cycles"] == pytest.approx(max(3 * coder, dens + coder))
+    assert ms == pytest.approx((T * d["per_step_cycles"] + 127 * (1760 - 118)) / 2.4e6)
+
+
+def test_schedule_bound_with_strips_by_brute_force():
+    h, w, G, S = 24, 10, 2, 2
+    rows = [(b * h) // (G * S) for b in range(G * S + 1)]
+    T = w + 3 * h - 3
+    want = 0
+    for t in range(T):
+        worst = 0
+        for g in range(G):
+            n = sum(1 for b in range(g, G * S, G) for y in range(rows[b], rows[b + 1])
+                    if 0 <= t - 3 * y < w)
+            worst = max(worst, n)
+        want += worst
+    assert bench.schedule_bound_px(h, w, G, S) == want
+    assert bench.schedule_bound_px(h, w, G, 1) >= want
