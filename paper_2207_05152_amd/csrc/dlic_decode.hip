@@ -284,7 +284,8 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
   // end, whatever its role.
   const int n_strips = STRIPS ? a.S : 1;
   const int GS = G * n_strips;
-  for (int sp = 0; sp < n_strips; ++sp) {
+  // one strip: a barrier, then every wave in its role; a wave may leave early
+  auto strip = [&](const int sp) {
   const int b = sp * G + g;
   const bool first_strip = sp == 0, last_strip = sp == n_strips - 1;
   const int r0 = group_row(b, H, GS), r1 = group_row(b + 1, H, GS);
@@ -887,8 +888,8 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
   } else if (!TABLES) {
     // -------------------------------------------------------- density waves
     // waves 4, 8, ... share the coder's SIMD and compute no densities
-    do {
-    if ((wave & 3) == 0) break;
+    {
+    if ((wave & 3) == 0) return;
     constexpr int nwork = dec_workers<Net>();
     const int w = wave - 1 - (wave >> 2);
     Net net;
@@ -1111,12 +1112,19 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
         atomicAdd(&a.prof[g * PROF_SLOTS + 7], n_tiles);
       }
     }
-    } while (false);
+    }
   }
-  // the strip is done on every wave; a failed strip ends the group
-  __syncthreads();
-  if (__builtin_amdgcn_readfirstlane(s_stop) != 0) break;
-  }  // strips
+  };
+  if constexpr (STRIPS) {
+    for (int sp = 0; sp < n_strips; ++sp) {
+      strip(sp);
+      // the strip is done on every wave; a failed strip ends the group
+      __syncthreads();
+      if (__builtin_amdgcn_readfirstlane(s_stop) != 0) break;
+    }
+  } else {
+    strip(0);
+  }
 }
 
 // One image: each workgroup takes its group by ticket, so group g - 1 was
