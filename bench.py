@@ -272,7 +272,8 @@ def precision_sweep(dl, torch, img, H, W, coder, hidden=128, reps=3):
                        f"stored as FP32 / BF16 / FP8 e4m3 weights with per-layer scales (BF16 "
                        f"activations) / FP8 weights and activations (activation multipliers "
                        f"calibrated on 8 images, seeds 1000-1007), "
-                       f"{coder.groups}x{coder.lanes_per_group} lanes")
+                       f"{coder.groups}x{coder.lanes_per_group} lanes, "
+                       f"{max(1, coder.strips)} row strips per group")
     return res
 
 
