@@ -268,6 +268,9 @@ def precision_sweep(dl, torch, img, H, W, coder, hidden=128, reps=3):
     for dtype in ("bf16", "fp8", "fp8a8"):
         res[dtype]["bpp_delta_vs_fp32"] = res[dtype]["bpp_total"] - res["fp32"]["bpp_total"]
     res["bf16_gate_0.01bpp"] = abs(res["bf16"]["bpp_delta_vs_fp32"]) <= 0.01
+    # BF16 over FP32 on the same GPU, image and layout (kernel times)
+    res["bf16_speedup_vs_fp32"] = {
+        d: res["bf16"][f"{d}_mpix_s"] / res["fp32"][f"{d}_mpix_s"] for d in ("encode", "decode")}
     res["workload"] = (f"{W}x{H} image (seed 1), MLP 12-{hidden}-{hidden}-15 (Glorot seed 3) "
                        f"stored as FP32 / BF16 / FP8 e4m3 weights with per-layer scales (BF16 "
                        f"activations) / FP8 weights and activations (activation multipliers "

@@ -1,6 +1,7 @@
 """The decode entry point that allocates nothing (a fixed workspace array in the library)
 against dlic_decode on the same streams: same pixels and status, on two calls in a row, the
-second with a smaller image, and a layout beyond the array's limit refused."""
+second with a smaller image (and the first with two row strips per group), and a layout
+beyond the array's limit refused."""
 import numpy as np
 import pytest
 import torch
@@ -28,12 +29,13 @@ def _decode_both(dev, bits, model, h, w, coder):
 @pytest.mark.parametrize("dtype,width", [("fp32", 64), ("bf16", 128)])
 def test_noalloc_decode_matches_decode_twice(dev, dtype, width):
     model = dl.Model(synth.xavier_mlp((12, width, width, 15), 3), dev, dtype=dtype)
-    # first a large image, then a smaller one: the second call must not see the first's
-    # records (the array keeps the last call's contents)
-    for h, w, G, L, seed in ((1536, 2048, 64, 4, 1), (300, 257, 6, 32, 2)):
+    # first a large image (the headline layout, two row strips per group: one record row
+    # per strip), then a smaller one with one strip: the second call must not see the
+    # first's records (the array keeps the last call's contents)
+    for h, w, G, L, S, seed in ((1536, 2048, 64, 4, 2, 1), (300, 257, 6, 32, 1, 2)):
         img = synth.synth_image(h, w, seed)
-        coder = dl.dlic_coder(G, L)
-        say("noalloc decode", dtype, width, h, w, G, L)
+        coder = dl.dlic_coder(G, L, S)
+        say("noalloc decode", dtype, width, h, w, G, L, S)
         bits = dl.encode(to_dev(img, dev), model, coder)
         ref, st_ref, got, st = _decode_both(dev, bits, model, h, w, coder)
         assert st_ref == 0 and st == 0, (st_ref, st)
