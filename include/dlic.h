@@ -259,7 +259,9 @@ dlic_status dlic_density(const dlic_model *model, const uint8_t *d_img, int32_t 
  * feature rows (d_feats: [n][12] FP32, n a multiple of 16) and writes their
  * outputs to d_out16 and d_out4 ([n][15] FP32).  In the 4-pixel form, rows
  * 4s + j with j >= lanes (1..4) are replaced by zero features, as the
- * decoder's unused tile rows; their d_out4 entries are unspecified.
+ * decoder's unused tile rows; their d_out4 entries are unspecified.  At H = 64
+ * the 4-pixel form runs twice, with its layer-2 weights in LDS and in
+ * registers (the decoder uses both); an output where the two differ is NaN.
  * model: FP32, h1 = h2 = 64 or 128 (DLIC_ERR_UNSUPPORTED otherwise). */
 dlic_status dlic_net_forms(const dlic_model *model, const float *d_feats, int64_t n,
                            int32_t lanes, float *d_out16, float *d_out4, hipStream_t stream);

@@ -1273,7 +1273,7 @@ static bool launch_batch_decode_h(int wtype, const Consts* K, const DevModel& m,
     case WT_F32:
       // as for one image: nets of 64 or 128 neurons on tiles of at most 4 pixels
       if (H >= 64 && lpp == 16) {
-        launch_batch_decode_k<NetF32x4<(H >= 64 ? H : 64)>, 16>(K, m, b, cap, s);
+        launch_batch_decode_k<NetF32x4<(H >= 64 ? H : 64), (H == 64)>, 16>(K, m, b, cap, s);
       } else {
         launch_batch_decode_t<NetF32<H, (H >= 64)>>(K, m, b, lpp, cap, s);
       }
@@ -1360,6 +1360,9 @@ static bool launch_decode_h(int wtype, const Consts* K, const DevModel& m, const
       // sub-round, latency-bound): the 4-pixel 4x4 MFMA form at H = 64 and
       // 128; wider layouts need the 9 density waves of the 12-wave form at
       // H = 64
+      // at 64 neurons the layer-2 weights sit in registers for one strip per
+      // group; the strip-looping kernels keep them in LDS, which measured faster
+      if (H == 64 && a.L <= 4 && a.S == 1) return launch_decode_lpp16<NetF32x4<64, true>>(K, m, a, s);
       if (H >= 64 && a.L <= 4) return launch_decode_lpp16<NetF32x4<(H >= 64 ? H : 64)>>(K, m, a, s);
       return launch_decode_t<NetF32<H, (H >= 64)>, false>(K, m, a, s);
     case WT_BF16: return launch_decode_t<NetBF16<H, WT_BF16, (H > 64)>, false>(K, m, a, s);

@@ -320,17 +320,22 @@ __device__ __forceinline__ f4 mfma_f32_4x4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
 }
 
-template <int H_>
+template <int H_, bool W2R = false>
 struct NetF32x4 {
   static_assert(H_ == 64 || H_ == 128, "4-pixel form for 64 or 128 neurons");
+  static_assert(!W2R || H_ == 64, "layer-2 weights in registers at 64 neurons only");
   static constexpr int H = H_, NT = H / 16;
   static constexpr int HALVES = H / 64;               // accumulators of 64 neurons
   static constexpr int QS = H / 4;                    // chain steps of a layer-3 quarter
   static constexpr bool DEC_WIDE = false;             // 8 waves per decoder workgroup
-  static constexpr int LDS_BYTES = H * H * 4;         // W2 in chain order
+  // W2 in chain order: in registers with W2R (64 per lane at H = 64; two waves
+  // per SIMD leave room), else in LDS
+  static constexpr bool W2_REG = W2R;
+  static constexpr int LDS_BYTES = W2_REG ? 0 : H * H * 4;
   static constexpr int ROW = H + 4;                   // scratch floats per pixel row
   static constexpr int SCRATCH_FLOATS = 2 * 4 * ROW;  // layer-1 rows, then layer-2 rows
   float a1[HALVES][K_IN];  // W1[64 h + lane][k]
+  float a2[W2_REG ? H : 1];  // W2[lane][kc(c)] along layer 2's chain (H = 64)
   float a3[QS];            // W3[lane % 16][k] along quarter lane / 16 of layer 3's chain
   float c1[HALVES][4], c2[HALVES][4], c3[4];
   float* xs = nullptr;
@@ -343,6 +348,7 @@ struct NetF32x4 {
   // in turn, W2[lane][kc(c)] and W2[64 + lane][kc(c)].  H = 64: f4 index
   // cq * 64 + lane holds W2[lane][kc(c)] for steps c = 4 cq .. 4 cq + 3.
   __device__ __forceinline__ static void stage(const DevModel& m, void* lds, int t, int n) {
+    if constexpr (W2_REG) return;
     const float* w2 = (const float*)m.w2;
     float* d = (float*)lds;
     for (int idx = t; idx < H * H; idx += n) {
@@ -364,6 +370,11 @@ struct NetF32x4 {
     for (int h = 0; h < HALVES; ++h)
 #pragma unroll
       for (int k = 0; k < K_IN; ++k) a1[h][k] = w1[(64 * h + lane) * K_IN + k];
+    if constexpr (W2_REG) {
+      const float* w2 = (const float*)m.w2;
+#pragma unroll
+      for (int c = 0; c < H; ++c) a2[c] = w2[lane * H + kc(c)];
+    }
 #pragma unroll
     for (int st = 0; st < QS; ++st)
       a3[st] = (i < N_OUT) ? w3[i * H + k3(q, st)] : 0.0f;
@@ -448,7 +459,8 @@ struct NetF32x4 {
         lo = mfma_f32_4x4(wb[2], hv[3], lo);
         hi = mfma_f32_4x4(wb[3], hv[3], hi);
       } else {
-        const f4 wa = w[c4 * 64 + lane];
+        const f4 wa = W2_REG ? f4{a2[4 * c4], a2[4 * c4 + 1], a2[4 * c4 + 2], a2[4 * c4 + 3]}
+                             : w[c4 * 64 + lane];
         lo = mfma_f32_4x4(wa[0], hv[0], lo);
         lo = mfma_f32_4x4(wa[1], hv[1], lo);
         lo = mfma_f32_4x4(wa[2], hv[2], lo);

@@ -204,9 +204,12 @@ __global__ __launch_bounds__(64) void net_forms_kernel(DevModel m, const float* 
                                                       float* __restrict__ out16,
                                                       float* __restrict__ out4) {
   using Net16 = NetF32<H>;
+  // the 4-pixel form with layer-2 weights in LDS, and at H = 64 also with them
+  // in registers: out4 holds the LDS form's outputs, NaN where the two differ
   using Net4 = NetF32x4<H>;
+  using Net4R = NetF32x4<H, (H == 64)>;
   __shared__ __attribute__((aligned(16))) char w16[Net16::LDS_BYTES > 0 ? Net16::LDS_BYTES : 16];
-  __shared__ __attribute__((aligned(16))) char w4[Net4::LDS_BYTES];
+  __shared__ __attribute__((aligned(16))) char w4[Net4::LDS_BYTES > 0 ? Net4::LDS_BYTES : 16];
   __shared__ __attribute__((aligned(16))) float xs[Net4::SCRATCH_FLOATS];
   const int lane = threadIdx.x, q = lane >> 4, p = lane & 15;
   Net16::stage(m, w16, lane, 64);
@@ -217,6 +220,9 @@ __global__ __launch_bounds__(64) void net_forms_kernel(DevModel m, const float* 
   Net4 b;
   b.load(m, lane);
   b.xs = xs;
+  Net4R br;
+  br.load(m, lane);
+  br.xs = xs;
   for (long long tile = blockIdx.x; tile * 16 < n; tile += gridDim.x) {
     const long long r16 = tile * 16 + p;
     float f[3];
@@ -233,7 +239,13 @@ __global__ __launch_bounds__(64) void net_forms_kernel(DevModel m, const float* 
       float g[3];
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) g[kk] = live ? feats[r4 * K_IN + 4 * kk + q] : 0.0f;
-      const f4 o4 = b.run(g[0], g[1], g[2], w4);
+      f4 o4 = b.run(g[0], g[1], g[2], w4);
+      if constexpr (H == 64) {
+        const f4 o4r = br.run(g[0], g[1], g[2], w4);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (__float_as_uint(o4r[r]) != __float_as_uint(o4[r])) o4[r] = __builtin_nanf("");
+      }
       if (p < 4) {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
