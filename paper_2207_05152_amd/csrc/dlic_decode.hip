@@ -208,9 +208,10 @@ __device__ __forceinline__ void coder_strip_end(const DecArgs& a, int g, bool la
   }
 }
 
-// STRIPS: the group may code several row strips (a.S); without it the strip
-// loop runs once and compiles away.
-template <class Net, bool TABLES, int LPP, bool DELAY = false, bool STRIPS = false>
+// STRIPS: the row strips per group this kernel form serves: 1 (one strip,
+// no loop), 2 (two strips in straight-line code, the lightest on registers), or
+// 0 (any number, a loop over them).
+template <class Net, bool TABLES, int LPP, bool DELAY = false, int STRIPS = 1>
 __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const DevModel& m,
                                              const DecArgs& a, const int g) {
   __shared__ float2 s_sd[LUT_N];
@@ -282,7 +283,7 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
   // previous strip); the coder's lane states, its word position and the word
   // ring carry over.  Every wave passes the barriers at the strip's start and
   // end, whatever its role.
-  const int n_strips = STRIPS ? a.S : 1;
+  const int n_strips = STRIPS == 0 ? a.S : STRIPS;
   const int GS = G * n_strips;
   // one strip: a barrier, then every wave in its role; a wave may leave early
   auto strip = [&](const int sp) {
@@ -1115,22 +1116,26 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
     }
   }
   };
-  if constexpr (STRIPS) {
+  if constexpr (STRIPS == 1) {
+    strip(0);
+  } else if constexpr (STRIPS == 2) {
+    strip(0);
+    // the strip is done on every wave; a failed strip ends the group
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_stop) == 0) strip(1);
+  } else {
     for (int sp = 0; sp < n_strips; ++sp) {
       strip(sp);
-      // the strip is done on every wave; a failed strip ends the group
       __syncthreads();
       if (__builtin_amdgcn_readfirstlane(s_stop) != 0) break;
     }
-  } else {
-    strip(0);
   }
 }
 
 // One image: each workgroup takes its group by ticket, so group g - 1 was
 // taken by a workgroup that is running or done before group g waits on it,
 // whatever order the dispatcher starts workgroups in.
-template <class Net, bool TABLES, int LPP, bool DELAY = false, bool STRIPS = false>
+template <class Net, bool TABLES, int LPP, bool DELAY = false, int STRIPS = 1>
 __global__ __launch_bounds__(dec_waves<Net>() * 64) void wavefront_decode_kernel(
     const Consts* __restrict__ K, DevModel m, DecArgs a) {
   __shared__ int s_group;
@@ -1304,29 +1309,24 @@ bool launch_batch_decode(int wtype, int width, const Consts* K, const DevModel& 
 template <class Net, bool TABLES, int LPP>
 static bool launch_wavefront(const Consts* K, const DevModel& m, const DecArgs& a, hipStream_t s) {
   const dim3 grid(a.G), block(dec_waves<Net>() * 64);
-  if (a.S > 1) {
+  // the delay-injecting forms (a test hook) are separate kernels, so that the
+  // production kernels carry no trace of it
+  auto go = [&](auto kern, auto kern_delay) {
     // With several strips per group, group 0's second strip waits for the last
     // group's first: every group's workgroup must be resident at once.
-    if (persistent_grid(wavefront_decode_kernel<Net, TABLES, LPP, false, true>, (int)block.x,
-                        a.G) < a.G)
-      return false;
-    if (a.delay_max > 0)
-      hipLaunchKernelGGL((wavefront_decode_kernel<Net, TABLES, LPP, true, true>), grid, block, 0,
-                         s, K, m, a);
-    else
-      hipLaunchKernelGGL((wavefront_decode_kernel<Net, TABLES, LPP, false, true>), grid, block, 0,
-                         s, K, m, a);
+    if (a.S > 1 && persistent_grid(kern, (int)block.x, a.G) < a.G) return false;
+    const auto k = a.delay_max > 0 ? kern_delay : kern;
+    hipLaunchKernelGGL(k, grid, block, 0, s, K, m, a);
     return true;
-  }
-  // the delay-injecting form (a test hook) is a separate kernel, so that the
-  // production kernel carries no trace of it
-  if (a.delay_max > 0)
-    hipLaunchKernelGGL((wavefront_decode_kernel<Net, TABLES, LPP, true>), grid, block, 0, s, K, m,
-                       a);
-  else
-    hipLaunchKernelGGL((wavefront_decode_kernel<Net, TABLES, LPP, false>), grid, block, 0, s, K,
-                       m, a);
-  return true;
+  };
+  if (a.S == 1)
+    return go(wavefront_decode_kernel<Net, TABLES, LPP, false, 1>,
+              wavefront_decode_kernel<Net, TABLES, LPP, true, 1>);
+  if (a.S == 2)
+    return go(wavefront_decode_kernel<Net, TABLES, LPP, false, 2>,
+              wavefront_decode_kernel<Net, TABLES, LPP, true, 2>);
+  return go(wavefront_decode_kernel<Net, TABLES, LPP, false, 0>,
+            wavefront_decode_kernel<Net, TABLES, LPP, true, 0>);
 }
 
 // The table-driven coder (no density waves) runs one lane per pixel.
