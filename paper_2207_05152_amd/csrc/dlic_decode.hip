@@ -29,6 +29,8 @@
 // group only waits for the one before it, whose workgroup took its ticket
 // earlier and is running or done, and every wait is bounded, so the grid
 // always drains.
+#include <type_traits>
+
 #include "dlic_device.hpp"
 #include "dlic_kernels.h"
 
@@ -187,6 +189,17 @@ __device__ __forceinline__ float bin_edge(int v) { return div255(2 * v - 256); }
 
 // Decode of group g of one stream by the whole workgroup.  LPP is
 // coder_lpp(L): how many coder lanes share each pixel's symbol search.
+// Layer 1's partial state of a net that splits layer 1 around the last
+// step's pixels (the 4-pixel net), else an empty stand-in.
+template <class Net, class = void>
+struct NetL1 {
+  struct type {};
+};
+template <class Net>
+struct NetL1<Net, std::void_t<typename Net::L1>> {
+  using type = typename Net::L1;
+};
+
 // The coder wave's end of a strip.  After the group's last strip every lane
 // must be back at its initial state and every word consumed; after an earlier
 // one the states and the word position go to LDS for the next strip, and a
@@ -912,19 +925,28 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       if (q >= P) break;
       const int slot_i = q & (NSLOT - 1);
       const int need = max(q - J + 1, q - NSLOT + 1);
+      // With the 4-pixel net a tile starts once the step before last is
+      // decoded (every window pixel but the up-right and the left one, which
+      // come with the last step, J sub-rounds before this one) and runs layer
+      // 1 that far; it then waits for the last step.
+      constexpr bool SPLIT = Net::SCRATCH_FLOATS > 0;
+      const int need_pre = SPLIT ? max(q - 2 * J + 1, q - NSLOT + 1) : need;
       if constexpr (DELAY) inject_delay(a, 8u + (uint32_t)wave, (uint32_t)g, (uint32_t)q);
       const unsigned long long c0 = a.prof ? clk_now() : 0ull;
-      if (!stuck) {
+      auto wait_decoded = [&](int n) {
+        if (stuck) return;
         uint32_t spins = 0;
-        while (lds_acquire(&s_decoded) < need) {
+        while (lds_acquire(&s_decoded) < n) {
           if (++spins > LDS_SPIN_LIMIT) {
             stuck = true;
             break;
           }
           __builtin_amdgcn_s_sleep(1);
         }
-      }
+      };
+      wait_decoded(need_pre);
       const unsigned long long c1 = a.prof ? clk_now() : 0ull;
+      unsigned long long c_late = 0;  // cycles of the second wait
       // density wave 0 keeps the stream ring ahead of the coder
       if (w == 0 && !bad) {
         const uint32_t end = s_end;
@@ -949,12 +971,13 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       const int y = r0 + rr;
       const int xc = t - SKEW * y;
       const bool valid = ln < L && rr < R && xc >= 0 && xc < W;
-      if (__ballot(valid) != 0ull) {
-        // the tile holding row r0 needs the group above's step t-1 in the
-        // ring; the courier has usually put it there already
-        if (rr == 0 && valid && lane == 0 && b > 0 && t - 1 <= up_last && !stuck) {
+      const bool any_valid = __ballot(valid) != 0ull;
+      // the tile holding row r0 needs the group above's step s in the ring;
+      // the courier has usually put it there already
+      auto wait_record = [&](int s) {
+        if (rr == 0 && valid && lane == 0 && b > 0 && s <= up_last && !stuck) {
           uint32_t spins = 0;
-          while (lds_acquire(&s_rcv) < t - 1) {
+          while (lds_acquire(&s_rcv) < s) {
             if (++spins > LDS_SPIN_LIMIT) {
               stuck = true;
               break;
@@ -962,28 +985,49 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
             __builtin_amdgcn_s_sleep(1);
           }
         }
-        // the three window pixels of this lane, read together (a neighbour
-        // outside the image reads ring slot 0 and is replaced by 0), scaled
-        // arithmetically to the table's value
-        float fk[3];
-        bool inside[3];
-        uint32_t pv[3];
-#pragma unroll
-        for (int kk = 0; kk < 3; ++kk) {
-          const int k = 4 * kk + q4;
-          const int yy = y + nb_dy(k), xx = xc + nb_dx(k);
-          inside[kk] = valid && yy >= 0 && xx >= 0 && xx < W;
-          pv[kk] = s_ring[inside[kk] ? (yy - r0 + 2) * 16 + (xx & 15) : 0];
+      };
+      // window pixel kk of this lane (feature 4 kk + q4; a neighbour outside
+      // the image reads ring slot 0 and is replaced by 0), scaled
+      // arithmetically to the table's value
+      auto feature = [&](int kk) {
+        const int k = 4 * kk + q4;
+        const int yy = y + nb_dy(k), xx = xc + nb_dx(k);
+        const bool inside = valid && yy >= 0 && xx >= 0 && xx < W;
+        const uint32_t pv = s_ring[inside ? (yy - r0 + 2) * 16 + (xx & 15) : 0];
+        const float sv = div255((int)(2 * pv) - 255);
+        return inside ? sv : 0.0f;
+      };
+      float fk[3] = {0.0f, 0.0f, 0.0f};
+      [[maybe_unused]] typename NetL1<Net>::type l1{};
+      if constexpr (SPLIT) {
+        if (any_valid) {
+          wait_record(t - 2);
+          // lane groups 1 and 3 hold features 9 and 11 in slot 2: read later
+          fk[0] = feature(0);
+          fk[1] = feature(1);
+          if ((q4 & 1) == 0) fk[2] = feature(2);
+          l1 = net.l1_pre(fk[0], fk[1], fk[2]);
         }
+        const unsigned long long cl0 = a.prof ? clk_now() : 0ull;
+        wait_decoded(need);
+        if (a.prof) c_late = clk_now() - cl0;
+      }
+      if (any_valid) {
+        wait_record(t - 1);
+        if constexpr (SPLIT) {
+          if ((q4 & 1) != 0) fk[2] = feature(2);
+        } else {
 #pragma unroll
-        for (int kk = 0; kk < 3; ++kk) {
-          const float sv = div255((int)(2 * pv[kk]) - 255);
-          fk[kk] = inside[kk] ? sv : 0.0f;
+          for (int kk = 0; kk < 3; ++kk) fk[kk] = feature(kk);
         }
         // the left neighbour (decoded last step) goes to the image
         if (valid && q4 == 0 && xc >= 1)
           a.img[(long long)y * W + xc - 1] = s_ring[(rr + 2) * 16 + ((xc - 1) & 15)];
-        const f4 o = net.run(fk[0], fk[1], fk[2], s_w2);
+        f4 o;
+        if constexpr (SPLIT)
+          o = net.finish(l1, fk[2], s_w2);
+        else
+          o = net.run(fk[0], fk[1], fk[2], s_w2);
         float* par = &s_par[slot_i][0];
         if (a.prof) {
           c_net = clk_now();
@@ -1080,10 +1124,10 @@ __device__ __forceinline__ void decode_group(const Consts* __restrict__ K, const
       if (lane == 0) lds_release(&s_done[slot_i][ti], q);
       if (a.prof) {
         const unsigned long long c2 = clk_now();
-        t_wait += c1 - c0;
-        t_busy += c2 - c1;
+        t_wait += c1 - c0 + c_late;
+        t_busy += c2 - c1 - c_late;
         if (c_net) {
-          t_net += c_net - c1;
+          t_net += c_net - c1 - c_late;
           t_head += c_head - c_net;
           t_tab += c2 - c_head;
         }

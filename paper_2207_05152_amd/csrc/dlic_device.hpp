@@ -401,43 +401,72 @@ struct NetF32x4 {
     return 16 * (n >> 4) + 4 * (n & 3) + ((n >> 2) & 3);
   }
 
+  // Layer 1 in two parts.  A decoder knows every feature of a pixel's window
+  // one wavefront step early except 9 (up-right) and 11 (left): l1_pre takes
+  // f0 and f1 of every lane group and f2 of groups 0 and 2 (features 8 and 10)
+  // and runs steps 0..8 of layer 1's chain; finish adds f2 of groups 1 and 3
+  // (features 9 and 11), runs steps 9..11 and the rest of the net.  The chain
+  // order is run's, so are the results, bit for bit.
+  struct L1 {
+    f4 acc[HALVES];
+  };
+
+  __device__ __forceinline__ L1 l1_pre(float f0, float f1, float f2) const {
+    const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    const int p = lane & 15, q = lane >> 4, j = lane & 3;
+    // the 12 features of pixel j in every lane 4 b + j (K order 0..11, as the
+    // 16x16 form's slots take them), through the layer-2 rows of the scratch
+    // (free until layer 2 ends)
+    float* ft = xs + 4 * ROW;
+    if (p < 4) {
+      ft[p * ROW + q] = f0;
+      ft[p * ROW + 4 + q] = f1;
+      if ((q & 1) == 0) ft[p * ROW + 8 + q] = f2;
+    }
+    wave_lds_handover();
+    const f4 fa = *reinterpret_cast<const f4*>(&ft[j * ROW]);
+    const f4 fb = *reinterpret_cast<const f4*>(&ft[j * ROW + 4]);
+    const float f8 = ft[j * ROW + 8];
+    const float fv[9] = {fa[0], fa[1], fa[2], fa[3], fb[0], fb[1], fb[2], fb[3], f8};
+    L1 l;
+#pragma unroll
+    for (int h = 0; h < HALVES; ++h) l.acc[h] = f4{c1[h][0], c1[h][1], c1[h][2], c1[h][3]};
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+      for (int h = 0; h < HALVES; ++h) l.acc[h] = mfma_f32_4x4(a1[h][k], fv[k], l.acc[h]);
+    return l;
+  }
+
   // Features as NetF32::run; the outputs of pixels 0..3 (lanes l % 16 < 4)
   // are NetF32<H>'s, the other lanes' are unspecified.
   __device__ __forceinline__ f4 run(float f0, float f1, float f2, const void* lds) const {
+    return finish(l1_pre(f0, f1, f2), f2, lds);
+  }
+
+  __device__ __forceinline__ f4 finish(L1 l, float f2, const void* lds) const {
     const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
     const int p = lane & 15, q = lane >> 4, j = lane & 3;
     float* h1t = xs;            // [pixel][chain step]
     float* h2t = xs + 4 * ROW;  // [pixel][neuron]
-    // layer 1 on the 4x4 form too: the 12 features of pixel j in every lane
-    // 4 b + j (K order 0..11, as the 16x16 form's slots take them), then
-    // neuron n = 16 n1 + 4 q + r goes to chain step 16 n1 + 4 r + q
-    float* ft = h2t;  // free until layer 2 ends
-    if (p < 4) {
-      ft[p * ROW + q] = f0;
-      ft[p * ROW + 4 + q] = f1;
-      ft[p * ROW + 8 + q] = f2;
-    }
+    float* ft = h2t;
+    if (p < 4 && (q & 1) != 0) ft[p * ROW + 8 + q] = f2;
     wave_lds_handover();
     {
-      const f4 fa = *reinterpret_cast<const f4*>(&ft[j * ROW]);
-      const f4 fb = *reinterpret_cast<const f4*>(&ft[j * ROW + 4]);
+      // steps 9..11, then neuron n = 16 n1 + 4 q + r goes to chain step
+      // 16 n1 + 4 r + q of layer 2
       const f4 fc = *reinterpret_cast<const f4*>(&ft[j * ROW + 8]);
-      const float fv[K_IN] = {fa[0], fa[1], fa[2], fa[3], fb[0], fb[1],
-                              fb[2], fb[3], fc[0], fc[1], fc[2], fc[3]};
-      f4 acc[HALVES];
 #pragma unroll
-      for (int h = 0; h < HALVES; ++h) acc[h] = f4{c1[h][0], c1[h][1], c1[h][2], c1[h][3]};
+      for (int k = 9; k < K_IN; ++k)
 #pragma unroll
-      for (int k = 0; k < K_IN; ++k)
-#pragma unroll
-        for (int h = 0; h < HALVES; ++h) acc[h] = mfma_f32_4x4(a1[h][k], fv[k], acc[h]);
+        for (int h = 0; h < HALVES; ++h) l.acc[h] = mfma_f32_4x4(a1[h][k], fc[k - 8], l.acc[h]);
       // lane 4 b + j holds neurons 64 h + 4 b + i of pixel j
       const int b = lane >> 2;
       const int c0 = 16 * (b >> 2) + (b & 3);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int h = 0; h < HALVES; ++h) h1t[j * ROW + 64 * h + c0 + 4 * i] = relu(acc[h][i]);
+        for (int h = 0; h < HALVES; ++h) h1t[j * ROW + 64 * h + c0 + 4 * i] = relu(l.acc[h][i]);
     }
     wave_lds_handover();
     // layer 2: the chain of H steps, both neuron halves at H = 128
