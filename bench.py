@@ -227,7 +227,7 @@ def measured_traffic(kernel: str):
 def precision_sweep(dl, torch, img, H, W, coder, hidden=128, reps=3):
     """Encode + decode of the same image with the 12-128-128-15 net stored as
     FP32, BF16 and FP8 e4m3: kernel-timed MPix/s, bpp and the bpp change
-    against FP32 (outside the timed region of the headline step)."""
+    against FP32 (outside the timed region of the main step)."""
     import synth
     weights = synth.xavier_mlp((12, hidden, hidden, 15), 3)
     n_px = H * W
@@ -284,8 +284,8 @@ def layout_sweep(dl, torch, img, H, W, model, probe, hidden,
                  layouts=((64, 4, 1), (64, 4, 3), (64, 4, 4), (128, 2, 1), (128, 2, 2),
                           (8, 32, 1), (16, 16, 1), (32, 8, 1), (256, 1, 1), (128, 4, 1),
                           (128, 4, 2), (192, 4, 1), (384, 4, 1), (48, 32, 1)), reps=3):
-    """The headline image and net coded with other coder layouts (G groups x L
-    lanes x S row strips per group).  Those up to 256 x 1 have the headline's 256
+    """The main step's image and net coded with other coder layouts (G groups x L
+    lanes x S row strips per group).  Those up to 256 x 1 have the main step's 256
     lanes; the decoder gives a pixel 16 coder lanes when L <= 4.  Strips spread
     over the image, and more lanes, cut the sequential sub-rounds per wavefront
     step, ceil(rows per strip / L); more lanes cost 4 flushed bytes per lane;
@@ -392,7 +392,7 @@ def deep_flops_per_px(hidden, k_in=12, n_out=256):
 def deep_sweep(dl, torch, img, H, W, hidden=128, layout=(48, 32), reps=2):
     """The paper's own network and head (six dense layers, softmax over 256 levels), BF16
     weights, on the same image: encode and decode kernel times, MPix/s, bpp and the
-    encoder density kernel's MFMA rate (outside the timed region of the headline step)."""
+    encoder density kernel's MFMA rate (outside the timed region of the main step)."""
     import synth
     m = dl.DeepModel(synth.xavier_deep(hidden, 3), "cuda:0")
     coder = dl.dlic_coder(*layout)
@@ -431,7 +431,7 @@ def volume_sweep(dl, torch, hidden=128, Z=35, size=256, layout=(8, 8), shifts=(0
     the step at which the first slice is complete; the same scan with a 12-input
     network, once with all slices in one 3-D wavefront and once slice by slice through the
     image decoder; and the 12-bit scan with 4096 output levels (outside the timed region of
-    the headline step)."""
+    the main step)."""
     import synth
     vol = torch.from_numpy(synth.mri_volume(2024, depth=Z, size=size)).cuda()
     vol12 = torch.from_numpy(synth.mri_volume(2024, depth=Z, size=size, bits=12).astype(np.int16)).cuda()
@@ -569,7 +569,7 @@ def main():
                     help="skip the extra decode with the in-kernel cycle counters (so that a "
                          "profiler's kernel averages cover the timed launches only)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the precision, batch and training sweeps after the headline step")
+                    help="skip the precision, batch and training sweeps after the main step")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the DLIC hot path here runs on a single MI355X "

@@ -77,7 +77,7 @@ def test_full_size_round_trip(dev, G, L):
 
 
 def test_full_size_round_trip_width128(dev):
-    # the 128-wide FP32 net at the headline layout: the decoder's 4-pixel form
+    # the 128-wide FP32 net at 64 groups x 4 lanes: the decoder's 4-pixel form
     # of layer 2 must reproduce the encoder's 16-pixel form bit for bit
     img = synth.synth_image(1536, 2048, 1)
     wts = synth.xavier_mlp((12, 128, 128, 15), 3)

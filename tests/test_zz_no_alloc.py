@@ -29,9 +29,9 @@ def _decode_both(dev, bits, model, h, w, coder):
 @pytest.mark.parametrize("dtype,width", [("fp32", 64), ("bf16", 128)])
 def test_noalloc_decode_matches_decode_twice(dev, dtype, width):
     model = dl.Model(synth.xavier_mlp((12, width, width, 15), 3), dev, dtype=dtype)
-    # first a large image (the headline layout, two row strips per group: one record row
-    # per strip), then a smaller one with one strip: the second call must not see the
-    # first's records (the array keeps the last call's contents)
+    # first a large image (2048x1536, 64 groups x 4 lanes, two row strips per group: one
+    # record row per strip), then a smaller one with one strip: the second call must not
+    # see the first's records (the array keeps the last call's contents)
     for h, w, G, L, S, seed in ((1536, 2048, 64, 4, 2, 1), (300, 257, 6, 32, 1, 2)):
         img = synth.synth_image(h, w, seed)
         coder = dl.dlic_coder(G, L, S)
