@@ -207,3 +207,22 @@ def test_errors(dev):
     dec, st2 = dl.decode(to_dev(np.frombuffer(bytes(raw), np.uint8), dev), m, check=False)
     torch.cuda.synchronize()
     assert st2 != 0 or not np.array_equal(dec.cpu().numpy(), img)
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "bf16", "fp8", "fp8a8"])
+@pytest.mark.parametrize("width,S", [(64, 2), (128, 2), (64, 3), (128, 5)])
+def test_every_precision_round_trips_with_strips(dev, dtype, width, S):
+    """Each network form of the decoder (4-pixel FP32, BF16, FP8 weights, FP8 weights and
+    activations) in its two-strip and its any-number-of-strips kernel."""
+    h, w, G, L = 120, 150, 4, 4
+    img = synth.synth_image(h, w, 31 + width + S)
+    wts = synth.xavier_mlp((12, width, width, 15), 3)
+    cal = [to_dev(synth.synth_image(64, 64, 1000 + i), dev) for i in range(2)]
+    m = dl.Model(wts, dev, dtype=dtype, calibration=cal if dtype == "fp8a8" else None)
+    coder = dl.dlic_coder(G, L, S)
+    say("strips precision", dtype, width, S)
+    bits = dl.encode(to_dev(img, dev), m, coder)
+    dec, st = dl.decode(bits, m, check=False)
+    torch.cuda.synchronize()
+    assert st == 0
+    assert np.array_equal(dec.cpu().numpy(), img)
